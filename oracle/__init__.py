@@ -1,0 +1,252 @@
+"""FP64 CPU oracle for volumetrically consistent Gaussian rasterisation.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark use it; the library never does.  It does not import the
+library and the library does not import it.
+
+The arithmetic lives in ``vgr_oracle.c`` (plain C, double precision, OpenMP
+over pixels); this module only compiles it, marshals numpy arrays and
+duck-typed scene / camera objects (attributes ``means, quats, scales, dens,
+sh, sh_degree`` and ``R, t, fx, fy, cx, cy, width, height, znear``).
+
+Passages followed (arXiv 2412.03378): the density mixture and Gaussian
+(Sec. 3.2), the alpha-blend without splatting (Sec. 4.1), the 1D Gaussian on
+a ray and its boxed full-line integral (Sec. 4.2, Supp. B), tomography as a
+sum of line integrals (Sec. 6.2).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vgr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cam(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32), ("znear", C.c_float),
+                ("pad", C.c_int32)]
+
+
+class _Settings(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
+                ("pad", C.c_int32), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
+
+
+@dataclass
+class Settings:
+    """Thresholds of the compositing rule (defaults follow the 3DGS
+    framework the paper builds on)."""
+    mode: str = "color"            # "color" | "xray"
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    x_min_xray: float = 1e-6
+    bg: tuple = (0.0, 0.0, 0.0)
+    act: str = "clamp"             # "clamp" | "softplus"
+
+    @staticmethod
+    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0)):
+        return Settings(mode=mode, alpha_min=1e-300, alpha_max=1.0 - 1e-12, T_min=0.0,
+                        x_min_xray=1e-300, bg=bg, act=act)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    fp = C.POINTER(C.c_float)
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    lp = C.POINTER(C.c_int64)
+    lib.orc_ray_integral.argtypes = [fp, fp, fp, C.c_float, dp, dp, dp]
+    lib.orc_sh_basis.argtypes = [C.c_int, dp, dp, dp]
+    lib.orc_render.argtypes = [C.c_int64, fp, fp, fp, fp, fp, C.POINTER(_Cam),
+                               C.POINTER(_Settings), C.c_int64, ip, dp, dp, lp, ip, dp, dp]
+    lib.orc_render_backward.argtypes = [C.c_int64, fp, fp, fp, fp, fp, C.POINTER(_Cam),
+                                        C.POINTER(_Settings), C.c_int64, ip, dp] + [dp] * 10
+    lib.orc_max_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def _cam(cam) -> _Cam:
+    c = _Cam()
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).reshape(9)]
+    c.t[:] = [float(v) for v in np.asarray(cam.t, np.float32).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def _settings(st: Settings, sh_degree: int) -> _Settings:
+    s = _Settings()
+    s.mode = 1 if st.mode == "xray" else 0
+    s.sh_degree = int(sh_degree)
+    s.act = 1 if st.act == "softplus" else 0
+    s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
+    s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
+    s.bg[:] = [float(v) for v in st.bg]
+    return s
+
+
+def all_pixels(cam) -> np.ndarray:
+    ys, xs = np.mgrid[0:int(cam.height), 0:int(cam.width)]
+    return np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
+
+
+def _scene_arrays(scene, mode):
+    means, quats = _f32(scene.means), _f32(scene.quats)
+    scales, dens = _f32(scene.scales), _f32(scene.dens)
+    sh = None
+    if mode != "xray":
+        sh = _f32(scene.sh)
+    return means, quats, scales, dens, sh
+
+
+def set_threads(n: int):
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def ray_integral(mean, quat, scale, dens, o, d):
+    """Full-line integral of one Gaussian along o + t d (d is normalised
+    here).  Returns dict(gamma, beta, Gmax, x, alpha)."""
+    lib = _load()
+    d = np.asarray(d, np.float64)
+    d = d / np.linalg.norm(d)
+    out = np.zeros(4, np.float64)
+    lib.orc_ray_integral(_ptr(_f32(mean), C.c_float), _ptr(_f32(quat), C.c_float),
+                         _ptr(_f32(scale), C.c_float), float(dens),
+                         _ptr(np.ascontiguousarray(o, np.float64), C.c_double),
+                         _ptr(np.ascontiguousarray(d), C.c_double), _ptr(out, C.c_double))
+    g, b, G, x = out
+    return dict(gamma=g, beta=b, Gmax=G, x=x, alpha=-math.expm1(-x))
+
+
+def sh_basis(degree, v):
+    """Real orthonormal SH (Condon-Shortley phase) at unit vector v:
+    returns (Y[(deg+1)^2], dY[(deg+1)^2, 3]) (gradient of the polynomial
+    extension)."""
+    lib = _load()
+    nb = (degree + 1) ** 2
+    Y = np.zeros(nb, np.float64)
+    dY = np.zeros((nb, 3), np.float64)
+    rc = lib.orc_sh_basis(int(degree), _ptr(np.ascontiguousarray(v, np.float64), C.c_double),
+                          _ptr(Y, C.c_double), _ptr(dY, C.c_double))
+    if rc:
+        raise ValueError("degree out of range")
+    return Y, dY
+
+
+def render(scene, cam, settings: Settings = None, pixels=None):
+    """Render one view.  ``pixels``: (P, 2) int array of (x, y), or None for
+    the whole image.  Returns dict with ``image`` ((C, P) or (C, H, W)),
+    ``T`` (final transmittance), ``last`` (index of the last blended
+    Gaussian, -1 if none), ``nblend``, ``margin`` (smallest relative
+    distance of any deciding test to its threshold) and ``untrunc`` (X-ray
+    sum without the x_min cut)."""
+    lib = _load()
+    st = settings or Settings()
+    full = pixels is None
+    pix = all_pixels(cam) if full else np.ascontiguousarray(np.asarray(pixels, np.int32))
+    P = pix.shape[0]
+    nch = 1 if st.mode == "xray" else 3
+    means, quats, scales, dens, sh = _scene_arrays(scene, st.mode)
+    out = np.zeros((P, nch), np.float64)
+    T = np.zeros(P, np.float64)
+    last = np.zeros(P, np.int64)
+    nblend = np.zeros(P, np.int32)
+    margin = np.zeros(P, np.float64)
+    untrunc = np.zeros(P, np.float64)
+    cam_s, set_s = _cam(cam), _settings(st, scene.sh_degree)
+    rc = lib.orc_render(int(means.shape[0]), _ptr(means, C.c_float), _ptr(quats, C.c_float),
+                        _ptr(scales, C.c_float), _ptr(dens, C.c_float), _ptr(sh, C.c_float),
+                        C.byref(cam_s), C.byref(set_s), P, _ptr(pix, C.c_int32),
+                        _ptr(out, C.c_double), _ptr(T, C.c_double), _ptr(last, C.c_int64),
+                        _ptr(nblend, C.c_int32), _ptr(margin, C.c_double),
+                        _ptr(untrunc, C.c_double))
+    if rc:
+        raise RuntimeError(f"orc_render failed ({rc})")
+    res = dict(image=out.T.copy(), T=T, last=last, nblend=nblend, margin=margin,
+               untrunc=untrunc, pixels=pix)
+    if full:
+        H, W = int(cam.height), int(cam.width)
+        res["image"] = res["image"].reshape(nch, H, W)
+        for k in ("T", "last", "nblend", "margin", "untrunc"):
+            res[k] = res[k].reshape(H, W)
+    return res
+
+
+def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=True):
+    """Gradients of sum(dL * image) w.r.t. means, quats, scales, dens, sh for
+    one view.  ``dL`` is (C, P) for a pixel list or (C, H, W) for the whole
+    image.  Returns dict of FP64 gradients and, if ``with_abs``, the sums of
+    absolute per-pixel contributions (``abs_*``) used to scale tolerances."""
+    lib = _load()
+    st = settings or Settings()
+    full = pixels is None
+    pix = all_pixels(cam) if full else np.ascontiguousarray(np.asarray(pixels, np.int32))
+    P = pix.shape[0]
+    nch = 1 if st.mode == "xray" else 3
+    g = np.ascontiguousarray(np.asarray(dL, np.float64).reshape(nch, P).T)
+    means, quats, scales, dens, sh = _scene_arrays(scene, st.mode)
+    n = means.shape[0]
+    nb = (scene.sh_degree + 1) ** 2
+    shapes = dict(means=(n, 3), quats=(n, 4), scales=(n, 3), dens=(n,), sh=(n, nb, 3))
+    grads = {k: np.zeros(s, np.float64) for k, s in shapes.items()}
+    absg = {k: (np.zeros(s, np.float64) if with_abs else None) for k, s in shapes.items()}
+    cam_s, set_s = _cam(cam), _settings(st, scene.sh_degree)
+    keys = ("means", "quats", "scales", "dens", "sh")
+    rc = lib.orc_render_backward(
+        int(n), _ptr(means, C.c_float), _ptr(quats, C.c_float), _ptr(scales, C.c_float),
+        _ptr(dens, C.c_float), _ptr(sh, C.c_float), C.byref(cam_s), C.byref(set_s), P,
+        _ptr(pix, C.c_int32), _ptr(g, C.c_double),
+        *[_ptr(grads[k], C.c_double) for k in keys],
+        *[_ptr(absg[k], C.c_double) for k in keys])
+    if rc:
+        raise RuntimeError(f"orc_render_backward failed ({rc})")
+    res = dict(grads)
+    if with_abs:
+        for k in keys:
+            res["abs_" + k] = absg[k]
+    return res

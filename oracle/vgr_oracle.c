@@ -1,0 +1,680 @@
+/*
+ * FP64 reference renderer for volumetrically consistent 3D Gaussian
+ * rasterisation (arXiv 2412.03378).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP library is
+ * checked against.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the library never does.  It shares no
+ * code, header, table or constant with the HIP path.
+ *
+ * Everything is evaluated per pixel, over every Gaussian, in double precision,
+ * straight from the paper's definitions, in world space:
+ *
+ *   density field        sigma(x) = sum_i kappa_i G_i(x)                (Sec. 3.2, eq. gauss_mixture)
+ *   unnormalised Gaussian G_i(x) = exp(-1/2 (x-mu)^T Sigma^-1 (x-mu))   (Sec. 3.2, eq. 3dgs_pdf)
+ *   ray                   r(t) = o + t d, |d| = 1, through the pixel centre
+ *   1D Gaussian on a ray  gamma = (mu-o)^T Sigma^-1 d / d^T Sigma^-1 d,
+ *                         beta  = (d^T Sigma^-1 d)^(-1/2)                (Sec. 4.2, eq. betagamma)
+ *   full-line integral    x = kappa sqrt(2 pi) beta G(o + gamma d),
+ *                         alpha = 1 - exp(-x)                            (Sec. 4.2, eq. our_trans_final)
+ *   compositing           C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j) (Sec. 4.1, eq. our_alpha_blend)
+ *   X-ray mode            I = sum_i x_i  (order independent)             (Sec. 6.2)
+ *
+ * Readings where the paper is silent (each is a settings field):
+ *   - Gaussians whose view-space mean depth is <= znear are dropped; the
+ *     remaining ones are composited in ascending (depth key, index) order,
+ *     where the depth key is the FP32 value fmaf(R20,mx, fmaf(R21,my,
+ *     fmaf(R22,mz, t2))) so that both implementations order ties identically.
+ *   - a Gaussian is skipped when alpha < alpha_min (x < -ln(1-alpha_min));
+ *     alpha is clamped to alpha_max (zero gradient when clamped);
+ *   - compositing stops before Gaussian i when T (1 - alpha_i) < T_min
+ *     (Gaussian i is not blended); afterwards C += T bg.
+ *   - colour c = act(sum_k sh_k Y_k(v) + 0.5), v = normalize(mu - o), with
+ *     real orthonormal spherical harmonics (Condon-Shortley phase), act =
+ *     max(.,0) or softplus with sharpness 10 (Supp. D).
+ *
+ * Decision margins: for every threshold test that decides the output (skip,
+ * clamp, terminate) the oracle reports the smallest relative distance to the
+ * threshold, so callers can set aside pixels where two results are both
+ * correct up to rounding.
+ *
+ * The backward pass is the analytic chain rule of the same formulas, with the
+ * transmittance in front of each Gaussian taken from forward prefix products.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+typedef struct {
+    float R[9];     /* world -> view rotation, row-major */
+    float t[3];     /* world -> view translation */
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float znear;
+    int32_t pad;
+} orc_camera;
+
+typedef struct {
+    int32_t mode;       /* 0 colour, 1 X-ray */
+    int32_t sh_degree;  /* 0..3 */
+    int32_t act;        /* 0 max(.,0), 1 softplus(10 y)/10 */
+    int32_t pad;
+    double alpha_min, alpha_max, T_min, x_min_xray;
+    double bg[3];
+} orc_settings;
+
+/* ------------------------------------------------------------------------ */
+/* small linear algebra                                                      */
+
+static void quat_rotation(const float qf[4], double R[9], double qn[4], double *qlen)
+{
+    double w = qf[0], x = qf[1], y = qf[2], z = qf[3];
+    double len = sqrt(w * w + x * x + y * y + z * z);
+    w /= len; x /= len; y /= len; z /= len;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+    if (qn) { qn[0] = w; qn[1] = x; qn[2] = y; qn[3] = z; }
+    if (qlen) *qlen = len;
+}
+
+/* Sigma^-1 = R diag(s^-2) R^T  (row-major 3x3) */
+static void precision_matrix(const double R[9], const float s[3], double P[9])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k)
+                acc += R[i * 3 + k] * R[j * 3 + k] / ((double)s[k] * (double)s[k]);
+            P[i * 3 + j] = acc;
+        }
+}
+
+static double quad_form(const double P[9], const double a[3], const double b[3])
+{
+    double acc = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) acc += a[i] * P[i * 3 + j] * b[j];
+    return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray integral of one Gaussian (Sec. 4.2).                                  */
+
+typedef struct {
+    double gamma, beta, Gmax, x;
+    double v[3];     /* mu - (o + gamma d) */
+    double a;        /* d^T P d */
+} ray_terms;
+
+static void ray_integral(const double mu[3], const double P[9], double kappa,
+                         const double o[3], const double d[3], ray_terms *rt)
+{
+    double dm[3] = { mu[0] - o[0], mu[1] - o[1], mu[2] - o[2] };
+    double a = quad_form(P, d, d);
+    double b = quad_form(P, dm, d);
+    double gamma = b / a;
+    double beta = 1.0 / sqrt(a);
+    double xp[3], diff[3];
+    for (int k = 0; k < 3; ++k) {
+        xp[k] = o[k] + gamma * d[k];
+        diff[k] = xp[k] - mu[k];
+    }
+    double Gmax = exp(-0.5 * quad_form(P, diff, diff));
+    rt->gamma = gamma;
+    rt->beta = beta;
+    rt->Gmax = Gmax;
+    rt->a = a;
+    for (int k = 0; k < 3; ++k) rt->v[k] = -diff[k];
+    rt->x = kappa * sqrt(2.0 * ORC_PI) * beta * Gmax;
+}
+
+/* Exported for closed-form pins: out = {gamma, beta, Gmax, x}. */
+int orc_ray_integral(const float mean[3], const float quat[4], const float scale[3],
+                     float dens, const double o[3], const double d[3], double out[4])
+{
+    double R[9], P[9], mu[3] = { mean[0], mean[1], mean[2] };
+    quat_rotation(quat, R, NULL, NULL);
+    precision_matrix(R, scale, P);
+    ray_terms rt;
+    ray_integral(mu, P, (double)dens, o, d, &rt);
+    out[0] = rt.gamma; out[1] = rt.beta; out[2] = rt.Gmax; out[3] = rt.x;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics from the associated Legendre functions.          */
+/*   Y_l^0  = K_l^0 P_l(z)                                                   */
+/*   Y_l^m  = sqrt2 K_l^m (-1)^m (d^m P_l/dz^m)(z) Re((x+iy)^m)   m > 0       */
+/*   Y_l^-m = sqrt2 K_l^m (-1)^m (d^m P_l/dz^m)(z) Im((x+iy)^m)   m > 0       */
+/* with K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), valid on the unit sphere  */
+/* (sin^m(theta) e^{i m phi} = (x+iy)^m).  Index k = l^2 + l + m.            */
+/* The gradient is that of this polynomial extension; callers project it     */
+/* onto the tangent plane.                                                   */
+
+#define ORC_MAX_DEG 4
+
+static double polyval(const double *c, int n, double z)
+{
+    double acc = 0;
+    for (int k = n - 1; k >= 0; --k) acc = acc * z + c[k];
+    return acc;
+}
+
+static double factorial(int n)
+{
+    double f = 1;
+    for (int k = 2; k <= n; ++k) f *= k;
+    return f;
+}
+
+int orc_sh_basis(int deg, const double v[3], double *Y, double *dY)
+{
+    if (deg < 0 || deg > ORC_MAX_DEG) return -1;
+    /* Legendre polynomial coefficients by Bonnet's recurrence */
+    double Pl[ORC_MAX_DEG + 2][ORC_MAX_DEG + 2];
+    memset(Pl, 0, sizeof Pl);
+    Pl[0][0] = 1;
+    Pl[1][1] = 1;
+    for (int l = 1; l < ORC_MAX_DEG; ++l)
+        for (int k = 0; k <= l + 1; ++k) {
+            double zp = k > 0 ? Pl[l][k - 1] : 0;
+            Pl[l + 1][k] = ((2 * l + 1) * zp - l * Pl[l - 1][k]) / (l + 1);
+        }
+    double x = v[0], y = v[1], z = v[2];
+    /* powers (x+iy)^m */
+    double re[ORC_MAX_DEG + 1], im[ORC_MAX_DEG + 1];
+    re[0] = 1; im[0] = 0;
+    for (int m = 1; m <= ORC_MAX_DEG; ++m) {
+        re[m] = re[m - 1] * x - im[m - 1] * y;
+        im[m] = re[m - 1] * y + im[m - 1] * x;
+    }
+    for (int l = 0; l <= deg; ++l) {
+        /* derivatives d^m P_l / dz^m for m = 0..l+1 */
+        double D[ORC_MAX_DEG + 3][ORC_MAX_DEG + 2];
+        memset(D, 0, sizeof D);
+        for (int k = 0; k <= l; ++k) D[0][k] = Pl[l][k];
+        for (int m = 1; m <= l + 1; ++m)
+            for (int k = 0; k <= l; ++k) D[m][k] = (k + 1 <= l) ? (k + 1) * D[m - 1][k + 1] : 0;
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double K = sqrt((2 * l + 1) / (4 * ORC_PI) * factorial(l - am) / factorial(l + am));
+            double dm = polyval(D[am], l + 1, z);
+            double dm1 = polyval(D[am + 1], l + 1, z);
+            int k = l * l + l + m;
+            double yv, gx, gy, gz;
+            if (m == 0) {
+                yv = K * dm; gx = 0; gy = 0; gz = K * dm1;
+            } else {
+                double c = sqrt(2.0) * K * ((am & 1) ? -1.0 : 1.0);
+                if (m > 0) {
+                    yv = c * dm * re[am];
+                    gx = c * dm * am * re[am - 1];
+                    gy = -c * dm * am * im[am - 1];
+                    gz = c * dm1 * re[am];
+                } else {
+                    yv = c * dm * im[am];
+                    gx = c * dm * am * im[am - 1];
+                    gy = c * dm * am * re[am - 1];
+                    gz = c * dm1 * im[am];
+                }
+            }
+            Y[k] = yv;
+            if (dY) { dY[3 * k] = gx; dY[3 * k + 1] = gy; dY[3 * k + 2] = gz; }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-view set-up                                                           */
+
+typedef struct {
+    int64_t n;
+    int64_t nvis;
+    int64_t *order;      /* visible Gaussians, ascending (key, index) */
+    float *key;
+    double *P;           /* n x 9 world-space Sigma^-1 */
+    double *rgb;         /* n x 3 colour for this view */
+    double *raw;         /* n x 3 colour before activation */
+    double o[3];
+} view_state;
+
+static const float *g_sort_key;
+
+static int cmp_key(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    float ka = g_sort_key[a], kb = g_sort_key[b];
+    if (ka < kb) return -1;
+    if (ka > kb) return 1;
+    return (a > b) - (a < b);
+}
+
+static double act_apply(int act, double y)
+{
+    if (act == 1) {
+        double s = 10.0 * y;
+        return (s > 0 ? s + log1p(exp(-s)) : log1p(exp(s))) / 10.0;
+    }
+    return y > 0 ? y : 0;
+}
+
+static double act_grad(int act, double y)
+{
+    if (act == 1) return 1.0 / (1.0 + exp(-10.0 * y));
+    return y > 0 ? 1.0 : 0.0;
+}
+
+/* Inverse of the world->view rotation as stored (FP32 storage makes R only
+   approximately orthonormal, so the exact inverse of the affine map is used). */
+static void inverse3(const float *Rf, double Ri[9])
+{
+    double R[9];
+    for (int k = 0; k < 9; ++k) R[k] = Rf[k];
+    double c0 = R[4] * R[8] - R[5] * R[7];
+    double c1 = R[5] * R[6] - R[3] * R[8];
+    double c2 = R[3] * R[7] - R[4] * R[6];
+    double det = R[0] * c0 + R[1] * c1 + R[2] * c2;
+    Ri[0] = c0 / det; Ri[1] = (R[2] * R[7] - R[1] * R[8]) / det; Ri[2] = (R[1] * R[5] - R[2] * R[4]) / det;
+    Ri[3] = c1 / det; Ri[4] = (R[0] * R[8] - R[2] * R[6]) / det; Ri[5] = (R[2] * R[3] - R[0] * R[5]) / det;
+    Ri[6] = c2 / det; Ri[7] = (R[1] * R[6] - R[0] * R[7]) / det; Ri[8] = (R[0] * R[4] - R[1] * R[3]) / det;
+}
+
+/* world-space camera centre o = -R^-1 t */
+static void camera_origin(const orc_camera *cam, double o[3])
+{
+    double Ri[9];
+    inverse3(cam->R, Ri);
+    for (int i = 0; i < 3; ++i)
+        o[i] = -(Ri[i * 3] * cam->t[0] + Ri[i * 3 + 1] * cam->t[1] + Ri[i * 3 + 2] * cam->t[2]);
+}
+
+/* world-space unit direction of the ray through the centre of pixel (px, py):
+   the view-space ray s*u with u = ((px+0.5-cx)/fx, (py+0.5-cy)/fy, 1) */
+static void pixel_ray(const orc_camera *cam, int px, int py, double d[3])
+{
+    double u[3] = { ((double)px + 0.5 - cam->cx) / cam->fx,
+                    ((double)py + 0.5 - cam->cy) / cam->fy, 1.0 };
+    double Ri[9];
+    inverse3(cam->R, Ri);
+    double len = 0;
+    for (int i = 0; i < 3; ++i) {
+        d[i] = Ri[i * 3] * u[0] + Ri[i * 3 + 1] * u[1] + Ri[i * 3 + 2] * u[2];
+        len += d[i] * d[i];
+    }
+    len = sqrt(len);
+    for (int i = 0; i < 3; ++i) d[i] /= len;
+}
+
+static float depth_key(const orc_camera *cam, const float *mu)
+{
+    const float *R = cam->R;
+    return fmaf(R[6], mu[0], fmaf(R[7], mu[1], fmaf(R[8], mu[2], cam->t[2])));
+}
+
+static int view_setup(view_state *vs, int64_t n, const float *means, const float *quats,
+                      const float *scales, const float *sh, const orc_camera *cam,
+                      const orc_settings *st)
+{
+    memset(vs, 0, sizeof *vs);
+    vs->n = n;
+    vs->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    vs->key = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    vs->P = (double *)malloc(sizeof(double) * 9 * (size_t)(n > 0 ? n : 1));
+    vs->rgb = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    vs->raw = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw) return -3;
+    camera_origin(cam, vs->o);
+    int nb = (st->sh_degree + 1) * (st->sh_degree + 1);
+    int64_t nvis = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double R[9];
+        quat_rotation(quats + 4 * i, R, NULL, NULL);
+        precision_matrix(R, scales + 3 * i, vs->P + 9 * i);
+        vs->key[i] = depth_key(cam, means + 3 * i);
+        if (st->mode == 0) {
+            double v[3], len = 0, Y[(ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)];
+            for (int k = 0; k < 3; ++k) { v[k] = means[3 * i + k] - vs->o[k]; len += v[k] * v[k]; }
+            len = sqrt(len);
+            for (int k = 0; k < 3; ++k) v[k] /= len;
+            orc_sh_basis(st->sh_degree, v, Y, NULL);
+            for (int ch = 0; ch < 3; ++ch) {
+                double acc = 0.5;
+                for (int k = 0; k < nb; ++k) acc += sh[((size_t)i * nb + k) * 3 + ch] * Y[k];
+                vs->raw[3 * i + ch] = acc;
+                vs->rgb[3 * i + ch] = act_apply(st->act, acc);
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (vs->key[i] > cam->znear) vs->order[nvis++] = i;
+    g_sort_key = vs->key;
+    qsort(vs->order, (size_t)nvis, sizeof(int64_t), cmp_key);
+    vs->nvis = nvis;
+    return 0;
+}
+
+static void view_free(view_state *vs)
+{
+    free(vs->order); free(vs->key); free(vs->P); free(vs->rgb); free(vs->raw);
+}
+
+static double rel_margin(double v, double thr)
+{
+    return fabs(v - thr) / fabs(thr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward.                                                                  */
+
+typedef struct {
+    int64_t idx;
+    double x, alpha, T;   /* T: transmittance in front of this Gaussian */
+    int clamped;
+} blend_rec;
+
+typedef struct {
+    blend_rec *rec;
+    int64_t cnt, cap;
+} blend_list;
+
+static void list_push(blend_list *bl, blend_rec r)
+{
+    if (bl->cnt == bl->cap) {
+        bl->cap = bl->cap ? 2 * bl->cap : 64;
+        bl->rec = (blend_rec *)realloc(bl->rec, sizeof(blend_rec) * (size_t)bl->cap);
+    }
+    bl->rec[bl->cnt++] = r;
+}
+
+/* Composite one pixel; fills out[3] (colour) or out[0] (X-ray). */
+static void shade_pixel(const view_state *vs, const float *means, const float *dens,
+                        const orc_settings *st, const double d[3], double *out,
+                        double *T_out, int64_t *last_out, int32_t *nblend_out,
+                        double *margin_out, double *untrunc_out, blend_list *bl)
+{
+    double margin = INFINITY;
+    if (st->mode == 1) {
+        /* X-ray: sum of line integrals, every visible Gaussian, any order */
+        double I = 0, full = 0;
+        int32_t cnt = 0;
+        for (int64_t r = 0; r < vs->nvis; ++r) {
+            int64_t i = vs->order[r];
+            double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+            ray_terms rt;
+            ray_integral(mu, vs->P + 9 * i, (double)dens[i], vs->o, d, &rt);
+            full += rt.x;
+            double m = rel_margin(rt.x, st->x_min_xray);
+            if (m < margin) margin = m;
+            if (rt.x >= st->x_min_xray) {
+                I += rt.x;
+                ++cnt;
+                if (bl) {
+                    blend_rec br = { i, rt.x, 0, 0, 0 };
+                    list_push(bl, br);
+                }
+            }
+        }
+        out[0] = I;
+        if (T_out) *T_out = exp(-I);
+        if (last_out) *last_out = -1;
+        if (nblend_out) *nblend_out = cnt;
+        if (margin_out) *margin_out = margin;
+        if (untrunc_out) *untrunc_out = full;
+        return;
+    }
+    double tau = -log1p(-st->alpha_min);
+    double xmax = -log1p(-st->alpha_max);
+    double T = 1.0, C[3] = { 0, 0, 0 };
+    int64_t last = -1;
+    int32_t cnt = 0;
+    for (int64_t r = 0; r < vs->nvis; ++r) {
+        int64_t i = vs->order[r];
+        double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+        ray_terms rt;
+        ray_integral(mu, vs->P + 9 * i, (double)dens[i], vs->o, d, &rt);
+        double m = rel_margin(rt.x, tau);
+        if (m < margin) margin = m;
+        if (rt.x < tau) continue;                      /* alpha < alpha_min */
+        double alpha = -expm1(-rt.x);
+        int clamped = 0;
+        m = rel_margin(rt.x, xmax);
+        if (m < margin) margin = m;
+        if (alpha > st->alpha_max) { alpha = st->alpha_max; clamped = 1; }
+        double Tn = T * (1.0 - alpha);
+        if (st->T_min > 0) {
+            m = rel_margin(Tn, st->T_min);
+            if (m < margin) margin = m;
+        }
+        if (Tn < st->T_min) break;                     /* stop before blending i */
+        for (int ch = 0; ch < 3; ++ch) C[ch] += vs->rgb[3 * i + ch] * alpha * T;
+        if (bl) {
+            blend_rec br = { i, rt.x, alpha, T, clamped };
+            list_push(bl, br);
+        }
+        T = Tn;
+        last = i;
+        ++cnt;
+    }
+    for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * st->bg[ch];
+    if (T_out) *T_out = T;
+    if (last_out) *last_out = last;
+    if (nblend_out) *nblend_out = cnt;
+    if (margin_out) *margin_out = margin;
+    if (untrunc_out) *untrunc_out = 0;
+}
+
+int orc_render(int64_t n, const float *means, const float *quats, const float *scales,
+               const float *dens, const float *sh, const orc_camera *cam,
+               const orc_settings *st, int64_t npix, const int32_t *pix, double *out,
+               double *T_out, int64_t *last_out, int32_t *nblend_out, double *margin_out,
+               double *untrunc_out)
+{
+    if (n < 0 || npix < 0 || !cam || !st) return -1;
+    if (st->mode == 0 && n > 0 && !sh) return -1;
+    view_state vs;
+    int rc = view_setup(&vs, n, means, quats, scales, sh, cam, st);
+    if (rc) { view_free(&vs); return rc; }
+    int C = st->mode == 1 ? 1 : 3;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npix; ++p) {
+        double d[3];
+        pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
+        shade_pixel(&vs, means, dens, st, d, out + C * p, T_out ? T_out + p : NULL,
+                    last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
+                    margin_out ? margin_out + p : NULL, untrunc_out ? untrunc_out + p : NULL,
+                    NULL);
+    }
+    view_free(&vs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward.                                                                 */
+
+/* dR/dq for R(q) with q = (w, x, y, z) unit; J[c][9] */
+static void rot_jacobian(const double q[4], double J[4][9])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double Jw[9] = { 0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0 };
+    double Jx[9] = { 0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x };
+    double Jy[9] = { -4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y };
+    double Jz[9] = { -4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0 };
+    memcpy(J[0], Jw, sizeof Jw);
+    memcpy(J[1], Jx, sizeof Jx);
+    memcpy(J[2], Jy, sizeof Jy);
+    memcpy(J[3], Jz, sizeof Jz);
+}
+
+static void atomic_add(double *dst, double v)
+{
+    #pragma omp atomic
+    *dst += v;
+}
+
+typedef struct {
+    double *g_means, *g_quats, *g_scales, *g_dens, *g_sh;
+    double *a_means, *a_quats, *a_scales, *a_dens, *a_sh;
+} grad_out;
+
+static void add2(double *g, double *a, double v)
+{
+    atomic_add(g, v);
+    if (a) atomic_add(a, fabs(v));
+}
+
+/* Chain dL/dx (line integral of Gaussian i on ray (o, d)) to mu, q, s, kappa. */
+static void chain_integral(int64_t i, double gx, const float *means, const float *quats,
+                           const float *scales, const float *dens, const double o[3],
+                           const double d[3], grad_out *go)
+{
+    double R[9], qn[4], qlen, P[9];
+    quat_rotation(quats + 4 * i, R, qn, &qlen);
+    precision_matrix(R, scales + 3 * i, P);
+    double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+    double kappa = dens[i];
+    ray_terms rt;
+    ray_integral(mu, P, kappa, o, d, &rt);
+    /* x = kappa sqrt(2pi) a^-1/2 exp(-D^2/2),  D^2 = v^T P v, v = mu - o - gamma d
+       dx/dkappa = sqrt(2pi) beta Gmax
+       dx/dP     = x (-1/2 d d^T / a - 1/2 v v^T)
+       dx/dmu    = -x P v                                                   */
+    double x = rt.x;
+    add2(go->g_dens + i, go->a_dens ? go->a_dens + i : NULL, gx * sqrt(2 * ORC_PI) * rt.beta * rt.Gmax);
+    double G[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            G[r * 3 + c] = gx * x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
+    for (int r = 0; r < 3; ++r) {
+        double pv = 0;
+        for (int c = 0; c < 3; ++c) pv += P[r * 3 + c] * rt.v[c];
+        add2(go->g_means + 3 * i + r, go->a_means ? go->a_means + 3 * i + r : NULL, -gx * x * pv);
+    }
+    /* P = sum_k s_k^-2 r_k r_k^T, r_k = column k of R */
+    double dR[9];
+    for (int k = 0; k < 3; ++k) {
+        double s = scales[3 * i + k];
+        double rk[3] = { R[k], R[3 + k], R[6 + k] };
+        double Gr[3];
+        for (int r = 0; r < 3; ++r) Gr[r] = G[r * 3] * rk[0] + G[r * 3 + 1] * rk[1] + G[r * 3 + 2] * rk[2];
+        double rGr = rk[0] * Gr[0] + rk[1] * Gr[1] + rk[2] * Gr[2];
+        add2(go->g_scales + 3 * i + k, go->a_scales ? go->a_scales + 3 * i + k : NULL,
+             -2.0 * rGr / (s * s * s));
+        for (int r = 0; r < 3; ++r) dR[r * 3 + k] = 2.0 * Gr[r] / (s * s);
+    }
+    double J[4][9], dqn[4];
+    rot_jacobian(qn, J);
+    for (int c = 0; c < 4; ++c) {
+        double acc = 0;
+        for (int e = 0; e < 9; ++e) acc += dR[e] * J[c][e];
+        dqn[c] = acc;
+    }
+    double dot = qn[0] * dqn[0] + qn[1] * dqn[1] + qn[2] * dqn[2] + qn[3] * dqn[3];
+    for (int c = 0; c < 4; ++c)
+        add2(go->g_quats + 4 * i + c, go->a_quats ? go->a_quats + 4 * i + c : NULL,
+             (dqn[c] - qn[c] * dot) / qlen);
+}
+
+/* Chain dL/d(colour after activation) to the SH coefficients and mu. */
+static void chain_colour(int64_t i, const double gc[3], const view_state *vs,
+                         const float *means, const float *sh, const orc_settings *st,
+                         grad_out *go)
+{
+    int nb = (st->sh_degree + 1) * (st->sh_degree + 1);
+    double v[3], len = 0;
+    for (int k = 0; k < 3; ++k) { v[k] = means[3 * i + k] - vs->o[k]; len += v[k] * v[k]; }
+    len = sqrt(len);
+    for (int k = 0; k < 3; ++k) v[k] /= len;
+    double Y[(ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)], dY[3 * (ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)];
+    orc_sh_basis(st->sh_degree, v, Y, dY);
+    double gv[3] = { 0, 0, 0 };
+    for (int ch = 0; ch < 3; ++ch) {
+        double graw = gc[ch] * act_grad(st->act, vs->raw[3 * i + ch]);
+        for (int k = 0; k < nb; ++k) {
+            size_t e = ((size_t)i * nb + k) * 3 + ch;
+            add2(go->g_sh + e, go->a_sh ? go->a_sh + e : NULL, graw * Y[k]);
+            for (int j = 0; j < 3; ++j) gv[j] += graw * sh[e] * dY[3 * k + j];
+        }
+    }
+    double vg = v[0] * gv[0] + v[1] * gv[1] + v[2] * gv[2];
+    for (int j = 0; j < 3; ++j)
+        add2(go->g_means + 3 * i + j, go->a_means ? go->a_means + 3 * i + j : NULL,
+             (gv[j] - v[j] * vg) / len);
+}
+
+int orc_render_backward(int64_t n, const float *means, const float *quats, const float *scales,
+                        const float *dens, const float *sh, const orc_camera *cam,
+                        const orc_settings *st, int64_t npix, const int32_t *pix,
+                        const double *dL, double *g_means, double *g_quats, double *g_scales,
+                        double *g_dens, double *g_sh, double *a_means, double *a_quats,
+                        double *a_scales, double *a_dens, double *a_sh)
+{
+    if (n < 0 || npix < 0 || !cam || !st) return -1;
+    if (st->mode == 0 && n > 0 && !sh) return -1;
+    view_state vs;
+    int rc = view_setup(&vs, n, means, quats, scales, sh, cam, st);
+    if (rc) { view_free(&vs); return rc; }
+    grad_out go = { g_means, g_quats, g_scales, g_dens, g_sh,
+                    a_means, a_quats, a_scales, a_dens, a_sh };
+    int C = st->mode == 1 ? 1 : 3;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npix; ++p) {
+        const double *g = dL + C * p;
+        if (C == 1 ? g[0] == 0 : (g[0] == 0 && g[1] == 0 && g[2] == 0)) continue;
+        double d[3], out[3];
+        pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
+        blend_list bl = { NULL, 0, 0 };
+        shade_pixel(&vs, means, dens, st, d, out, NULL, NULL, NULL, NULL, NULL, &bl);
+        if (st->mode == 1) {
+            for (int64_t r = 0; r < bl.cnt; ++r)
+                chain_integral(bl.rec[r].idx, g[0], means, quats, scales, dens, vs.o, d, &go);
+        } else {
+            /* S: colour composited behind the current Gaussian, ending in bg */
+            double S[3] = { st->bg[0], st->bg[1], st->bg[2] };
+            for (int64_t r = bl.cnt - 1; r >= 0; --r) {
+                const blend_rec *br = &bl.rec[r];
+                int64_t i = br->idx;
+                double galpha = 0, gc[3];
+                for (int ch = 0; ch < 3; ++ch) {
+                    double c = vs.rgb[3 * i + ch];
+                    galpha += g[ch] * br->T * (c - S[ch]);
+                    gc[ch] = g[ch] * br->alpha * br->T;
+                }
+                if (!br->clamped)
+                    chain_integral(i, galpha * exp(-br->x), means, quats, scales, dens, vs.o, d, &go);
+                chain_colour(i, gc, &vs, means, sh, st, &go);
+                for (int ch = 0; ch < 3; ++ch)
+                    S[ch] = vs.rgb[3 * i + ch] * br->alpha + (1.0 - br->alpha) * S[ch];
+            }
+        }
+        free(bl.rec);
+    }
+    view_free(&vs);
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
