@@ -1,0 +1,199 @@
+/*
+ * vgr.h - C ABI of libvgr, an MI355X (gfx950) implementation of the hot path
+ * of "Volumetrically Consistent 3D Gaussian Rasterization" (arXiv 2412.03378).
+ *
+ * What is computed.  A scene is a mixture of 3D Gaussians with density
+ * sigma(x) = sum_i kappa_i G_i(x) (Sec. 3.2, eq. gauss_mixture).  For the ray
+ * o + t d through a pixel centre (|d| = 1), each Gaussian's full-line
+ * integral is x_i = kappa_i sqrt(2 pi) beta_i G_i(o + gamma_i d) with
+ * beta_i = (d^T Sigma_i^-1 d)^(-1/2) (Sec. 4.2, eq. betagamma and the boxed
+ * eq. our_trans_final), its opacity alpha_i = 1 - exp(-x_i), and colour mode
+ * composites C = sum_i c_i alpha_i prod_{j<i}(1 - alpha_j) front to back
+ * (Sec. 4.1, eq. our_alpha_blend).  X-ray mode returns I = sum_i x_i
+ * (Sec. 6.2, Beer-Lambert line integral).  The rules the paper leaves open
+ * (thresholds, order of ties, colour model) are fields of vgr_settings and are
+ * documented there.
+ *
+ * Conventions shared by every entry point.
+ *   - Return value: VGR_OK (0) or a negative VGR_ERR_* code; the message of
+ *     the last failure is returned by vgr_last_error().  Nothing is thrown.
+ *   - Pointers are DEVICE pointers (HIP, the context's device) to contiguous
+ *     FP32 row-major arrays owned by the caller, unless marked "host".  The
+ *     library never frees caller memory.
+ *   - All GPU work is enqueued on the context's stream (vgr_set_stream) and
+ *     the calls return without waiting for it, except where noted.
+ *   - A context is not thread safe; use one context per host thread / stream.
+ *   - The context owns its workspace (device memory that only grows) and the
+ *     state the last forward saved for the backward.
+ */
+#ifndef VGR_H
+#define VGR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VGR_OK = 0,
+    VGR_ERR_INVALID_ARG = -1,   /* a null pointer, bad size or bad setting */
+    VGR_ERR_HIP = -2,           /* a HIP runtime call failed */
+    VGR_ERR_OOM = -3,           /* workspace allocation failed */
+    VGR_ERR_CAPACITY = -4,      /* a fixed-capacity (graph) run overflowed */
+    VGR_ERR_NOT_CAPTURED = -5,  /* vgr_graph_launch without a captured graph */
+    VGR_ERR_NO_FORWARD = -6     /* backward / aux query without a forward */
+};
+
+/* Pinhole camera (host struct).  World -> view: x_v = R x_w + t, OpenCV axes
+ * (x right, y down, z forward).  Pixel (px, py) has its centre at
+ * (px + 0.5, py + 0.5); its view-space ray direction is proportional to
+ * ((px + 0.5 - cx)/fx, (py + 0.5 - cy)/fy, 1).  Gaussians whose view-space
+ * mean depth is <= znear are not rendered. */
+typedef struct {
+    float R[9];          /* row-major rotation */
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float znear;
+    int32_t reserved;
+} vgr_camera;
+
+enum { VGR_MODE_COLOR = 0, VGR_MODE_XRAY = 1 };
+enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
+
+/* Rendering rules.  Defaults in brackets (vgr_default_settings).
+ *   mode        colour compositing or X-ray line integrals [COLOR]
+ *   sh_degree   0..3, real spherical harmonics with the Condon-Shortley
+ *               phase, basis index k = l^2 + l + m [0]
+ *   alpha_min   a Gaussian with alpha < alpha_min is skipped for that pixel
+ *               [1/255]
+ *   alpha_max   alpha is clamped to alpha_max, with zero gradient [0.99]
+ *   T_min       compositing stops before the Gaussian that would take the
+ *               transmittance below T_min; it is not blended [1e-4]
+ *   x_min_xray  X-ray mode drops terms x_i < x_min_xray [1e-6]
+ *   bg          background colour, C += T_final * bg [0,0,0]
+ *   act         colour c = act(sum_k sh_k Y_k(v) + 0.5), v the unit vector
+ *               from the camera centre to the mean; max(.,0) or
+ *               softplus(10 y)/10 (Supp. D) [CLAMP0]
+ *   tile_w/h    screen tile in pixels, one of 8x8, 16x8, 16x16, 32x8;
+ *               0 = the context's tuned choice (16x16 until tuned) [0, 0]
+ * Gaussians are composited in ascending order of the FP32 view-space depth
+ * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
+ * keep the input index order.  The result does not depend on the tile size:
+ * tiles only bound, conservatively, where alpha >= alpha_min can occur. */
+typedef struct {
+    int32_t mode;
+    int32_t sh_degree;
+    float alpha_min, alpha_max, T_min, x_min_xray;
+    float bg[3];
+    int32_t act;
+    int32_t tile_w, tile_h;
+    int32_t reserved[2];
+} vgr_settings;
+
+/* Counters of the last forward (host struct). */
+typedef struct {
+    int64_t instances;       /* (Gaussian, tile) pairs emitted, all views */
+    int64_t capacity;        /* instance capacity of the workspace */
+    int64_t visible;         /* (Gaussian, view) pairs that survived culling */
+    int64_t pairs_tested;    /* filled when pair counting is on: (pixel,     */
+    int64_t pairs_full;      /*   Gaussian) pairs visited, pairs evaluated   */
+    int64_t pairs_blended;   /*   past the cheap bound test, pairs blended   */
+    int64_t bwd_pairs_tested;   /* the same three counts for the backward  */
+    int64_t bwd_pairs_full;     /*   rasteriser of the last backward       */
+    int64_t bwd_pairs_blended;
+    int32_t overflow;        /* 1 if a fixed-capacity run dropped instances */
+    int32_t tile_w, tile_h;  /* tile used */
+    int32_t n_views;
+} vgr_stats;
+
+typedef struct vgr_ctx vgr_ctx;
+
+/* Fill *s with the defaults listed above. */
+void vgr_default_settings(vgr_settings *s);
+
+/* Create a context on HIP device `device` (the null stream until
+ * vgr_set_stream).  *out receives the handle.  Allocates a small amount of
+ * host pinned and device memory.  VGR_ERR_INVALID_ARG, VGR_ERR_HIP. */
+int vgr_create(vgr_ctx **out, int device);
+
+/* Release the context and all its memory; waits for its stream first.
+ * NULL is accepted. */
+void vgr_destroy(vgr_ctx *ctx);
+
+/* Enqueue all later work on `hip_stream` (a hipStream_t; NULL = null
+ * stream). */
+int vgr_set_stream(vgr_ctx *ctx, void *hip_stream);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *vgr_last_error(const vgr_ctx *ctx);
+
+/* Forward render of n Gaussians into n_views views (Sec. 4.1-4.2, Sec. 6.2).
+ *   means  n x 3, world-space mean mu_i
+ *   quats  n x 4, rotation (w, x, y, z); normalised inside, need not be unit
+ *   scales n x 3, standard deviations along the rotated axes, > 0
+ *          (Sigma_i = R_i diag(s_i^2) R_i^T)
+ *   dens   n, density kappa_i >= 0 (units 1/length)
+ *   sh     n x (sh_degree+1)^2 x 3 colour coefficients (COLOR); may be NULL
+ *          in XRAY mode
+ *   cams   host array of n_views cameras (1 <= n_views <= 64)
+ *   out    host array of n_views device pointers: view v receives
+ *          3 x H_v x W_v (COLOR, channel-major) or H_v x W_v (XRAY)
+ * The state needed by vgr_render_backward (sorted lists, per-pixel final
+ * transmittance and last contributor) is kept in ctx until the next forward.
+ * Synchronises the stream once, to size the instance lists.
+ * Errors: VGR_ERR_INVALID_ARG (bad sizes, settings or null pointers),
+ * VGR_ERR_OOM, VGR_ERR_HIP. */
+int vgr_render_forward(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
+                       const float *means, const float *quats, const float *scales,
+                       const float *dens, const float *sh, int32_t n_views,
+                       const vgr_camera *cams, float *const *out);
+
+/* Backward of the last forward on this context: given dL/d(out) (host array
+ * of n_views device pointers, same shapes as `out`), ADD the gradients to
+ * d_means (n x 3), d_quats (n x 4), d_scales (n x 3), d_dens (n) and d_sh
+ * (same shape as sh; may be NULL in XRAY mode).  Gradients flow through the
+ * quaternion normalisation; clamped, skipped and unblended (Gaussian, pixel)
+ * pairs contribute zero.  The parameter arrays given to the forward must
+ * still hold the same values.  Errors: VGR_ERR_NO_FORWARD,
+ * VGR_ERR_INVALID_ARG, VGR_ERR_HIP. */
+int vgr_render_backward(vgr_ctx *ctx, const float *const *dL_dout, float *d_means,
+                        float *d_quats, float *d_scales, float *d_dens, float *d_sh);
+
+/* Per-pixel state of view `view` of the last forward, copied (on the
+ * stream) into caller arrays of H x W: final transmittance T_final (may be
+ * NULL) and the index of the last blended Gaussian, -1 if none (may be NULL;
+ * in XRAY mode the number of terms summed).  VGR_ERR_NO_FORWARD,
+ * VGR_ERR_INVALID_ARG. */
+int vgr_get_aux(vgr_ctx *ctx, int32_t view, float *T_final, int32_t *last_index);
+
+/* Counters of the last forward.  Waits for the stream.  When counting is on
+ * (vgr_set_counting) the pair counters of the rasteriser are filled. */
+int vgr_get_stats(vgr_ctx *ctx, vgr_stats *out);
+
+/* Turn pair counting in the rasterisers on (1) or off (0).  Counting runs
+ * separate instrumented kernel variants; timing runs keep it off. */
+int vgr_set_counting(vgr_ctx *ctx, int enable);
+
+/* Stage timing with HIP events recorded on the context's stream around each
+ * stage (preprocess, sorts, emission, ranges, rasterisers, preprocess
+ * backward) of every forward and backward call made since
+ * vgr_set_timing(ctx, 1) (which waits for the stream and starts a new
+ * series).  vgr_get_timing waits for the stream and writes, for up to `cap`
+ * stages, the stage name (static strings) and its mean duration in ms over
+ * those calls; *count receives the number of stages written. */
+int vgr_set_timing(vgr_ctx *ctx, int enable);
+int vgr_get_timing(vgr_ctx *ctx, int32_t cap, const char **names, float *ms, int32_t *count);
+
+/* Stable LSD radix sort of n (key, value) pairs on the low `bits` bits of
+ * key, in place (keys, vals: device u32 arrays of n).  This is the sort the
+ * rasteriser uses to order (tile, depth); exposed for testing.  Equal keys
+ * keep their input order.  VGR_ERR_INVALID_ARG, VGR_ERR_OOM, VGR_ERR_HIP. */
+int vgr_sort_pairs(vgr_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VGR_H */

@@ -1,0 +1,620 @@
+// Context, workspace and the C ABI declared in include/vgr.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "vgr_internal.h"
+
+using namespace vgr;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+enum Stage {
+    ST_PREPROCESS, ST_SORT_DEPTH, ST_SCAN_EMIT, ST_SORT_TILES, ST_RANGES, ST_RASTER_FWD,
+    ST_ZERO_GRAD, ST_RASTER_BWD, ST_PREPROCESS_BWD, ST_COUNT
+};
+const char *kStageNames[ST_COUNT] = {
+    "preprocess_fwd", "sort_depth", "scan_emit", "sort_tiles", "tile_ranges", "raster_fwd",
+    "zero_record_grads", "raster_bwd", "preprocess_bwd"
+};
+
+}  // namespace
+
+struct vgr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // workspace
+    DevBuf geom, color, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
+    DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id;
+    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views;
+    ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
+    hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
+    bool stage_pending[2] = { false, false };
+    uint32_t *h_words = nullptr;      // pinned, 8 words
+    int64_t inst_capacity = 0;
+
+    // saved forward
+    bool have_fwd = false;
+    RenderParams rp{};
+    Buffers buf{};
+    int64_t K = 0;
+    int64_t total_pix = 0;
+    std::vector<ViewInfo> vinfo;
+    const float *means = nullptr, *quats = nullptr, *scales = nullptr, *dens = nullptr,
+                *sh = nullptr;
+
+    bool counting = false;
+    bool timing = false;
+    // timing: one set of events per forward / backward call since timing was
+    // switched on; stage st spans events [st] .. [st + 1] of its set
+    struct EvSet { hipEvent_t ev[ST_COUNT + 1]; bool used[ST_COUNT]; };
+    std::vector<EvSet> evsets;
+    size_t ev_next = 0;
+    EvSet *cur = nullptr;
+    int tuned_w = 16, tuned_h = 16;
+};
+
+namespace {
+
+int fail(vgr_ctx *c, int code, const char *fmt, ...)
+{
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(c, expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((c), VGR_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                              \
+    } while (0)
+
+// Grow-only device buffer; contents are not preserved.
+int ensure(vgr_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return VGR_OK;
+    size_t want = bytes + bytes / 4;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, VGR_ERR_HIP, "sync: %s", hipGetErrorString(e));
+        hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&p, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, VGR_ERR_OOM, "hipMalloc(%zu) failed", bytes);
+    }
+    b.p = p;
+    b.bytes = want;
+    return VGR_OK;
+}
+
+template <class T>
+T *ptr(DevBuf &b)
+{
+    return reinterpret_cast<T *>(b.p);
+}
+
+bool valid_tile(int w, int h)
+{
+    return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8);
+}
+
+void inverse3(const float *Rf, double *Ri)
+{
+    double R[9];
+    for (int k = 0; k < 9; ++k) R[k] = Rf[k];
+    double c0 = R[4] * R[8] - R[5] * R[7];
+    double c1 = R[5] * R[6] - R[3] * R[8];
+    double c2 = R[3] * R[7] - R[4] * R[6];
+    double det = R[0] * c0 + R[1] * c1 + R[2] * c2;
+    Ri[0] = c0 / det; Ri[1] = (R[2] * R[7] - R[1] * R[8]) / det; Ri[2] = (R[1] * R[5] - R[2] * R[4]) / det;
+    Ri[3] = c1 / det; Ri[4] = (R[0] * R[8] - R[2] * R[6]) / det; Ri[5] = (R[2] * R[3] - R[0] * R[5]) / det;
+    Ri[6] = c2 / det; Ri[7] = (R[1] * R[6] - R[0] * R[7]) / det; Ri[8] = (R[0] * R[4] - R[1] * R[3]) / det;
+}
+
+// Start a timed call: take the next event set (created on first use).
+int timing_begin(vgr_ctx *c)
+{
+    c->cur = nullptr;
+    if (!c->timing) return VGR_OK;
+    if (c->ev_next == c->evsets.size()) {
+        vgr_ctx::EvSet es{};
+        for (auto &e : es.ev) HIP_TRY(c, hipEventCreate(&e));
+        c->evsets.push_back(es);
+    }
+    c->cur = &c->evsets[c->ev_next++];
+    for (bool &u : c->cur->used) u = false;
+    return VGR_OK;
+}
+
+void mark(vgr_ctx *c, int st)
+{
+    if (!c->cur) return;
+    (void)hipEventRecord(c->cur->ev[st], c->stream);
+    c->cur->used[st] = true;
+}
+
+void mark_end(vgr_ctx *c, int st)
+{
+    if (!c->cur) return;
+    (void)hipEventRecord(c->cur->ev[st + 1], c->stream);
+}
+
+int bits_for(int64_t v)
+{
+    int b = 1;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+// Copy the view table to the device through pinned staging slot `slot`,
+// waiting first for the previous copy out of that slot to finish.
+int upload_views(vgr_ctx *c, int slot, const std::vector<ViewInfo> &vinfo)
+{
+    ViewInfo *h = c->h_views + slot * kMaxViews;
+    if (c->stage_pending[slot]) HIP_TRY(c, hipEventSynchronize(c->stage_ev[slot]));
+    memcpy(h, vinfo.data(), sizeof(ViewInfo) * vinfo.size());
+    HIP_TRY(c, hipMemcpyAsync(c->views.p, h, sizeof(ViewInfo) * vinfo.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipEventRecord(c->stage_ev[slot], c->stream));
+    c->stage_pending[slot] = true;
+    return VGR_OK;
+}
+
+Buffers make_buffers(vgr_ctx *c)
+{
+    Buffers b{};
+    b.geom = ptr<float4>(c->geom);
+    b.color = ptr<float4>(c->color);
+    b.depth_key = ptr<uint32_t>(c->depth_key);
+    b.item_ids = ptr<uint32_t>(c->item_ids);
+    b.key2 = ptr<uint32_t>(c->key2);
+    b.item2 = ptr<uint32_t>(c->item2);
+    b.counts = ptr<uint32_t>(c->counts);
+    b.cnt_sorted = ptr<uint32_t>(c->cnt_sorted);
+    b.offsets = ptr<uint32_t>(c->offsets);
+    b.rect = ptr<ushort4>(c->rect);
+    b.inst_key = ptr<uint32_t>(c->inst_key);
+    b.inst_val = ptr<uint32_t>(c->inst_val);
+    b.inst_key2 = ptr<uint32_t>(c->inst_key2);
+    b.inst_val2 = ptr<uint32_t>(c->inst_val2);
+    b.ranges = ptr<uint2>(c->ranges);
+    b.T_final = ptr<float>(c->T_final);
+    b.last_pos = ptr<int32_t>(c->last_pos);
+    b.last_id = ptr<int32_t>(c->last_id);
+    b.rgrad = ptr<float4>(c->rgrad);
+    b.d_total = ptr<uint32_t>(c->words);
+    b.counters = ptr<unsigned long long>(c->counters);
+    b.views = ptr<ViewInfo>(c->views);
+    return b;
+}
+
+int check_ptr(vgr_ctx *c, const void *p, const char *name)
+{
+    if (!p) return fail(c, VGR_ERR_INVALID_ARG, "%s is NULL", name);
+    return VGR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vgr_default_settings(vgr_settings *s)
+{
+    if (!s) return;
+    memset(s, 0, sizeof *s);
+    s->mode = VGR_MODE_COLOR;
+    s->sh_degree = 0;
+    s->alpha_min = 1.0f / 255.0f;
+    s->alpha_max = 0.99f;
+    s->T_min = 1e-4f;
+    s->x_min_xray = 1e-6f;
+    s->act = VGR_ACT_CLAMP0;
+}
+
+int vgr_create(vgr_ctx **out, int device)
+{
+    if (!out) return VGR_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return VGR_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return VGR_ERR_HIP;
+    vgr_ctx *c = new vgr_ctx();
+    c->device = device;
+    int rc;
+    if (hipHostMalloc((void **)&c->h_views, sizeof(ViewInfo) * 2 * kMaxViews, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->stage_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->stage_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_words, sizeof(uint32_t) * 8, hipHostMallocDefault) != hipSuccess) {
+        vgr_destroy(c);
+        return VGR_ERR_HIP;
+    }
+    if ((rc = ensure(c, c->views, sizeof(ViewInfo) * kMaxViews)) ||
+        (rc = ensure(c, c->words, sizeof(uint32_t) * 8)) ||
+        (rc = ensure(c, c->counters, sizeof(unsigned long long) * 8))) {
+        vgr_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return VGR_OK;
+}
+
+void vgr_destroy(vgr_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *all[] = { &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
+                      &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
+                      &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
+                      &c->last_pos, &c->last_id, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
+                      &c->words, &c->counters, &c->views };
+    for (DevBuf *b : all)
+        if (b->p) hipFree(b->p);
+    if (c->h_views) hipHostFree(c->h_views);
+    for (auto &e : c->stage_ev)
+        if (e) hipEventDestroy(e);
+    if (c->h_words) hipHostFree(c->h_words);
+    for (auto &es : c->evsets)
+        for (auto &e : es.ev) hipEventDestroy(e);
+    delete c;
+}
+
+int vgr_set_stream(vgr_ctx *c, void *stream)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    return VGR_OK;
+}
+
+const char *vgr_last_error(const vgr_ctx *c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+int vgr_set_counting(vgr_ctx *c, int enable)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->counting = enable != 0;
+    return VGR_OK;
+}
+
+int vgr_set_timing(vgr_ctx *c, int enable)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    c->ev_next = 0;
+    c->cur = nullptr;
+    return VGR_OK;
+}
+
+int vgr_get_timing(vgr_ctx *c, int32_t cap, const char **names, float *ms, int32_t *count)
+{
+    if (!c || !count) return VGR_ERR_INVALID_ARG;
+    *count = 0;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int n = 0;
+    for (int st = 0; st < ST_COUNT && n < cap; ++st) {
+        double tot = 0.0;
+        int calls = 0;
+        for (size_t k = 0; k < c->ev_next; ++k) {
+            const vgr_ctx::EvSet &es = c->evsets[k];
+            if (!es.used[st]) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, es.ev[st], es.ev[st + 1]) != hipSuccess) {
+                (void)hipGetLastError();
+                continue;
+            }
+            tot += t;
+            ++calls;
+        }
+        if (!calls) continue;
+        if (names) names[n] = kStageNames[st];
+        if (ms) ms[n] = (float)(tot / calls);
+        ++n;
+    }
+    *count = n;
+    return VGR_OK;
+}
+
+int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                       const float *quats, const float *scales, const float *dens,
+                       const float *sh, int32_t n_views, const vgr_camera *cams,
+                       float *const *out)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    c->have_fwd = false;
+    if (!st) return fail(c, VGR_ERR_INVALID_ARG, "settings is NULL");
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(c, VGR_ERR_INVALID_ARG, "bad n %lld", (long long)n);
+    if (n_views < 1 || n_views > kMaxViews)
+        return fail(c, VGR_ERR_INVALID_ARG, "n_views must be in [1, %d]", kMaxViews);
+    if ((int64_t)n * n_views >= (int64_t)0xFFFFFFFF)
+        return fail(c, VGR_ERR_INVALID_ARG, "n * n_views too large");
+    if (st->mode != VGR_MODE_COLOR && st->mode != VGR_MODE_XRAY)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad mode");
+    if (st->mode == VGR_MODE_COLOR && (st->sh_degree < 0 || st->sh_degree > 3))
+        return fail(c, VGR_ERR_INVALID_ARG, "sh_degree must be 0..3");
+    if (st->act != VGR_ACT_CLAMP0 && st->act != VGR_ACT_SOFTPLUS10)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad act");
+    if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
+        !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
+        return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
+    if (!cams || !out) return fail(c, VGR_ERR_INVALID_ARG, "cams/out is NULL");
+    int rc;
+    if (n > 0) {
+        if ((rc = check_ptr(c, means, "means")) || (rc = check_ptr(c, quats, "quats")) ||
+            (rc = check_ptr(c, scales, "scales")) || (rc = check_ptr(c, dens, "dens")))
+            return rc;
+        if (st->mode == VGR_MODE_COLOR && (rc = check_ptr(c, sh, "sh"))) return rc;
+    }
+    int tw = st->tile_w, th = st->tile_h;
+    if (tw == 0 && th == 0) { tw = c->tuned_w; th = c->tuned_h; }
+    if (!valid_tile(tw, th)) return fail(c, VGR_ERR_INVALID_ARG, "unsupported tile %dx%d", tw, th);
+
+    HIP_TRY(c, hipSetDevice(c->device));
+    RenderParams rp{};
+    rp.mode = st->mode;
+    rp.sh_degree = st->mode == VGR_MODE_COLOR ? st->sh_degree : 0;
+    rp.act = st->act;
+    rp.n_views = n_views;
+    rp.n = n;
+    rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;
+    rp.tau2 = (float)((double)rp.tau * 1.4426950408889634);
+    rp.ymax = (float)(-log2(1.0 - (double)st->alpha_max));
+    rp.T_min = st->T_min;
+    for (int k = 0; k < 3; ++k) rp.bg[k] = st->bg[k];
+    rp.tile_w = tw;
+    rp.tile_h = th;
+
+    // views
+    std::vector<ViewInfo> vinfo(n_views);
+    int64_t tiles = 0, pix = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const vgr_camera &cm = cams[v];
+        if (cm.width <= 0 || cm.height <= 0 || cm.width > 16384 || cm.height > 16384)
+            return fail(c, VGR_ERR_INVALID_ARG, "view %d: bad size %dx%d", v, cm.width, cm.height);
+        if (!(cm.fx > 0.f) || !(cm.fy > 0.f))
+            return fail(c, VGR_ERR_INVALID_ARG, "view %d: bad focal length", v);
+        if (!out[v]) return fail(c, VGR_ERR_INVALID_ARG, "out[%d] is NULL", v);
+        ViewInfo &vi = vinfo[v];
+        memset(&vi, 0, sizeof vi);
+        memcpy(vi.R, cm.R, sizeof vi.R);
+        memcpy(vi.t, cm.t, sizeof vi.t);
+        vi.fx = cm.fx; vi.fy = cm.fy; vi.cx = cm.cx; vi.cy = cm.cy;
+        vi.znear = cm.znear;
+        double Ri[9];
+        inverse3(cm.R, Ri);
+        for (int a = 0; a < 3; ++a)
+            vi.o[a] = (float)-(Ri[a * 3] * cm.t[0] + Ri[a * 3 + 1] * cm.t[1] + Ri[a * 3 + 2] * cm.t[2]);
+        vi.width = cm.width;
+        vi.height = cm.height;
+        vi.tiles_x = (cm.width + tw - 1) / tw;
+        vi.tiles_y = (cm.height + th - 1) / th;
+        vi.tile_off = (int32_t)tiles;
+        vi.pix_off = pix;
+        vi.out = out[v];
+        vi.dL = nullptr;
+        tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+        pix += (int64_t)cm.width * cm.height;
+    }
+    if (tiles >= (int64_t)1 << 30) return fail(c, VGR_ERR_INVALID_ARG, "too many tiles");
+    rp.total_tiles = (int32_t)tiles;
+
+    const int64_t m = n * n_views;
+    if ((rc = ensure(c, c->geom, sizeof(float4) * 4 * m)) ||
+        (rc = ensure(c, c->color, sizeof(float4) * (rp.mode == VGR_MODE_COLOR ? m : 1))) ||
+        (rc = ensure(c, c->depth_key, 4 * m)) || (rc = ensure(c, c->item_ids, 4 * m)) ||
+        (rc = ensure(c, c->key2, 4 * m)) || (rc = ensure(c, c->item2, 4 * m)) ||
+        (rc = ensure(c, c->counts, 4 * m)) || (rc = ensure(c, c->cnt_sorted, 4 * m)) ||
+        (rc = ensure(c, c->offsets, 4 * (m + 1))) || (rc = ensure(c, c->rect, 8 * m)) ||
+        (rc = ensure(c, c->ranges, 8 * tiles)) || (rc = ensure(c, c->T_final, 4 * pix)) ||
+        (rc = ensure(c, c->last_pos, 4 * pix)) || (rc = ensure(c, c->last_id, 4 * pix)) ||
+        (rc = ensure(c, c->scan_tmp, 4 * scan_tmp_words(m > 0 ? m : 1))) ||
+        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(m > 0 ? m : 1))) ||
+        (rc = ensure(c, c->inst_key, 4)) || (rc = ensure(c, c->inst_val, 4)) ||
+        (rc = ensure(c, c->inst_key2, 4)) || (rc = ensure(c, c->inst_val2, 4)))
+        return rc;
+
+    hipStream_t s = c->stream;
+    if ((rc = upload_views(c, 0, vinfo))) return rc;
+    Buffers b = make_buffers(c);
+    if ((rc = timing_begin(c))) return rc;
+
+    int64_t K = 0;
+    if (m > 0) {
+        mark(c, ST_PREPROCESS);
+        HIP_TRY(c, launch_preprocess(rp, b, means, quats, scales, dens, sh, s));
+        mark_end(c, ST_PREPROCESS);
+        // depth order of all (view, Gaussian) items; ties keep the item order
+        mark(c, ST_SORT_DEPTH);
+        HIP_TRY(c, launch_fill_u32(b.d_total + 2, (uint32_t)m, 1, s));
+        HIP_TRY(c, launch_radix_sort(b.depth_key, b.item_ids, b.key2, b.item2, b.d_total + 2, m, 32,
+                                     ptr<uint32_t>(c->sort_tmp), s));
+        mark_end(c, ST_SORT_DEPTH);
+        mark(c, ST_SCAN_EMIT);
+        HIP_TRY(c, launch_gather_counts(b, m, s));
+        HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, m, ptr<uint32_t>(c->scan_tmp), true, s));
+        HIP_TRY(c, hipMemcpyAsync(c->h_words, b.offsets + m, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        K = c->h_words[0];
+        if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
+            (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
+            (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > m ? K : m))))
+            return rc;
+        c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
+        b = make_buffers(c);
+        HIP_TRY(c, launch_finalize_count(b, m, K, s));
+        HIP_TRY(c, launch_emit(rp, b, m, K, s));
+        mark_end(c, ST_SCAN_EMIT);
+        mark(c, ST_SORT_TILES);
+        HIP_TRY(c, launch_radix_sort(b.inst_key, b.inst_val, b.inst_key2, b.inst_val2, b.d_total, K,
+                                     bits_for(tiles), ptr<uint32_t>(c->sort_tmp), s));
+        mark_end(c, ST_SORT_TILES);
+    } else {
+        HIP_TRY(c, launch_fill_u32(b.d_total, 0u, 2, s));
+    }
+    mark(c, ST_RANGES);
+    HIP_TRY(c, launch_ranges(b, K, rp.total_tiles, s));
+    mark_end(c, ST_RANGES);
+    if (c->counting)
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 6, s));
+    mark(c, ST_RASTER_FWD);
+    HIP_TRY(c, launch_raster_fwd(rp, b, c->counting, s));
+    mark_end(c, ST_RASTER_FWD);
+
+    c->rp = rp;
+    c->buf = b;
+    c->K = K;
+    c->total_pix = pix;
+    c->vinfo = vinfo;
+    c->means = means; c->quats = quats; c->scales = scales; c->dens = dens; c->sh = sh;
+    c->have_fwd = true;
+    return VGR_OK;
+}
+
+int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, float *d_quats,
+                        float *d_scales, float *d_dens, float *d_sh)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward to differentiate");
+    if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
+    const RenderParams &rp = c->rp;
+    int rc;
+    if (rp.n > 0) {
+        if ((rc = check_ptr(c, d_means, "d_means")) || (rc = check_ptr(c, d_quats, "d_quats")) ||
+            (rc = check_ptr(c, d_scales, "d_scales")) || (rc = check_ptr(c, d_dens, "d_dens")))
+            return rc;
+        if (rp.mode == VGR_MODE_COLOR && (rc = check_ptr(c, d_sh, "d_sh"))) return rc;
+    }
+    for (int v = 0; v < rp.n_views; ++v) {
+        if (!dL[v]) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout[%d] is NULL", v);
+        c->vinfo[v].dL = dL[v];
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t m = rp.n * rp.n_views;
+    if ((rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1)))) return rc;
+    hipStream_t s = c->stream;
+    if ((rc = upload_views(c, 1, c->vinfo))) return rc;
+    Buffers b = c->buf;
+    b.rgrad = ptr<float4>(c->rgrad);
+    if (m == 0) return VGR_OK;
+    if ((rc = timing_begin(c))) return rc;
+    mark(c, ST_ZERO_GRAD);
+    HIP_TRY(c, launch_fill_f32(reinterpret_cast<float *>(b.rgrad), 0.0f, 16 * m, s));
+    mark_end(c, ST_ZERO_GRAD);
+    mark(c, ST_RASTER_BWD);
+    if (c->counting)
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters) + 6, 0u, 6, s));
+    HIP_TRY(c, launch_raster_bwd(rp, b, c->counting, s));
+    mark_end(c, ST_RASTER_BWD);
+    mark(c, ST_PREPROCESS_BWD);
+    HIP_TRY(c, launch_preprocess_bwd(rp, b, c->means, c->quats, c->scales, c->dens, c->sh, d_means,
+                                     d_quats, d_scales, d_dens, d_sh, s));
+    mark_end(c, ST_PREPROCESS_BWD);
+    return VGR_OK;
+}
+
+int vgr_get_aux(vgr_ctx *c, int32_t view, float *T_final, int32_t *last_index)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward");
+    if (view < 0 || view >= c->rp.n_views) return fail(c, VGR_ERR_INVALID_ARG, "bad view");
+    const ViewInfo &vi = c->vinfo[view];
+    const size_t np = (size_t)vi.width * vi.height;
+    if (T_final)
+        HIP_TRY(c, hipMemcpyAsync(T_final, ptr<float>(c->T_final) + vi.pix_off, 4 * np,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    if (last_index)
+        HIP_TRY(c, hipMemcpyAsync(last_index, ptr<int32_t>(c->last_id) + vi.pix_off, 4 * np,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    return VGR_OK;
+}
+
+int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
+{
+    if (!c || !out) return VGR_ERR_INVALID_ARG;
+    memset(out, 0, sizeof *out);
+    if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t words[2];
+    HIP_TRY(c, hipMemcpy(words, c->words.p, sizeof words, hipMemcpyDeviceToHost));
+    unsigned long long cnt[8] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (c->counting) HIP_TRY(c, hipMemcpy(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost));
+    out->instances = words[0];
+    out->overflow = (int32_t)words[1];
+    out->capacity = c->inst_capacity;
+    out->pairs_tested = (int64_t)cnt[0];
+    out->pairs_full = (int64_t)cnt[1];
+    out->pairs_blended = (int64_t)cnt[2];
+    out->bwd_pairs_tested = (int64_t)cnt[3];
+    out->bwd_pairs_full = (int64_t)cnt[4];
+    out->bwd_pairs_blended = (int64_t)cnt[5];
+    out->tile_w = c->rp.tile_w;
+    out->tile_h = c->rp.tile_h;
+    out->n_views = c->rp.n_views;
+    // visible (Gaussian, view) items = items with a nonzero tile count
+    const int64_t m = c->rp.n * c->rp.n_views;
+    if (m > 0) {
+        std::vector<uint32_t> counts(m);
+        HIP_TRY(c, hipMemcpy(counts.data(), c->counts.p, 4 * m, hipMemcpyDeviceToHost));
+        int64_t vis = 0;
+        for (uint32_t x : counts) vis += x > 0;
+        out->visible = vis;
+    }
+    return VGR_OK;
+}
+
+int vgr_sort_pairs(vgr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (n < 0 || n > (int64_t)0xFFFFFFF || bits < 1 || bits > 32)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad n or bits");
+    if (n == 0) return VGR_OK;
+    if (!keys || !vals) return fail(c, VGR_ERR_INVALID_ARG, "keys/vals NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc;
+    if ((rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(n)))) return rc;
+    // the ping-pong halves live in the instance buffers (not part of any saved forward)
+    if ((rc = ensure(c, c->inst_key2, 4 * n)) || (rc = ensure(c, c->inst_val2, 4 * n))) return rc;
+    c->have_fwd = false;
+    hipStream_t s = c->stream;
+    uint32_t *dn = ptr<uint32_t>(c->words) + 2;
+    HIP_TRY(c, launch_fill_u32(dn, (uint32_t)n, 1, s));
+    HIP_TRY(c, launch_radix_sort(keys, vals, ptr<uint32_t>(c->inst_key2), ptr<uint32_t>(c->inst_val2),
+                                 dn, n, bits, ptr<uint32_t>(c->sort_tmp), s));
+    return VGR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,565 @@
+// Per-(Gaussian, view) preprocessing, instance emission and tile ranges, and
+// the preprocess backward that chains record gradients to the parameters.
+//
+// In view space, with L = diag(1/s) Rc^T (Sigma^-1 = L^T L) and m the mean, a
+// pixel ray u = (ux, uy, 1) gives the quantities of Sec. 4.2 (eq. betagamma):
+//   d^T Sigma^-1 d = |L u|^2 / |u|^2,   beta = |u| / |L u|,
+//   minimum Mahalanobis distance D^2 = |Lm x Lu|^2 / |Lu|^2 (Lagrange
+//   identity, free of the cancellation in c - b^2/a),
+// and the full-line integral x = kappa sqrt(2 pi) beta exp(-D^2/2).  The record
+// re-centres this on the ray through the mean, u0 = m / mz: with a = L (u - u0),
+// Lm x Lu = mz (v0 x a) for v0 = L u0, which keeps FP32 accuracy when the pixel
+// ray passes close to the mean (see the layout in vgr_internal.h).
+//
+// Tile bound: since beta <= s_max, alpha >= alpha_min requires
+// D^2 <= D2max = 2 ln(kappa sqrt(2 pi) s_max / tau), i.e. the pixel's line meets
+// the ellipsoid (x-m)^T Sigma^-1 (x-m) <= D2max.  The image of that ellipsoid
+// is bounded by the conic whose dual is K (D2max Sigma - m m^T) K^T, and its
+// tangent lines x = const give the exact screen bounding box used for binning
+// (a conservative replacement of the 3-sigma screen-space heuristic that the
+// paper notes should be adjusted for this rendering model, Sec. 7).
+#include "vgr_internal.h"
+
+namespace vgr {
+
+namespace {
+
+// Real spherical harmonics (Condon-Shortley phase), k = l^2 + l + m, written
+// as Cartesian polynomials of the unit direction (x, y, z).
+__device__ constexpr float kPi = 3.14159265358979323846f;
+#define SHC(num, den) (__builtin_sqrtf((num) / ((den) * kPi)))
+__device__ inline void sh_basis(int deg, float x, float y, float z, float *Y)
+{
+    const float c0 = 0.5f * SHC(1.0f, 1.0f);
+    Y[0] = c0;
+    if (deg < 1) return;
+    const float c1 = SHC(3.0f, 4.0f);
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (deg < 2) return;
+    const float a = 0.5f * SHC(15.0f, 1.0f), b = 0.25f * SHC(5.0f, 1.0f),
+                c = 0.25f * SHC(15.0f, 1.0f);
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = a * x * y;
+    Y[5] = -a * y * z;
+    Y[6] = b * (2.0f * zz - xx - yy);
+    Y[7] = -a * x * z;
+    Y[8] = c * (xx - yy);
+    if (deg < 3) return;
+    const float d = 0.25f * SHC(35.0f, 2.0f), e = 0.5f * SHC(105.0f, 1.0f),
+                f = 0.25f * SHC(21.0f, 2.0f), g = 0.25f * SHC(7.0f, 1.0f),
+                h = 0.25f * SHC(105.0f, 1.0f);
+    Y[9] = -d * y * (3.0f * xx - yy);
+    Y[10] = e * x * y * z;
+    Y[11] = -f * y * (4.0f * zz - xx - yy);
+    Y[12] = g * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -f * x * (4.0f * zz - xx - yy);
+    Y[14] = h * z * (xx - yy);
+    Y[15] = -d * x * (xx - 3.0f * yy);
+}
+
+// Gradient of the same polynomials: G[k] = (dY/dx, dY/dy, dY/dz).
+__device__ inline void sh_basis_grad(int deg, float x, float y, float z, float3 *G)
+{
+    G[0] = make_float3(0.f, 0.f, 0.f);
+    if (deg < 1) return;
+    const float c1 = SHC(3.0f, 4.0f);
+    G[1] = make_float3(0.f, -c1, 0.f);
+    G[2] = make_float3(0.f, 0.f, c1);
+    G[3] = make_float3(-c1, 0.f, 0.f);
+    if (deg < 2) return;
+    const float a = 0.5f * SHC(15.0f, 1.0f), b = 0.25f * SHC(5.0f, 1.0f),
+                c = 0.25f * SHC(15.0f, 1.0f);
+    G[4] = make_float3(a * y, a * x, 0.f);
+    G[5] = make_float3(0.f, -a * z, -a * y);
+    G[6] = make_float3(-2.f * b * x, -2.f * b * y, 4.f * b * z);
+    G[7] = make_float3(-a * z, 0.f, -a * x);
+    G[8] = make_float3(2.f * c * x, -2.f * c * y, 0.f);
+    if (deg < 3) return;
+    const float d = 0.25f * SHC(35.0f, 2.0f), e = 0.5f * SHC(105.0f, 1.0f),
+                f = 0.25f * SHC(21.0f, 2.0f), g = 0.25f * SHC(7.0f, 1.0f),
+                h = 0.25f * SHC(105.0f, 1.0f);
+    const float xx = x * x, yy = y * y, zz = z * z;
+    G[9] = make_float3(-6.f * d * x * y, -3.f * d * (xx - yy), 0.f);
+    G[10] = make_float3(e * y * z, e * x * z, e * x * y);
+    G[11] = make_float3(2.f * f * x * y, -f * (4.f * zz - xx - 3.f * yy), -8.f * f * y * z);
+    G[12] = make_float3(-6.f * g * x * z, -6.f * g * y * z, g * (6.f * zz - 3.f * xx - 3.f * yy));
+    G[13] = make_float3(-f * (4.f * zz - 3.f * xx - yy), 2.f * f * x * y, -8.f * f * x * z);
+    G[14] = make_float3(2.f * h * x * z, -2.f * h * y * z, h * (xx - yy));
+    G[15] = make_float3(-3.f * d * (xx - yy), 6.f * d * x * y, 0.f);
+}
+#undef SHC
+
+__device__ inline float act_fwd(int act, float y)
+{
+    if (act == VGR_ACT_SOFTPLUS10) {
+        const float s = 10.0f * y;
+        return (s > 0.0f ? s + log1pf(expf(-s)) : log1pf(expf(s))) * 0.1f;
+    }
+    return fmaxf(y, 0.0f);
+}
+
+__device__ inline float act_grad(int act, float y)
+{
+    if (act == VGR_ACT_SOFTPLUS10) return 1.0f / (1.0f + expf(-10.0f * y));
+    return y > 0.0f ? 1.0f : 0.0f;
+}
+
+// Rotation of the normalised quaternion q = (w, x, y, z), row-major.
+__device__ inline void quat_to_rot(float w, float x, float y, float z, float *R)
+{
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+struct GaussView {
+    float qn[4], qlen;
+    float Rc[9];     // R_view R(q)
+    float inv_s[3];
+    float m[3];      // view-space mean (m[2] is the depth key value)
+    float L[9];
+    float p[3];
+};
+
+__device__ inline void gauss_view(const ViewInfo &vi, const float *mu, const float *q,
+                                  const float *s, GaussView &g)
+{
+    const float *R = vi.R;
+    g.m[0] = __fmaf_rn(R[0], mu[0], __fmaf_rn(R[1], mu[1], __fmaf_rn(R[2], mu[2], vi.t[0])));
+    g.m[1] = __fmaf_rn(R[3], mu[0], __fmaf_rn(R[4], mu[1], __fmaf_rn(R[5], mu[2], vi.t[1])));
+    g.m[2] = __fmaf_rn(R[6], mu[0], __fmaf_rn(R[7], mu[1], __fmaf_rn(R[8], mu[2], vi.t[2])));
+    float len2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    g.qlen = sqrtf(len2);
+    const float il = 1.0f / g.qlen;
+    for (int k = 0; k < 4; ++k) g.qn[k] = q[k] * il;
+    float Rq[9];
+    quat_to_rot(g.qn[0], g.qn[1], g.qn[2], g.qn[3], Rq);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            g.Rc[a * 3 + c] = R[a * 3] * Rq[c] + R[a * 3 + 1] * Rq[3 + c] + R[a * 3 + 2] * Rq[6 + c];
+    for (int k = 0; k < 3; ++k) g.inv_s[k] = 1.0f / s[k];
+    // L[k][j] = Rc[j][k] / s_k
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) g.L[k * 3 + j] = g.Rc[j * 3 + k] * g.inv_s[k];
+    for (int k = 0; k < 3; ++k)
+        g.p[k] = g.L[k * 3] * g.m[0] + g.L[k * 3 + 1] * g.m[1] + g.L[k * 3 + 2] * g.m[2];
+}
+
+// Screen extent along one image axis (normalised coordinate u = x/z) of the
+// ellipsoid {(x-m)^T S^-1 (x-m) <= 1}: roots of
+// (mz^2 - S22) u^2 - 2 (ma mz - Sa2) u + (ma^2 - Saa) = 0.  The discriminant is
+// expanded so that the ma^2 mz^2 terms cancel analytically; minor = Saa S22 - Sa2^2.
+__device__ inline bool axis_extent(float Saa, float Sa2, float S22, float minor, float ma,
+                                   float mz, float &lo, float &hi)
+{
+    const float A = mz * mz - S22;
+    if (!(A > 1e-6f * mz * mz)) return false;
+    const float B = ma * mz - Sa2;
+    float disc = Saa * mz * mz - 2.0f * Sa2 * ma * mz + S22 * ma * ma - minor;
+    disc = fmaxf(disc, 0.0f);
+    const float sq = sqrtf(disc);
+    lo = (B - sq) / A;
+    hi = (B + sq) / A;
+    return true;
+}
+
+__device__ inline void pixel_span(bool ok, float lo, float hi, float f, float c, int size,
+                                  int &p0, int &p1)
+{
+    if (!ok) {
+        p0 = 0;
+        p1 = size - 1;
+        return;
+    }
+    float X0 = fmaf(f, lo, c), X1 = fmaf(f, hi, c);
+    // pixel centres at p + 0.5; pad one pixel for FP32 rounding
+    X0 = fmaxf(X0 - 1.5f, -4.0f);
+    X1 = fminf(X1 + 0.5f, (float)size + 4.0f);
+    p0 = (int)floorf(X0);
+    p1 = (int)ceilf(X1);
+    p0 = max(p0, 0);
+    p1 = min(p1, size - 1);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
+                                                         const float *__restrict__ means,
+                                                         const float *__restrict__ quats,
+                                                         const float *__restrict__ scales,
+                                                         const float *__restrict__ dens,
+                                                         const float *__restrict__ sh)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (i >= rp.n) return;
+    const ViewInfo &vi = b.views[v];
+    const int64_t item = (int64_t)v * rp.n + i;
+    const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+    const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
+    const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
+    const float kappa = dens[i];
+
+    uint32_t key = 0xFFFFFFFFu, count = 0;
+    ushort4 rect = make_ushort4(0, 0, 0, 0);
+    const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
+    const float K = kappa * kSqrt2Pi;
+    const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
+    if (z > vi.znear && K * smax > rp.tau) {
+        GaussView g;
+        gauss_view(vi, mu, q, s, g);
+        const float D2max = 2.0f * logf(K * smax / rp.tau);
+        // S = D2max Sigma_view, Sigma_view = Rc diag(s^2) Rc^T
+        const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
+        float S[9];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                S[a * 3 + c] = D2max * (g.Rc[a * 3] * g.Rc[c * 3] * s2[0] +
+                                        g.Rc[a * 3 + 1] * g.Rc[c * 3 + 1] * s2[1] +
+                                        g.Rc[a * 3 + 2] * g.Rc[c * 3 + 2] * s2[2]);
+        // 2x2 minors (rows a and 2) by Cauchy-Binet, free of cancellation
+        float minor[2];
+        for (int a = 0; a < 2; ++a) {
+            float acc = 0.0f;
+            for (int k = 0; k < 3; ++k)
+                for (int l = k + 1; l < 3; ++l) {
+                    const float det = g.Rc[a * 3 + k] * g.Rc[6 + l] - g.Rc[a * 3 + l] * g.Rc[6 + k];
+                    acc += s2[k] * s2[l] * det * det;
+                }
+            minor[a] = D2max * D2max * acc;
+        }
+        float lo, hi;
+        int x0, x1, y0, y1;
+        bool okx = axis_extent(S[0], S[2], S[8], minor[0], g.m[0], g.m[2], lo, hi);
+        pixel_span(okx, lo, hi, vi.fx, vi.cx, vi.width, x0, x1);
+        bool oky = axis_extent(S[4], S[5], S[8], minor[1], g.m[1], g.m[2], lo, hi);
+        pixel_span(oky, lo, hi, vi.fy, vi.cy, vi.height, y0, y1);
+        if (x0 <= x1 && y0 <= y1) {
+            const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
+            const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;
+            count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            rect = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,
+                                (unsigned short)ty1);
+            key = __float_as_uint(z);
+            // view-space mean and projected centre in FP64: their rounding sets
+            // how precisely the pixel offsets of small, distant Gaussians are known
+            const double mx = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
+            const double my = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
+            const double mzd = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
+            const double u0x = mx / mzd, u0y = my / mzd;
+            const double cxp = (double)vi.fx * u0x + vi.cx, cyp = (double)vi.fy * u0y + vi.cy;
+            const double hx = rint(cxp), hy = rint(cyp);
+            const float v0[3] = {
+                (float)(g.L[0] * u0x + g.L[1] * u0y + g.L[2]),
+                (float)(g.L[3] * u0x + g.L[4] * u0y + g.L[5]),
+                (float)(g.L[6] * u0x + g.L[7] * u0y + g.L[8]) };
+            const float mz = (float)mzd;
+            const float ifx = 1.0f / vi.fx, ify = 1.0f / vi.fy;
+            float4 *gp = b.geom + item * 4;
+            gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
+            gp[1] = make_float4(g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify);
+            gp[2] = make_float4(g.L[6] * ifx, g.L[7] * ify, v0[0], v0[1]);
+            gp[3] = make_float4(v0[2], mz, K * kLog2e, D2max * (1.0f + 1e-4f) / (mz * mz));
+            if (rp.mode == VGR_MODE_COLOR) {
+                float dx = mu[0] - vi.o[0], dy = mu[1] - vi.o[1], dz = mu[2] - vi.o[2];
+                const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                dx *= il; dy *= il; dz *= il;
+                float Y[16];
+                sh_basis(DEG, dx, dy, dz, Y);
+                constexpr int NB = (DEG + 1) * (DEG + 1);
+                const float *c3 = sh + i * NB * 3;
+                float rgb[3];
+                for (int ch = 0; ch < 3; ++ch) {
+                    float acc = 0.5f;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) acc = fmaf(c3[k * 3 + ch], Y[k], acc);
+                    rgb[ch] = act_fwd(rp.act, acc);
+                }
+                b.color[item] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+            }
+        }
+    }
+    b.depth_key[item] = key;
+    b.item_ids[item] = (uint32_t)item;
+    b.counts[item] = count;
+    b.rect[item] = rect;
+}
+
+__global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
+                                     const uint32_t *__restrict__ counts,
+                                     uint32_t *__restrict__ out, int64_t m)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) out[j] = counts[sorted_items[j]];
+}
+
+// Instance count K = offsets[m], clamped to the capacity (overflow flag).
+__global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int64_t m,
+                                      int64_t capacity, uint32_t *__restrict__ d_total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t K = offsets[m];
+        d_total[0] = (int64_t)K > capacity ? (uint32_t)capacity : K;
+        d_total[1] = (int64_t)K > capacity ? 1u : 0u;
+    }
+}
+
+// One thread per Gaussian in depth order writes its (tile, Gaussian) pairs.
+__global__ __launch_bounds__(256) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
+                                                   int64_t capacity)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t c = b.cnt_sorted[j];
+    if (c == 0) return;
+    const uint32_t item = b.item_ids[j];
+    const ushort4 r = b.rect[item];
+    const int v = (int)(item / (uint64_t)rp.n);
+    const ViewInfo &vi = b.views[v];
+    int64_t pos = b.offsets[j];
+    for (int ty = r.y; ty <= r.w; ++ty)
+        for (int tx = r.x; tx <= r.z; ++tx) {
+            if (pos < capacity) {
+                b.inst_key[pos] = (uint32_t)(vi.tile_off + ty * vi.tiles_x + tx);
+                b.inst_val[pos] = item;
+            }
+            ++pos;
+        }
+}
+
+__global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ d_total,
+                              uint2 *__restrict__ ranges, int64_t bound)
+{
+    const int64_t K = d_total[0];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K && j < bound;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[j];
+        if (j == 0 || keys[j - 1] != k) ranges[k].x = (uint32_t)j;
+        if (j == K - 1 || keys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_f32_kernel(float *__restrict__ p, float v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------ backward ---
+
+// dL/dR(q) -> dL/dq for the normalised quaternion (w, x, y, z).
+__device__ inline void rot_to_quat_grad(const float *q, const float *G, float *dq)
+{
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    dq[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    dq[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] +
+                   w * G[7] - 2.f * x * G[8]);
+    dq[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
+                   z * G[7] - 2.f * y * G[8]);
+    dq[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] +
+                   y * G[5] + x * G[6] + y * G[7]);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(128) void preprocess_bwd_kernel(
+    RenderParams rp, Buffers b, const float *__restrict__ means, const float *__restrict__ quats,
+    const float *__restrict__ scales, const float *__restrict__ dens, const float *__restrict__ sh,
+    float *__restrict__ d_means, float *__restrict__ d_quats, float *__restrict__ d_scales,
+    float *__restrict__ d_dens, float *__restrict__ d_sh)
+{
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rp.n) return;
+    const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+    const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
+    const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
+    float gmu[3] = { 0.f, 0.f, 0.f }, gqn[4] = { 0.f, 0.f, 0.f, 0.f }, gs[3] = { 0.f, 0.f, 0.f };
+    float gk = 0.f;
+    float gsh[NB * 3];
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) gsh[k] = 0.f;
+    bool any = false;
+    float qn[4] = { 0.f, 0.f, 0.f, 0.f }, qlen = 1.f;
+    for (int v = 0; v < rp.n_views; ++v) {
+        const int64_t item = (int64_t)v * rp.n + i;
+        const float4 *rg = b.rgrad + item * 4;
+        const float4 r0 = rg[0], r1 = rg[1], r2 = rg[2], r3 = rg[3];
+        const float gr[16] = { r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                               r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w };
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) nz |= gr[k] != 0.0f;
+        if (!nz) continue;
+        any = true;
+        const ViewInfo &vi = b.views[v];
+        GaussView g;
+        gauss_view(vi, mu, q, s, g);
+        for (int k = 0; k < 4; ++k) qn[k] = g.qn[k];
+        qlen = g.qlen;
+        gk += gr[9] * (kSqrt2Pi * kLog2e);
+        // Sigma^-1 = Rc diag(s^-2) Rc^T with dL/dSigma^-1 = -1/2 L^-1 M L^-T, L^-1 = Rc diag(s):
+        //   dL/ds_k = M_kk / s_k,  dL/dRc[:,k] = -(1/s_k) sum_j Rc[:,j] s_j M_jk
+        const float Mm[9] = { gr[0], gr[1], gr[2], gr[1], gr[3], gr[4], gr[2], gr[4], gr[5] };
+        float dRc[9];
+        for (int k = 0; k < 3; ++k) {
+            gs[k] += Mm[k * 3 + k] * g.inv_s[k];
+            for (int a = 0; a < 3; ++a) {
+                float acc = 0.f;
+                for (int j = 0; j < 3; ++j) acc += g.Rc[a * 3 + j] * s[j] * Mm[j * 3 + k];
+                dRc[a * 3 + k] = -acc * g.inv_s[k];
+            }
+        }
+        // dL/dm = -L^T Z
+        float dm[3];
+        for (int j = 0; j < 3; ++j)
+            dm[j] = -(g.L[j] * gr[6] + g.L[3 + j] * gr[7] + g.L[6 + j] * gr[8]);
+        // Rc = R_view R(q)  ->  dR(q) = R_view^T dRc
+        float dRq[9];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                dRq[a * 3 + c] = vi.R[a] * dRc[c] + vi.R[3 + a] * dRc[3 + c] + vi.R[6 + a] * dRc[6 + c];
+        float dq[4];
+        rot_to_quat_grad(g.qn, dRq, dq);
+        for (int k = 0; k < 4; ++k) gqn[k] += dq[k];
+        // m = R_view mu + t
+        for (int j = 0; j < 3; ++j)
+            gmu[j] += vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];
+        if (rp.mode == VGR_MODE_COLOR) {
+            float vx = mu[0] - vi.o[0], vy = mu[1] - vi.o[1], vz = mu[2] - vi.o[2];
+            const float len = sqrtf(vx * vx + vy * vy + vz * vz);
+            const float il = 1.0f / len;
+            vx *= il; vy *= il; vz *= il;
+            float Y[16];
+            float3 G[16];
+            sh_basis(DEG, vx, vy, vz, Y);
+            sh_basis_grad(DEG, vx, vy, vz, G);
+            const float *c3 = sh + i * NB * 3;
+            float gv[3] = { 0.f, 0.f, 0.f };
+            for (int ch = 0; ch < 3; ++ch) {
+                float raw = 0.5f;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) raw = fmaf(c3[k * 3 + ch], Y[k], raw);
+                const float graw = gr[10 + ch] * act_grad(rp.act, raw);
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    gsh[k * 3 + ch] += graw * Y[k];
+                    const float w = graw * c3[k * 3 + ch];
+                    gv[0] += w * G[k].x;
+                    gv[1] += w * G[k].y;
+                    gv[2] += w * G[k].z;
+                }
+            }
+            const float vg = vx * gv[0] + vy * gv[1] + vz * gv[2];
+            gmu[0] += (gv[0] - vx * vg) * il;
+            gmu[1] += (gv[1] - vy * vg) * il;
+            gmu[2] += (gv[2] - vz * vg) * il;
+        }
+    }
+    if (!any) return;
+    for (int j = 0; j < 3; ++j) d_means[3 * i + j] += gmu[j];
+    const float dot = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
+    for (int k = 0; k < 4; ++k) d_quats[4 * i + k] += (gqn[k] - qn[k] * dot) / qlen;
+    for (int k = 0; k < 3; ++k) d_scales[3 * i + k] += gs[k];
+    d_dens[i] += gk;
+    if (rp.mode == VGR_MODE_COLOR && d_sh) {
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) d_sh[i * NB * 3 + k] += gsh[k];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int threads)
+{
+    int64_t g = (n + threads - 1) / threads;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    fill_u32_kernel<<<g, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    fill_f32_kernel<<<g, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const float *means,
+                             const float *quats, const float *scales, const float *dens,
+                             const float *sh, hipStream_t s)
+{
+    dim3 grid(grid_for(rp.n, 256), rp.n_views);
+    switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
+    case 0: preprocess_kernel<0><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+    case 1: preprocess_kernel<1><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+    case 2: preprocess_kernel<2><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+    default: preprocess_kernel<3><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)
+{
+    gather_counts_kernel<<<grid_for(m, 256), 256, 0, s>>>(b.item_ids, b.counts, b.cnt_sorted, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s)
+{
+    finalize_count_kernel<<<1, 64, 0, s>>>(b.offsets, m, capacity, b.d_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
+                       hipStream_t s)
+{
+    emit_kernel<<<grid_for(m, 256), 256, 0, s>>>(rp, b, m, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u,
+                                   2 * (int64_t)total_tiles, s);
+    if (e != hipSuccess) return e;
+    if (bound <= 0) return hipSuccess;
+    unsigned g = grid_for(bound, 256);
+    if (g > 16384) g = 16384;
+    ranges_kernel<<<g, 256, 0, s>>>(b.inst_key, b.d_total, b.ranges, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
+                                 const float *quats, const float *scales, const float *dens,
+                                 const float *sh, float *d_means, float *d_quats,
+                                 float *d_scales, float *d_dens, float *d_sh, hipStream_t s)
+{
+    const unsigned g = grid_for(rp.n, 128);
+    switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
+    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
+    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
+    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
+    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vgr

@@ -1,0 +1,305 @@
+// Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
+// pairs, written for wave64 gfx950.  The rasteriser uses them to order the
+// (tile, depth) instance lists: a per-tile depth order is the sorting step the
+// 3DGS-style tile rasteriser relies on (Sec. 3.2 and Sec. 7 of the paper: the
+// Gaussians are assumed sorted front to back).
+//
+// Radix pass = histogram kernel + exclusive scan of the digit-major histogram
+// table + scatter kernel.  The scatter ranks keys stably inside a 4096-key
+// tile: each wave owns 1024 consecutive keys, ranks 64 keys at a time by
+// matching digits with one ballot per digit bit, and keeps running per-digit
+// counters in LDS; wave and block offsets are added afterwards.
+#include "vgr_internal.h"
+
+namespace vgr {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;   // 4096
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across the 256 threads of a block; *total gets the sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        uint32_t s = wsum[i];
+        off += (i < w) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *__restrict__ in,
+                                                               int64_t n,
+                                                               uint32_t *__restrict__ partial)
+{
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
+        if (idx < n) acc += in[idx];
+    }
+    uint32_t total;
+    block_exclusive_scan(acc, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the nb block sums in place, chunk by chunk.
+__global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t *__restrict__ partial,
+                                                                 int64_t nb,
+                                                                 uint32_t *__restrict__ total_out)
+{
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kTile) {
+        uint32_t v[kItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            int64_t idx = base + (int64_t)threadIdx.x * kItems + i;
+            v[i] = idx < nb ? partial[idx] : 0u;
+            s += v[i];
+        }
+        uint32_t chunk_total;
+        uint32_t off = block_exclusive_scan(s, &chunk_total) + carry;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            int64_t idx = base + (int64_t)threadIdx.x * kItems + i;
+            if (idx < nb) partial[idx] = off;
+            off += v[i];
+        }
+        carry += chunk_total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t *__restrict__ in,
+                                                             uint32_t *__restrict__ out,
+                                                             int64_t n,
+                                                             const uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t tile[kTile];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
+        tile[i * kThreads + threadIdx.x] = idx < n ? in[idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        v[i] = tile[threadIdx.x * kItems + i];
+        s += v[i];
+    }
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(s, &total) + partial[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        tile[threadIdx.x * kItems + i] = off;
+        off += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
+        if (idx < n) out[idx] = tile[i * kThreads + threadIdx.x];
+    }
+}
+
+// ---------------------------------------------------------------- radix ---
+
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
+                                                              const uint32_t *__restrict__ d_n,
+                                                              int shift, uint32_t mask,
+                                                              uint32_t *__restrict__ hist, int nb)
+{
+    __shared__ uint32_t h[kWaves][256];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) h[k][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = *d_n;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base < n) {
+#pragma unroll 4
+        for (int i = 0; i < kItems; ++i) {
+            int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
+            if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) s += h[k][threadIdx.x];
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+    const uint32_t *__restrict__ d_n, int shift, int dbits, const uint32_t *__restrict__ offs,
+    int nb)
+{
+    __shared__ uint32_t cnt[kWaves][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int64_t n = *d_n;
+    const int64_t blk_base = (int64_t)blockIdx.x * kTile;
+    if (blk_base >= n) return;   // uniform across the block
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) cnt[k][threadIdx.x] = 0;
+    __syncthreads();
+
+    const int64_t wbase = blk_base + (int64_t)w * (kTile / kWaves);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t k[kItems], v[kItems], r[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = wbase + i * 64 + lane;
+        bool valid = idx < n;
+        k[i] = valid ? keys[idx] : 0u;
+        v[i] = valid ? vals[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = wbase + i * 64 + lane;
+        bool valid = idx < n;
+        uint32_t d = (k[i] >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < dbits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t prev = valid ? cnt[w][d] : 0u;
+        r[i] = prev + below;
+        if (valid && below == 0) cnt[w][d] = prev + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t run = offs[(int64_t)d * nb + blockIdx.x];
+#pragma unroll
+        for (int k2 = 0; k2 < kWaves; ++k2) {
+            uint32_t c = cnt[k2][d];
+            cnt[k2][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t idx = wbase + i * 64 + lane;
+        if (idx < n) {
+            uint32_t d = (k[i] >> shift) & mask;
+            uint32_t pos = cnt[w][d] + r[i];
+            keys_out[pos] = k[i];
+            vals_out[pos] = v[i];
+        }
+    }
+}
+
+__global__ void copy_pairs_kernel(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v,
+                                  uint32_t *__restrict__ ko, uint32_t *__restrict__ vo,
+                                  const uint32_t *__restrict__ d_n, int64_t bound)
+{
+    const int64_t n = *d_n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n && i < bound;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        ko[i] = k[i];
+        vo[i] = v[i];
+    }
+}
+
+inline int64_t blocks_for(int64_t n) { return (n + kTile - 1) / kTile; }
+
+}  // namespace
+
+int64_t scan_tmp_words(int64_t n)
+{
+    return blocks_for(n) + 1;
+}
+
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                           bool write_total, hipStream_t s)
+{
+    if (n <= 0) {
+        if (write_total) return launch_fill_u32(out, 0u, 1, s);
+        return hipSuccess;
+    }
+    const int64_t nb = blocks_for(n);
+    scan_reduce_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(in, n, tmp);
+    scan_partials_kernel<<<1, kThreads, 0, s>>>(tmp, nb, write_total ? out + n : nullptr);
+    scan_down_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(in, out, n, tmp);
+    return hipGetLastError();
+}
+
+int64_t radix_tmp_words(int64_t n_bound)
+{
+    const int64_t nb = blocks_for(n_bound > 0 ? n_bound : 1);
+    const int64_t table = 256 * nb;
+    return 2 * table + scan_tmp_words(table);
+}
+
+hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                             const uint32_t *d_n, int64_t n_bound, int bits, uint32_t *tmp,
+                             hipStream_t s)
+{
+    if (n_bound <= 0 || bits <= 0) return hipSuccess;
+    const int64_t nb = blocks_for(n_bound);
+    const int64_t table = 256 * nb;
+    uint32_t *hist = tmp;
+    uint32_t *offs = tmp + table;
+    uint32_t *stmp = tmp + 2 * table;
+    const int passes = (bits + 7) / 8;
+    // spread the bits evenly over the passes (each at most 8)
+    int shift = 0;
+    uint32_t *ki = keys, *vi = vals, *ko = keys2, *vo = vals2;
+    for (int p = 0; p < passes; ++p) {
+        const int dbits = (bits - shift + (passes - p) - 1) / (passes - p);
+        const uint32_t mask = (1u << dbits) - 1u;
+        radix_hist_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(ki, d_n, shift, mask, hist,
+                                                                        (int)nb);
+        hipError_t e = launch_scan_u32(hist, offs, table, stmp, false, s);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(
+            ki, vi, ko, vo, d_n, shift, dbits, offs, (int)nb);
+        shift += dbits;
+        uint32_t *t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    if (ki != keys) {
+        const int64_t grid = (n_bound + 255) / 256 < 65536 ? (n_bound + 255) / 256 : 65536;
+        copy_pairs_kernel<<<dim3((unsigned)grid), 256, 0, s>>>(ki, vi, keys, vals, d_n, n_bound);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vgr

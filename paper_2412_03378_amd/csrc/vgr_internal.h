@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP translation units of libvgr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vgr.h"
+
+namespace vgr {
+
+// log2(e), ln(2), sqrt(2 pi) and sqrt(log2(e)/2), the scale folded into the
+// record so that the rasteriser's exponent is exp2(-(log2 e / 2) D^2).
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kSqrt2Pi = 2.5066282746310002f;
+constexpr float kHalfLog2eSqrt = 0.8493218002880191f;
+
+constexpr int kMaxViews = 64;
+constexpr int kGeomFloats = 16;   // rasteriser record, see Record layout below
+constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
+
+// Rasteriser record of one (Gaussian, view), 16 floats (4 float4), in the
+// Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view R(q)), so that
+// Sigma_v^-1 = L^T L, and m the view-space mean (computed in FP64):
+//   g0 = (hx, hy, lx, ly)       projected mean (fx mx/mz + cx, fy my/mz + cy) in
+//                               pixels, split into an integer hi part h and an
+//                               FP32 residual l (|l| <= 0.5), so that the pixel
+//                               offset (p + 0.5 - h) - l keeps full precision
+//   g1 = (A00, A01, A10, A11)   A = L[:, 0:2] diag(1/fx, 1/fy)
+//   g2 = (A20, A21, v0x, v0y)   v0 = L m / mz: L applied to the ray through the mean
+//   g3 = (v0z, mz, K', E')      K' = kappa sqrt(2 pi) log2 e;
+//                               E' = D2max (1 + 1e-4) / mz^2
+// For the pixel with centre (px + 0.5, py + 0.5), ray u = (ux, uy, 1), and
+// pixel offset d = (px + 0.5, py + 0.5) - h - l:
+//   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)
+//   D^2 = mz^2 |v0 x a|^2 / |w|^2   (minimum Mahalanobis distance of the ray;
+//                                    free of cancellation near the centre)
+//   beta = |u| / |w|,  log2(e) x = K' |u| exp2(-(log2 e / 2) D^2) / |w|.
+//   bound test |v0 x a|^2 > E' |w|^2  <=>  D^2 > D2max (1 + 1e-4).
+// Colour record (COLOR mode): r, g, b, 0 after the activation.
+//
+// Record gradient, 16 floats, as moments in the Gaussian's L-frame.  Per pixel,
+// with t = dL/d(ln x), v = m - gamma u (mean minus closest ray point) and
+// z = L v = mz (w x n) / |w|^2 (no cancellation), Sec. 4.2 gives
+//   d ln x / dm = -Sigma^-1 v = -L^T z,
+//   d ln x / dSigma^-1 = -1/2 (u u^T / u^T Sigma^-1 u + v v^T)
+//                      = -1/2 L^-1 (w w^T / |w|^2 + z z^T) L^-T,
+// so the sums  M = sum t (w w^T/|w|^2 + z z^T)  (symmetric) and  Z = sum t z
+// carry the whole geometric gradient:
+//   [0..5] M00 M01 M02 M11 M12 M22, [6..8] Z, [9] dL/dK', [10..12] dL/dc, [13..15] 0.
+
+struct ViewInfo {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float znear;
+    float o[3];          // world camera centre -R^-1 t (for the SH direction)
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_off;    // first global tile id of this view
+    int32_t pad0;
+    int64_t pix_off;     // offset of this view in per-pixel workspace arrays
+    float *out;          // caller image
+    const float *dL;     // caller upstream gradient (backward)
+};
+
+struct RenderParams {
+    int32_t mode;
+    int32_t sh_degree;
+    int32_t act;
+    int32_t n_views;
+    int64_t n;           // Gaussians
+    float tau;           // skip threshold on x (colour: -ln(1-alpha_min); xray: x_min)
+    float tau2;          // tau * log2(e)
+    float ymax;          // -log2(1 - alpha_max)
+    float T_min;
+    float bg[3];
+    int32_t tile_w, tile_h;
+    int32_t total_tiles;
+};
+
+// Device workspace views handed to kernels.
+struct Buffers {
+    float4 *geom;        // n_views * n records (4 float4 each)
+    float4 *color;       // n_views * n
+    uint32_t *depth_key; // n_views * n
+    uint32_t *item_ids;  // n_views * n (item = view * n + Gaussian; sorted by depth)
+    uint32_t *key2;      // n_views * n, sort ping-pong
+    uint32_t *item2;     // n_views * n, sort ping-pong
+    uint32_t *counts;    // n_views * n, tiles per item (item order)
+    uint32_t *cnt_sorted;// n_views * n, tiles per item in depth order
+    uint32_t *offsets;   // n_views * n + 1, exclusive scan of cnt_sorted
+    ushort4 *rect;       // n_views * n, tile rectangle [x0, y0, x1, y1]
+    uint32_t *inst_key;  // capacity: global tile id
+    uint32_t *inst_val;  // capacity: item
+    uint32_t *inst_key2; // capacity, sort ping-pong
+    uint32_t *inst_val2; // capacity, sort ping-pong
+    uint2 *ranges;       // total tiles
+    float *T_final;      // total pixels
+    int32_t *last_pos;   // total pixels: list position of last blended (-1)
+    int32_t *last_id;    // total pixels: Gaussian index of last blended (-1)
+    float4 *rgrad;       // n_views * n * 4 float4 (record gradients)
+    uint32_t *d_total;   // [0] = instance count K, [1] overflow flag
+    unsigned long long *counters;  // pair counters: forward [0..2], backward [3..5]
+    const ViewInfo *views;
+};
+
+// ---- launches (each returns hipSuccess or the first error) ----
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+
+hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const float *means,
+                             const float *quats, const float *scales, const float *dens,
+                             const float *sh, hipStream_t s);
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s);
+hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s);
+hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
+                       hipStream_t s);
+hipError_t launch_ranges(const Buffers &b, int64_t capacity_bound, int32_t total_tiles,
+                         hipStream_t s);
+hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool count,
+                             hipStream_t s);
+hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
+                             hipStream_t s);
+hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
+                                 const float *quats, const float *scales, const float *dens,
+                                 const float *sh, float *d_means, float *d_quats,
+                                 float *d_scales, float *d_dens, float *d_sh, hipStream_t s);
+
+// Exclusive scan of n u32 values (n host-known), out may alias nothing;
+// out[n] receives the total when write_total.  tmp: scan_tmp_words(n) u32.
+int64_t scan_tmp_words(int64_t n);
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                           bool write_total, hipStream_t s);
+
+// Radix sort of (key, val) u32 pairs; element count read from *d_n on the
+// device, grids sized for n_bound.  Ping-pong buffers keys/vals <-> keys2/vals2;
+// the sorted result ends in (keys, vals).  tmp: radix_tmp_words(n_bound).
+int64_t radix_tmp_words(int64_t n_bound);
+hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
+                             const uint32_t *d_n, int64_t n_bound, int bits, uint32_t *tmp,
+                             hipStream_t s);
+
+}  // namespace vgr

@@ -1,0 +1,206 @@
+"""Python face of libvgr: a context wrapper over PyTorch device tensors and a
+``torch.autograd.Function``.  Every step of the rendering runs in the HIP
+library; this module only marshals pointers, shapes and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Settings:
+    """Rendering rules (see vgr_settings in include/vgr.h)."""
+    mode: str = "color"              # "color" | "xray"
+    sh_degree: int = 0
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    x_min_xray: float = 1e-6
+    bg: tuple = (0.0, 0.0, 0.0)
+    act: str = "clamp"               # "clamp" | "softplus"
+    tile: tuple = (0, 0)             # (0, 0): the context's tuned tile
+
+    def to_c(self) -> L.vgr_settings:
+        s = L.vgr_settings()
+        s.mode = L.VGR_MODE_XRAY if self.mode == "xray" else L.VGR_MODE_COLOR
+        s.sh_degree = int(self.sh_degree)
+        s.alpha_min, s.alpha_max = float(self.alpha_min), float(self.alpha_max)
+        s.T_min, s.x_min_xray = float(self.T_min), float(self.x_min_xray)
+        s.bg[:] = [float(v) for v in self.bg]
+        s.act = L.VGR_ACT_SOFTPLUS10 if self.act == "softplus" else L.VGR_ACT_CLAMP0
+        s.tile_w, s.tile_h = int(self.tile[0]), int(self.tile[1])
+        return s
+
+    @staticmethod
+    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), sh_degree=0):
+        """Smallest thresholds FP32 allows (for finite-difference checks)."""
+        return Settings(mode=mode, sh_degree=sh_degree, alpha_min=1e-30, alpha_max=1 - 2 ** -20,
+                        T_min=0.0, x_min_xray=1e-30, bg=bg, act=act)
+
+
+def camera_struct(cam) -> L.vgr_camera:
+    """Any object with R (3x3), t (3), fx, fy, cx, cy, width, height, znear."""
+    c = L.vgr_camera()
+    R = [float(v) for v in torch.as_tensor(cam.R, dtype=torch.float32).reshape(9)]
+    t = [float(v) for v in torch.as_tensor(cam.t, dtype=torch.float32).reshape(3)]
+    c.R[:] = R
+    c.t[:] = t
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def _dev_ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != torch.float32 and t.dtype != torch.int32 and t.dtype != torch.uint32:
+        raise ValueError(f"unexpected dtype {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Renderer:
+    """Owns one vgr context (workspace + the state saved by the last forward)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.vgr_create(C.byref(h), int(device)))
+        self._h = h
+        self.device = int(device)
+        self.n_views = 0
+        self.shapes = []
+        self.mode = "color"
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.vgr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(self._lib.vgr_set_stream(self._h, C.c_void_p(s)), self._h)
+
+    def forward(self, means, quats, scales, dens, sh, cams: Sequence, settings: Settings,
+                outs: Optional[List[torch.Tensor]] = None) -> List[torch.Tensor]:
+        """Render ``cams`` (host camera objects).  Returns one image per view:
+        (3, H, W) in colour mode, (H, W) in X-ray mode."""
+        self._sync_stream()
+        n = int(means.shape[0])
+        ncam = len(cams)
+        cam_arr = (L.vgr_camera * ncam)(*[camera_struct(c) for c in cams])
+        if outs is None:
+            outs = []
+            for c in cams:
+                shape = (int(c.height), int(c.width)) if settings.mode == "xray" else \
+                        (3, int(c.height), int(c.width))
+                outs.append(torch.empty(shape, dtype=torch.float32, device=means.device))
+        out_ptrs = (C.c_void_p * ncam)(*[o.data_ptr() for o in outs])
+        st = settings.to_c()
+        rc = self._lib.vgr_render_forward(
+            self._h, C.byref(st), n, _dev_ptr(means), _dev_ptr(quats), _dev_ptr(scales),
+            _dev_ptr(dens), _dev_ptr(sh) if settings.mode != "xray" else None, ncam, cam_arr,
+            out_ptrs)
+        L.check(rc, self._h)
+        self.n_views = ncam
+        self.shapes = [tuple(o.shape) for o in outs]
+        self.mode = settings.mode
+        return outs
+
+    def backward(self, dL: Sequence[torch.Tensor], d_means, d_quats, d_scales, d_dens, d_sh):
+        """Add the gradients of the last forward to the given tensors."""
+        self._sync_stream()
+        dLc = [g.contiguous().float() for g in dL]
+        ptrs = (C.c_void_p * len(dLc))(*[g.data_ptr() for g in dLc])
+        rc = self._lib.vgr_render_backward(self._h, ptrs, _dev_ptr(d_means), _dev_ptr(d_quats),
+                                           _dev_ptr(d_scales), _dev_ptr(d_dens),
+                                           _dev_ptr(d_sh))
+        L.check(rc, self._h)
+
+    def aux(self, view: int, height: int, width: int, device=None):
+        """(T_final, last contributor index) of one view of the last forward."""
+        self._sync_stream()
+        dev = device or torch.device("cuda", self.device)
+        T = torch.empty((height, width), dtype=torch.float32, device=dev)
+        last = torch.empty((height, width), dtype=torch.int32, device=dev)
+        L.check(self._lib.vgr_get_aux(self._h, int(view), _dev_ptr(T), _dev_ptr(last)), self._h)
+        return T, last
+
+    def stats(self) -> dict:
+        s = L.vgr_stats()
+        L.check(self._lib.vgr_get_stats(self._h, C.byref(s)), self._h)
+        return {k: getattr(s, k) for k, _ in L.vgr_stats._fields_}
+
+    def set_counting(self, on: bool):
+        L.check(self._lib.vgr_set_counting(self._h, int(bool(on))), self._h)
+
+    def set_timing(self, on: bool):
+        L.check(self._lib.vgr_set_timing(self._h, int(bool(on))), self._h)
+
+    def timing(self) -> dict:
+        cap = 16
+        names = (C.c_char_p * cap)()
+        ms = (C.c_float * cap)()
+        cnt = C.c_int32()
+        L.check(self._lib.vgr_get_timing(self._h, cap, names, ms, C.byref(cnt)), self._h)
+        return {names[i].decode(): float(ms[i]) for i in range(cnt.value)}
+
+    def sort_pairs(self, keys: torch.Tensor, vals: torch.Tensor, bits: int):
+        """In-place stable radix sort of (u32 key, u32 value) device pairs."""
+        self._sync_stream()
+        assert keys.dtype in (torch.int32, torch.uint32) and vals.dtype in (torch.int32, torch.uint32)
+        rc = self._lib.vgr_sort_pairs(self._h, _dev_ptr(keys), _dev_ptr(vals), int(keys.numel()),
+                                      int(bits))
+        L.check(rc, self._h)
+
+
+class _VolRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, settings, cams, means, quats, scales, dens, sh):
+        outs = renderer.forward(means, quats, scales, dens, sh, cams, settings)
+        ctx.renderer = renderer
+        ctx.settings = settings
+        ctx.save_for_backward(means, quats, scales, dens, sh if sh is not None else torch.empty(0))
+        ctx.has_sh = sh is not None and settings.mode != "xray"
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *gouts):
+        means, quats, scales, dens, sh = ctx.saved_tensors
+        gm = torch.zeros_like(means)
+        gq = torch.zeros_like(quats)
+        gs = torch.zeros_like(scales)
+        gd = torch.zeros_like(dens)
+        gsh = torch.zeros_like(sh) if ctx.has_sh else None
+        gl = [g if g is not None else torch.zeros(s, device=means.device)
+              for g, s in zip(gouts, ctx.renderer.shapes)]
+        ctx.renderer.backward(gl, gm, gq, gs, gd, gsh)
+        return None, None, None, gm, gq, gs, gd, gsh
+
+
+def render(means, quats, scales, dens, sh, cams, settings: Settings = None,
+           renderer: Renderer = None):
+    """Differentiable render of ``cams``; returns a tuple of per-view images.
+    A renderer keeps the state of one forward for its backward: pass one per
+    in-flight graph node (a fresh one is made when none is given)."""
+    settings = settings or Settings()
+    renderer = renderer or Renderer(means.device.index or 0)
+    return _VolRender.apply(renderer, settings, list(cams), means.contiguous(),
+                            quats.contiguous(), scales.contiguous(), dens.contiguous(),
+                            None if sh is None else sh.contiguous())

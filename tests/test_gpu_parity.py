@@ -1,0 +1,231 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes: the oracle-sized workloads (128x128 / 1k Gaussians and smaller crops)
+span many tiles and ragged edge tiles; the full-size workloads are checked on
+sampled pixels in test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import gpu_helpers as G
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def R(dev):
+    from paper_2412_03378_amd import Renderer
+    return Renderer(0)
+
+
+def _settings(**kw):
+    from paper_2412_03378_amd import Settings
+    return Settings(**kw)
+
+
+def _oset(st):
+    return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
+                           T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act)
+
+
+# ------------------------------------------------------------------ sort ---
+
+@pytest.mark.parametrize("n,bits,kind", [
+    (1, 8, "random"), (4095, 13, "random"), (4096, 13, "random"), (100003, 13, "random"),
+    (262144, 32, "random"), (50000, 20, "equal"), (70001, 16, "sorted"),
+    (70001, 16, "reversed"), (33333, 32, "max"), (65536, 7, "random"), (0, 8, "random")])
+def test_radix_sort_stable(R, dev, n, bits, kind):
+    rng = np.random.default_rng(n + bits)
+    hi = (1 << bits) - 1
+    if kind == "random":
+        k = rng.integers(0, hi + 1, n, dtype=np.uint64)
+    elif kind == "equal":
+        k = np.full(n, 12345 & hi, np.uint64)
+    elif kind == "sorted":
+        k = np.sort(rng.integers(0, hi + 1, n, dtype=np.uint64))
+    elif kind == "reversed":
+        k = np.sort(rng.integers(0, hi + 1, n, dtype=np.uint64))[::-1].copy()
+    else:
+        k = np.full(n, hi, np.uint64)
+        k[::7] = 0
+    k = k.astype(np.uint32)
+    v = np.arange(n, dtype=np.uint32)
+    kt = torch.from_numpy(k.view(np.int32)).to(dev)
+    vt = torch.from_numpy(v.view(np.int32)).to(dev)
+    R.sort_pairs(kt, vt, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(kt.cpu().numpy().view(np.uint32), k[order])
+    assert np.array_equal(vt.cpu().numpy().view(np.uint32), v[order])
+
+
+# ------------------------------------------------------- config 1 forward ---
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return scenes.config1()
+
+
+@pytest.fixture(scope="module")
+def cfg1_ref(cfg1):
+    return oracle.render(cfg1.scene, cfg1.cams[0], oracle.Settings())
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
+def test_config1_forward(R, dev, cfg1, cfg1_ref, tile):
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    st = _settings(tile=tile)
+    img = R.forward(*G.device_scene(sc, dev), [cam], st)[0]
+    T, last = R.aux(0, cam.height, cam.width)
+    torch.cuda.synchronize()
+    e_ok, nflag, e_flag = G.compare_image(img.cpu().numpy(), cfg1_ref["image"], cfg1_ref["margin"])
+    print(f"tile {tile}: max err {e_ok:.3g}, flagged {nflag} (max {e_flag:.3g})")
+    assert e_ok <= G.IMG_TOL
+    assert e_flag <= G.FLIP_TOL
+    assert nflag <= 0.01 * cam.width * cam.height
+    ok = cfg1_ref["margin"] > G.MARGIN
+    assert np.abs(T.cpu().numpy() - cfg1_ref["T"])[ok].max() <= G.IMG_TOL
+    assert np.array_equal(last.cpu().numpy()[ok], cfg1_ref["last"][ok])
+
+
+def test_tile_shape_independence(R, dev, cfg1):
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    base = None
+    for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
+        img = R.forward(*G.device_scene(sc, dev), [cam], _settings(tile=tile))[0].cpu().numpy()
+        if base is None:
+            base = img
+        else:
+            assert np.abs(img - base).max() <= 1e-6
+
+
+def test_forward_deterministic(R, dev, cfg1):
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    a = R.forward(*G.device_scene(sc, dev), [cam], _settings())[0].cpu().numpy()
+    b = R.forward(*G.device_scene(sc, dev), [cam], _settings())[0].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------ config 1 backward ---
+
+@pytest.mark.parametrize("act,tile", [("clamp", (16, 16)), ("softplus", (8, 8))])
+def test_config1_backward(R, dev, cfg1, act, tile):
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    st = _settings(act=act, tile=tile, bg=(0.1, 0.2, 0.3))
+    ost = _oset(st)
+    ref = oracle.render(sc, cam, ost)
+    rng = np.random.default_rng(5)
+    dL = rng.standard_normal((3, cam.height, cam.width)) * (ref["margin"] > G.MARGIN)
+    gref = oracle.render_backward(sc, cam, ost, dL)
+    t = G.device_scene(sc, dev)
+    R.forward(*t, [cam], st)
+    grads = [torch.zeros_like(x) for x in t]
+    R.backward([torch.from_numpy(dL.astype(np.float32)).to(dev)], *grads)
+    torch.cuda.synchronize()
+    ratios = {name: G.grad_errors(g.cpu().numpy(), gref[name], gref["abs_" + name])
+              for name, g in zip(("means", "quats", "scales", "dens", "sh"), grads)}
+    print("worst ratios", ratios)
+    assert max(ratios.values()) <= 1.0, ratios
+
+
+# ------------------------------------------------------------- X-ray mode ---
+
+def _xray_small(n=3000, size=96, views=3, seed=4):
+    wl = scenes.config4(n=n, n_views=64, size=size, seed=seed, with_grad=False)
+    return wl.scene, [wl.cams[k] for k in (0, 16, 40)][:views]
+
+
+def test_xray_forward_backward(R, dev):
+    sc, cams = _xray_small()
+    st = _settings(mode="xray")
+    ost = _oset(st)
+    t = G.device_scene(sc, dev)
+    imgs = R.forward(*t, cams, st)
+    rng = np.random.default_rng(9)
+    dLs, refs = [], []
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc, cam, ost)
+        refs.append(ref)
+        e_ok, nflag, e_flag = G.compare_image(imgs[v].cpu().numpy()[None], ref["image"],
+                                              ref["margin"], xray=True)
+        print(f"view {v}: rel err {e_ok:.3g} flagged {nflag}")
+        assert e_ok <= G.XRAY_REL
+        dLs.append(rng.standard_normal((cam.height, cam.width)) * (ref["margin"] > G.MARGIN))
+    grads = [torch.zeros_like(x) for x in t[:4]]
+    R.backward([torch.from_numpy(d.astype(np.float32)).to(dev) for d in dLs], *grads, None)
+    torch.cuda.synchronize()
+    gsum = {k: 0 for k in ("means", "quats", "scales", "dens")}
+    asum = dict(gsum)
+    for cam, d in zip(cams, dLs):
+        g = oracle.render_backward(sc, cam, ost, d[None])
+        for k in gsum:
+            gsum[k] = gsum[k] + g[k]
+            asum[k] = asum[k] + g["abs_" + k]
+    ratios = {name: G.grad_errors(g.cpu().numpy(), gsum[name], asum[name])
+              for name, g in zip(("means", "quats", "scales", "dens"), grads)}
+    print("worst ratios", ratios)
+    assert max(ratios.values()) <= 1.0, ratios
+
+
+# -------------------------------------------------- batching, edge cases ---
+
+def test_batched_equals_single(R, dev):
+    wl = scenes.config3(n=4000, n_views=5, with_grad=False)
+    sc = wl.scene
+    cams = [scenes.Camera(c.R, c.t, c.fx / 8, c.fy / 8, c.cx / 8, c.cy / 8, c.width // 8,
+                          c.height // 8) for c in wl.cams]
+    st = _settings(sh_degree=3, tile=(16, 8))
+    t = G.device_scene(sc, dev)
+    many = [x.cpu().numpy() for x in R.forward(*t, cams, st)]
+    for v, cam in enumerate(cams):
+        one = R.forward(*t, [cam], st)[0].cpu().numpy()
+        assert np.array_equal(one, many[v])
+
+
+def test_empty_and_degenerate(R, dev):
+    st = _settings(bg=(0.25, 0.5, 0.75))
+    cam = scenes.axis_camera(4.0, 7, 5, 60.0)
+    z = torch.zeros((0, 3), device=dev)
+    img = R.forward(z, torch.zeros((0, 4), device=dev), z, torch.zeros((0,), device=dev),
+                    torch.zeros((0, 1, 3), device=dev), [cam], st)[0].cpu().numpy()
+    assert np.allclose(img, np.array([0.25, 0.5, 0.75])[:, None, None])
+    # everything behind the camera or zero density: background everywhere
+    sc = scenes.config1(n=50, width=7, height=5).scene
+    means = sc.means.copy()
+    means[:, 2] = -10.0
+    sc2 = scenes.Scene(means, sc.quats, sc.scales, sc.dens, sc.sh, 0)
+    img = R.forward(*G.device_scene(sc2, dev), [cam], st)[0].cpu().numpy()
+    assert np.allclose(img, np.array([0.25, 0.5, 0.75])[:, None, None])
+    sc3 = scenes.Scene(sc.means, sc.quats, sc.scales, np.zeros_like(sc.dens), sc.sh, 0)
+    img = R.forward(*G.device_scene(sc3, dev), [cam], st)[0].cpu().numpy()
+    assert np.allclose(img, np.array([0.25, 0.5, 0.75])[:, None, None])
+    # 1x1 image
+    cam1 = scenes.axis_camera(4.0, 1, 1, 60.0)
+    sc4 = scenes.config1(n=200).scene
+    img = R.forward(*G.device_scene(sc4, dev), [cam1], _settings())[0].cpu().numpy()
+    ref = oracle.render(sc4, cam1, oracle.Settings())
+    assert np.abs(img - ref["image"]).max() <= G.IMG_TOL
+
+
+def test_invalid_arguments(R, dev):
+    from paper_2412_03378_amd import _lib
+    cam = scenes.axis_camera(4.0, 8, 8, 60.0)
+    sc = scenes.config1(n=10, width=8, height=8).scene
+    t = G.device_scene(sc, dev)
+    with pytest.raises(_lib.VgrError) as e:
+        R.forward(*t, [cam], _settings(tile=(12, 12)))
+    assert e.value.code == _lib.VGR_ERR_INVALID_ARG
+    with pytest.raises(_lib.VgrError) as e:
+        R.forward(*t, [cam], _settings(sh_degree=5))
+    assert e.value.code == _lib.VGR_ERR_INVALID_ARG
