@@ -62,8 +62,13 @@ def _step(r, params, grads, cams, st, dLs):
     r.backward(dLs, *grads)
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def bench_headline(args, torch, dev):
     from paper_2412_03378_amd import Renderer, Settings, scenes
+    _log("generating the 1M-Gaussian 1080p scene")
     wl = scenes.config2()
     params = _device_scene(wl.scene, dev, torch)
     dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
@@ -72,9 +77,11 @@ def bench_headline(args, torch, dev):
     st = Settings(sh_degree=3, tile=tile)
     r = Renderer(0)
     cams = wl.cams
+    _log("warm-up")
     for _ in range(args.warmup):
         _step(r, params, grads, cams, st, dLs)
     torch.cuda.synchronize()
+    _log("timed steps")
     r.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -107,6 +114,7 @@ def bench_headline(args, torch, dev):
 
 def bench_batched(args, torch, dev):
     from paper_2412_03378_amd import Renderer, Settings, scenes
+    _log("generating the 3M-Gaussian 16-view scene")
     wl = scenes.config3()
     params = _device_scene(wl.scene, dev, torch)
     dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
@@ -116,6 +124,8 @@ def bench_batched(args, torch, dev):
     nv = len(wl.cams)
     res = {}
     for mode in ("batched", "single"):
+        _log(f"{mode} views")
+
         def run():
             if mode == "batched":
                 _step(r, params, grads, wl.cams, st, dLs)
@@ -216,6 +226,7 @@ def main():
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3)}
     if not args.no_cpu_baseline:
+        _log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(h["wl"], args.cpu_pixels)
     print(json.dumps(out), flush=True)
 

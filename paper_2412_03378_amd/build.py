@@ -22,6 +22,9 @@ ARCH = os.environ.get("VGR_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
+    # no implicit contraction: the backward recomputes the forward's decisions
+    # bit for bit, so every fused multiply-add in the kernels is written out
+    "-ffp-contract=off",
     # packed FP32 VALU forms are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

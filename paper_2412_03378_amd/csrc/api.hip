@@ -23,7 +23,7 @@ enum Stage {
     ST_ZERO_GRAD, ST_RASTER_BWD, ST_PREPROCESS_BWD, ST_COUNT
 };
 const char *kStageNames[ST_COUNT] = {
-    "preprocess_fwd", "sort_depth", "scan_emit", "sort_tiles", "tile_ranges", "raster_fwd",
+    "preprocess_fwd", "sort_depth", "scan_emit", "sort_tiles", "tile_ranges_order", "raster_fwd",
     "zero_record_grads", "raster_bwd", "preprocess_bwd"
 };
 
@@ -37,6 +37,7 @@ struct vgr_ctx {
     // workspace
     DevBuf geom, color, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id;
+    DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views;
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
@@ -206,6 +207,10 @@ Buffers make_buffers(vgr_ctx *c)
     b.inst_key2 = ptr<uint32_t>(c->inst_key2);
     b.inst_val2 = ptr<uint32_t>(c->inst_val2);
     b.ranges = ptr<uint2>(c->ranges);
+    b.tile_key = ptr<uint32_t>(c->tile_key);
+    b.tile_order = ptr<uint32_t>(c->tile_order);
+    b.tile_key2 = ptr<uint32_t>(c->tile_key2);
+    b.tile_order2 = ptr<uint32_t>(c->tile_order2);
     b.T_final = ptr<float>(c->T_final);
     b.last_pos = ptr<int32_t>(c->last_pos);
     b.last_id = ptr<int32_t>(c->last_id);
@@ -275,7 +280,8 @@ void vgr_destroy(vgr_ctx *c)
     DevBuf *all[] = { &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
                       &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
-                      &c->last_pos, &c->last_id, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
+                      &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
+                      &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
                       &c->words, &c->counters, &c->views };
     for (DevBuf *b : all)
         if (b->p) hipFree(b->p);
@@ -431,16 +437,19 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     rp.total_tiles = (int32_t)tiles;
 
     const int64_t m = n * n_views;
-    if ((rc = ensure(c, c->geom, sizeof(float4) * 4 * m)) ||
+    const int64_t sort_n = m > tiles ? m : tiles;
+    if ((rc = ensure(c, c->geom, sizeof(float4) * kGeomVec * m)) ||
         (rc = ensure(c, c->color, sizeof(float4) * (rp.mode == VGR_MODE_COLOR ? m : 1))) ||
         (rc = ensure(c, c->depth_key, 4 * m)) || (rc = ensure(c, c->item_ids, 4 * m)) ||
         (rc = ensure(c, c->key2, 4 * m)) || (rc = ensure(c, c->item2, 4 * m)) ||
         (rc = ensure(c, c->counts, 4 * m)) || (rc = ensure(c, c->cnt_sorted, 4 * m)) ||
         (rc = ensure(c, c->offsets, 4 * (m + 1))) || (rc = ensure(c, c->rect, 8 * m)) ||
         (rc = ensure(c, c->ranges, 8 * tiles)) || (rc = ensure(c, c->T_final, 4 * pix)) ||
+        (rc = ensure(c, c->tile_key, 4 * tiles)) || (rc = ensure(c, c->tile_order, 4 * tiles)) ||
+        (rc = ensure(c, c->tile_key2, 4 * tiles)) || (rc = ensure(c, c->tile_order2, 4 * tiles)) ||
         (rc = ensure(c, c->last_pos, 4 * pix)) || (rc = ensure(c, c->last_id, 4 * pix)) ||
         (rc = ensure(c, c->scan_tmp, 4 * scan_tmp_words(m > 0 ? m : 1))) ||
-        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(m > 0 ? m : 1))) ||
+        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(sort_n > 0 ? sort_n : 1))) ||
         (rc = ensure(c, c->inst_key, 4)) || (rc = ensure(c, c->inst_val, 4)) ||
         (rc = ensure(c, c->inst_key2, 4)) || (rc = ensure(c, c->inst_val2, 4)))
         return rc;
@@ -469,7 +478,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
         K = c->h_words[0];
         if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
             (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
-            (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > m ? K : m))))
+            (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > sort_n ? K : sort_n))))
             return rc;
         c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
         b = make_buffers(c);
@@ -485,6 +494,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     }
     mark(c, ST_RANGES);
     HIP_TRY(c, launch_ranges(b, K, rp.total_tiles, s));
+    HIP_TRY(c, launch_tile_order(b, rp.total_tiles, ptr<uint32_t>(c->sort_tmp), s));
     mark_end(c, ST_RANGES);
     if (c->counting)
         HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 6, s));

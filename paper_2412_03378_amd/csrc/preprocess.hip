@@ -256,11 +256,38 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 (float)(g.L[6] * u0x + g.L[7] * u0y + g.L[8]) };
             const float mz = (float)mzd;
             const float ifx = 1.0f / vi.fx, ify = 1.0f / vi.fy;
-            float4 *gp = b.geom + item * 4;
+            const float A[6] = { g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify,
+                                 g.L[6] * ifx, g.L[7] * ify };
+            // bound pre-test form (FP64): with G = A^T A, gv = A^T v0, V = |v0|^2,
+            // D' = D2max (1 + 1e-4):  Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V),
+            // l = -gv / V
+            float Q00 = 0.f, Q01 = 0.f, Q11 = 0.f, l0 = 0.f, l1 = 0.f;
+            {
+                const double Dp = (double)D2max * (1.0 + 1e-4);
+                double G00 = 0, G01 = 0, G11 = 0, g0 = 0, g1 = 0, V = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const double ak0 = A[2 * k], ak1 = A[2 * k + 1], vk = v0[k];
+                    G00 += ak0 * ak0; G01 += ak0 * ak1; G11 += ak1 * ak1;
+                    g0 += ak0 * vk; g1 += ak1 * vk; V += vk * vk;
+                }
+                const double mz2 = mzd * mzd, den = Dp * V;
+                const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) / den;
+                const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) / den;
+                const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) / den;
+                const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
+                const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
+                const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
+                if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
+                    Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
+                    l0 = (float)(-g0 / V); l1 = (float)(-g1 / V);
+                }
+            }
+            float4 *gp = b.geom + item * kGeomVec;
             gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
-            gp[1] = make_float4(g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify);
-            gp[2] = make_float4(g.L[6] * ifx, g.L[7] * ify, v0[0], v0[1]);
-            gp[3] = make_float4(v0[2], mz, K * kLog2e, D2max * (1.0f + 1e-4f) / (mz * mz));
+            gp[1] = make_float4(A[0], A[1], A[2], A[3]);
+            gp[2] = make_float4(A[4], A[5], v0[0], v0[1]);
+            gp[3] = make_float4(v0[2], mz, K * kLog2e, Q11);
+            gp[4] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
             if (rp.mode == VGR_MODE_COLOR) {
                 float dx = mu[0] - vi.o[0], dy = mu[1] - vi.o[1], dz = mu[2] - vi.o[2];
                 const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -338,6 +365,18 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t 
         if (j == 0 || keys[j - 1] != k) ranges[k].x = (uint32_t)j;
         if (j == K - 1 || keys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
     }
+}
+
+// Cost key of each tile for the heaviest-first order: 0xFFFF - min(len, 0xFFFF).
+__global__ void tile_key_kernel(const uint2 *__restrict__ ranges, uint32_t *__restrict__ key,
+                                uint32_t *__restrict__ order, int32_t n)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    key[t] = 0xFFFFu - min(len, 0xFFFFu);
+    order[t] = (uint32_t)t;
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -545,6 +584,18 @@ hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, h
     if (g > 16384) g = 16384;
     ranges_kernel<<<g, 256, 0, s>>>(b.inst_key, b.d_total, b.ranges, bound);
     return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
+                             hipStream_t s)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    tile_key_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, b.tile_key, b.tile_order,
+                                                                total_tiles);
+    hipError_t e = launch_fill_u32(b.d_total + 3, (uint32_t)total_tiles, 1, s);
+    if (e != hipSuccess) return e;
+    return launch_radix_sort(b.tile_key, b.tile_order, b.tile_key2, b.tile_order2, b.d_total + 3,
+                             total_tiles, 16, sort_tmp, s);
 }
 
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,

@@ -1,21 +1,24 @@
 // Tile rasteriser, forward and backward, for gfx950 (wave64).
 //
 // One wave (64 lanes) owns one screen tile of TW x TH pixels; lane l holds the
-// TW*TH/64 pixels of column l % TW, rows l / TW + k * (64 / TW).  The tile's
+// TW*TH/64 pixels of column l % TW, rows l / TW + k * (64 / TW) ("slot" k).
+// Tiles are launched heaviest list first, so that the long lists of dense
+// regions start early and the short ones fill the tail.  The tile's
 // depth-sorted Gaussian list is walked in batches of 64 records staged in LDS
 // (structure of arrays; every lane reads the same record, a broadcast).
 //
-// Per (pixel, Gaussian) pair, with u = (ux, uy, 1) the pixel's view-space ray
-// and the record (centre h + l, A, v0, mz, K', E'; see vgr_internal.h):
-//   d = pixel centre - h - l,  a = A d,  w = v0 + a,  n = v0 x a,
-//   num = |n|^2,  qw = |w|^2,  se = (log2 e / 2) mz^2
-//   bound test: num > E' qw  =>  alpha < alpha_min, skip (no transcendental)
-//   r = 1/sqrt(qw), y = K' |u| r exp2(-se num r^2)        (= log2(e) x, Sec. 4.2)
+// Per (pixel, Gaussian) pair, with the record (centre h + l, A, v0, mz, K',
+// bound form Q, l; see vgr_internal.h) and d = pixel centre - h - l:
+//   bound pre-test f(d) = d^T Q d + 2 l^T d - 1 > margin  =>  alpha < alpha_min
+//   a = A d,  w = v0 + a,  n = v0 x a,  num = |n|^2,  qw = |w|^2
+//   r = 1/sqrt(qw), y = K' |u| r exp2(-se num r^2), se = (log2 e / 2) mz^2
+//                                               (y = log2(e) x, Sec. 4.2)
 //   skip if y < tau log2(e); y = min(y, -log2(1 - alpha_max))
 //   1 - alpha = exp2(-y); stop the pixel when T (1 - alpha) < T_min, else
 //   C += c alpha T, T *= 1 - alpha                          (Sec. 4.1)
-// The lane's column shares d_x, A[:,0] d_x and v0 + A[:,0] d_x over its pixels;
-// uy[] holds the pixel-centre row coordinates.
+// The pre-test costs three operations per pixel; everything after it runs
+// under one wave-uniform branch per slot (taken when any lane's pixel in the
+// slot passes), with per-lane selects instead of nested execution masks.
 // The wave leaves its list as soon as every one of its pixels has stopped.
 // X-ray mode sums y over the whole list instead (Sec. 6.2).
 //
@@ -37,25 +40,42 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 struct Rec {
-    float hx, hy, lx, ly, A00, A01, A10, A11, A20, A21, v0x, v0y, v0z, mz, K, E, se;
+    float hx, hy, lx, ly, A00, A01, A10, A11, A20, A21, v0x, v0y, v0z, mz, K, Q11, Q00, Q01x2,
+        l0x2, l1x2, se;
 };
 
-__device__ __forceinline__ Rec load_rec(const float4 *g0, const float4 *g1, const float4 *g2,
-                                        const float4 *g3, int q)
+struct Stage {
+    float4 g[kGeomVec][64];
+    float4 c[64];
+    uint32_t item[64];
+};
+
+__device__ __forceinline__ Rec load_rec(const Stage &st, int q)
 {
-    const float4 a = g0[q], b = g1[q], c = g2[q], d = g3[q];
+    const float4 a = st.g[0][q], b = st.g[1][q], c = st.g[2][q], d = st.g[3][q], e = st.g[4][q];
     Rec r;
     r.hx = a.x; r.hy = a.y; r.lx = a.z; r.ly = a.w;
     r.A00 = b.x; r.A01 = b.y; r.A10 = b.z; r.A11 = b.w;
     r.A20 = c.x; r.A21 = c.y; r.v0x = c.z; r.v0y = c.w;
-    r.v0z = d.x; r.mz = d.y; r.K = d.z; r.E = d.w;
+    r.v0z = d.x; r.mz = d.y; r.K = d.z; r.Q11 = d.w;
+    r.Q00 = e.x; r.Q01x2 = e.y; r.l0x2 = e.z; r.l1x2 = e.w;
     r.se = (0.5f * kLog2e) * r.mz * r.mz;
     return r;
 }
 
-// Per-lane column terms shared by the lane's pixels (pxc = px + 0.5).
+__device__ __forceinline__ void stage_record(Stage &st, const Buffers &b, int lane, uint32_t item,
+                                             bool color)
+{
+    const float4 *gp = b.geom + (size_t)item * kGeomVec;
+#pragma unroll
+    for (int v = 0; v < kGeomVec; ++v) st.g[v][lane] = gp[v];
+    if (color) st.c[lane] = b.color[item];
+    st.item[lane] = item;
+}
+
+// Per-lane terms shared by the lane's pixels (pxc = px + 0.5).
 struct ColTerms {
-    float dx, ax0, ax1, ax2, wx0, wx1, wx2;
+    float dx, ax0, ax1, ax2, wx0, wx1, wx2, f0, f1;
 };
 
 __device__ __forceinline__ ColTerms col_terms(const Rec &r, float pxc)
@@ -68,30 +88,37 @@ __device__ __forceinline__ ColTerms col_terms(const Rec &r, float pxc)
     c.wx0 = r.v0x + c.ax0;
     c.wx1 = r.v0y + c.ax1;
     c.wx2 = r.v0z + c.ax2;
+    c.f0 = __fmaf_rn(c.dx, __fmaf_rn(r.Q00, c.dx, r.l0x2), -1.0f);
+    c.f1 = __fmaf_rn(r.Q01x2, c.dx, r.l1x2);
     return c;
 }
 
-// Geometry of one pair (pyc = py + 0.5).  Returns false when the bound test
-// rejects the pair.
+// Bound pre-test of one pixel (pyc = py + 0.5): true if alpha >= alpha_min is
+// possible.  Writes the row offset.
+__device__ __forceinline__ bool pre_test(const Rec &r, const ColTerms &c, float pyc, float &dy)
+{
+    dy = (pyc - r.hy) - r.ly;
+    const float f = __fmaf_rn(dy, __fmaf_rn(r.Q11, dy, c.f1), c.f0);
+    return !(f > kConicMargin);
+}
+
 struct PairGeom {
-    float dy, a0, a1, a2, w0, w1, w2, n0, n1, n2, num, qw;
+    float a0, a1, a2, w0, w1, w2, n0, n1, n2, num, qw;
 };
 
-__device__ __forceinline__ bool pair_geom(const Rec &r, const ColTerms &c, float pyc, PairGeom &g)
+__device__ __forceinline__ void pair_geom(const Rec &r, const ColTerms &c, float dy, PairGeom &g)
 {
-    g.dy = (pyc - r.hy) - r.ly;
-    g.a0 = __fmaf_rn(r.A01, g.dy, c.ax0);
-    g.a1 = __fmaf_rn(r.A11, g.dy, c.ax1);
-    g.a2 = __fmaf_rn(r.A21, g.dy, c.ax2);
-    g.w0 = __fmaf_rn(r.A01, g.dy, c.wx0);
-    g.w1 = __fmaf_rn(r.A11, g.dy, c.wx1);
-    g.w2 = __fmaf_rn(r.A21, g.dy, c.wx2);
+    g.a0 = __fmaf_rn(r.A01, dy, c.ax0);
+    g.a1 = __fmaf_rn(r.A11, dy, c.ax1);
+    g.a2 = __fmaf_rn(r.A21, dy, c.ax2);
+    g.w0 = __fmaf_rn(r.A01, dy, c.wx0);
+    g.w1 = __fmaf_rn(r.A11, dy, c.wx1);
+    g.w2 = __fmaf_rn(r.A21, dy, c.wx2);
     g.n0 = __fmaf_rn(r.v0y, g.a2, -r.v0z * g.a1);
     g.n1 = __fmaf_rn(r.v0z, g.a0, -r.v0x * g.a2);
     g.n2 = __fmaf_rn(r.v0x, g.a1, -r.v0y * g.a0);
     g.num = __fmaf_rn(g.n0, g.n0, __fmaf_rn(g.n1, g.n1, g.n2 * g.n2));
     g.qw = __fmaf_rn(g.w0, g.w0, __fmaf_rn(g.w1, g.w1, g.w2 * g.w2));
-    return !(g.num > r.E * g.qw);
 }
 
 template <int TW, int TH>
@@ -114,9 +141,10 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    __shared__ float4 s_g0[64], s_g1[64], s_g2[64], s_g3[64], s_c[64];
+    constexpr bool COLOR = MODE == VGR_MODE_COLOR;
+    __shared__ Stage st;
 
-    const int gt = blockIdx.x;
+    const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
     const int lt = gt - vi.tile_off;
@@ -128,15 +156,15 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     const float pxc = (float)px + 0.5f;
     const float ux = (pxc - vi.cx) / vi.fx;
 
-    float uy[PPL], un[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    float pyc[PPL], un[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
     int last[PPL];
     bool act[PPL];
     uint32_t c_test = 0, c_full = 0, c_blend = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RS;
-        uy[k] = (float)py + 0.5f;   // pixel-centre row coordinate
-        const float uyn = (uy[k] - vi.cy) / vi.fy;
+        pyc[k] = (float)py + 0.5f;
+        const float uyn = (pyc[k] - vi.cy) / vi.fy;
         un[k] = sqrtf(ux * ux + uyn * uyn + 1.0f);
         act[k] = px < W && py < H;
         T[k] = 1.0f;
@@ -147,66 +175,61 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     const float tau2 = rp.tau2, ymax = rp.ymax, Tmin = rp.T_min;
 
     for (uint32_t bs = range.x; bs < range.y; bs += 64) {
-        bool anyact = false;
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) anyact |= act[k];
-        if (!__any(anyact)) break;
         const uint32_t j = bs + lane;
-        if (j < range.y) {
-            const uint32_t item = b.inst_val[j];
-            const float4 *gp = b.geom + (size_t)item * 4;
-            s_g0[lane] = gp[0];
-            s_g1[lane] = gp[1];
-            s_g2[lane] = gp[2];
-            s_g3[lane] = gp[3];
-            if (MODE == VGR_MODE_COLOR) s_c[lane] = b.color[item];
-        }
+        if (j < range.y) stage_record(st, b, lane, b.inst_val[j], COLOR);
         __syncthreads();
         const int nb = (int)min(64u, range.y - bs);
+        bool alive = true;
         for (int qi = 0; qi < nb; ++qi) {
-            if (MODE == VGR_MODE_COLOR) {
-                bool a2 = false;
+            if (COLOR) {
+                bool any = false;
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) a2 |= act[k];
-                if (!__any(a2)) break;
+                for (int k = 0; k < PPL; ++k) any |= act[k];
+                if (!__any(any)) {
+                    alive = false;
+                    break;
+                }
             }
-            const Rec r = load_rec(s_g0, s_g1, s_g2, s_g3, qi);
+            const Rec r = load_rec(st, qi);
             float4 col;
-            if (MODE == VGR_MODE_COLOR) col = s_c[qi];
+            if (COLOR) col = st.c[qi];
             const ColTerms ct = col_terms(r, pxc);
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                if (!act[k]) continue;
-                if (COUNT) ++c_test;
+                float dy;
+                const bool near = pre_test(r, ct, pyc[k], dy);   // always evaluated: sets dy
+                const bool pass = act[k] && near;
+                if (COUNT) c_test += act[k] ? 1u : 0u;
+                if (!__any(pass)) continue;           // wave-uniform
+                if (COUNT) c_full += pass ? 1u : 0u;
                 PairGeom g;
-                if (!pair_geom(r, ct, uy[k], g)) continue;
-                if (COUNT) ++c_full;
+                pair_geom(r, ct, dy, g);
                 const float rq = fast_rsq(g.qw);
                 const float ex = fast_exp2(-(r.se * g.num * (rq * rq)));
-                float y = r.K * un[k] * rq * ex;
-                if (y < tau2) continue;
-                if (MODE == VGR_MODE_COLOR) {
-                    y = fminf(y, ymax);
-                    const float om = fast_exp2(-y);
+                const float y = r.K * un[k] * rq * ex;
+                const bool bl = pass && !(y < tau2);
+                if (COLOR) {
+                    const float om = fast_exp2(-fminf(y, ymax));
                     const float Tn = T[k] * om;
-                    if (Tn < Tmin) {
-                        act[k] = false;
-                        continue;
-                    }
-                    const float wgt = (1.0f - om) * T[k];
+                    const bool stop = bl && Tn < Tmin;
+                    const bool dob = bl && !stop;
+                    const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
                     C0[k] = __fmaf_rn(col.x, wgt, C0[k]);
                     C1[k] = __fmaf_rn(col.y, wgt, C1[k]);
                     C2[k] = __fmaf_rn(col.z, wgt, C2[k]);
-                    T[k] = Tn;
-                    last[k] = (int)(bs + qi);
+                    T[k] = dob ? Tn : T[k];
+                    last[k] = dob ? (int)(bs + qi) : last[k];
+                    act[k] = act[k] && !stop;
+                    if (COUNT) c_blend += dob ? 1u : 0u;
                 } else {
-                    C0[k] += y;
-                    last[k] += 1;   // number of terms (starts at -1)
+                    C0[k] += bl ? y : 0.0f;
+                    last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
+                    if (COUNT) c_blend += bl ? 1u : 0u;
                 }
-                if (COUNT) ++c_blend;
             }
         }
         __syncthreads();
+        if (!alive) break;
     }
 
     const int64_t HW = (int64_t)W * H;
@@ -216,7 +239,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         if (px < W && py < H) {
             const int64_t idx = (int64_t)py * W + px;
             const int64_t pidx = vi.pix_off + idx;
-            if (MODE == VGR_MODE_COLOR) {
+            if (COLOR) {
                 vi.out[idx] = __fmaf_rn(T[k], rp.bg[0], C0[k]);
                 vi.out[HW + idx] = __fmaf_rn(T[k], rp.bg[1], C1[k]);
                 vi.out[2 * HW + idx] = __fmaf_rn(T[k], rp.bg[2], C2[k]);
@@ -286,11 +309,11 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr int NCH = MODE == VGR_MODE_COLOR ? 3 : 1;
-    __shared__ float4 s_g0[64], s_g1[64], s_g2[64], s_g3[64], s_c[64];
-    __shared__ uint32_t s_item[64];
+    constexpr bool COLOR = MODE == VGR_MODE_COLOR;
+    constexpr int NCH = COLOR ? 3 : 1;
+    __shared__ Stage st;
 
-    const int gt = blockIdx.x;
+    const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
     const int lt = gt - vi.tile_off;
@@ -304,15 +327,15 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     const float ux = (pxc - vi.cx) / vi.fx;
     const uint2 range = b.ranges[gt];
 
-    float uy[PPL], un[PPL], T[PPL], g[PPL][NCH], B[PPL][NCH];
+    float pyc[PPL], un[PPL], T[PPL], g[PPL][NCH], B[PPL][NCH];
     int last[PPL];
     int maxlast = -1;
     uint32_t c_test = 0, c_full = 0, c_blend = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RS;
-        uy[k] = (float)py + 0.5f;   // pixel-centre row coordinate
-        const float uyn = (uy[k] - vi.cy) / vi.fy;
+        pyc[k] = (float)py + 0.5f;
+        const float uyn = (pyc[k] - vi.cy) / vi.fy;
         un[k] = sqrtf(ux * ux + uyn * uyn + 1.0f);
         const bool inside = px < W && py < H;
         const int64_t idx = (int64_t)py * W + px;
@@ -336,22 +359,13 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
         const int bs = max((int)range.x, be - 64);
         const int j = bs + lane;
-        if (j < be) {
-            const uint32_t item = b.inst_val[j];
-            const float4 *gp = b.geom + (size_t)item * 4;
-            s_item[lane] = item;
-            s_g0[lane] = gp[0];
-            s_g1[lane] = gp[1];
-            s_g2[lane] = gp[2];
-            s_g3[lane] = gp[3];
-            if (MODE == VGR_MODE_COLOR) s_c[lane] = b.color[item];
-        }
+        if (j < be) stage_record(st, b, lane, b.inst_val[j], COLOR);
         __syncthreads();
         for (int qi = be - 1 - bs; qi >= 0; --qi) {
             const int jpos = bs + qi;
-            const Rec r = load_rec(s_g0, s_g1, s_g2, s_g3, qi);
+            const Rec r = load_rec(st, qi);
             float4 col;
-            if (MODE == VGR_MODE_COLOR) col = s_c[qi];
+            if (COLOR) col = st.c[qi];
             const ColTerms ct = col_terms(r, pxc);
             float acc[16];
 #pragma unroll
@@ -359,19 +373,23 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             bool touched = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                if (jpos > last[k]) continue;
-                if (COUNT) ++c_test;
+                float dy;
+                const bool inl = jpos <= last[k];
+                const bool near = pre_test(r, ct, pyc[k], dy);   // always evaluated: sets dy
+                const bool pass = inl && near;
+                if (COUNT) c_test += inl ? 1u : 0u;
+                if (!__any(pass)) continue;           // wave-uniform
+                if (COUNT) c_full += pass ? 1u : 0u;
                 PairGeom pg;
-                if (!pair_geom(r, ct, uy[k], pg)) continue;
-                if (COUNT) ++c_full;
+                pair_geom(r, ct, dy, pg);
                 const float rq = fast_rsq(pg.qw);
                 const float rq2 = rq * rq;
                 const float ex = fast_exp2(-(r.se * pg.num * rq2));
                 const float y = r.K * un[k] * rq * ex;
-                if (y < tau2) continue;
-                if (COUNT) ++c_blend;
-                float dy;
-                if (MODE == VGR_MODE_COLOR) {
+                const bool bl = pass && !(y < tau2);
+                if (COUNT) c_blend += bl ? 1u : 0u;
+                float dy_;
+                if (COLOR) {
                     const bool clamped = y > ymax;
                     const float om = fast_exp2(-fminf(y, ymax));
                     const float inv = fast_rcp(om);
@@ -380,24 +398,25 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     const float da = g[k][0] * (col.x * Tb - B[k][0] * inv) +
                                      g[k][1] * (col.y * Tb - B[k][1] * inv) +
                                      g[k][2] * (col.z * Tb - B[k][2] * inv);
-                    const float wgt = alpha * Tb;
+                    const float wgt = bl ? alpha * Tb : 0.0f;
                     acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
                     acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
                     acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
                     B[k][0] = __fmaf_rn(col.x, wgt, B[k][0]);
                     B[k][1] = __fmaf_rn(col.y, wgt, B[k][1]);
                     B[k][2] = __fmaf_rn(col.z, wgt, B[k][2]);
-                    T[k] = Tb;
-                    dy = clamped ? 0.0f : da * kLn2 * om;
+                    T[k] = bl ? Tb : T[k];
+                    dy_ = (bl && !clamped) ? da * kLn2 * om : 0.0f;
                 } else {
-                    dy = g[k][0] * kLn2;
+                    dy_ = bl ? g[k][0] * kLn2 : 0.0f;
                 }
-                touched = true;
+                touched |= bl;
                 // t = dL/d(ln x) = dL/dy * y;  dL/dK' = dy |u| r exp2(-e)
-                const float t = dy * y;
-                acc[9] = __fmaf_rn(dy, un[k] * rq * ex, acc[9]);
+                // (selected, not multiplied, to zero for lanes that do not blend)
+                const float t = bl ? dy_ * y : 0.0f;
+                acc[9] += bl ? dy_ * (un[k] * rq * ex) : 0.0f;
                 // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|
-                const float cz = r.mz * rq2;
+                const float cz = bl ? r.mz * rq2 : 0.0f;
                 const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);
                 const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
                 const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
@@ -414,10 +433,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             }
             if (__any(touched)) {
                 const float tot = wave_reduce16(acc, lane);
-                if ((lane & 3) == 0) {
-                    const uint32_t item = s_item[qi];
-                    atomicAdd(rg + (size_t)item * 16 + red_idx, tot);
-                }
+                if ((lane & 3) == 0) atomicAdd(rg + (size_t)st.item[qi] * 16 + red_idx, tot);
             }
         }
         __syncthreads();

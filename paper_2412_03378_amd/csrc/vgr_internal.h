@@ -16,10 +16,11 @@ constexpr float kSqrt2Pi = 2.5066282746310002f;
 constexpr float kHalfLog2eSqrt = 0.8493218002880191f;
 
 constexpr int kMaxViews = 64;
-constexpr int kGeomFloats = 16;   // rasteriser record, see Record layout below
+constexpr int kGeomVec = 5;       // float4 per rasteriser record, see layout below
+constexpr float kConicMargin = 0.05f;
 constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 
-// Rasteriser record of one (Gaussian, view), 16 floats (4 float4), in the
+// Rasteriser record of one (Gaussian, view), 20 floats (5 float4), in the
 // Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view R(q)), so that
 // Sigma_v^-1 = L^T L, and m the view-space mean (computed in FP64):
 //   g0 = (hx, hy, lx, ly)       projected mean (fx mx/mz + cx, fy my/mz + cy) in
@@ -28,15 +29,20 @@ constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 //                               offset (p + 0.5 - h) - l keeps full precision
 //   g1 = (A00, A01, A10, A11)   A = L[:, 0:2] diag(1/fx, 1/fy)
 //   g2 = (A20, A21, v0x, v0y)   v0 = L m / mz: L applied to the ray through the mean
-//   g3 = (v0z, mz, K', E')      K' = kappa sqrt(2 pi) log2 e;
-//                               E' = D2max (1 + 1e-4) / mz^2
+//   g3 = (v0z, mz, K', Q11)     K' = kappa sqrt(2 pi) log2 e
+//   g4 = (Q00, 2 Q01, 2 l0, 2 l1)
 // For the pixel with centre (px + 0.5, py + 0.5), ray u = (ux, uy, 1), and
 // pixel offset d = (px + 0.5, py + 0.5) - h - l:
 //   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)
 //   D^2 = mz^2 |v0 x a|^2 / |w|^2   (minimum Mahalanobis distance of the ray;
 //                                    free of cancellation near the centre)
 //   beta = |u| / |w|,  log2(e) x = K' |u| exp2(-(log2 e / 2) D^2) / |w|.
-//   bound test |v0 x a|^2 > E' |w|^2  <=>  D^2 > D2max (1 + 1e-4).
+// Bound pre-test: f(d) = d^T Q d + 2 l^T d - 1 has the sign of D^2 - D2max
+// (it is |w|^2 (D^2 - D2max) / (D2max |v0|^2)), so f > 0.05 proves
+// alpha < alpha_min for that pixel at a cost of three FP32 operations.  The
+// margin covers the FP32 evaluation error when the 2x2 form Q is positive
+// definite with condition number <= 1e4; otherwise Q = l = 0 (f = -1, no
+// pixel is rejected early).
 // Colour record (COLOR mode): r, g, b, 0 after the activation.
 //
 // Record gradient, 16 floats, as moments in the Gaussian's L-frame.  Per pixel,
@@ -81,7 +87,7 @@ struct RenderParams {
 
 // Device workspace views handed to kernels.
 struct Buffers {
-    float4 *geom;        // n_views * n records (4 float4 each)
+    float4 *geom;        // n_views * n records (kGeomVec float4 each)
     float4 *color;       // n_views * n
     uint32_t *depth_key; // n_views * n
     uint32_t *item_ids;  // n_views * n (item = view * n + Gaussian; sorted by depth)
@@ -96,6 +102,10 @@ struct Buffers {
     uint32_t *inst_key2; // capacity, sort ping-pong
     uint32_t *inst_val2; // capacity, sort ping-pong
     uint2 *ranges;       // total tiles
+    uint32_t *tile_key;  // total tiles: cost key, then sorted
+    uint32_t *tile_order;// total tiles: tiles by decreasing list length
+    uint32_t *tile_key2; // total tiles, sort ping-pong
+    uint32_t *tile_order2;
     float *T_final;      // total pixels
     int32_t *last_pos;   // total pixels: list position of last blended (-1)
     int32_t *last_id;    // total pixels: Gaussian index of last blended (-1)
@@ -118,6 +128,9 @@ hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int6
                        hipStream_t s);
 hipError_t launch_ranges(const Buffers &b, int64_t capacity_bound, int32_t total_tiles,
                          hipStream_t s);
+// Order tiles by decreasing list length (heaviest first) into b.tile_order.
+hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
+                             hipStream_t s);
 hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
