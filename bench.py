@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tile", type=int, nargs=2, default=(16, 16))
+    ap.add_argument("--tile", type=int, nargs=2, default=(8, 8))
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=128)

@@ -77,7 +77,7 @@ enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
  *               from the camera centre to the mean; max(.,0) or
  *               softplus(10 y)/10 (Supp. D) [CLAMP0]
  *   tile_w/h    screen tile in pixels, one of 8x8, 16x8, 16x16, 32x8;
- *               0 = the context's tuned choice (16x16 until tuned) [0, 0]
+ *               0 = the context's tuned choice (8x8 until vgr_autotune) [0, 0]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -142,7 +142,8 @@ const char *vgr_last_error(const vgr_ctx *ctx);
  *          3 x H_v x W_v (COLOR, channel-major) or H_v x W_v (XRAY)
  * The state needed by vgr_render_backward (sorted lists, per-pixel final
  * transmittance and last contributor) is kept in ctx until the next forward.
- * Synchronises the stream once, to size the instance lists.
+ * Waits once on the host, for an event recorded right after the preprocess
+ * (the instance count that sizes the lists), while the depth sort proceeds.
  * Errors: VGR_ERR_INVALID_ARG (bad sizes, settings or null pointers),
  * VGR_ERR_OOM, VGR_ERR_HIP. */
 int vgr_render_forward(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
@@ -185,6 +186,51 @@ int vgr_set_counting(vgr_ctx *ctx, int enable);
  * those calls; *count receives the number of stages written. */
 int vgr_set_timing(vgr_ctx *ctx, int enable);
 int vgr_get_timing(vgr_ctx *ctx, int32_t cap, const char **names, float *ms, int32_t *count);
+
+/* Capture one whole training step - optional zeroing of the parameter
+ * gradients, the forward of all n_views views and the backward - into a HIP
+ * graph, for callers that replay the same step (same pointers, sizes and
+ * cameras; new values in the arrays) without per-call host work.  Arguments
+ * are those of vgr_render_forward and vgr_render_backward together; the
+ * pointers are recorded and must stay valid while the graph is used.
+ * The call first runs the step once eagerly (its results are valid), then
+ * captures with instance lists of capacity_factor (>= 1; default 1.25) times
+ * the instance count measured there: graph replays never wait on the host,
+ * so a replay whose scene needs more instances than that drops the surplus
+ * and raises a device flag that vgr_graph_check reports.  A later call that
+ * grows the context's workspace invalidates the graph.  The stream is the
+ * context's stream (a private non-blocking stream when that is the null
+ * stream).  Errors: as forward/backward, VGR_ERR_HIP on capture failure. */
+int vgr_graph_capture(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
+                      const float *means, const float *quats, const float *scales,
+                      const float *dens, const float *sh, int32_t n_views,
+                      const vgr_camera *cams, float *const *out, const float *const *dL_dout,
+                      float *d_means, float *d_quats, float *d_scales, float *d_dens,
+                      float *d_sh, float capacity_factor, int32_t zero_grads);
+
+/* Enqueue one replay of the captured graph.  VGR_ERR_NOT_CAPTURED if there is
+ * none or it was invalidated; otherwise returns without waiting. */
+int vgr_graph_launch(vgr_ctx *ctx);
+
+/* Wait for the replays enqueued so far.  Returns VGR_ERR_CAPACITY (and
+ * clears the flag) if any of them overflowed its instance lists since the
+ * last check - their outputs are then incomplete and the caller re-captures
+ * - else VGR_OK.  *instances (may be NULL) receives the last replay's
+ * instance count. */
+int vgr_graph_check(vgr_ctx *ctx, int64_t *instances);
+
+/* Time the step (forward, plus backward when dL_dout is not NULL) for each
+ * tile shape 8x8, 16x8, 16x16, 32x8 with HIP events over `iters` calls after
+ * one warm-up call, keep the fastest as the context's tile for settings with
+ * tile_w = tile_h = 0, and report it in *best_tile_w, *best_tile_h and the
+ * mean ms of each candidate in ms_per_candidate[4] (any may be NULL).  The
+ * gradient arrays receive the sum of all the backward passes run. */
+int vgr_autotune(vgr_ctx *ctx, const vgr_settings *settings, int64_t n, const float *means,
+                 const float *quats, const float *scales, const float *dens, const float *sh,
+                 int32_t n_views, const vgr_camera *cams, float *const *out,
+                 const float *const *dL_dout, float *d_means, float *d_quats,
+                 float *d_scales, float *d_dens, float *d_sh, int32_t iters,
+                 int32_t *best_tile_w, int32_t *best_tile_h, float *ms_per_candidate);
 
 /* Stable LSD radix sort of n (key, value) pairs on the low `bits` bits of
  * key, in place (keys, vals: device u32 arrays of n).  This is the sort the

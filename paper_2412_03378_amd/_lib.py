@@ -73,6 +73,19 @@ _SIGNATURES = {
     "vgr_get_timing": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                  C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "vgr_sort_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "vgr_graph_capture": (C.c_int, [C.c_void_p, C.POINTER(vgr_settings), C.c_int64, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.POINTER(vgr_camera), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_float, C.c_int32]),
+    "vgr_graph_launch": (C.c_int, [C.c_void_p]),
+    "vgr_graph_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "vgr_autotune": (C.c_int, [C.c_void_p, C.POINTER(vgr_settings), C.c_int64, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                               C.POINTER(vgr_camera), C.POINTER(C.c_void_p),
+                               C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
 }
 
 EXPORTED = tuple(_SIGNATURES)

@@ -41,6 +41,7 @@ struct vgr_ctx {
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views;
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
+    hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
     bool stage_pending[2] = { false, false };
     uint32_t *h_words = nullptr;      // pinned, 8 words
     int64_t inst_capacity = 0;
@@ -63,7 +64,15 @@ struct vgr_ctx {
     std::vector<EvSet> evsets;
     size_t ev_next = 0;
     EvSet *cur = nullptr;
-    int tuned_w = 16, tuned_h = 16;
+    int tuned_w = 8, tuned_h = 8;
+
+    // captured forward + backward (hipGraph)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_valid = false;
+    hipStream_t own_stream = nullptr;   // capture stream when the caller uses the null stream
+    DevBuf views_graph;
+    int64_t graph_cap = 0;
 };
 
 namespace {
@@ -95,7 +104,9 @@ int ensure(vgr_ctx *c, DevBuf &b, size_t bytes)
     size_t want = bytes + bytes / 4;
     if (b.p) {
         hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && c->own_stream) e = hipStreamSynchronize(c->own_stream);
         if (e != hipSuccess) return fail(c, VGR_ERR_HIP, "sync: %s", hipGetErrorString(e));
+        c->graph_valid = false;   // a captured graph holds the old addresses
         hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
@@ -258,6 +269,7 @@ int vgr_create(vgr_ctx **out, int device)
     if (hipHostMalloc((void **)&c->h_views, sizeof(ViewInfo) * 2 * kMaxViews, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->stage_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->stage_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&c->h_words, sizeof(uint32_t) * 8, hipHostMallocDefault) != hipSuccess) {
         vgr_destroy(c);
         return VGR_ERR_HIP;
@@ -277,7 +289,11 @@ void vgr_destroy(vgr_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf *all[] = { &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
+    if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    DevBuf *all[] = { &c->views_graph, &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
                       &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
@@ -288,6 +304,7 @@ void vgr_destroy(vgr_ctx *c)
     if (c->h_views) hipHostFree(c->h_views);
     for (auto &e : c->stage_ev)
         if (e) hipEventDestroy(e);
+    if (c->k_ev) hipEventDestroy(c->k_ev);
     if (c->h_words) hipHostFree(c->h_words);
     for (auto &es : c->evsets)
         for (auto &e : es.ev) hipEventDestroy(e);
@@ -352,14 +369,21 @@ int vgr_get_timing(vgr_ctx *c, int32_t cap, const char **names, float *ms, int32
     return VGR_OK;
 }
 
-int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
-                       const float *quats, const float *scales, const float *dens,
-                       const float *sh, int32_t n_views, const vgr_camera *cams,
-                       float *const *out)
+}  // extern "C"
+
+namespace {
+
+// Validated call: render rules, per-view tables and workspace sizes.
+struct Prepared {
+    RenderParams rp{};
+    std::vector<ViewInfo> vinfo;
+    int64_t m = 0, tiles = 0, pix = 0, sort_n = 0;
+};
+
+int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+            const float *quats, const float *scales, const float *dens, const float *sh,
+            int32_t n_views, const vgr_camera *cams, float *const *out, Prepared &p)
 {
-    if (!c) return VGR_ERR_INVALID_ARG;
-    c->err.clear();
-    c->have_fwd = false;
     if (!st) return fail(c, VGR_ERR_INVALID_ARG, "settings is NULL");
     if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(c, VGR_ERR_INVALID_ARG, "bad n %lld", (long long)n);
     if (n_views < 1 || n_views > kMaxViews)
@@ -387,8 +411,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     if (tw == 0 && th == 0) { tw = c->tuned_w; th = c->tuned_h; }
     if (!valid_tile(tw, th)) return fail(c, VGR_ERR_INVALID_ARG, "unsupported tile %dx%d", tw, th);
 
-    HIP_TRY(c, hipSetDevice(c->device));
-    RenderParams rp{};
+    RenderParams &rp = p.rp;
     rp.mode = st->mode;
     rp.sh_degree = st->mode == VGR_MODE_COLOR ? st->sh_degree : 0;
     rp.act = st->act;
@@ -402,8 +425,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     rp.tile_w = tw;
     rp.tile_h = th;
 
-    // views
-    std::vector<ViewInfo> vinfo(n_views);
+    p.vinfo.assign(n_views, ViewInfo{});
     int64_t tiles = 0, pix = 0;
     for (int v = 0; v < n_views; ++v) {
         const vgr_camera &cm = cams[v];
@@ -412,8 +434,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
         if (!(cm.fx > 0.f) || !(cm.fy > 0.f))
             return fail(c, VGR_ERR_INVALID_ARG, "view %d: bad focal length", v);
         if (!out[v]) return fail(c, VGR_ERR_INVALID_ARG, "out[%d] is NULL", v);
-        ViewInfo &vi = vinfo[v];
-        memset(&vi, 0, sizeof vi);
+        ViewInfo &vi = p.vinfo[v];
         memcpy(vi.R, cm.R, sizeof vi.R);
         memcpy(vi.t, cm.t, sizeof vi.t);
         vi.fx = cm.fx; vi.fy = cm.fy; vi.cx = cm.cx; vi.cy = cm.cy;
@@ -435,9 +456,11 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     }
     if (tiles >= (int64_t)1 << 30) return fail(c, VGR_ERR_INVALID_ARG, "too many tiles");
     rp.total_tiles = (int32_t)tiles;
-
-    const int64_t m = n * n_views;
-    const int64_t sort_n = m > tiles ? m : tiles;
+    p.m = n * n_views;
+    p.tiles = tiles;
+    p.pix = pix;
+    p.sort_n = p.m > tiles ? p.m : tiles;
+    const int64_t m = p.m;
     if ((rc = ensure(c, c->geom, sizeof(float4) * kGeomVec * m)) ||
         (rc = ensure(c, c->color, sizeof(float4) * (rp.mode == VGR_MODE_COLOR ? m : 1))) ||
         (rc = ensure(c, c->depth_key, 4 * m)) || (rc = ensure(c, c->item_ids, 4 * m)) ||
@@ -445,24 +468,41 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
         (rc = ensure(c, c->counts, 4 * m)) || (rc = ensure(c, c->cnt_sorted, 4 * m)) ||
         (rc = ensure(c, c->offsets, 4 * (m + 1))) || (rc = ensure(c, c->rect, 8 * m)) ||
         (rc = ensure(c, c->ranges, 8 * tiles)) || (rc = ensure(c, c->T_final, 4 * pix)) ||
-        (rc = ensure(c, c->tile_key, 4 * tiles)) || (rc = ensure(c, c->tile_order, 4 * tiles)) ||
+        (rc = ensure(c, c->tile_key, 4 * (tiles > 64 ? tiles : 64))) ||
+        (rc = ensure(c, c->tile_order, 4 * tiles)) ||
         (rc = ensure(c, c->tile_key2, 4 * tiles)) || (rc = ensure(c, c->tile_order2, 4 * tiles)) ||
         (rc = ensure(c, c->last_pos, 4 * pix)) || (rc = ensure(c, c->last_id, 4 * pix)) ||
         (rc = ensure(c, c->scan_tmp, 4 * scan_tmp_words(m > 0 ? m : 1))) ||
-        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(sort_n > 0 ? sort_n : 1))) ||
+        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(p.sort_n > 0 ? p.sort_n : 1))) ||
         (rc = ensure(c, c->inst_key, 4)) || (rc = ensure(c, c->inst_val, 4)) ||
         (rc = ensure(c, c->inst_key2, 4)) || (rc = ensure(c, c->inst_val2, 4)))
         return rc;
+    return VGR_OK;
+}
 
-    hipStream_t s = c->stream;
-    if ((rc = upload_views(c, 0, vinfo))) return rc;
+// Enqueue the forward on stream s.  cap < 0 (eager): wait on an event for the
+// instance count and size the lists exactly.  cap >= 0 (graph capture): the
+// lists have `cap` entries, nothing waits, overflow is flagged on the device.
+int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const float *quats,
+                    const float *scales, const float *dens, const float *sh,
+                    const ViewInfo *views_dev, int64_t cap, hipStream_t s, Buffers &out_b,
+                    int64_t &out_K)
+{
+    const RenderParams &rp = p.rp;
+    const int64_t m = p.m;
+    int rc;
     Buffers b = make_buffers(c);
-    if ((rc = timing_begin(c))) return rc;
-
+    b.views = views_dev;
     int64_t K = 0;
     if (m > 0) {
         mark(c, ST_PREPROCESS);
+        HIP_TRY(c, launch_fill_u32(b.d_total + 4, 0u, 1, s));
         HIP_TRY(c, launch_preprocess(rp, b, means, quats, scales, dens, sh, s));
+        if (cap < 0) {
+            // the instance count K travels to the host while the depth sort runs
+            HIP_TRY(c, hipMemcpyAsync(c->h_words, b.d_total + 4, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipEventRecord(c->k_ev, s));
+        }
         mark_end(c, ST_PREPROCESS);
         // depth order of all (view, Gaussian) items; ties keep the item order
         mark(c, ST_SORT_DEPTH);
@@ -473,21 +513,25 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
         mark(c, ST_SCAN_EMIT);
         HIP_TRY(c, launch_gather_counts(b, m, s));
         HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, m, ptr<uint32_t>(c->scan_tmp), true, s));
-        HIP_TRY(c, hipMemcpyAsync(c->h_words, b.offsets + m, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        K = c->h_words[0];
-        if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
-            (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
-            (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > sort_n ? K : sort_n))))
-            return rc;
-        c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
-        b = make_buffers(c);
+        if (cap < 0) {
+            HIP_TRY(c, hipEventSynchronize(c->k_ev));
+            K = c->h_words[0];
+            if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
+                (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
+                (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > p.sort_n ? K : p.sort_n))))
+                return rc;
+            c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
+            b = make_buffers(c);
+            b.views = views_dev;
+        } else {
+            K = cap;
+        }
         HIP_TRY(c, launch_finalize_count(b, m, K, s));
         HIP_TRY(c, launch_emit(rp, b, m, K, s));
         mark_end(c, ST_SCAN_EMIT);
         mark(c, ST_SORT_TILES);
         HIP_TRY(c, launch_radix_sort(b.inst_key, b.inst_val, b.inst_key2, b.inst_val2, b.d_total, K,
-                                     bits_for(tiles), ptr<uint32_t>(c->sort_tmp), s));
+                                     bits_for(p.tiles), ptr<uint32_t>(c->sort_tmp), s));
         mark_end(c, ST_SORT_TILES);
     } else {
         HIP_TRY(c, launch_fill_u32(b.d_total, 0u, 2, s));
@@ -501,12 +545,77 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     mark(c, ST_RASTER_FWD);
     HIP_TRY(c, launch_raster_fwd(rp, b, c->counting, s));
     mark_end(c, ST_RASTER_FWD);
+    out_b = b;
+    out_K = K;
+    return VGR_OK;
+}
 
-    c->rp = rp;
+int enqueue_backward(vgr_ctx *c, const RenderParams &rp, const Buffers &b_fwd,
+                     const ViewInfo *views_dev, const float *means, const float *quats,
+                     const float *scales, const float *dens, const float *sh, float *d_means,
+                     float *d_quats, float *d_scales, float *d_dens, float *d_sh, hipStream_t s)
+{
+    const int64_t m = rp.n * rp.n_views;
+    if (m == 0) return VGR_OK;
+    Buffers b = b_fwd;
+    b.rgrad = ptr<float4>(c->rgrad);
+    b.views = views_dev;
+    mark(c, ST_ZERO_GRAD);
+    HIP_TRY(c, launch_fill_f32(reinterpret_cast<float *>(b.rgrad), 0.0f, 16 * m, s));
+    mark_end(c, ST_ZERO_GRAD);
+    mark(c, ST_RASTER_BWD);
+    if (c->counting)
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters) + 6, 0u, 6, s));
+    HIP_TRY(c, launch_raster_bwd(rp, b, c->counting, s));
+    mark_end(c, ST_RASTER_BWD);
+    mark(c, ST_PREPROCESS_BWD);
+    HIP_TRY(c, launch_preprocess_bwd(rp, b, means, quats, scales, dens, sh, d_means, d_quats,
+                                     d_scales, d_dens, d_sh, s));
+    mark_end(c, ST_PREPROCESS_BWD);
+    return VGR_OK;
+}
+
+int check_grads(vgr_ctx *c, const RenderParams &rp, float *d_means, float *d_quats,
+                float *d_scales, float *d_dens, float *d_sh)
+{
+    int rc;
+    if (rp.n > 0) {
+        if ((rc = check_ptr(c, d_means, "d_means")) || (rc = check_ptr(c, d_quats, "d_quats")) ||
+            (rc = check_ptr(c, d_scales, "d_scales")) || (rc = check_ptr(c, d_dens, "d_dens")))
+            return rc;
+        if (rp.mode == VGR_MODE_COLOR && (rc = check_ptr(c, d_sh, "d_sh"))) return rc;
+    }
+    return VGR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                       const float *quats, const float *scales, const float *dens,
+                       const float *sh, int32_t n_views, const vgr_camera *cams,
+                       float *const *out)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    c->have_fwd = false;
+    HIP_TRY(c, hipSetDevice(c->device));
+    Prepared p;
+    int rc;
+    if ((rc = prepare(c, st, n, means, quats, scales, dens, sh, n_views, cams, out, p))) return rc;
+    if ((rc = upload_views(c, 0, p.vinfo))) return rc;
+    if ((rc = timing_begin(c))) return rc;
+    Buffers b;
+    int64_t K;
+    if ((rc = enqueue_forward(c, p, means, quats, scales, dens, sh, ptr<ViewInfo>(c->views), -1,
+                              c->stream, b, K)))
+        return rc;
+    c->rp = p.rp;
     c->buf = b;
     c->K = K;
-    c->total_pix = pix;
-    c->vinfo = vinfo;
+    c->total_pix = p.pix;
+    c->vinfo = p.vinfo;
     c->means = means; c->quats = quats; c->scales = scales; c->dens = dens; c->sh = sh;
     c->have_fwd = true;
     return VGR_OK;
@@ -521,12 +630,7 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
     const RenderParams &rp = c->rp;
     int rc;
-    if (rp.n > 0) {
-        if ((rc = check_ptr(c, d_means, "d_means")) || (rc = check_ptr(c, d_quats, "d_quats")) ||
-            (rc = check_ptr(c, d_scales, "d_scales")) || (rc = check_ptr(c, d_dens, "d_dens")))
-            return rc;
-        if (rp.mode == VGR_MODE_COLOR && (rc = check_ptr(c, d_sh, "d_sh"))) return rc;
-    }
+    if ((rc = check_grads(c, rp, d_means, d_quats, d_scales, d_dens, d_sh))) return rc;
     for (int v = 0; v < rp.n_views; ++v) {
         if (!dL[v]) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout[%d] is NULL", v);
         c->vinfo[v].dL = dL[v];
@@ -534,25 +638,10 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t m = rp.n * rp.n_views;
     if ((rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1)))) return rc;
-    hipStream_t s = c->stream;
     if ((rc = upload_views(c, 1, c->vinfo))) return rc;
-    Buffers b = c->buf;
-    b.rgrad = ptr<float4>(c->rgrad);
-    if (m == 0) return VGR_OK;
     if ((rc = timing_begin(c))) return rc;
-    mark(c, ST_ZERO_GRAD);
-    HIP_TRY(c, launch_fill_f32(reinterpret_cast<float *>(b.rgrad), 0.0f, 16 * m, s));
-    mark_end(c, ST_ZERO_GRAD);
-    mark(c, ST_RASTER_BWD);
-    if (c->counting)
-        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters) + 6, 0u, 6, s));
-    HIP_TRY(c, launch_raster_bwd(rp, b, c->counting, s));
-    mark_end(c, ST_RASTER_BWD);
-    mark(c, ST_PREPROCESS_BWD);
-    HIP_TRY(c, launch_preprocess_bwd(rp, b, c->means, c->quats, c->scales, c->dens, c->sh, d_means,
-                                     d_quats, d_scales, d_dens, d_sh, s));
-    mark_end(c, ST_PREPROCESS_BWD);
-    return VGR_OK;
+    return enqueue_backward(c, rp, c->buf, ptr<ViewInfo>(c->views), c->means, c->quats, c->scales,
+                            c->dens, c->sh, d_means, d_quats, d_scales, d_dens, d_sh, c->stream);
 }
 
 int vgr_get_aux(vgr_ctx *c, int32_t view, float *T_final, int32_t *last_index)
@@ -624,6 +713,178 @@ int vgr_sort_pairs(vgr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int32_
     HIP_TRY(c, launch_fill_u32(dn, (uint32_t)n, 1, s));
     HIP_TRY(c, launch_radix_sort(keys, vals, ptr<uint32_t>(c->inst_key2), ptr<uint32_t>(c->inst_val2),
                                  dn, n, bits, ptr<uint32_t>(c->sort_tmp), s));
+    return VGR_OK;
+}
+
+int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                      const float *quats, const float *scales, const float *dens, const float *sh,
+                      int32_t n_views, const vgr_camera *cams, float *const *out,
+                      const float *const *dL, float *d_means, float *d_quats, float *d_scales,
+                      float *d_dens, float *d_sh, float capacity_factor, int32_t zero_grads)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
+    if (!(capacity_factor >= 1.0f)) capacity_factor = 1.25f;
+    int rc;
+    // one eager pass sizes every buffer and measures the instance count
+    const bool counting = c->counting, timing = c->timing;
+    c->counting = false;
+    c->timing = false;
+    c->cur = nullptr;
+    rc = vgr_render_forward(c, st, n, means, quats, scales, dens, sh, n_views, cams, out);
+    if (!rc) rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh);
+    c->counting = counting;
+    c->timing = timing;
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Prepared p;
+    if ((rc = prepare(c, st, n, means, quats, scales, dens, sh, n_views, cams, out, p))) return rc;
+    const int64_t cap = (int64_t)ceil((double)c->K * capacity_factor) + 4096;
+    const int64_t m = p.m;
+    if ((rc = ensure(c, c->inst_key, 4 * cap)) || (rc = ensure(c, c->inst_val, 4 * cap)) ||
+        (rc = ensure(c, c->inst_key2, 4 * cap)) || (rc = ensure(c, c->inst_val2, 4 * cap)) ||
+        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(cap > p.sort_n ? cap : p.sort_n))) ||
+        (rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1))) ||
+        (rc = ensure(c, c->views_graph, sizeof(ViewInfo) * kMaxViews)))
+        return rc;
+    c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
+    for (int v = 0; v < n_views; ++v) {
+        if (!dL[v]) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout[%d] is NULL", v);
+        p.vinfo[v].dL = dL[v];
+    }
+    HIP_TRY(c, hipMemcpy(c->views_graph.p, p.vinfo.data(), sizeof(ViewInfo) * n_views,
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, launch_fill_u32(ptr<uint32_t>(c->words) + 5, 0u, 1, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->graph_exec) { hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    c->graph_valid = false;
+    hipStream_t s = c->stream;
+    if (!s) {
+        if (!c->own_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+        s = c->own_stream;
+    }
+    const bool counting2 = c->counting;
+    c->counting = false;
+    c->cur = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    Buffers b;
+    int64_t K;
+    rc = VGR_OK;
+    if (zero_grads && n > 0) {
+        hipError_t e = launch_fill_f32(d_means, 0.f, 3 * n, s);
+        if (e == hipSuccess) e = launch_fill_f32(d_quats, 0.f, 4 * n, s);
+        if (e == hipSuccess) e = launch_fill_f32(d_scales, 0.f, 3 * n, s);
+        if (e == hipSuccess) e = launch_fill_f32(d_dens, 0.f, n, s);
+        if (e == hipSuccess && p.rp.mode == VGR_MODE_COLOR && d_sh)
+            e = launch_fill_f32(d_sh, 0.f, 3 * n * (p.rp.sh_degree + 1) * (p.rp.sh_degree + 1), s);
+        if (e != hipSuccess) rc = fail(c, VGR_ERR_HIP, "capture: %s", hipGetErrorString(e));
+    }
+    const ViewInfo *vg = ptr<ViewInfo>(c->views_graph);
+    if (!rc) rc = enqueue_forward(c, p, means, quats, scales, dens, sh, vg, cap, s, b, K);
+    if (!rc)
+        rc = enqueue_backward(c, p.rp, b, vg, means, quats, scales, dens, sh, d_means, d_quats,
+                              d_scales, d_dens, d_sh, s);
+    c->counting = counting2;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, VGR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(c, VGR_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    c->graph = g;
+    c->graph_cap = cap;
+    c->graph_valid = true;
+    // the captured pass also serves as the saved forward of this context
+    c->rp = p.rp;
+    c->buf = b;
+    c->K = cap;
+    c->vinfo = p.vinfo;
+    c->means = means; c->quats = quats; c->scales = scales; c->dens = dens; c->sh = sh;
+    c->have_fwd = false;
+    return VGR_OK;
+}
+
+int vgr_graph_launch(vgr_ctx *c)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    if (!c->graph_valid || !c->graph_exec)
+        return fail(c, VGR_ERR_NOT_CAPTURED, "no valid captured graph (re-capture after reallocation)");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream ? c->stream : c->own_stream));
+    return VGR_OK;
+}
+
+int vgr_graph_check(vgr_ctx *c, int64_t *instances)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    if (!c->graph_exec) return fail(c, VGR_ERR_NOT_CAPTURED, "no captured graph");
+    hipStream_t s = c->stream ? c->stream : c->own_stream;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    uint32_t words[6];
+    HIP_TRY(c, hipMemcpy(words, c->words.p, sizeof words, hipMemcpyDeviceToHost));
+    if (instances) *instances = words[0];
+    if (words[5]) {
+        const uint32_t zero = 0;
+        HIP_TRY(c, hipMemcpy(ptr<uint32_t>(c->words) + 5, &zero, 4, hipMemcpyHostToDevice));
+        return fail(c, VGR_ERR_CAPACITY,
+                    "a graph launch needed more than %lld instances; re-capture",
+                    (long long)c->graph_cap);
+    }
+    return VGR_OK;
+}
+
+int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                 const float *quats, const float *scales, const float *dens, const float *sh,
+                 int32_t n_views, const vgr_camera *cams, float *const *out,
+                 const float *const *dL, float *d_means, float *d_quats, float *d_scales,
+                 float *d_dens, float *d_sh, int32_t iters, int32_t *best_w, int32_t *best_h,
+                 float *ms_per_candidate)
+{
+    if (!c || !st) return VGR_ERR_INVALID_ARG;
+    static const int cand[4][2] = { { 8, 8 }, { 16, 8 }, { 16, 16 }, { 32, 8 } };
+    if (iters < 1) iters = 3;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const bool timing = c->timing;
+    c->timing = false;
+    float best = 1e30f;
+    int bi = -1, rc = VGR_OK;
+    for (int k = 0; k < 4 && !rc; ++k) {
+        vgr_settings s2 = *st;
+        s2.tile_w = cand[k][0];
+        s2.tile_h = cand[k][1];
+        float ms = 0.f;
+        for (int it = 0; it <= iters && !rc; ++it) {   // the first pass warms up
+            if (it == 1) (void)hipEventRecord(e0, c->stream);
+            rc = vgr_render_forward(c, &s2, n, means, quats, scales, dens, sh, n_views, cams, out);
+            if (!rc && dL)
+                rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh);
+        }
+        if (rc) break;
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= iters;
+        if (ms_per_candidate) ms_per_candidate[k] = ms;
+        if (ms < best) { best = ms; bi = k; }
+    }
+    c->timing = timing;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    c->tuned_w = cand[bi][0];
+    c->tuned_h = cand[bi][1];
+    if (best_w) *best_w = c->tuned_w;
+    if (best_h) *best_h = c->tuned_h;
     return VGR_OK;
 }
 

@@ -17,7 +17,7 @@
 // is bounded by the conic whose dual is K (D2max Sigma - m m^T) K^T, and its
 // tangent lines x = const give the exact screen bounding box used for binning
 // (a conservative replacement of the 3-sigma screen-space heuristic that the
-// paper notes should be adjusted for this rendering model, Sec. 7).
+// paper notes should be adjusted for this rendering model, Sec. 8, future work).
 #include "vgr_internal.h"
 
 namespace vgr {
@@ -191,9 +191,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                                                          const float *__restrict__ dens,
                                                          const float *__restrict__ sh)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
-    if (i >= rp.n) return;
+    const bool valid = i0 < rp.n;
+    const int64_t i = valid ? i0 : rp.n - 1;   // threads past the end mirror the last Gaussian
     const ViewInfo &vi = b.views[v];
     const int64_t item = (int64_t)v * rp.n + i;
     const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
     const float K = kappa * kSqrt2Pi;
     const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
-    if (z > vi.znear && K * smax > rp.tau) {
+    if (valid && z > vi.znear && K * smax > rp.tau) {
         GaussView g;
         gauss_view(vi, mu, q, s, g);
         const float D2max = 2.0f * logf(K * smax / rp.tau);
@@ -307,10 +308,17 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
             }
         }
     }
-    b.depth_key[item] = key;
-    b.item_ids[item] = (uint32_t)item;
-    b.counts[item] = count;
-    b.rect[item] = rect;
+    if (valid) {
+        b.depth_key[item] = key;
+        b.item_ids[item] = (uint32_t)item;
+        b.counts[item] = count;
+        b.rect[item] = rect;
+    }
+    // total instance count K, for sizing the instance lists before the scan
+    uint32_t wsum = count;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(b.d_total + 4, wsum);
 }
 
 __global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
@@ -329,30 +337,63 @@ __global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int6
         const uint32_t K = offsets[m];
         d_total[0] = (int64_t)K > capacity ? (uint32_t)capacity : K;
         d_total[1] = (int64_t)K > capacity ? 1u : 0u;
+        if ((int64_t)K > capacity) d_total[5] = 1u;   // sticky until the host clears it
     }
 }
 
-// One thread per Gaussian in depth order writes its (tile, Gaussian) pairs.
-__global__ __launch_bounds__(256) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
-                                                   int64_t capacity)
+// Emission of the (tile, Gaussian) pairs in depth order.  Each one-wave block
+// owns 64 consecutive depth-sorted Gaussians; their instance ranges are
+// contiguous, and the lanes write 64 consecutive instances at a time, each lane
+// finding the Gaussian that owns its instance by binary search over the 64
+// offsets in LDS.
+__global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
+                                                  int64_t capacity)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t c = b.cnt_sorted[j];
-    if (c == 0) return;
-    const uint32_t item = b.item_ids[j];
-    const ushort4 r = b.rect[item];
-    const int v = (int)(item / (uint64_t)rp.n);
-    const ViewInfo &vi = b.views[v];
-    int64_t pos = b.offsets[j];
-    for (int ty = r.y; ty <= r.w; ++ty)
-        for (int tx = r.x; tx <= r.z; ++tx) {
+    __shared__ uint32_t s_off[64];
+    __shared__ uint32_t s_item[64];
+    __shared__ ushort4 s_rect[64];
+    const int lane = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int64_t j = j0 + lane;
+    const int64_t jend = min(j0 + 64, m);
+    const uint32_t base = b.offsets[j0];
+    const uint32_t total = b.offsets[jend] - base;
+    if (j < m) {
+        const uint32_t item = b.item_ids[j];
+        s_off[lane] = b.offsets[j] - base;
+        s_item[lane] = item;
+        s_rect[lane] = b.rect[item];
+    } else {
+        s_off[lane] = total;
+        s_item[lane] = 0;
+        s_rect[lane] = make_ushort4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        if (e < total) {
+            // largest g with s_off[g] <= e (entries with no instances share the
+            // offset of the next owner, which the search prefers)
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const ushort4 r = s_rect[lo];
+            const uint32_t local = e - s_off[lo];
+            const uint32_t rw = (uint32_t)r.z - r.x + 1u;
+            const uint32_t ty = r.y + local / rw, tx = r.x + local % rw;
+            const uint32_t item = s_item[lo];
+            const int vv = (int)(item / (uint64_t)rp.n);
+            const ViewInfo &vi = b.views[vv];
+            const int64_t pos = (int64_t)base + e;
             if (pos < capacity) {
-                b.inst_key[pos] = (uint32_t)(vi.tile_off + ty * vi.tiles_x + tx);
+                b.inst_key[pos] = (uint32_t)(vi.tile_off + (int)ty * vi.tiles_x + (int)tx);
                 b.inst_val[pos] = item;
             }
-            ++pos;
         }
+    }
 }
 
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ d_total,
@@ -367,16 +408,51 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t 
     }
 }
 
-// Cost key of each tile for the heaviest-first order: 0xFFFF - min(len, 0xFFFF).
-__global__ void tile_key_kernel(const uint2 *__restrict__ ranges, uint32_t *__restrict__ key,
-                                uint32_t *__restrict__ order, int32_t n)
+// Heaviest-first launch order of the tiles, by a counting sort on 32 buckets
+// of the list length (2 buckets per octave, longest first).  The order within
+// a bucket is arbitrary: it only steers scheduling, never results.
+__device__ inline int tile_bucket(uint32_t len)
 {
+    if (len == 0) return 31;
+    const int lg = 31 - __clz(len);                        // floor(log2 len)
+    const int half = (len >> (lg > 0 ? lg - 1 : 0)) & 1;   // upper half of the octave
+    return max(0, 30 - min(30, 2 * lg + half));
+}
+
+__global__ void tile_hist_kernel(const uint2 *__restrict__ ranges, uint32_t *__restrict__ hist,
+                                 int32_t n)
+{
+    __shared__ uint32_t h[32];
+    if (threadIdx.x < 32) h[threadIdx.x] = 0;
+    __syncthreads();
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const uint2 r = ranges[t];
-    const uint32_t len = r.y - r.x;
-    key[t] = 0xFFFFu - min(len, 0xFFFFu);
-    order[t] = (uint32_t)t;
+    if (t < n) {
+        const uint2 r = ranges[t];
+        atomicAdd(&h[tile_bucket(r.y - r.x)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void tile_place_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ hist,
+                                  uint32_t *__restrict__ cursor, uint32_t *__restrict__ order,
+                                  int32_t n)
+{
+    __shared__ uint32_t base[32];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < 32; ++k) {
+            base[k] = acc;
+            acc += hist[k];
+        }
+    }
+    __syncthreads();
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const uint2 r = ranges[t];
+        const int k = tile_bucket(r.y - r.x);
+        order[base[k] + atomicAdd(&cursor[k], 1u)] = (uint32_t)t;
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)
@@ -570,7 +646,7 @@ hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, 
 hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
                        hipStream_t s)
 {
-    emit_kernel<<<grid_for(m, 256), 256, 0, s>>>(rp, b, m, capacity);
+    emit_kernel<<<grid_for(m, 64), 64, 0, s>>>(rp, b, m, capacity);   // one wave per 64 Gaussians
     return hipGetLastError();
 }
 
@@ -589,13 +665,15 @@ hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, h
 hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
                              hipStream_t s)
 {
+    (void)sort_tmp;
     if (total_tiles <= 0) return hipSuccess;
-    tile_key_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, b.tile_key, b.tile_order,
-                                                                total_tiles);
-    hipError_t e = launch_fill_u32(b.d_total + 3, (uint32_t)total_tiles, 1, s);
+    uint32_t *hist = b.tile_key, *cursor = b.tile_key + 32;   // 64 words of scratch
+    hipError_t e = launch_fill_u32(hist, 0u, 64, s);
     if (e != hipSuccess) return e;
-    return launch_radix_sort(b.tile_key, b.tile_order, b.tile_key2, b.tile_order2, b.d_total + 3,
-                             total_tiles, 16, sort_tmp, s);
+    tile_hist_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, hist, total_tiles);
+    tile_place_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, hist, cursor,
+                                                                  b.tile_order, total_tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,

@@ -1,11 +1,12 @@
 // Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
 // pairs, written for wave64 gfx950.  The rasteriser uses them to order the
-// (tile, depth) instance lists: a per-tile depth order is the sorting step the
-// 3DGS-style tile rasteriser relies on (Sec. 3.2 and Sec. 7 of the paper: the
-// Gaussians are assumed sorted front to back).
+// (tile, depth) instance lists: the compositing assumes the Gaussians sorted
+// front to back (Sec. 3.2), and the tile rasteriser sorts them per tile rather
+// than per pixel (Sec. 7, Limitations).
 //
-// Radix pass = histogram kernel + exclusive scan of the digit-major histogram
-// table + scatter kernel.  The scatter ranks keys stably inside a 4096-key
+// Radix pass = histogram kernel + per-digit exclusive scan of the digit-major
+// table of per-block counts (one block per digit) + scatter kernel, which adds
+// the digit starts (a scan of the 256 digit totals) itself.  The scatter ranks keys stably inside a 4096-key
 // tile: each wave owns 1024 consecutive keys, ranks 64 keys at a time by
 // matching digits with one ballot per digit bit, and keeps running per-digit
 // counters in LDS; wave and block offsets are added afterwards.
@@ -159,11 +160,41 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s;
 }
 
+// One block per digit: exclusive scan, in place, of that digit's row of the
+// digit-major table (the per-block counts), and the row total into tot[d].
+__global__ __launch_bounds__(kThreads) void radix_rowscan_kernel(uint32_t *__restrict__ table,
+                                                                 int nb,
+                                                                 uint32_t *__restrict__ tot)
+{
+    uint32_t *row = table + (int64_t)blockIdx.x * nb;
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kTile) {
+        uint32_t v[kItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int idx = base + threadIdx.x * kItems + i;
+            v[i] = idx < nb ? row[idx] : 0u;
+            s += v[i];
+        }
+        uint32_t chunk;
+        uint32_t off = block_exclusive_scan(s, &chunk) + carry;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int idx = base + threadIdx.x * kItems + i;
+            if (idx < nb) row[idx] = off;
+            off += v[i];
+        }
+        carry += chunk;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const uint32_t *__restrict__ d_n, int shift, int dbits, const uint32_t *__restrict__ offs,
-    int nb)
+    const uint32_t *__restrict__ tot, int nb)
 {
     __shared__ uint32_t cnt[kWaves][256];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -171,6 +202,9 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const int64_t n = *d_n;
     const int64_t blk_base = (int64_t)blockIdx.x * kTile;
     if (blk_base >= n) return;   // uniform across the block
+    // start of each digit = exclusive scan of the digit totals
+    uint32_t tot_all;
+    const uint32_t digit_start = block_exclusive_scan(tot[threadIdx.x], &tot_all);
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) cnt[k][threadIdx.x] = 0;
     __syncthreads();
@@ -204,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __syncthreads();
     {
         const int d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * nb + blockIdx.x];
+        uint32_t run = digit_start + offs[(int64_t)d * nb + blockIdx.x];
 #pragma unroll
         for (int k2 = 0; k2 < kWaves; ++k2) {
             uint32_t c = cnt[k2][d];
@@ -263,8 +297,7 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
 int64_t radix_tmp_words(int64_t n_bound)
 {
     const int64_t nb = blocks_for(n_bound > 0 ? n_bound : 1);
-    const int64_t table = 256 * nb;
-    return 2 * table + scan_tmp_words(table);
+    return 256 * nb + 256;
 }
 
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
@@ -274,9 +307,8 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
     if (n_bound <= 0 || bits <= 0) return hipSuccess;
     const int64_t nb = blocks_for(n_bound);
     const int64_t table = 256 * nb;
-    uint32_t *hist = tmp;
-    uint32_t *offs = tmp + table;
-    uint32_t *stmp = tmp + 2 * table;
+    uint32_t *hist = tmp;            // digit-major per-block counts, then their row scans
+    uint32_t *tot = tmp + table;     // per-digit totals
     const int passes = (bits + 7) / 8;
     // spread the bits evenly over the passes (each at most 8)
     int shift = 0;
@@ -286,10 +318,9 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
         const uint32_t mask = (1u << dbits) - 1u;
         radix_hist_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(ki, d_n, shift, mask, hist,
                                                                         (int)nb);
-        hipError_t e = launch_scan_u32(hist, offs, table, stmp, false, s);
-        if (e != hipSuccess) return e;
+        radix_rowscan_kernel<<<256, kThreads, 0, s>>>(hist, (int)nb, tot);
         radix_scatter_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(
-            ki, vi, ko, vo, d_n, shift, dbits, offs, (int)nb);
+            ki, vi, ko, vo, d_n, shift, dbits, hist, tot, (int)nb);
         shift += dbits;
         uint32_t *t;
         t = ki; ki = ko; ko = t;

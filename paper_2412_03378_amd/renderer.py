@@ -161,6 +161,53 @@ class Renderer:
         L.check(self._lib.vgr_get_timing(self._h, cap, names, ms, C.byref(cnt)), self._h)
         return {names[i].decode(): float(ms[i]) for i in range(cnt.value)}
 
+    def _step_args(self, params, cams, settings, outs, dL, grads):
+        means, quats, scales, dens, sh = params
+        ncam = len(cams)
+        cam_arr = (L.vgr_camera * ncam)(*[camera_struct(c) for c in cams])
+        out_ptrs = (C.c_void_p * ncam)(*[o.data_ptr() for o in outs])
+        dl_ptrs = None
+        if dL is not None:
+            dl_ptrs = (C.c_void_p * ncam)(*[g.data_ptr() for g in dL])
+        st = settings.to_c()
+        xray = settings.mode == "xray"
+        gsh = None if (xray or grads is None) else grads[4]
+        gp = [None] * 5 if grads is None else [_dev_ptr(grads[k]) for k in range(4)] + [_dev_ptr(gsh)]
+        keep = (cam_arr, out_ptrs, dl_ptrs, st)
+        args = (C.byref(st), int(means.shape[0]), _dev_ptr(means), _dev_ptr(quats),
+                _dev_ptr(scales), _dev_ptr(dens), None if xray else _dev_ptr(sh), ncam, cam_arr,
+                out_ptrs, dl_ptrs, *gp)
+        return keep, args
+
+    def graph_capture(self, params, cams, settings, outs, dL, grads, capacity_factor=1.25,
+                      zero_grads=True):
+        """Capture forward + backward of these exact tensors into a HIP graph
+        (see vgr_graph_capture).  The tensors must stay alive and in place."""
+        self._sync_stream()
+        keep, args = self._step_args(params, cams, settings, outs, dL, grads)
+        self._graph_keep = (keep, params, outs, dL, grads)
+        L.check(self._lib.vgr_graph_capture(self._h, *args, float(capacity_factor),
+                                            int(bool(zero_grads))), self._h)
+
+    def graph_launch(self):
+        L.check(self._lib.vgr_graph_launch(self._h), self._h)
+
+    def graph_check(self):
+        """Wait for the replays; raise VgrError(VGR_ERR_CAPACITY) on overflow."""
+        k = C.c_int64()
+        L.check(self._lib.vgr_graph_check(self._h, C.byref(k)), self._h)
+        return int(k.value)
+
+    def autotune(self, params, cams, settings, outs, dL=None, grads=None, iters=3):
+        """Pick the fastest tile shape for this workload; returns ((w, h), ms list)."""
+        self._sync_stream()
+        keep, args = self._step_args(params, cams, settings, outs, dL, grads)
+        bw, bh = C.c_int32(), C.c_int32()
+        ms = (C.c_float * 4)()
+        L.check(self._lib.vgr_autotune(self._h, *args, int(iters), C.byref(bw), C.byref(bh), ms),
+                self._h)
+        return (bw.value, bh.value), [float(x) for x in ms]
+
     def sort_pairs(self, keys: torch.Tensor, vals: torch.Tensor, bits: int):
         """In-place stable radix sort of (u32 key, u32 value) device pairs."""
         self._sync_stream()

@@ -178,7 +178,9 @@ def clustered_means(rng, n, n_clusters, box=3.0, std_range=(0.05, 0.5)):
 
 def _sh_random(rng, n, degree, std):
     k = (degree + 1) ** 2
-    return rng.normal(0.0, std, (n, k, 3))
+    out = rng.standard_normal((n, k, 3), dtype=np.float32)
+    out *= np.float32(std)
+    return out
 
 
 def _f32(a):
@@ -219,7 +221,7 @@ def _clustered_scene(rng, n, n_clusters, sh_degree=3):
 
 
 def _upstream(rng, cams, channels=3):
-    return [_f32(rng.standard_normal((channels, c.height, c.width))) for c in cams]
+    return [rng.standard_normal((channels, c.height, c.width), dtype=np.float32) for c in cams]
 
 
 def config2(n=1_000_000, width=1920, height=1080, n_clusters=64, seed=2,

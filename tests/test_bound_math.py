@@ -1,0 +1,94 @@
+"""CPU checks of the two screen-space bounds the rasteriser relies on, written
+from their derivations (not from the kernel code):
+
+1. The exact alpha bound: beta <= s_max gives x <= kappa sqrt(2 pi) s_max
+   exp(-D^2/2), so alpha >= alpha_min needs D^2 <= D2max.  The pixels whose
+   ray meets the ellipsoid {(x-m)^T Sigma^-1 (x-m) <= D2max} lie inside the
+   bounding box of the conic with dual K (D2max Sigma - m m^T) K^T.  Every
+   pixel where the oracle finds x >= tau must be inside that box.
+2. The pre-test form f(d) = d^T Q d + 2 l^T d - 1 built from the record
+   (a = A d, w = v0 + a) has the sign of D^2 - D'.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import helpers as H
+from paper_2412_03378_amd import scenes
+
+
+def _view(cam, mu, q, s):
+    R = cam.R.astype(np.float64)
+    m = R @ np.asarray(mu, np.float64) + cam.t.astype(np.float64)
+    Rc = R @ H.rotation_matrix(q)
+    return m, Rc, np.asarray(s, np.float64)
+
+
+def _bbox(cam, m, Rc, s, D2):
+    K = np.array([[cam.fx, 0, cam.cx], [0, cam.fy, cam.cy], [0, 0, 1.0]])
+    Sigma = Rc @ np.diag(s * s) @ Rc.T
+    Cs = K @ (D2 * Sigma - np.outer(m, m)) @ K.T
+    if Cs[2, 2] >= 0:
+        return None
+    out = []
+    for a in (0, 1):
+        disc = Cs[a, 2] ** 2 - Cs[a, a] * Cs[2, 2]
+        r = np.sqrt(max(disc, 0.0))
+        out += sorted([(Cs[a, 2] + r) / Cs[2, 2], (Cs[a, 2] - r) / Cs[2, 2]])
+    return out  # x0, x1, y0, y1 in pixel coordinates (pixel centres at p + 0.5)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dual_conic_box_contains_every_visible_pixel(seed):
+    rng = np.random.default_rng(seed)
+    cam = scenes.look_at(rng.normal(0, 1, 3) * 0 + [0.3, -0.2, -3.0], (0, 0, 0), 64, 48, 45.0)
+    tau = -math.log1p(-1.0 / 255.0)
+    for _ in range(25):
+        mu = np.float32(rng.uniform(-0.4, 0.4, 3))
+        q = np.float32(rng.standard_normal(4))
+        s = np.float32(np.exp(rng.uniform(np.log(0.01), np.log(0.12), 3)))
+        kappa = float(np.float32(np.exp(rng.uniform(np.log(0.5), np.log(40)))))
+        m, Rc, s64 = _view(cam, mu, q, s)
+        Kk = kappa * math.sqrt(2 * math.pi) * s64.max()
+        if Kk <= tau:
+            continue
+        D2 = 2 * math.log(Kk / tau)
+        box = _bbox(cam, m, Rc, s64, D2)
+        sc = H.scene([mu], [s], kappa, quats=[q])
+        x = -np.log(oracle.render(sc, cam, oracle.Settings.no_thresholds())["T"])
+        ys, xs = np.nonzero(x >= tau)
+        if box is None or not len(xs):
+            continue
+        assert np.all(xs + 0.5 >= box[0] - 1e-6) and np.all(xs + 0.5 <= box[1] + 1e-6)
+        assert np.all(ys + 0.5 >= box[2] - 1e-6) and np.all(ys + 0.5 <= box[3] + 1e-6)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pre_test_form_has_the_sign_of_the_distance_excess(seed):
+    rng = np.random.default_rng(100 + seed)
+    cam = scenes.axis_camera(4.0, 96, 72, 50.0)
+    for _ in range(40):
+        mu = rng.uniform(-0.5, 0.5, 3)
+        m, Rc, s = _view(cam, mu, rng.standard_normal(4), np.exp(rng.uniform(-4.5, -2, 3)))
+        L = (Rc / s[None, :]).T
+        A = L[:, :2] @ np.diag([1 / cam.fx, 1 / cam.fy])
+        v0 = L @ (m / m[2])
+        Dp = rng.uniform(2.0, 20.0)
+        G = A.T @ A
+        gv = A.T @ v0
+        V = v0 @ v0
+        Q = (m[2] ** 2 * (V * G - np.outer(gv, gv)) - Dp * G) / (Dp * V)
+        l = -gv / V
+        centre = np.array([cam.fx * m[0] / m[2] + cam.cx, cam.fy * m[1] / m[2] + cam.cy])
+        for d in rng.normal(0, 25, (50, 2)):
+            p = centre + d
+            u = np.array([(p[0] - cam.cx) / cam.fx, (p[1] - cam.cy) / cam.fy, 1.0])
+            w = L @ u
+            pm = L @ m
+            D2 = np.sum(np.cross(pm, w) ** 2) / (w @ w)      # Lagrange identity
+            f = d @ Q @ d + 2 * l @ d - 1
+            a = A @ d
+            assert np.allclose(w, v0 + a)
+            assert f == pytest.approx((w @ w) * (D2 - Dp) / (Dp * V), rel=1e-9, abs=1e-9)

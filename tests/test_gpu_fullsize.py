@@ -1,0 +1,160 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, on outputs the FP64 oracle can compute one by one:
+
+* forward: sampled pixels of the full-size render;
+* backward: an upstream gradient that is non-zero only at sampled pixels,
+  so the exact parameter gradient is the oracle's backward over those pixels.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import gpu_helpers as G
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def R(dev):
+    from paper_2412_03378_amd import Renderer
+    return Renderer(0)
+
+
+def _settings(**kw):
+    from paper_2412_03378_amd import Settings
+    return Settings(**kw)
+
+
+def _oset(st):
+    return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
+                           T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act)
+
+
+def _pixels(cam, n, seed):
+    rng = np.random.default_rng(seed)
+    W, H = cam.width, cam.height
+    pts = [(0, 0), (W - 1, 0), (0, H - 1), (W - 1, H - 1), (W // 2, H // 2)]
+    pts += list(zip(rng.integers(0, W, n).tolist(), rng.integers(0, H, n).tolist()))
+    return np.array(pts, np.int32)
+
+
+def _check_forward(img, T, last, sc, cam, st, pix, xray=False):
+    ref = oracle.render(sc, cam, _oset(st), pixels=pix)
+    if xray:
+        got = img[pix[:, 1], pix[:, 0]][None]
+    else:
+        got = img[:, pix[:, 1], pix[:, 0]]
+    e_ok, nflag, e_flag = G.compare_image(got, ref["image"], ref["margin"], xray=xray)
+    print(f"{len(pix)} pixels: max err {e_ok:.3g}, flagged {nflag} (max {e_flag:.3g})")
+    assert e_ok <= (G.XRAY_REL if xray else G.IMG_TOL)
+    assert e_flag <= (1e-2 if xray else G.FLIP_TOL)
+    ok = ref["margin"] > G.MARGIN
+    if not xray:
+        assert np.abs(T[pix[:, 1], pix[:, 0]] - ref["T"])[ok].max() <= G.IMG_TOL
+        assert np.array_equal(last[pix[:, 1], pix[:, 0]][ok], ref["last"][ok])
+    return ref
+
+
+def _sparse_backward(R, dev, t, sc, cams, st, pix_per_view, seed, has_sh):
+    """Backward with dL non-zero only at unflagged sampled pixels."""
+    rng = np.random.default_rng(seed)
+    nch = 1 if st.mode == "xray" else 3
+    R.forward(*t, cams, st)
+    dLs, sparse = [], []
+    for cam, pix in zip(cams, pix_per_view):
+        ref = oracle.render(sc, cam, _oset(st), pixels=pix)
+        keep = pix[ref["margin"] > G.MARGIN]
+        g = rng.standard_normal((nch, len(keep)))
+        full = np.zeros((nch, cam.height, cam.width), np.float32)
+        full[:, keep[:, 1], keep[:, 0]] = g
+        dLs.append(torch.from_numpy(full if nch == 3 else full[0]).to(dev))
+        sparse.append((keep, g))
+    grads = [torch.zeros_like(x) for x in t[:4]] + [torch.zeros_like(t[4]) if has_sh else None]
+    R.backward(dLs, *grads)
+    torch.cuda.synchronize()
+    names = ("means", "quats", "scales", "dens") + (("sh",) if has_sh else ())
+    gsum = {k: 0.0 for k in names}
+    asum = {k: 0.0 for k in names}
+    for cam, (keep, g) in zip(cams, sparse):
+        o = oracle.render_backward(sc, cam, _oset(st), g, pixels=keep)
+        for k in names:
+            gsum[k] = gsum[k] + o[k]
+            asum[k] = asum[k] + o["abs_" + k]
+    ratios = {k: G.grad_errors(gr.cpu().numpy(), gsum[k], asum[k])
+              for k, gr in zip(names, grads)}
+    print("worst ratios", ratios)
+    assert max(ratios.values()) <= 1.0, ratios
+
+
+TILE = (8, 8)
+
+
+@pytest.fixture(scope="module")
+def cfg2(dev):
+    wl = scenes.config2(with_grad=False)
+    return wl, G.device_scene(wl.scene, dev)
+
+
+def test_config2_forward_sampled(R, cfg2):
+    wl, t = cfg2
+    cam = wl.cams[0]
+    st = _settings(sh_degree=3, tile=TILE)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    T, last = R.aux(0, cam.height, cam.width)
+    _check_forward(img, T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
+                   _pixels(cam, 96, 21))
+
+
+def test_config2_backward_sparse(R, dev, cfg2):
+    wl, t = cfg2
+    st = _settings(sh_degree=3, tile=TILE)
+    _sparse_backward(R, dev, t, wl.scene, wl.cams, st, [_pixels(wl.cams[0], 40, 22)], 23, True)
+
+
+def test_config4_xray_sampled(R, dev):
+    wl = scenes.config4(with_grad=False)
+    t = G.device_scene(wl.scene, dev)
+    st = _settings(mode="xray", tile=TILE)
+    imgs = R.forward(*t, wl.cams, st)
+    for v in (0, 21, 42, 63):
+        _check_forward(imgs[v].cpu().numpy(), None, None, wl.scene, wl.cams[v], st,
+                       _pixels(wl.cams[v], 24, 40 + v), xray=True)
+    cams = [wl.cams[5], wl.cams[37]]
+    _sparse_backward(R, dev, t, wl.scene, cams, st, [_pixels(c, 16, 50 + k) for k, c in
+                                                      enumerate(cams)], 51, False)
+
+
+def test_config3_batched_sampled(R, dev):
+    wl = scenes.config3(with_grad=False)
+    t = G.device_scene(wl.scene, dev)
+    st = _settings(sh_degree=3, tile=TILE)
+    imgs = [x.cpu().numpy() for x in R.forward(*t, wl.cams, st)]
+    for v in (0, 7, 15):
+        T, last = R.aux(v, wl.cams[v].height, wl.cams[v].width)
+        _check_forward(imgs[v], T.cpu().numpy(), last.cpu().numpy(), wl.scene, wl.cams[v], st,
+                       _pixels(wl.cams[v], 16, 60 + v))
+    for v in (3, 12):
+        one = R.forward(*t, [wl.cams[v]], st)[0].cpu().numpy()
+        assert np.array_equal(one, imgs[v])
+
+
+def test_config5_two_views_sampled(R, dev):
+    wl = scenes.config5(with_grad=False)
+    t = G.device_scene(wl.scene, dev)
+    st = _settings(sh_degree=3, tile=TILE)
+    cams = [wl.cams[0], wl.cams[33]]
+    imgs = [x.cpu().numpy() for x in R.forward(*t, cams, st)]
+    for v, cam in enumerate(cams):
+        T, last = R.aux(v, cam.height, cam.width)
+        _check_forward(imgs[v], T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
+                       _pixels(cam, 12, 70 + v))

@@ -1,0 +1,103 @@
+"""hipGraph capture of a whole forward+backward step, and the autotuner.
+
+A captured step is replayed several times with ordinary eager work and
+synchronisations between replays; every replay must equal the eager result
+bit for bit.  Capacity overflow is forced from the host (the scene grows after
+capture) and must be reported, not silently ignored.
+"""
+import numpy as np
+import pytest
+
+import gpu_helpers as G
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+def _setup(dev, n=3000, views=3, seed=8):
+    from paper_2412_03378_amd import Settings
+    wl = scenes.config3(n=n, n_views=8, seed=seed, with_grad=False)
+    cams = [scenes.Camera(c.R, c.t, c.fx / 6, c.fy / 6, c.cx / 6, c.cy / 6, c.width // 6,
+                          c.height // 6) for c in wl.cams[:views]]
+    params = list(G.device_scene(wl.scene, dev))
+    outs = [torch.empty((3, c.height, c.width), device=dev) for c in cams]
+    rng = np.random.default_rng(seed)
+    dL = [torch.from_numpy(rng.standard_normal((3, c.height, c.width)).astype(np.float32)).to(dev)
+          for c in cams]
+    grads = [torch.zeros_like(p) for p in params]
+    return Settings(sh_degree=3, tile=(16, 8)), cams, params, outs, dL, grads
+
+
+def _eager(dev, st, cams, params, dL):
+    from paper_2412_03378_amd import Renderer
+    r = Renderer(0)
+    imgs = [x.clone() for x in r.forward(*params, cams, st)]
+    grads = [torch.zeros_like(p) for p in params]
+    r.backward(dL, *grads)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in imgs], [g.cpu().numpy() for g in grads]
+
+
+def test_graph_replays_equal_eager(dev):
+    from paper_2412_03378_amd import Renderer
+    st, cams, params, outs, dL, grads = _setup(dev)
+    ref_img, ref_g = _eager(dev, st, cams, params, dL)
+    r = Renderer(0)
+    r.graph_capture(params, cams, st, outs, dL, grads, capacity_factor=1.25, zero_grads=True)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(-1.0)
+        r.graph_launch()
+        r.graph_check()
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device=dev).sum()
+        torch.cuda.synchronize()
+        assert np.isfinite(float(junk))
+        for a, b in zip(outs, ref_img):
+            assert np.array_equal(a.cpu().numpy(), b), f"replay {rep}"
+        for a, b in zip(grads, ref_g):
+            # gradient sums use FP32 atomics: equal up to the order of additions
+            assert np.allclose(a.cpu().numpy(), b, rtol=1e-4, atol=1e-6 * np.abs(b).max()), rep
+
+
+def test_graph_overflow_is_reported(dev):
+    from paper_2412_03378_amd import Renderer, _lib
+    st, cams, params, outs, dL, grads = _setup(dev, seed=9)
+    r = Renderer(0)
+    r.graph_capture(params, cams, st, outs, dL, grads, capacity_factor=1.0)
+    r.graph_launch()
+    r.graph_check()
+    params[2].mul_(3.0)     # bigger Gaussians cover more tiles than captured
+    r.graph_launch()
+    with pytest.raises(_lib.VgrError) as e:
+        r.graph_check()
+    assert e.value.code == _lib.VGR_ERR_CAPACITY
+    # a new capture fits the grown scene and matches the eager result again
+    ref_img, _ = _eager(dev, st, cams, params, dL)
+    r.graph_capture(params, cams, st, outs, dL, grads, capacity_factor=1.25)
+    r.graph_launch()
+    r.graph_check()
+    for a, b in zip(outs, ref_img):
+        assert np.array_equal(a.cpu().numpy(), b)
+
+
+def test_autotune_picks_a_valid_tile(dev):
+    from paper_2412_03378_amd import Renderer, Settings
+    st, cams, params, outs, dL, grads = _setup(dev, seed=10)
+    r = Renderer(0)
+    best, ms = r.autotune(params, cams, st, outs, dL, grads, iters=2)
+    assert best in [(8, 8), (16, 8), (16, 16), (32, 8)]
+    assert all(m > 0 for m in ms)
+    auto = [x.cpu().numpy() for x in r.forward(*params, cams, Settings(sh_degree=3))]
+    explicit = [x.cpu().numpy() for x in r.forward(*params, cams, Settings(sh_degree=3, tile=best))]
+    for a, b in zip(auto, explicit):
+        assert np.array_equal(a, b)
