@@ -40,6 +40,28 @@ F_TEST, F_SHARED, F_FULL = 34, 7, 9
 F_BLEND_FWD = {"color": 12, "xray": 1}
 F_BLEND_BWD = {"color": 32 + 57, "xray": 1 + 57}
 PEAK_FP32 = 157.3e12    # MI355X published FP32 vector peak (FLOP/s)
+CALIB_COPY_BYTES = 1 << 28   # plain device copy used to calibrate the HBM byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_raster_8x8_1M_1080p.json")
+
+
+def _kernel_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2412_03378_amd", "csrc", "raster.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    import json as _json
+    try:
+        t = _json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("raster_source_sha256_16") != _kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def _flops(tested, full, blended, ppl, mode, direction):
@@ -106,7 +128,7 @@ def bench_headline(args, torch, dev):
     dom = max(kern, key=lambda k: stages.get(k, 0.0))
     achieved = kern[dom] / (stages[dom] * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": _traffic(dom),
                 "flops_per_launch": kern[dom], "launch_ms": stages[dom]}
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl,
                 flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd})
@@ -148,6 +170,81 @@ def bench_batched(args, torch, dev):
     return res, wl
 
 
+def bench_xray(args, torch, dev):
+    """64 cone-beam projections of a 500k-Gaussian volume, fwd+bwd in one call."""
+    from paper_2412_03378_amd import Renderer, Settings, scenes
+    _log("generating the 500k-Gaussian X-ray scene")
+    wl = scenes.config4()
+    params = _device_scene(wl.scene, dev, torch)
+    dLs = [torch.from_numpy(d[0]).to(dev) for d in wl.dL]
+    grads = [torch.zeros_like(p) for p in params[:4]] + [None]
+    st = Settings(mode="xray", tile=tuple(args.tile))
+    r = Renderer(0)
+    for _ in range(max(1, args.warmup // 2)):
+        _step(r, params, grads, wl.cams, st, dLs)
+    torch.cuda.synchronize()
+    r.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        _step(r, params, grads, wl.cams, st, dLs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.batched_steps
+    stages = r.timing()
+    r.set_timing(False)
+    r.set_counting(True)
+    _step(r, params, grads, wl.cams, st, dLs)
+    stats = r.stats()
+    r.set_counting(False)
+    ppl = args.tile[0] * args.tile[1] / 64.0
+    fl = {"raster_fwd": _flops(stats["pairs_tested"], stats["pairs_full"], stats["pairs_blended"],
+                               ppl, "xray", "fwd"),
+          "raster_bwd": _flops(stats["bwd_pairs_tested"], stats["bwd_pairs_full"],
+                               stats["bwd_pairs_blended"], ppl, "xray", "bwd")}
+    out = {"workload": "X-ray: 64 cone-beam views 512x512, 500k Gaussians, fwd+bwd in one call",
+           "ms_per_step": round(dt * 1e3, 3), "views_per_s": round(len(wl.cams) / dt, 1),
+           "instances": stats["instances"],
+           "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+           "tflops": {k: round(v / (stages[k] * 1e-3) / 1e12, 2) for k, v in fl.items()
+                      if stages.get(k)}}
+    del params, grads, dLs
+    return out
+
+
+def bench_train(args, torch, dev, views_per_call=16):
+    """Training-step scale: 6M Gaussians, 64 views 1920x1080, forward + backward
+    with the parameter gradients accumulated over all views (4 calls of 16)."""
+    from paper_2412_03378_amd import Renderer, Settings, scenes
+    _log("generating the 6M-Gaussian 64-view scene")
+    wl = scenes.config5()
+    params = _device_scene(wl.scene, dev, torch)
+    dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
+    grads = [torch.zeros_like(p) for p in params]
+    st = Settings(sh_degree=3, tile=tuple(args.tile))
+    r = Renderer(0)
+    nv = len(wl.cams)
+
+    def step():
+        for g in grads:
+            g.zero_()
+        for v0 in range(0, nv, views_per_call):
+            cams = wl.cams[v0:v0 + views_per_call]
+            r.forward(*params, cams, st)
+            r.backward(dLs[v0:v0 + views_per_call], *grads)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.train_steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.train_steps
+    out = {"workload": "training step: 6M Gaussians (1024 clusters), SH3, 64 views 1920x1080, "
+                       "fwd+bwd accumulated into FP32 parameter gradients, 16 views per call",
+           "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1)}
+    del params, grads, dLs
+    return out
+
+
 def cpu_baseline(wl, n_pix):
     """FP64 oracle, forward + backward on n_pix pixels of the headline frame
     (all Gaussians per pixel), extrapolated to the whole frame."""
@@ -175,6 +272,47 @@ def cpu_baseline(wl, n_pix):
                       f"{cam.width * cam.height} pixels plus the per-view set-up"}
 
 
+def write_traffic(fetch_csv, write_csv, out_path=TRAFFIC_FILE):
+    """Per-launch HBM bytes of the rasteriser kernels from two rocprofv3 --pmc
+    runs of `bench.py --profile` (counter FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch), each scaled by the reading of the same counter for the plain
+    copy of CALIB_COPY_BYTES that the profile run starts with."""
+    import csv
+    import statistics
+
+    def read(path, counter):
+        per = {}
+        for row in csv.DictReader(open(path)):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row.get("Kernel_Name", "")
+            per.setdefault(name, []).append(float(row["Counter_Value"]))
+        return per
+
+    res = {"raster_source_sha256_16": _kernel_source_hash(), "calibration_bytes": CALIB_COPY_BYTES,
+           "kernels": {}}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = read(path, counter)
+        copies = [v for k, vs in per.items() if "copyBuffer" in k or "copy" in k.lower()
+                  for v in vs]
+        ref = max(copies) * 1024.0        # KiB -> bytes, the big calibration copy
+        scale = CALIB_COPY_BYTES / ref
+        res[counter + "_scale"] = scale
+        for k, vs in per.items():
+            for short in ("raster_fwd_kernel", "raster_bwd_kernel"):
+                if short in k and "true>" not in k:       # timed (non-counting) variants
+                    key = short.replace("_kernel", "")
+                    d = res["kernels"].setdefault(key, {})
+                    d[counter + "_KiB_median"] = statistics.median(vs)
+                    d[counter.lower() + "_bytes"] = statistics.median(vs) * 1024.0 * scale
+    for k, d in res["kernels"].items():
+        if "fetch_size_bytes" in d and "write_size_bytes" in d:
+            d["bytes_per_launch"] = d["fetch_size_bytes"] + d["write_size_bytes"]
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,9 +321,24 @@ def main():
     ap.add_argument("--tile", type=int, nargs=2, default=(8, 8))
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-xray", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=2)
     ap.add_argument("--cpu-pixels", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter-based traffic summary from two rocprofv3 --pmc "
+                         "counter_collection.csv files and exit")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: one plain device copy of known size "
+                         "(counter calibration), then warm-up and timed headline steps only")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
+    if args.profile:
+        args.no_batched = args.no_xray = args.no_train = True
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(views would shard across GPUs with an all-reduce of parameter "
@@ -196,6 +349,12 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
+    if args.profile:
+        src = torch.ones(CALIB_COPY_BYTES // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = bench_headline(args, torch, dev)
     out = {
         "metric": "ms per fwd+bwd, 1M Gaussians @1080p; views/sec batched vs single-view",
@@ -225,6 +384,12 @@ def main():
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3)}
+    if not args.no_xray:
+        torch.cuda.empty_cache()
+        out["xray"] = bench_xray(args, torch, dev)
+    if not args.no_train:
+        torch.cuda.empty_cache()
+        out["train"] = bench_train(args, torch, dev)
     if not args.no_cpu_baseline:
         _log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(h["wl"], args.cpu_pixels)

@@ -107,7 +107,7 @@ int ensure(vgr_ctx *c, DevBuf &b, size_t bytes)
         if (e == hipSuccess && c->own_stream) e = hipStreamSynchronize(c->own_stream);
         if (e != hipSuccess) return fail(c, VGR_ERR_HIP, "sync: %s", hipGetErrorString(e));
         c->graph_valid = false;   // a captured graph holds the old addresses
-        hipFree(b.p);
+        (void)hipFree(b.p);
         b.p = nullptr;
         b.bytes = 0;
     }
@@ -290,9 +290,9 @@ void vgr_destroy(vgr_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
-    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) hipGraphDestroy(c->graph);
-    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     DevBuf *all[] = { &c->views_graph, &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
                       &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
@@ -300,14 +300,14 @@ void vgr_destroy(vgr_ctx *c)
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
                       &c->words, &c->counters, &c->views };
     for (DevBuf *b : all)
-        if (b->p) hipFree(b->p);
-    if (c->h_views) hipHostFree(c->h_views);
+        if (b->p) (void)hipFree(b->p);
+    if (c->h_views) (void)hipHostFree(c->h_views);
     for (auto &e : c->stage_ev)
-        if (e) hipEventDestroy(e);
-    if (c->k_ev) hipEventDestroy(c->k_ev);
-    if (c->h_words) hipHostFree(c->h_words);
+        if (e) (void)hipEventDestroy(e);
+    if (c->k_ev) (void)hipEventDestroy(c->k_ev);
+    if (c->h_words) (void)hipHostFree(c->h_words);
     for (auto &es : c->evsets)
-        for (auto &e : es.ev) hipEventDestroy(e);
+        for (auto &e : es.ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -757,8 +757,8 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
                          hipMemcpyHostToDevice));
     HIP_TRY(c, launch_fill_u32(ptr<uint32_t>(c->words) + 5, 0u, 1, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->graph_exec) { hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
-    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
     c->graph_valid = false;
     hipStream_t s = c->stream;
     if (!s) {
@@ -790,13 +790,13 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(c, VGR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(c, VGR_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     c->graph = g;
@@ -878,8 +878,8 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
         if (ms < best) { best = ms; bi = k; }
     }
     c->timing = timing;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     c->tuned_w = cand[bi][0];
     c->tuned_h = cand[bi][1];

@@ -471,19 +471,6 @@ __global__ void fill_f32_kernel(float *__restrict__ p, float v, int64_t n)
 
 // ------------------------------------------------------------ backward ---
 
-// dL/dR(q) -> dL/dq for the normalised quaternion (w, x, y, z).
-__device__ inline void rot_to_quat_grad(const float *q, const float *G, float *dq)
-{
-    const float w = q[0], x = q[1], y = q[2], z = q[3];
-    dq[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
-    dq[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] +
-                   w * G[7] - 2.f * x * G[8]);
-    dq[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
-                   z * G[7] - 2.f * y * G[8]);
-    dq[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] +
-                   y * G[5] + x * G[6] + y * G[7]);
-}
-
 template <int DEG>
 __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     RenderParams rp, Buffers b, const float *__restrict__ means, const float *__restrict__ quats,
@@ -497,7 +484,7 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
     const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
-    float gmu[3] = { 0.f, 0.f, 0.f }, gqn[4] = { 0.f, 0.f, 0.f, 0.f }, gs[3] = { 0.f, 0.f, 0.f };
+    float gmu[3] = { 0.f, 0.f, 0.f }, gth[3] = { 0.f, 0.f, 0.f }, gs[3] = { 0.f, 0.f, 0.f };
     float gk = 0.f;
     float gsh[NB * 3];
 #pragma unroll
@@ -521,30 +508,20 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         for (int k = 0; k < 4; ++k) qn[k] = g.qn[k];
         qlen = g.qlen;
         gk += gr[9] * (kSqrt2Pi * kLog2e);
-        // Sigma^-1 = Rc diag(s^-2) Rc^T with dL/dSigma^-1 = -1/2 L^-1 M L^-T, L^-1 = Rc diag(s):
-        //   dL/ds_k = M_kk / s_k,  dL/dRc[:,k] = -(1/s_k) sum_j Rc[:,j] s_j M_jk
-        const float Mm[9] = { gr[0], gr[1], gr[2], gr[1], gr[3], gr[4], gr[2], gr[4], gr[5] };
-        float dRc[9];
-        for (int k = 0; k < 3; ++k) {
-            gs[k] += Mm[k * 3 + k] * g.inv_s[k];
-            for (int a = 0; a < 3; ++a) {
-                float acc = 0.f;
-                for (int j = 0; j < 3; ++j) acc += g.Rc[a * 3 + j] * s[j] * Mm[j * 3 + k];
-                dRc[a * 3 + k] = -acc * g.inv_s[k];
-            }
-        }
+        // Sigma^-1 = Rc diag(s^-2) Rc^T with dL/dSigma^-1 = -1/2 L^-1 M L^-T, L^-1 = Rc diag(s),
+        // so dL/dRc = -Rc diag(s) M diag(1/s):
+        //   scales: dL/ds_k = M_kk / s_k;
+        //   rotation: for the body-frame perturbation Rc -> Rc (I + [dtheta]x),
+        //   dL/dtheta = vee(W - W^T) with W = Rc^T dL/dRc = -diag(s) M diag(1/s),
+        //   i.e. dL/dtheta_x = M12 (s1/s2 - s2/s1) and cyclically.
+        for (int k = 0; k < 3; ++k) gs[k] += gr[k == 0 ? 0 : (k == 1 ? 3 : 5)] * g.inv_s[k];
+        gth[0] += gr[4] * ((s[1] * s[1] - s[2] * s[2]) * g.inv_s[1] * g.inv_s[2]);
+        gth[1] += gr[2] * ((s[2] * s[2] - s[0] * s[0]) * g.inv_s[2] * g.inv_s[0]);
+        gth[2] += gr[1] * ((s[0] * s[0] - s[1] * s[1]) * g.inv_s[0] * g.inv_s[1]);
         // dL/dm = -L^T Z
         float dm[3];
         for (int j = 0; j < 3; ++j)
             dm[j] = -(g.L[j] * gr[6] + g.L[3 + j] * gr[7] + g.L[6 + j] * gr[8]);
-        // Rc = R_view R(q)  ->  dR(q) = R_view^T dRc
-        float dRq[9];
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c)
-                dRq[a * 3 + c] = vi.R[a] * dRc[c] + vi.R[3 + a] * dRc[3 + c] + vi.R[6 + a] * dRc[6 + c];
-        float dq[4];
-        rot_to_quat_grad(g.qn, dRq, dq);
-        for (int k = 0; k < 4; ++k) gqn[k] += dq[k];
         // m = R_view mu + t
         for (int j = 0; j < 3; ++j)
             gmu[j] += vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];
@@ -581,8 +558,16 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     }
     if (!any) return;
     for (int j = 0; j < 3; ++j) d_means[3 * i + j] += gmu[j];
-    const float dot = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
-    for (int k = 0; k < 4; ++k) d_quats[4 * i + k] += (gqn[k] - qn[k] * dot) / qlen;
+    // body-frame rotation gradient -> quaternion: q -> q (x) (1, dtheta/2), so
+    // dL/dq = 2 q (x) (0, dL/dtheta) / |q| (already orthogonal to q)
+    {
+        const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+        const float c = 2.0f / qlen;
+        d_quats[4 * i + 0] += c * -(x * gth[0] + y * gth[1] + z * gth[2]);
+        d_quats[4 * i + 1] += c * (w * gth[0] + y * gth[2] - z * gth[1]);
+        d_quats[4 * i + 2] += c * (w * gth[1] + z * gth[0] - x * gth[2]);
+        d_quats[4 * i + 3] += c * (w * gth[2] + x * gth[1] - y * gth[0]);
+    }
     for (int k = 0; k < 3; ++k) d_scales[3 * i + k] += gs[k];
     d_dens[i] += gk;
     if (rp.mode == VGR_MODE_COLOR && d_sh) {

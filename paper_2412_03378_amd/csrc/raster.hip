@@ -28,7 +28,8 @@
 // sum starting at T_final * bg.  The geometric gradient of each pair is kept
 // as moments in the Gaussian's L-frame (see the record-gradient layout in
 // vgr_internal.h).  Per Gaussian, the 16 partial sums of the wave are reduced
-// with a transpose-reduce (17 shuffles) and added with one 16-lane atomic.
+// with a transpose-reduce (lane-swap instructions for the two wide steps) and
+// added with one 16-lane atomic.
 #include "vgr_internal.h"
 
 namespace vgr {
@@ -262,28 +263,33 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     }
 }
 
-// Sum v[0..15] over the 64 lanes.  Afterwards lane l with (l & 3) == 0 holds
-// the total of index ((l>>5)&1)*8 + ((l>>4)&1)*4 + ((l>>3)&1)*2 + ((l>>2)&1).
+// Sum v[0..15] over the 64 lanes (transpose-reduce).  Afterwards lane l with
+// (l & 3) == 0 holds the total of index l / 4.
+//   step 1: v_permlane32_swap pairs (v[k], v[k+8]); after the add, lanes 0-31
+//           hold index k and lanes 32-63 index k + 8;
+//   step 2: v_permlane16_swap pairs (v[k], v[k+4]); row r (16 lanes) now
+//           holds indices 4 r + k, k = 0..3;
+//   steps 3-5: exchanges across lane bits 3, 2 (keep/send halves) and 1, 0.
+__device__ __forceinline__ float swap_add32(float &a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_add16(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
 {
-    {
-        const bool hi = lane & 32;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float send = hi ? v[k] : v[k + 8];
-            const float keep = hi ? v[k + 8] : v[k];
-            v[k] = keep + __shfl_xor(send, 32, 64);
-        }
-    }
-    {
-        const bool hi = lane & 16;
+    for (int k = 0; k < 8; ++k) v[k] = swap_add32(v[k], v[k + 8]);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float send = hi ? v[k] : v[k + 4];
-            const float keep = hi ? v[k + 4] : v[k];
-            v[k] = keep + __shfl_xor(send, 16, 64);
-        }
-    }
+    for (int k = 0; k < 4; ++k) v[k] = swap_add16(v[k], v[k + 4]);
     {
         const bool hi = lane & 8;
 #pragma unroll
@@ -353,8 +359,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     if (maxlast < (int)range.x) return;   // uniform: no pixel of this tile blended anything
     const float tau2 = rp.tau2, ymax = rp.ymax;
     float *rg = reinterpret_cast<float *>(b.rgrad);
-    const int red_idx = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-                        ((lane >> 2) & 1);
+    const int red_idx = lane >> 2;   // index held by the reducing lanes
 
     for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
         const int bs = max((int)range.x, be - 64);

@@ -1,0 +1,43 @@
+"""The torch.autograd.Function binding: loss.backward() through render()
+gives the gradients of the explicit C ABI backward (same kernels)."""
+import numpy as np
+import pytest
+
+import gpu_helpers as G
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("mode", ["color", "xray"])
+def test_autograd_matches_explicit_backward(mode):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2412_03378_amd import Renderer, Settings, render
+    dev = torch.device("cuda", 0)
+    wl = scenes.config1(n=400, width=40, height=32)
+    cams = [wl.cams[0], scenes.axis_camera(3.5, 24, 20, 50.0)]
+    st = Settings(mode=mode, tile=(8, 8))
+    t = [x.clone().requires_grad_(True) if x is not None else None
+         for x in G.device_scene(wl.scene, dev)]
+    if mode == "xray":
+        t[4] = None
+    imgs = render(*t, cams, st)
+    rng = np.random.default_rng(3)
+    w = [torch.from_numpy(rng.standard_normal(tuple(i.shape)).astype(np.float32)).to(dev)
+         for i in imgs]
+    loss = sum((i * wi).sum() for i, wi in zip(imgs, w))
+    loss.backward()
+    r = Renderer(0)
+    base = [x.detach() if x is not None else None for x in t]
+    r.forward(*base, cams, st)
+    grads = [torch.zeros_like(x) if x is not None else None for x in base]
+    r.backward(w, *grads)
+    torch.cuda.synchronize()
+    for a, b in zip(t, grads):
+        if a is None:
+            continue
+        assert np.allclose(a.grad.cpu().numpy(), b.cpu().numpy(), rtol=1e-4,
+                           atol=1e-6 * float(b.abs().max()) + 1e-12)
