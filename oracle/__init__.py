@@ -88,7 +88,7 @@ def _load():
     lib.orc_render.argtypes = [C.c_int64, fp, fp, fp, fp, fp, C.POINTER(_Cam),
                                C.POINTER(_Settings), C.c_int64, ip, dp, dp, lp, ip, dp, dp]
     lib.orc_render_backward.argtypes = [C.c_int64, fp, fp, fp, fp, fp, C.POINTER(_Cam),
-                                        C.POINTER(_Settings), C.c_int64, ip, dp] + [dp] * 10
+                                        C.POINTER(_Settings), C.c_int64, ip, dp] + [dp] * 15
     lib.orc_max_threads.restype = C.c_int
     lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -221,7 +221,9 @@ def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=Tr
     """Gradients of sum(dL * image) w.r.t. means, quats, scales, dens, sh for
     one view.  ``dL`` is (C, P) for a pixel list or (C, H, W) for the whole
     image.  Returns dict of FP64 gradients and, if ``with_abs``, the sums of
-    absolute per-pixel contributions (``abs_*``) used to scale tolerances."""
+    absolute per-pixel contributions (``abs_*``) and the FP32 error scales
+    (``err_*``: the same sums without cancellation of the upstream factor,
+    each pair weighted by its rounding amplification) used for tolerances."""
     lib = _load()
     st = settings or Settings()
     full = pixels is None
@@ -235,6 +237,7 @@ def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=Tr
     shapes = dict(means=(n, 3), quats=(n, 4), scales=(n, 3), dens=(n,), sh=(n, nb, 3))
     grads = {k: np.zeros(s, np.float64) for k, s in shapes.items()}
     absg = {k: (np.zeros(s, np.float64) if with_abs else None) for k, s in shapes.items()}
+    errg = {k: (np.zeros(s, np.float64) if with_abs else None) for k, s in shapes.items()}
     cam_s, set_s = _cam(cam), _settings(st, scene.sh_degree)
     keys = ("means", "quats", "scales", "dens", "sh")
     rc = lib.orc_render_backward(
@@ -242,11 +245,13 @@ def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=Tr
         _ptr(dens, C.c_float), _ptr(sh, C.c_float), C.byref(cam_s), C.byref(set_s), P,
         _ptr(pix, C.c_int32), _ptr(g, C.c_double),
         *[_ptr(grads[k], C.c_double) for k in keys],
-        *[_ptr(absg[k], C.c_double) for k in keys])
+        *[_ptr(absg[k], C.c_double) for k in keys],
+        *[_ptr(errg[k], C.c_double) for k in keys])
     if rc:
         raise RuntimeError(f"orc_render_backward failed ({rc})")
     res = dict(grads)
     if with_abs:
         for k in keys:
             res["abs_" + k] = absg[k]
+            res["err_" + k] = errg[k]
     return res

@@ -520,21 +520,32 @@ static void atomic_add(double *dst, double v)
     *dst += v;
 }
 
+/* g_*: gradients; a_*: sums of |per-pixel contribution|; e_*: FP32 error
+   scales, sums of w |contribution| where the contribution is formed from an
+   upstream factor without cancellation and w counts how strongly a relative
+   rounding error in its inputs is amplified (see orc_render_backward). */
 typedef struct {
     double *g_means, *g_quats, *g_scales, *g_dens, *g_sh;
     double *a_means, *a_quats, *a_scales, *a_dens, *a_sh;
+    double *e_means, *e_quats, *e_scales, *e_dens, *e_sh;
 } grad_out;
 
-static void add2(double *g, double *a, double v)
+/* unit: the contribution per unit upstream factor; g: the upstream factor;
+   ge: its cancellation-free magnitude times the amplification weight. */
+static void add3(double *g, double *a, double *e, int64_t off, double unit, double gx, double ge)
 {
-    atomic_add(g, v);
-    if (a) atomic_add(a, fabs(v));
+    atomic_add(g + off, gx * unit);
+    if (a) atomic_add(a + off, fabs(gx * unit));
+    if (e) atomic_add(e + off, fabs(ge * unit));
 }
 
-/* Chain dL/dx (line integral of Gaussian i on ray (o, d)) to mu, q, s, kappa. */
-static void chain_integral(int64_t i, double gx, const float *means, const float *quats,
-                           const float *scales, const float *dens, const double o[3],
-                           const double d[3], grad_out *go)
+/* Chain dL/dx = gx (line integral of Gaussian i on ray (o, d)) to mu, q, s,
+   kappa.  For the error scale (see grad_out), gabs is |gx| formed without
+   cancellation and the weight is 1 + D^2/2 + w_extra: a relative error e in
+   D^2 becomes D^2 e / 2 in x = ... exp(-D^2/2). */
+static void chain_integral(int64_t i, double gx, double gabs, double w_extra, const float *means,
+                           const float *quats, const float *scales, const float *dens,
+                           const double o[3], const double d[3], grad_out *go)
 {
     double R[9], qn[4], qlen, P[9];
     quat_rotation(quats + 4 * i, R, qn, &qlen);
@@ -548,16 +559,19 @@ static void chain_integral(int64_t i, double gx, const float *means, const float
        dx/dP     = x (-1/2 d d^T / a - 1/2 v v^T)
        dx/dmu    = -x P v                                                   */
     double x = rt.x;
-    add2(go->g_dens + i, go->a_dens ? go->a_dens + i : NULL, gx * sqrt(2 * ORC_PI) * rt.beta * rt.Gmax);
-    double G[9];
+    double Pv[3], D2 = 0;
+    for (int r = 0; r < 3; ++r) {
+        Pv[r] = P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2];
+        D2 += rt.v[r] * Pv[r];
+    }
+    const double ge = gabs * (1.0 + 0.5 * D2 + w_extra);
+    add3(go->g_dens, go->a_dens, go->e_dens, i, sqrt(2 * ORC_PI) * rt.beta * rt.Gmax, gx, ge);
+    double G[9];   /* dx/dP per unit gx */
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
-            G[r * 3 + c] = gx * x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
-    for (int r = 0; r < 3; ++r) {
-        double pv = 0;
-        for (int c = 0; c < 3; ++c) pv += P[r * 3 + c] * rt.v[c];
-        add2(go->g_means + 3 * i + r, go->a_means ? go->a_means + 3 * i + r : NULL, -gx * x * pv);
-    }
+            G[r * 3 + c] = x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
+    for (int r = 0; r < 3; ++r)
+        add3(go->g_means, go->a_means, go->e_means, 3 * i + r, -x * Pv[r], gx, ge);
     /* P = sum_k s_k^-2 r_k r_k^T, r_k = column k of R */
     double dR[9];
     for (int k = 0; k < 3; ++k) {
@@ -566,8 +580,7 @@ static void chain_integral(int64_t i, double gx, const float *means, const float
         double Gr[3];
         for (int r = 0; r < 3; ++r) Gr[r] = G[r * 3] * rk[0] + G[r * 3 + 1] * rk[1] + G[r * 3 + 2] * rk[2];
         double rGr = rk[0] * Gr[0] + rk[1] * Gr[1] + rk[2] * Gr[2];
-        add2(go->g_scales + 3 * i + k, go->a_scales ? go->a_scales + 3 * i + k : NULL,
-             -2.0 * rGr / (s * s * s));
+        add3(go->g_scales, go->a_scales, go->e_scales, 3 * i + k, -2.0 * rGr / (s * s * s), gx, ge);
         for (int r = 0; r < 3; ++r) dR[r * 3 + k] = 2.0 * Gr[r] / (s * s);
     }
     double J[4][9], dqn[4];
@@ -579,12 +592,11 @@ static void chain_integral(int64_t i, double gx, const float *means, const float
     }
     double dot = qn[0] * dqn[0] + qn[1] * dqn[1] + qn[2] * dqn[2] + qn[3] * dqn[3];
     for (int c = 0; c < 4; ++c)
-        add2(go->g_quats + 4 * i + c, go->a_quats ? go->a_quats + 4 * i + c : NULL,
-             (dqn[c] - qn[c] * dot) / qlen);
+        add3(go->g_quats, go->a_quats, go->e_quats, 4 * i + c, (dqn[c] - qn[c] * dot) / qlen, gx, ge);
 }
 
 /* Chain dL/d(colour after activation) to the SH coefficients and mu. */
-static void chain_colour(int64_t i, const double gc[3], const view_state *vs,
+static void chain_colour(int64_t i, const double gc[3], double w, const view_state *vs,
                          const float *means, const float *sh, const orc_settings *st,
                          grad_out *go)
 {
@@ -595,27 +607,57 @@ static void chain_colour(int64_t i, const double gc[3], const view_state *vs,
     for (int k = 0; k < 3; ++k) v[k] /= len;
     double Y[(ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)], dY[3 * (ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)];
     orc_sh_basis(st->sh_degree, v, Y, dY);
-    double gv[3] = { 0, 0, 0 };
+    double gv[3] = { 0, 0, 0 }, gva[3] = { 0, 0, 0 };
     for (int ch = 0; ch < 3; ++ch) {
         double graw = gc[ch] * act_grad(st->act, vs->raw[3 * i + ch]);
         for (int k = 0; k < nb; ++k) {
             size_t e = ((size_t)i * nb + k) * 3 + ch;
-            add2(go->g_sh + e, go->a_sh ? go->a_sh + e : NULL, graw * Y[k]);
-            for (int j = 0; j < 3; ++j) gv[j] += graw * sh[e] * dY[3 * k + j];
+            add3(go->g_sh, go->a_sh, go->e_sh, (int64_t)e, Y[k], graw, w * graw);
+            for (int j = 0; j < 3; ++j) {
+                gv[j] += graw * sh[e] * dY[3 * k + j];
+                gva[j] += fabs(graw * sh[e] * dY[3 * k + j]);
+            }
         }
     }
     double vg = v[0] * gv[0] + v[1] * gv[1] + v[2] * gv[2];
-    for (int j = 0; j < 3; ++j)
-        add2(go->g_means + 3 * i + j, go->a_means ? go->a_means + 3 * i + j : NULL,
-             (gv[j] - v[j] * vg) / len);
+    double vga = fabs(v[0]) * gva[0] + fabs(v[1]) * gva[1] + fabs(v[2]) * gva[2];
+    for (int j = 0; j < 3; ++j) {
+        double c = (gv[j] - v[j] * vg) / len;
+        double ca = (gva[j] + fabs(v[j]) * vga) / len;
+        add3(go->g_means, go->a_means, NULL, 3 * i + j, c, 1.0, 0.0);
+        if (go->e_means) atomic_add(go->e_means + 3 * i + j, w * ca);
+    }
 }
 
+/* Squared Mahalanobis distance of Gaussian i from the ray (o, d). */
+static double pair_D2(int64_t i, const float *means, const float *quats, const float *scales,
+                      const float *dens, const double o[3], const double d[3])
+{
+    double R[9], qn[4], qlen, P[9];
+    quat_rotation(quats + 4 * i, R, qn, &qlen);
+    precision_matrix(R, scales + 3 * i, P);
+    double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+    ray_terms rt;
+    ray_integral(mu, P, dens[i], o, d, &rt);
+    double D2 = 0;
+    for (int r = 0; r < 3; ++r)
+        D2 += rt.v[r] * (P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2]);
+    return D2;
+}
+
+/* Error scales (e_*): the contribution of each blended pair is weighted by
+   1 + D^2/2 (the exponential's amplification of a relative error in D^2) plus,
+   in colour mode, the number of compositing steps between the pair and the end
+   of the pixel's list (a reverse replay of T and the colour behind carries one
+   rounding per step); the upstream factor dL/dalpha is taken as
+   sum |dL/dC| T (|c| + |S|), without the cancellation of c - S. */
 int orc_render_backward(int64_t n, const float *means, const float *quats, const float *scales,
                         const float *dens, const float *sh, const orc_camera *cam,
                         const orc_settings *st, int64_t npix, const int32_t *pix,
                         const double *dL, double *g_means, double *g_quats, double *g_scales,
                         double *g_dens, double *g_sh, double *a_means, double *a_quats,
-                        double *a_scales, double *a_dens, double *a_sh)
+                        double *a_scales, double *a_dens, double *a_sh, double *e_means,
+                        double *e_quats, double *e_scales, double *e_dens, double *e_sh)
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
@@ -623,7 +665,8 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
     int rc = view_setup(&vs, n, means, quats, scales, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
     grad_out go = { g_means, g_quats, g_scales, g_dens, g_sh,
-                    a_means, a_quats, a_scales, a_dens, a_sh };
+                    a_means, a_quats, a_scales, a_dens, a_sh,
+                    e_means, e_quats, e_scales, e_dens, e_sh };
     int C = st->mode == 1 ? 1 : 3;
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < npix; ++p) {
@@ -635,22 +678,30 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         shade_pixel(&vs, means, dens, st, d, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
-                chain_integral(bl.rec[r].idx, g[0], means, quats, scales, dens, vs.o, d, &go);
+                chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,
+                               vs.o, d, &go);
         } else {
             /* S: colour composited behind the current Gaussian, ending in bg */
             double S[3] = { st->bg[0], st->bg[1], st->bg[2] };
             for (int64_t r = bl.cnt - 1; r >= 0; --r) {
                 const blend_rec *br = &bl.rec[r];
                 int64_t i = br->idx;
-                double galpha = 0, gc[3];
+                double galpha = 0, gabs = 0, gc[3];
                 for (int ch = 0; ch < 3; ++ch) {
                     double c = vs.rgb[3 * i + ch];
                     galpha += g[ch] * br->T * (c - S[ch]);
+                    gabs += fabs(g[ch]) * br->T * (fabs(c) + fabs(S[ch]));
                     gc[ch] = g[ch] * br->alpha * br->T;
                 }
+                const double steps = (double)(bl.cnt - 1 - r);
+                const double ex = exp(-br->x);
                 if (!br->clamped)
-                    chain_integral(i, galpha * exp(-br->x), means, quats, scales, dens, vs.o, d, &go);
-                chain_colour(i, gc, &vs, means, sh, st, &go);
+                    chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales, dens,
+                                   vs.o, d, &go);
+                double w = 1.0 + steps;
+                if (go.e_means || go.e_sh)
+                    w += 0.5 * pair_D2(i, means, quats, scales, dens, vs.o, d);
+                chain_colour(i, gc, w, &vs, means, sh, st, &go);
                 for (int ch = 0; ch < 3; ++ch)
                     S[ch] = vs.rgb[3 * i + ch] * br->alpha + (1.0 - br->alpha) * S[ch];
             }

@@ -85,14 +85,18 @@ def _sparse_backward(R, dev, t, sc, cams, st, pix_per_view, seed, has_sh):
     names = ("means", "quats", "scales", "dens") + (("sh",) if has_sh else ())
     gsum = {k: 0.0 for k in names}
     asum = {k: 0.0 for k in names}
+    esum = {k: 0.0 for k in names}
     for cam, (keep, g) in zip(cams, sparse):
         o = oracle.render_backward(sc, cam, _oset(st), g, pixels=keep)
         for k in names:
             gsum[k] = gsum[k] + o[k]
             asum[k] = asum[k] + o["abs_" + k]
-    ratios = {k: G.grad_errors(gr.cpu().numpy(), gsum[k], asum[k])
-              for k, gr in zip(names, grads)}
+            esum[k] = esum[k] + o["err_" + k]
+    got = {k: gr.cpu().numpy() for k, gr in zip(names, grads)}
+    ratios = {k: G.grad_errors(got[k], gsum[k], asum[k], esum[k]) for k in names}
     print("worst ratios", ratios)
+    for k in names:
+        print(k, G.grad_worst(got[k], gsum[k], asum[k], esum[k]))
     assert max(ratios.values()) <= 1.0, ratios
 
 

@@ -133,7 +133,8 @@ def test_config1_backward(R, dev, cfg1, act, tile):
     grads = [torch.zeros_like(x) for x in t]
     R.backward([torch.from_numpy(dL.astype(np.float32)).to(dev)], *grads)
     torch.cuda.synchronize()
-    ratios = {name: G.grad_errors(g.cpu().numpy(), gref[name], gref["abs_" + name])
+    ratios = {name: G.grad_errors(g.cpu().numpy(), gref[name], gref["abs_" + name],
+                                  gref["err_" + name])
               for name, g in zip(("means", "quats", "scales", "dens", "sh"), grads)}
     print("worst ratios", ratios)
     assert max(ratios.values()) <= 1.0, ratios
@@ -167,12 +168,14 @@ def test_xray_forward_backward(R, dev):
     torch.cuda.synchronize()
     gsum = {k: 0 for k in ("means", "quats", "scales", "dens")}
     asum = dict(gsum)
+    esum = dict(gsum)
     for cam, d in zip(cams, dLs):
         g = oracle.render_backward(sc, cam, ost, d[None])
         for k in gsum:
             gsum[k] = gsum[k] + g[k]
             asum[k] = asum[k] + g["abs_" + k]
-    ratios = {name: G.grad_errors(g.cpu().numpy(), gsum[name], asum[name])
+            esum[k] = esum[k] + g["err_" + k]
+    ratios = {name: G.grad_errors(g.cpu().numpy(), gsum[name], asum[name], esum[name])
               for name, g in zip(("means", "quats", "scales", "dens"), grads)}
     print("worst ratios", ratios)
     assert max(ratios.values()) <= 1.0, ratios

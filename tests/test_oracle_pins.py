@@ -494,3 +494,35 @@ def test_fd_gradients_with_thresholds():
     an = oracle.render_backward(sc, cam, st, dc)
     assert an["dens"][0] == 0.0
     assert an["sh"][0, 0, 0] == pytest.approx(0.99 * scenes.Y00, rel=1e-12)
+
+
+# ------------------------------------------------ FP32 error scales (tests) ---
+
+def test_error_scale_weights():
+    """err_* (the tolerance scale of the GPU gradient tests) weighs a pair by
+    1 + D^2/2 and, in colour mode, drops the cancellation of c - S; for one
+    isotropic Gaussian both follow from the closed form, and on a random scene
+    err_* >= abs_* everywhere."""
+    s, kappa = f32(0.1), 2.0
+    one = H.scene([[0.03, -0.02, 0.0]], [s] * 3, kappa, rgb=[[0.8, 0.3, 0.6]])
+    cam = H.odd_camera(9, 30.0, 4.0)
+    px = (5, 3)
+    o, d = H.pixel_ray_world(cam, *px)
+    D2 = (H.point_line_distance(one.means[0], o, d) / s) ** 2
+    w = 1.0 + 0.5 * D2
+    g = oracle.render_backward(one, cam, oracle.Settings(mode="xray"), np.array([[1.5]]),
+                               pixels=[px])
+    assert g["err_dens"][0] == pytest.approx(w * g["abs_dens"][0], rel=1e-7)
+    assert np.allclose(g["err_means"], w * g["abs_means"], rtol=1e-7)
+    bg = (0.1, 0.2, 0.3)
+    st = oracle.Settings(act="clamp", bg=bg, alpha_min=1e-30)
+    g = oracle.render_backward(one, cam, st, np.array([[1.0], [0.0], [0.0]]), pixels=[px])
+    c = 0.8
+    ratio = (abs(c) + abs(bg[0])) / abs(c - bg[0])
+    assert g["err_dens"][0] == pytest.approx(ratio * w * g["abs_dens"][0], rel=1e-7)
+    wl = scenes.config1(n=150, width=17, height=13)
+    rng = np.random.default_rng(3)
+    dL = rng.standard_normal((3, 13, 17))
+    g = oracle.render_backward(wl.scene, wl.cams[0], oracle.Settings(), dL)
+    for k in ("means", "quats", "scales", "dens", "sh"):
+        assert np.all(g["err_" + k] >= g["abs_" + k] * (1 - 1e-12)), k
