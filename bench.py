@@ -372,8 +372,9 @@ def main():
                    "tile": list(args.tile), "instances": h["stats"]["instances"]},
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "pairs": {k: h["stats"][k] for k in ("pairs_tested", "pairs_full", "pairs_blended",
-                                             "bwd_pairs_tested", "bwd_pairs_full",
-                                             "bwd_pairs_blended")},
+                                             "visits", "visits_full", "bwd_pairs_tested",
+                                             "bwd_pairs_full", "bwd_pairs_blended", "bwd_visits",
+                                             "bwd_visits_full")},
         "roofline": h["roofline"],
     }
     if not args.no_batched:

@@ -100,9 +100,14 @@ typedef struct {
     int64_t pairs_tested;    /* filled when pair counting is on: (pixel,     */
     int64_t pairs_full;      /*   Gaussian) pairs visited, pairs evaluated   */
     int64_t pairs_blended;   /*   past the cheap bound test, pairs blended   */
-    int64_t bwd_pairs_tested;   /* the same three counts for the backward  */
+    int64_t visits;          /* wave-level: (Gaussian, pixel slot of a wave)  */
+    int64_t visits_full;     /*   steps, and those that took the evaluation   */
+                             /*   branch (some pixel passed the bound test)   */
+    int64_t bwd_pairs_tested;   /* the same five counts for the backward   */
     int64_t bwd_pairs_full;     /*   rasteriser of the last backward       */
     int64_t bwd_pairs_blended;
+    int64_t bwd_visits;
+    int64_t bwd_visits_full;
     int32_t overflow;        /* 1 if a fixed-capacity run dropped instances */
     int32_t tile_w, tile_h;  /* tile used */
     int32_t n_views;

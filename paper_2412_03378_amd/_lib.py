@@ -41,8 +41,10 @@ class vgr_settings(C.Structure):
 class vgr_stats(C.Structure):
     _fields_ = [("instances", C.c_int64), ("capacity", C.c_int64), ("visible", C.c_int64),
                 ("pairs_tested", C.c_int64), ("pairs_full", C.c_int64),
-                ("pairs_blended", C.c_int64), ("bwd_pairs_tested", C.c_int64),
+                ("pairs_blended", C.c_int64), ("visits", C.c_int64),
+                ("visits_full", C.c_int64), ("bwd_pairs_tested", C.c_int64),
                 ("bwd_pairs_full", C.c_int64), ("bwd_pairs_blended", C.c_int64),
+                ("bwd_visits", C.c_int64), ("bwd_visits_full", C.c_int64),
                 ("overflow", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("n_views", C.c_int32)]
 

@@ -35,7 +35,7 @@ struct vgr_ctx {
     std::string err;
 
     // workspace
-    DevBuf geom, color, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
+    DevBuf geom, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views;
@@ -204,7 +204,6 @@ Buffers make_buffers(vgr_ctx *c)
 {
     Buffers b{};
     b.geom = ptr<float4>(c->geom);
-    b.color = ptr<float4>(c->color);
     b.depth_key = ptr<uint32_t>(c->depth_key);
     b.item_ids = ptr<uint32_t>(c->item_ids);
     b.key2 = ptr<uint32_t>(c->key2);
@@ -276,7 +275,7 @@ int vgr_create(vgr_ctx **out, int device)
     }
     if ((rc = ensure(c, c->views, sizeof(ViewInfo) * kMaxViews)) ||
         (rc = ensure(c, c->words, sizeof(uint32_t) * 8)) ||
-        (rc = ensure(c, c->counters, sizeof(unsigned long long) * 8))) {
+        (rc = ensure(c, c->counters, sizeof(unsigned long long) * 16))) {
         vgr_destroy(c);
         return rc;
     }
@@ -293,7 +292,7 @@ void vgr_destroy(vgr_ctx *c)
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
-    DevBuf *all[] = { &c->views_graph, &c->geom, &c->color, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
+    DevBuf *all[] = { &c->views_graph, &c->geom, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
                       &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
@@ -461,8 +460,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     p.pix = pix;
     p.sort_n = p.m > tiles ? p.m : tiles;
     const int64_t m = p.m;
-    if ((rc = ensure(c, c->geom, sizeof(float4) * kGeomVec * m)) ||
-        (rc = ensure(c, c->color, sizeof(float4) * (rp.mode == VGR_MODE_COLOR ? m : 1))) ||
+    if ((rc = ensure(c, c->geom, sizeof(float4) * kRecVec * (m > 0 ? m : 1))) ||
         (rc = ensure(c, c->depth_key, 4 * m)) || (rc = ensure(c, c->item_ids, 4 * m)) ||
         (rc = ensure(c, c->key2, 4 * m)) || (rc = ensure(c, c->item2, 4 * m)) ||
         (rc = ensure(c, c->counts, 4 * m)) || (rc = ensure(c, c->cnt_sorted, 4 * m)) ||
@@ -541,7 +539,7 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     HIP_TRY(c, launch_tile_order(b, rp.total_tiles, ptr<uint32_t>(c->sort_tmp), s));
     mark_end(c, ST_RANGES);
     if (c->counting)
-        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 6, s));
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
     mark(c, ST_RASTER_FWD);
     HIP_TRY(c, launch_raster_fwd(rp, b, c->counting, s));
     mark_end(c, ST_RASTER_FWD);
@@ -565,7 +563,7 @@ int enqueue_backward(vgr_ctx *c, const RenderParams &rp, const Buffers &b_fwd,
     mark_end(c, ST_ZERO_GRAD);
     mark(c, ST_RASTER_BWD);
     if (c->counting)
-        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters) + 6, 0u, 6, s));
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters) + 16, 0u, 16, s));
     HIP_TRY(c, launch_raster_bwd(rp, b, c->counting, s));
     mark_end(c, ST_RASTER_BWD);
     mark(c, ST_PREPROCESS_BWD);
@@ -668,7 +666,7 @@ int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     uint32_t words[2];
     HIP_TRY(c, hipMemcpy(words, c->words.p, sizeof words, hipMemcpyDeviceToHost));
-    unsigned long long cnt[8] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    unsigned long long cnt[16] = {};
     if (c->counting) HIP_TRY(c, hipMemcpy(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost));
     out->instances = words[0];
     out->overflow = (int32_t)words[1];
@@ -676,9 +674,13 @@ int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
     out->pairs_tested = (int64_t)cnt[0];
     out->pairs_full = (int64_t)cnt[1];
     out->pairs_blended = (int64_t)cnt[2];
-    out->bwd_pairs_tested = (int64_t)cnt[3];
-    out->bwd_pairs_full = (int64_t)cnt[4];
-    out->bwd_pairs_blended = (int64_t)cnt[5];
+    out->visits = (int64_t)cnt[3];
+    out->visits_full = (int64_t)cnt[4];
+    out->bwd_pairs_tested = (int64_t)cnt[8];
+    out->bwd_pairs_full = (int64_t)cnt[9];
+    out->bwd_pairs_blended = (int64_t)cnt[10];
+    out->bwd_visits = (int64_t)cnt[11];
+    out->bwd_visits_full = (int64_t)cnt[12];
     out->tile_w = c->rp.tile_w;
     out->tile_h = c->rp.tile_h;
     out->n_views = c->rp.n_views;

@@ -183,6 +183,48 @@ __device__ inline void pixel_span(bool ok, float lo, float hi, float f, float c,
     p1 = min(p1, size - 1);
 }
 
+// Tile culling.  The bound pre-test rejects a pixel when f(d) > kConicMargin;
+// a tile of the Gaussian's rectangle is emitted only if the larger ellipse
+// {f <= kCullLevel} meets the pixel-centre span of the tile, so that every
+// dropped tile holds only pixels the pre-test would reject (the gap between
+// the two levels covers FP32 rounding of both evaluations).  With the ellipse
+// written as X = a Y -/+ sqrt(P - R Y^2) (X, Y: pixel column and row minus the
+// ellipse centre (cx, cy) in the convention px = d + centre - 0.5), the tiles
+// of one tile row form one interval: the extreme X over the row's Y span sits
+// at the clamped Y of the ellipse's leftmost (yl) and rightmost (-yl) points.
+struct CullRows {
+    float cx, cy, a, P, R, ymax, yl, on;
+};
+
+__device__ __forceinline__ int floor_div(int a, int b)
+{
+    return a >= 0 ? a / b : -((b - 1 - a) / b);
+}
+
+__device__ __forceinline__ bool cull_row(const CullRows &c, int ty, int tw, int th, int rx0,
+                                         int rx1, int &t0, int &t1)
+{
+    if (!(c.on > 0.0f)) {   // no usable bound form: the whole rectangle row
+        t0 = rx0;
+        t1 = rx1;
+        return true;
+    }
+    float ya = (float)(ty * th) - c.cy, yb = ya + (float)(th - 1);
+    ya = fmaxf(ya, -c.ymax);
+    yb = fminf(yb, c.ymax);
+    if (!(ya <= yb)) return false;
+    const float yl = fminf(fmaxf(c.yl, ya), yb), yr = fminf(fmaxf(-c.yl, ya), yb);
+    const float left = c.a * yl - sqrtf(fmaxf(c.P - c.R * yl * yl, 0.0f));
+    const float right = c.a * yr + sqrtf(fmaxf(c.P - c.R * yr * yr, 0.0f));
+    const float lim = 1.0e6f;
+    const float pl = ceilf(fminf(fmaxf(c.cx + left - kCullPad, -lim), lim));
+    const float pr = floorf(fminf(fmaxf(c.cx + right + kCullPad, -lim), lim));
+    if (!(pl <= pr)) return false;
+    t0 = max(rx0, floor_div((int)pl, tw));
+    t1 = min(rx1, floor_div((int)pr, tw));
+    return t0 <= t1;
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
                                                          const float *__restrict__ means,
@@ -239,7 +281,6 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
         if (x0 <= x1 && y0 <= y1) {
             const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
             const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;
-            count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
             rect = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,
                                 (unsigned short)ty1);
             key = __float_as_uint(z);
@@ -263,6 +304,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
             // D' = D2max (1 + 1e-4):  Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V),
             // l = -gv / V
             float Q00 = 0.f, Q01 = 0.f, Q11 = 0.f, l0 = 0.f, l1 = 0.f;
+            CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
             {
                 const double Dp = (double)D2max * (1.0 + 1e-4);
                 double G00 = 0, G01 = 0, G11 = 0, g0 = 0, g1 = 0, V = 0;
@@ -279,16 +321,38 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
                 const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
                 if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
+                    const double el0 = -g0 / V, el1 = -g1 / V;
                     Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
-                    l0 = (float)(-g0 / V); l1 = (float)(-g1 / V);
+                    l0 = (float)el0; l1 = (float)el1;
+                    // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
+                    const double dx0 = -(q11 * el0 - q01 * el1) / det;
+                    const double dy0 = -(q00 * el1 - q01 * el0) / det;
+                    const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
+                    cr.cx = (float)(cxp + dx0 - 0.5);
+                    cr.cy = (float)(cyp + dy0 - 0.5);
+                    cr.a = (float)(-q01 / q00);
+                    cr.P = (float)(rho / q00);
+                    cr.R = (float)(det / (q00 * q00));
+                    cr.ymax = (float)sqrt(rho * q00 / det);
+                    cr.yl = (float)(q01 * sqrt(rho / (det * q11)));
+                    cr.on = 1.0f;
                 }
             }
-            float4 *gp = b.geom + item * kGeomVec;
+            // tiles of the rectangle that the bound ellipse reaches, row by row
+            for (int ty = ty0; ty <= ty1; ++ty) {
+                int t0, t1;
+                if (cull_row(cr, ty, rp.tile_w, rp.tile_h, tx0, tx1, t0, t1))
+                    count += (uint32_t)(t1 - t0 + 1);
+            }
+            float4 *gp = b.geom + item * kRecVec;
             gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
-            gp[1] = make_float4(A[0], A[1], A[2], A[3]);
-            gp[2] = make_float4(A[4], A[5], v0[0], v0[1]);
-            gp[3] = make_float4(v0[2], mz, K * kLog2e, Q11);
-            gp[4] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
+            gp[1] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
+            gp[2] = make_float4(Q11, A[0], A[2], A[4]);
+            gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
+            gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
+            gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
+            gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);
+            float rgb[3] = { 0.0f, 0.0f, 0.0f };
             if (rp.mode == VGR_MODE_COLOR) {
                 float dx = mu[0] - vi.o[0], dy = mu[1] - vi.o[1], dz = mu[2] - vi.o[2];
                 const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -297,17 +361,17 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 sh_basis(DEG, dx, dy, dz, Y);
                 constexpr int NB = (DEG + 1) * (DEG + 1);
                 const float *c3 = sh + i * NB * 3;
-                float rgb[3];
                 for (int ch = 0; ch < 3; ++ch) {
                     float acc = 0.5f;
 #pragma unroll
                     for (int k = 0; k < NB; ++k) acc = fmaf(c3[k * 3 + ch], Y[k], acc);
                     rgb[ch] = act_fwd(rp.act, acc);
                 }
-                b.color[item] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
             }
+            gp[5] = make_float4(rgb[0], rgb[1], rgb[2], mz);
         }
     }
+    if (count == 0) key = 0xFFFFFFFFu;
     if (valid) {
         b.depth_key[item] = key;
         b.item_ids[item] = (uint32_t)item;
@@ -343,30 +407,81 @@ __global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int6
 
 // Emission of the (tile, Gaussian) pairs in depth order.  Each one-wave block
 // owns 64 consecutive depth-sorted Gaussians; their instance ranges are
-// contiguous, and the lanes write 64 consecutive instances at a time, each lane
-// finding the Gaussian that owns its instance by binary search over the 64
-// offsets in LDS.
+// contiguous.  Each lane first lists its Gaussian's non-empty tile rows (the
+// culled row intervals, in LDS); then the lanes write 64 consecutive instances
+// at a time, each lane finding the Gaussian that owns its instance by binary
+// search over the 64 offsets, and the row by a short scan of that Gaussian's
+// row list.  A block whose row lists do not fit in LDS walks the rows per
+// instance instead.
+constexpr int kEmitRows = 1024;
+
 __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
                                                   int64_t capacity)
 {
     __shared__ uint32_t s_off[64];
     __shared__ uint32_t s_item[64];
     __shared__ ushort4 s_rect[64];
+    __shared__ CullRows s_cull[64];
+    __shared__ int32_t s_toff[64], s_tx[64];
+    __shared__ uint32_t s_rbeg[65];
+    __shared__ uint32_t s_rstart[kEmitRows];   // first local instance of the row
+    __shared__ uint32_t s_rtile[kEmitRows];    // row << 16 | first tile column
     const int lane = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
     const int64_t j = j0 + lane;
     const int64_t jend = min(j0 + 64, m);
     const uint32_t base = b.offsets[j0];
     const uint32_t total = b.offsets[jend] - base;
+    CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
+    ushort4 rect = make_ushort4(0, 0, 0, 0);
+    uint32_t my_off = total;
     if (j < m) {
         const uint32_t item = b.item_ids[j];
-        s_off[lane] = b.offsets[j] - base;
+        my_off = b.offsets[j] - base;
+        rect = b.rect[item];
+        const float4 c6 = b.geom[(size_t)item * kRecVec + 6];
+        const float4 c7 = b.geom[(size_t)item * kRecVec + 7];
+        cr = CullRows{ c6.x, c6.y, c6.z, c6.w, c7.x, c7.y, c7.z, c7.w };
+        const ViewInfo &vi = b.views[(int)(item / (uint64_t)rp.n)];
         s_item[lane] = item;
-        s_rect[lane] = b.rect[item];
+        s_toff[lane] = vi.tile_off;
+        s_tx[lane] = vi.tiles_x;
     } else {
-        s_off[lane] = total;
         s_item[lane] = 0;
-        s_rect[lane] = make_ushort4(0, 0, 0, 0);
+        s_toff[lane] = 0;
+        s_tx[lane] = 0;
+    }
+    s_off[lane] = my_off;
+    s_rect[lane] = rect;
+    s_cull[lane] = cr;
+    const bool has = j < m && (j + 1 < jend ? b.offsets[j + 1] - base : total) > my_off;
+    // non-empty rows of this lane's Gaussian, and their prefix over the wave
+    uint32_t nrows = 0;
+    if (has)
+        for (int row = rect.y; row <= rect.w; ++row) {
+            int t0, t1;
+            nrows += cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1) ? 1u : 0u;
+        }
+    uint32_t incl = nrows;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    const uint32_t rows_total = __shfl(incl, 63, 64);
+    const bool table = rows_total <= (uint32_t)kEmitRows;   // wave-uniform
+    s_rbeg[lane] = incl - nrows;
+    if (lane == 63) s_rbeg[64] = incl;
+    if (table && has) {
+        uint32_t k = incl - nrows, acc = 0;
+        for (int row = rect.y; row <= rect.w; ++row) {
+            int t0, t1;
+            if (!cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1)) continue;
+            s_rstart[k] = acc;
+            s_rtile[k] = ((uint32_t)row << 16) | (uint32_t)t0;
+            acc += (uint32_t)(t1 - t0 + 1);
+            ++k;
+        }
     }
     __syncthreads();
     for (uint32_t e0 = 0; e0 < total; e0 += 64) {
@@ -380,17 +495,36 @@ __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, in
                 if (s_off[mid] <= e) lo = mid;
                 else hi = mid - 1;
             }
-            const ushort4 r = s_rect[lo];
-            const uint32_t local = e - s_off[lo];
-            const uint32_t rw = (uint32_t)r.z - r.x + 1u;
-            const uint32_t ty = r.y + local / rw, tx = r.x + local % rw;
-            const uint32_t item = s_item[lo];
-            const int vv = (int)(item / (uint64_t)rp.n);
-            const ViewInfo &vi = b.views[vv];
+            int local = (int)(e - s_off[lo]);
+            int tx, ty;
+            if (table) {
+                uint32_t k = s_rbeg[lo];
+                const uint32_t kend = s_rbeg[lo + 1];
+                while (k + 1 < kend && s_rstart[k + 1] <= (uint32_t)local) ++k;
+                ty = (int)(s_rtile[k] >> 16);
+                tx = (int)(s_rtile[k] & 0xFFFFu) + local - (int)s_rstart[k];
+            } else {
+                // the local-th tile of the culled rectangle, row by row (the
+                // same row intervals the preprocess counted)
+                const ushort4 r = s_rect[lo];
+                const CullRows c = s_cull[lo];
+                tx = r.x;
+                ty = r.y;
+                for (int row = r.y; row <= r.w; ++row) {
+                    int t0, t1;
+                    if (!cull_row(c, row, rp.tile_w, rp.tile_h, r.x, r.z, t0, t1)) continue;
+                    if (local <= t1 - t0) {
+                        tx = t0 + local;
+                        ty = row;
+                        break;
+                    }
+                    local -= t1 - t0 + 1;
+                }
+            }
             const int64_t pos = (int64_t)base + e;
             if (pos < capacity) {
-                b.inst_key[pos] = (uint32_t)(vi.tile_off + (int)ty * vi.tiles_x + (int)tx);
-                b.inst_val[pos] = item;
+                b.inst_key[pos] = (uint32_t)(s_toff[lo] + ty * s_tx[lo] + tx);
+                b.inst_val[pos] = s_item[lo];
             }
         }
     }
@@ -438,7 +572,8 @@ __global__ void tile_place_kernel(const uint2 *__restrict__ ranges, const uint32
                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ order,
                                   int32_t n)
 {
-    __shared__ uint32_t base[32];
+    __shared__ uint32_t base[32], local[32], start[32];
+    if (threadIdx.x < 32) local[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (int k = 0; k < 32; ++k) {
@@ -448,11 +583,19 @@ __global__ void tile_place_kernel(const uint2 *__restrict__ ranges, const uint32
     }
     __syncthreads();
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = 0;
+    uint32_t rank = 0;
     if (t < n) {
         const uint2 r = ranges[t];
-        const int k = tile_bucket(r.y - r.x);
-        order[base[k] + atomicAdd(&cursor[k], 1u)] = (uint32_t)t;
+        k = tile_bucket(r.y - r.x);
+        rank = atomicAdd(&local[k], 1u);   // LDS: rank within this block's bucket
     }
+    __syncthreads();
+    // one global cursor update per (block, bucket)
+    if (threadIdx.x < 32 && local[threadIdx.x])
+        start[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], local[threadIdx.x]);
+    __syncthreads();
+    if (t < n) order[base[k] + start[k] + rank] = (uint32_t)t;
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n)

@@ -2,10 +2,11 @@
 //
 // One wave (64 lanes) owns one screen tile of TW x TH pixels; lane l holds the
 // TW*TH/64 pixels of column l % TW, rows l / TW + k * (64 / TW) ("slot" k).
-// Tiles are launched heaviest list first, so that the long lists of dense
-// regions start early and the short ones fill the tail.  The tile's
-// depth-sorted Gaussian list is walked in batches of 64 records staged in LDS
-// (structure of arrays; every lane reads the same record, a broadcast).
+// Tiles are launched in the order of b.tile_order (heaviest lists first).
+// The tile's depth-sorted Gaussian list is walked in batches of 64 records
+// staged in LDS (structure of arrays; every lane reads the same record, a
+// broadcast).  A step reads the three float4 of the bound pre-test first and
+// the other three only when some pixel of the slot passes it.
 //
 // Per (pixel, Gaussian) pair, with the record (centre h + l, A, v0, mz, K',
 // bound form Q, l; see vgr_internal.h) and d = pixel centre - h - l:
@@ -28,67 +29,70 @@
 // sum starting at T_final * bg.  The geometric gradient of each pair is kept
 // as moments in the Gaussian's L-frame (see the record-gradient layout in
 // vgr_internal.h).  Per Gaussian, the 16 partial sums of the wave are reduced
-// with a transpose-reduce (lane-swap instructions for the two wide steps) and
-// added with one 16-lane atomic.
+// with a transpose-reduce (lane-swap and DPP moves, no LDS) and added with one
+// 16-lane atomic.
 #include "vgr_internal.h"
 
 namespace vgr {
 
 namespace {
 
+constexpr int kStageVec = 6;   // record float4 the rasteriser uses (g0..g5)
+
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-struct Rec {
-    float hx, hy, lx, ly, A00, A01, A10, A11, A20, A21, v0x, v0y, v0z, mz, K, Q11, Q00, Q01x2,
-        l0x2, l1x2, se;
-};
-
 struct Stage {
-    float4 g[kGeomVec][64];
-    float4 c[64];
+    float4 g[kStageVec][64];
     uint32_t item[64];
 };
 
-__device__ __forceinline__ Rec load_rec(const Stage &st, int q)
+// Fields of the bound pre-test (g0..g2) and of the full evaluation (g3..g5).
+struct PreRec {
+    float hx, hy, lx, ly, Q00, Q01x2, l0x2, l1x2, Q11, A00, A10, A20;
+};
+struct FullRec {
+    float A01, A11, A21, v0x, v0y, v0z, K, se, c0, c1, c2, mz;
+};
+
+__device__ __forceinline__ PreRec load_pre(const Stage &st, int q)
 {
-    const float4 a = st.g[0][q], b = st.g[1][q], c = st.g[2][q], d = st.g[3][q], e = st.g[4][q];
-    Rec r;
+    const float4 a = st.g[0][q], b = st.g[1][q], c = st.g[2][q];
+    PreRec r;
     r.hx = a.x; r.hy = a.y; r.lx = a.z; r.ly = a.w;
-    r.A00 = b.x; r.A01 = b.y; r.A10 = b.z; r.A11 = b.w;
-    r.A20 = c.x; r.A21 = c.y; r.v0x = c.z; r.v0y = c.w;
-    r.v0z = d.x; r.mz = d.y; r.K = d.z; r.Q11 = d.w;
-    r.Q00 = e.x; r.Q01x2 = e.y; r.l0x2 = e.z; r.l1x2 = e.w;
-    r.se = (0.5f * kLog2e) * r.mz * r.mz;
+    r.Q00 = b.x; r.Q01x2 = b.y; r.l0x2 = b.z; r.l1x2 = b.w;
+    r.Q11 = c.x; r.A00 = c.y; r.A10 = c.z; r.A20 = c.w;
     return r;
 }
 
-__device__ __forceinline__ void stage_record(Stage &st, const Buffers &b, int lane, uint32_t item,
-                                             bool color)
+__device__ __forceinline__ FullRec load_full(const Stage &st, int q)
 {
-    const float4 *gp = b.geom + (size_t)item * kGeomVec;
+    const float4 a = st.g[3][q], b = st.g[4][q], c = st.g[5][q];
+    FullRec r;
+    r.A01 = a.x; r.A11 = a.y; r.A21 = a.z; r.v0x = a.w;
+    r.v0y = b.x; r.v0z = b.y; r.K = b.z; r.se = b.w;
+    r.c0 = c.x; r.c1 = c.y; r.c2 = c.z; r.mz = c.w;
+    return r;
+}
+
+__device__ __forceinline__ void stage_record(Stage &st, const Buffers &b, int lane, uint32_t item)
+{
+    const float4 *gp = b.geom + (size_t)item * kRecVec;
 #pragma unroll
-    for (int v = 0; v < kGeomVec; ++v) st.g[v][lane] = gp[v];
-    if (color) st.c[lane] = b.color[item];
+    for (int v = 0; v < kStageVec; ++v) st.g[v][lane] = gp[v];
     st.item[lane] = item;
 }
 
-// Per-lane terms shared by the lane's pixels (pxc = px + 0.5).
+// Per-lane terms of the pre-test shared by the lane's pixels (pxc = px + 0.5).
 struct ColTerms {
-    float dx, ax0, ax1, ax2, wx0, wx1, wx2, f0, f1;
+    float dx, f0, f1;
 };
 
-__device__ __forceinline__ ColTerms col_terms(const Rec &r, float pxc)
+__device__ __forceinline__ ColTerms col_terms(const PreRec &r, float pxc)
 {
     ColTerms c;
     c.dx = (pxc - r.hx) - r.lx;
-    c.ax0 = r.A00 * c.dx;
-    c.ax1 = r.A10 * c.dx;
-    c.ax2 = r.A20 * c.dx;
-    c.wx0 = r.v0x + c.ax0;
-    c.wx1 = r.v0y + c.ax1;
-    c.wx2 = r.v0z + c.ax2;
     c.f0 = __fmaf_rn(c.dx, __fmaf_rn(r.Q00, c.dx, r.l0x2), -1.0f);
     c.f1 = __fmaf_rn(r.Q01x2, c.dx, r.l1x2);
     return c;
@@ -96,7 +100,7 @@ __device__ __forceinline__ ColTerms col_terms(const Rec &r, float pxc)
 
 // Bound pre-test of one pixel (pyc = py + 0.5): true if alpha >= alpha_min is
 // possible.  Writes the row offset.
-__device__ __forceinline__ bool pre_test(const Rec &r, const ColTerms &c, float pyc, float &dy)
+__device__ __forceinline__ bool pre_test(const PreRec &r, const ColTerms &c, float pyc, float &dy)
 {
     dy = (pyc - r.hy) - r.ly;
     const float f = __fmaf_rn(dy, __fmaf_rn(r.Q11, dy, c.f1), c.f0);
@@ -107,14 +111,17 @@ struct PairGeom {
     float a0, a1, a2, w0, w1, w2, n0, n1, n2, num, qw;
 };
 
-__device__ __forceinline__ void pair_geom(const Rec &r, const ColTerms &c, float dy, PairGeom &g)
+__device__ __forceinline__ void pair_geom(const PreRec &p, const FullRec &r, float dx, float dy,
+                                          PairGeom &g)
 {
-    g.a0 = __fmaf_rn(r.A01, dy, c.ax0);
-    g.a1 = __fmaf_rn(r.A11, dy, c.ax1);
-    g.a2 = __fmaf_rn(r.A21, dy, c.ax2);
-    g.w0 = __fmaf_rn(r.A01, dy, c.wx0);
-    g.w1 = __fmaf_rn(r.A11, dy, c.wx1);
-    g.w2 = __fmaf_rn(r.A21, dy, c.wx2);
+    const float ax0 = p.A00 * dx, ax1 = p.A10 * dx, ax2 = p.A20 * dx;
+    const float wx0 = r.v0x + ax0, wx1 = r.v0y + ax1, wx2 = r.v0z + ax2;
+    g.a0 = __fmaf_rn(r.A01, dy, ax0);
+    g.a1 = __fmaf_rn(r.A11, dy, ax1);
+    g.a2 = __fmaf_rn(r.A21, dy, ax2);
+    g.w0 = __fmaf_rn(r.A01, dy, wx0);
+    g.w1 = __fmaf_rn(r.A11, dy, wx1);
+    g.w2 = __fmaf_rn(r.A21, dy, wx2);
     g.n0 = __fmaf_rn(r.v0y, g.a2, -r.v0z * g.a1);
     g.n1 = __fmaf_rn(r.v0z, g.a0, -r.v0x * g.a2);
     g.n2 = __fmaf_rn(r.v0x, g.a1, -r.v0y * g.a0);
@@ -136,6 +143,13 @@ __device__ __forceinline__ int find_view(const ViewInfo *views, int n_views, int
         if (views[k].tile_off <= gt) v = k;
     return v;
 }
+
+// Pair counts (per lane) and wave-level visit counts (kept by lane 0): a
+// visit is one Gaussian against one slot of the wave's pixels; a full visit
+// is one that takes the evaluation branch.
+struct Counts {
+    uint32_t test = 0, full = 0, blend = 0, visits = 0, visits_full = 0;
+};
 
 template <int TW, int TH, int MODE, bool COUNT>
 __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers b)
@@ -160,7 +174,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     float pyc[PPL], un[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL];
     int last[PPL];
     bool act[PPL];
-    uint32_t c_test = 0, c_full = 0, c_blend = 0;
+    Counts n;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RS;
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 
     for (uint32_t bs = range.x; bs < range.y; bs += 64) {
         const uint32_t j = bs + lane;
-        if (j < range.y) stage_record(st, b, lane, b.inst_val[j], COLOR);
+        if (j < range.y) stage_record(st, b, lane, b.inst_val[j]);
         __syncthreads();
         const int nb = (int)min(64u, range.y - bs);
         bool alive = true;
@@ -191,41 +205,46 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     break;
                 }
             }
-            const Rec r = load_rec(st, qi);
-            float4 col;
-            if (COLOR) col = st.c[qi];
-            const ColTerms ct = col_terms(r, pxc);
+            const PreRec pr = load_pre(st, qi);
+            const ColTerms ct = col_terms(pr, pxc);
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 float dy;
-                const bool near = pre_test(r, ct, pyc[k], dy);   // always evaluated: sets dy
+                const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
                 const bool pass = act[k] && near;
-                if (COUNT) c_test += act[k] ? 1u : 0u;
-                if (!__any(pass)) continue;           // wave-uniform
-                if (COUNT) c_full += pass ? 1u : 0u;
+                const bool anyp = __any(pass);
+                if (COUNT) {
+                    n.test += act[k] ? 1u : 0u;
+                    const bool anyl = __any(act[k]);
+                    n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                    n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
+                }
+                if (!anyp) continue;                  // wave-uniform
+                if (COUNT) n.full += pass ? 1u : 0u;
+                const FullRec fr = load_full(st, qi);
                 PairGeom g;
-                pair_geom(r, ct, dy, g);
+                pair_geom(pr, fr, ct.dx, dy, g);
                 const float rq = fast_rsq(g.qw);
-                const float ex = fast_exp2(-(r.se * g.num * (rq * rq)));
-                const float y = r.K * un[k] * rq * ex;
+                const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
-                if (COLOR) {
+                if constexpr (COLOR) {
                     const float om = fast_exp2(-fminf(y, ymax));
                     const float Tn = T[k] * om;
                     const bool stop = bl && Tn < Tmin;
                     const bool dob = bl && !stop;
                     const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
-                    C0[k] = __fmaf_rn(col.x, wgt, C0[k]);
-                    C1[k] = __fmaf_rn(col.y, wgt, C1[k]);
-                    C2[k] = __fmaf_rn(col.z, wgt, C2[k]);
+                    C0[k] = __fmaf_rn(fr.c0, wgt, C0[k]);
+                    C1[k] = __fmaf_rn(fr.c1, wgt, C1[k]);
+                    C2[k] = __fmaf_rn(fr.c2, wgt, C2[k]);
                     T[k] = dob ? Tn : T[k];
                     last[k] = dob ? (int)(bs + qi) : last[k];
                     act[k] = act[k] && !stop;
-                    if (COUNT) c_blend += dob ? 1u : 0u;
+                    if (COUNT) n.blend += dob ? 1u : 0u;
                 } else {
                     C0[k] += bl ? y : 0.0f;
                     last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
-                    if (COUNT) c_blend += bl ? 1u : 0u;
+                    if (COUNT) n.blend += bl ? 1u : 0u;
                 }
             }
         }
@@ -257,9 +276,11 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         }
     }
     if (COUNT) {
-        atomicAdd(&b.counters[0], (unsigned long long)c_test);
-        atomicAdd(&b.counters[1], (unsigned long long)c_full);
-        atomicAdd(&b.counters[2], (unsigned long long)c_blend);
+        atomicAdd(&b.counters[0], (unsigned long long)n.test);
+        atomicAdd(&b.counters[1], (unsigned long long)n.full);
+        atomicAdd(&b.counters[2], (unsigned long long)n.blend);
+        atomicAdd(&b.counters[3], (unsigned long long)n.visits);
+        atomicAdd(&b.counters[4], (unsigned long long)n.visits_full);
     }
 }
 
@@ -269,7 +290,11 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 //           hold index k and lanes 32-63 index k + 8;
 //   step 2: v_permlane16_swap pairs (v[k], v[k+4]); row r (16 lanes) now
 //           holds indices 4 r + k, k = 0..3;
-//   steps 3-5: exchanges across lane bits 3, 2 (keep/send halves) and 1, 0.
+//   step 3: lanes l and l ^ 8 (DPP row rotate by 8) keep one pair of indices
+//           each and send the other;
+//   step 4: lanes l and 7 - l of each 8-lane half row (DPP half mirror) keep
+//           one index each and send the other;
+//   step 5: sums within each quad (DPP quad permutations).
 __device__ __forceinline__ float swap_add32(float &a, float b)
 {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
@@ -284,6 +309,19 @@ __device__ __forceinline__ float swap_add16(float a, float b)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// DPP lane moves (gfx9 encodings): row rotate right by 8, half-row mirror,
+// quad permutations [2,3,0,1] and [1,0,3,2].
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppQuadXor1 = 0xB1;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
 {
 #pragma unroll
@@ -296,17 +334,17 @@ __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
         for (int k = 0; k < 2; ++k) {
             const float send = hi ? v[k] : v[k + 2];
             const float keep = hi ? v[k + 2] : v[k];
-            v[k] = keep + __shfl_xor(send, 8, 64);
+            v[k] = keep + dpp_move<kDppRowRor8>(send);
         }
     }
     {
         const bool hi = lane & 4;
         const float send = hi ? v[0] : v[1];
         const float keep = hi ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, 4, 64);
+        v[0] = keep + dpp_move<kDppRowHalfMirror>(send);
     }
-    v[0] += __shfl_xor(v[0], 2, 64);
-    v[0] += __shfl_xor(v[0], 1, 64);
+    v[0] += dpp_move<kDppQuadXor2>(v[0]);
+    v[0] += dpp_move<kDppQuadXor1>(v[0]);
     return v[0];
 }
 
@@ -336,7 +374,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     float pyc[PPL], un[PPL], T[PPL], g[PPL][NCH], B[PPL][NCH];
     int last[PPL];
     int maxlast = -1;
-    uint32_t c_test = 0, c_full = 0, c_blend = 0;
+    Counts n;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         const int py = py0 + k * RS;
@@ -359,19 +397,16 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     if (maxlast < (int)range.x) return;   // uniform: no pixel of this tile blended anything
     const float tau2 = rp.tau2, ymax = rp.ymax;
     float *rg = reinterpret_cast<float *>(b.rgrad);
-    const int red_idx = lane >> 2;   // index held by the reducing lanes
 
     for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
         const int bs = max((int)range.x, be - 64);
         const int j = bs + lane;
-        if (j < be) stage_record(st, b, lane, b.inst_val[j], COLOR);
+        if (j < be) stage_record(st, b, lane, b.inst_val[j]);
         __syncthreads();
         for (int qi = be - 1 - bs; qi >= 0; --qi) {
             const int jpos = bs + qi;
-            const Rec r = load_rec(st, qi);
-            float4 col;
-            if (COLOR) col = st.c[qi];
-            const ColTerms ct = col_terms(r, pxc);
+            const PreRec pr = load_pre(st, qi);
+            const ColTerms ct = col_terms(pr, pxc);
             float acc[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
@@ -380,36 +415,43 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             for (int k = 0; k < PPL; ++k) {
                 float dy;
                 const bool inl = jpos <= last[k];
-                const bool near = pre_test(r, ct, pyc[k], dy);   // always evaluated: sets dy
+                const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
                 const bool pass = inl && near;
-                if (COUNT) c_test += inl ? 1u : 0u;
-                if (!__any(pass)) continue;           // wave-uniform
-                if (COUNT) c_full += pass ? 1u : 0u;
+                const bool anyp = __any(pass);
+                if (COUNT) {
+                    n.test += inl ? 1u : 0u;
+                    const bool anyl = __any(inl);
+                    n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                    n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
+                }
+                if (!anyp) continue;                  // wave-uniform
+                if (COUNT) n.full += pass ? 1u : 0u;
+                const FullRec fr = load_full(st, qi);
                 PairGeom pg;
-                pair_geom(r, ct, dy, pg);
+                pair_geom(pr, fr, ct.dx, dy, pg);
                 const float rq = fast_rsq(pg.qw);
                 const float rq2 = rq * rq;
-                const float ex = fast_exp2(-(r.se * pg.num * rq2));
-                const float y = r.K * un[k] * rq * ex;
+                const float ex = fast_exp2(-(fr.se * pg.num * rq2));
+                const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
-                if (COUNT) c_blend += bl ? 1u : 0u;
+                if (COUNT) n.blend += bl ? 1u : 0u;
                 float dy_;
-                if (COLOR) {
+                if constexpr (COLOR) {
                     const bool clamped = y > ymax;
                     const float om = fast_exp2(-fminf(y, ymax));
                     const float inv = fast_rcp(om);
                     const float alpha = 1.0f - om;
                     const float Tb = T[k] * inv;
-                    const float da = g[k][0] * (col.x * Tb - B[k][0] * inv) +
-                                     g[k][1] * (col.y * Tb - B[k][1] * inv) +
-                                     g[k][2] * (col.z * Tb - B[k][2] * inv);
+                    const float da = g[k][0] * (fr.c0 * Tb - B[k][0] * inv) +
+                                     g[k][1] * (fr.c1 * Tb - B[k][1] * inv) +
+                                     g[k][2] * (fr.c2 * Tb - B[k][2] * inv);
                     const float wgt = bl ? alpha * Tb : 0.0f;
                     acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
                     acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
                     acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
-                    B[k][0] = __fmaf_rn(col.x, wgt, B[k][0]);
-                    B[k][1] = __fmaf_rn(col.y, wgt, B[k][1]);
-                    B[k][2] = __fmaf_rn(col.z, wgt, B[k][2]);
+                    B[k][0] = __fmaf_rn(fr.c0, wgt, B[k][0]);
+                    B[k][1] = __fmaf_rn(fr.c1, wgt, B[k][1]);
+                    B[k][2] = __fmaf_rn(fr.c2, wgt, B[k][2]);
                     T[k] = bl ? Tb : T[k];
                     dy_ = (bl && !clamped) ? da * kLn2 * om : 0.0f;
                 } else {
@@ -421,7 +463,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const float t = bl ? dy_ * y : 0.0f;
                 acc[9] += bl ? dy_ * (un[k] * rq * ex) : 0.0f;
                 // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|
-                const float cz = bl ? r.mz * rq2 : 0.0f;
+                const float cz = bl ? fr.mz * rq2 : 0.0f;
                 const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);
                 const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
                 const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
@@ -438,15 +480,18 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             }
             if (__any(touched)) {
                 const float tot = wave_reduce16(acc, lane);
-                if ((lane & 3) == 0) atomicAdd(rg + (size_t)st.item[qi] * 16 + red_idx, tot);
+                if ((lane & 3) == 0)
+                    atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
             }
         }
         __syncthreads();
     }
     if (COUNT) {
-        atomicAdd(&b.counters[3], (unsigned long long)c_test);
-        atomicAdd(&b.counters[4], (unsigned long long)c_full);
-        atomicAdd(&b.counters[5], (unsigned long long)c_blend);
+        atomicAdd(&b.counters[8], (unsigned long long)n.test);
+        atomicAdd(&b.counters[9], (unsigned long long)n.full);
+        atomicAdd(&b.counters[10], (unsigned long long)n.blend);
+        atomicAdd(&b.counters[11], (unsigned long long)n.visits);
+        atomicAdd(&b.counters[12], (unsigned long long)n.visits_full);
     }
 }
 

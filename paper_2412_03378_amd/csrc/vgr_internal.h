@@ -16,21 +16,28 @@ constexpr float kSqrt2Pi = 2.5066282746310002f;
 constexpr float kHalfLog2eSqrt = 0.8493218002880191f;
 
 constexpr int kMaxViews = 64;
-constexpr int kGeomVec = 5;       // float4 per rasteriser record, see layout below
+constexpr int kRecVec = 8;        // float4 per rasteriser record (128 bytes), see layout below
 constexpr float kConicMargin = 0.05f;
+constexpr float kCullLevel = 0.1f;   // tile culling level of the bound form (> kConicMargin)
+constexpr float kCullPad = 0.02f;    // pixels added on both ends of a culled row span
 constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 
-// Rasteriser record of one (Gaussian, view), 20 floats (5 float4), in the
-// Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view R(q)), so that
-// Sigma_v^-1 = L^T L, and m the view-space mean (computed in FP64):
+// Rasteriser record of one (Gaussian, view), 128 bytes (8 float4, one cache
+// line), in the Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view
+// R(q)), so that Sigma_v^-1 = L^T L, and m the view-space mean (computed in
+// FP64).  The fields of the bound pre-test come first, so that a rasteriser
+// step that rejects every pixel reads three float4:
 //   g0 = (hx, hy, lx, ly)       projected mean (fx mx/mz + cx, fy my/mz + cy) in
 //                               pixels, split into an integer hi part h and an
 //                               FP32 residual l (|l| <= 0.5), so that the pixel
 //                               offset (p + 0.5 - h) - l keeps full precision
-//   g1 = (A00, A01, A10, A11)   A = L[:, 0:2] diag(1/fx, 1/fy)
-//   g2 = (A20, A21, v0x, v0y)   v0 = L m / mz: L applied to the ray through the mean
-//   g3 = (v0z, mz, K', Q11)     K' = kappa sqrt(2 pi) log2 e
-//   g4 = (Q00, 2 Q01, 2 l0, 2 l1)
+//   g1 = (Q00, 2 Q01, 2 l0, 2 l1)
+//   g2 = (Q11, A00, A10, A20)   A = L[:, 0:2] diag(1/fx, 1/fy)
+//   g3 = (A01, A11, A21, v0x)   v0 = L m / mz: L applied to the ray through the mean
+//   g4 = (v0y, v0z, K', se)     K' = kappa sqrt(2 pi) log2 e,  se = (log2 e / 2) mz^2
+//   g5 = (r, g, b, mz)          colour after the activation (0 in X-ray mode)
+//   g6 = (cx, cy, a, P)         tile-culling ellipse (see cull_row in the
+//   g7 = (R, ymax, yl, on)        preprocess source); on = 0: no culling
 // For the pixel with centre (px + 0.5, py + 0.5), ray u = (ux, uy, 1), and
 // pixel offset d = (px + 0.5, py + 0.5) - h - l:
 //   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)
@@ -43,7 +50,6 @@ constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 // margin covers the FP32 evaluation error when the 2x2 form Q is positive
 // definite with condition number <= 1e4; otherwise Q = l = 0 (f = -1, no
 // pixel is rejected early).
-// Colour record (COLOR mode): r, g, b, 0 after the activation.
 //
 // Record gradient, 16 floats, as moments in the Gaussian's L-frame.  Per pixel,
 // with t = dL/d(ln x), v = m - gamma u (mean minus closest ray point) and
@@ -87,8 +93,7 @@ struct RenderParams {
 
 // Device workspace views handed to kernels.
 struct Buffers {
-    float4 *geom;        // n_views * n records (kGeomVec float4 each)
-    float4 *color;       // n_views * n
+    float4 *geom;        // n_views * n records (kRecVec float4 each)
     uint32_t *depth_key; // n_views * n
     uint32_t *item_ids;  // n_views * n (item = view * n + Gaussian; sorted by depth)
     uint32_t *key2;      // n_views * n, sort ping-pong

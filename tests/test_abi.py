@@ -42,3 +42,30 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
         finally:
             _lib._lib = saved
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes mirrors of the public structs have the C compiler's sizes and
+    field offsets for include/vgr.h."""
+    import subprocess
+    from paper_2412_03378_amd import _lib
+    src = tmp_path / "layout.c"
+    fields = {name: [f for f, _ in getattr(_lib, name)._fields_]
+              for name in ("vgr_camera", "vgr_settings", "vgr_stats")}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vgr.h"', "int main(void) {"]
+    for name, fs in fields.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in fs:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = dict(zip(out[0::2], (int(x) for x in out[1::2])))
+    for name, fs in fields.items():
+        st = getattr(_lib, name)
+        assert got[name] == ctypes.sizeof(st), name
+        for f in fs:
+            assert got[f"{name}.{f}"] == getattr(st, f).offset, (name, f)

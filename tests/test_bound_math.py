@@ -92,3 +92,57 @@ def test_pre_test_form_has_the_sign_of_the_distance_excess(seed):
             a = A @ d
             assert np.allclose(w, v0 + a)
             assert f == pytest.approx((w @ w) * (D2 - Dp) / (Dp * V), rel=1e-9, abs=1e-9)
+
+
+def _row_interval(Q, l, c, ya, yb):
+    """x-extent of {d : d^T Q d + 2 l^T d - 1 <= c} within the strip ya <= y <= yb,
+    from the closed form the tile culling uses: centre d0 = -Q^-1 l,
+    rho = 1 + c + l^T Q^-1 l, X = a Y -/+ sqrt(P - R Y^2), extreme X at the
+    clamped Y of the leftmost / rightmost points (None if the strip misses)."""
+    det = Q[0, 0] * Q[1, 1] - Q[0, 1] ** 2
+    d0 = -np.linalg.solve(Q, l)
+    rho = 1 + c - l @ d0
+    a, P, R = -Q[0, 1] / Q[0, 0], rho / Q[0, 0], det / Q[0, 0] ** 2
+    ymax = math.sqrt(rho * Q[0, 0] / det)
+    yl = Q[0, 1] * math.sqrt(rho / (det * Q[1, 1]))
+    lo, hi = max(ya - d0[1], -ymax), min(yb - d0[1], ymax)
+    if lo > hi:
+        return None
+    y1 = min(max(yl, lo), hi)
+    y2 = min(max(-yl, lo), hi)
+    left = a * y1 - math.sqrt(max(P - R * y1 * y1, 0.0))
+    right = a * y2 + math.sqrt(max(P - R * y2 * y2, 0.0))
+    return d0[0] + left, d0[0] + right
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_culling_row_interval_is_the_strip_extent(seed):
+    """Brute force over a dense grid: every point of the ellipse inside the
+    strip lies in the closed-form interval, and both ends are reached."""
+    rng = np.random.default_rng(200 + seed)
+    for _ in range(30):
+        B = rng.normal(0, 1, (2, 2))
+        Q = B @ B.T + 0.05 * np.eye(2)
+        Q /= rng.uniform(4, 60) ** 2
+        l = rng.normal(0, 0.05, 2)
+        c = 0.1
+        d0 = -np.linalg.solve(Q, l)
+        rho = 1 + c - l @ d0
+        ext = 1.2 * math.sqrt(rho / np.linalg.eigvalsh(Q)[0])   # grid covers the ellipse
+        ya = d0[1] + rng.uniform(-1.2, 1.0) * ext
+        yb = ya + rng.uniform(0.5, 12.0)
+        xs = np.linspace(d0[0] - ext, d0[0] + ext, 1201)
+        ys = np.linspace(ya, yb, 61)
+        X, Y = np.meshgrid(xs, ys)
+        f = Q[0, 0] * X * X + 2 * Q[0, 1] * X * Y + Q[1, 1] * Y * Y + 2 * (l[0] * X + l[1] * Y) - 1
+        inside = f <= c
+        iv = _row_interval(Q, l, c, ya, yb)
+        if iv is None:
+            assert not inside.any()
+            continue
+        if not inside.any():
+            continue
+        step = xs[1] - xs[0]
+        assert X[inside].min() >= iv[0] - 1e-9 and X[inside].max() <= iv[1] + 1e-9
+        assert X[inside].min() <= iv[0] + 2 * step + 0.05 * ext / 60
+        assert X[inside].max() >= iv[1] - 2 * step - 0.05 * ext / 60
