@@ -38,7 +38,7 @@ struct vgr_ctx {
     DevBuf geom, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
-    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views;
+    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts;
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
@@ -226,6 +226,7 @@ Buffers make_buffers(vgr_ctx *c)
     b.last_id = ptr<int32_t>(c->last_id);
     b.rgrad = ptr<float4>(c->rgrad);
     b.d_total = ptr<uint32_t>(c->words);
+    b.blk_counts = ptr<uint32_t>(c->blk_counts);
     b.counters = ptr<unsigned long long>(c->counters);
     b.views = ptr<ViewInfo>(c->views);
     return b;
@@ -297,7 +298,7 @@ void vgr_destroy(vgr_ctx *c)
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
-                      &c->words, &c->counters, &c->views };
+                      &c->words, &c->counters, &c->views, &c->blk_counts };
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (c->h_views) (void)hipHostFree(c->h_views);
@@ -461,6 +462,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     p.sort_n = p.m > tiles ? p.m : tiles;
     const int64_t m = p.m;
     if ((rc = ensure(c, c->geom, sizeof(float4) * kRecVec * (m > 0 ? m : 1))) ||
+        (rc = ensure(c, c->blk_counts, 4 * (preprocess_blocks(n, n_views) + 1))) ||
         (rc = ensure(c, c->depth_key, 4 * m)) || (rc = ensure(c, c->item_ids, 4 * m)) ||
         (rc = ensure(c, c->key2, 4 * m)) || (rc = ensure(c, c->item2, 4 * m)) ||
         (rc = ensure(c, c->counts, 4 * m)) || (rc = ensure(c, c->cnt_sorted, 4 * m)) ||
@@ -494,7 +496,6 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     int64_t K = 0;
     if (m > 0) {
         mark(c, ST_PREPROCESS);
-        HIP_TRY(c, launch_fill_u32(b.d_total + 4, 0u, 1, s));
         HIP_TRY(c, launch_preprocess(rp, b, means, quats, scales, dens, sh, s));
         if (cap < 0) {
             // the instance count K travels to the host while the depth sort runs

@@ -289,7 +289,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
             const double mx = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
             const double my = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
             const double mzd = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
-            const double u0x = mx / mzd, u0y = my / mzd;
+            const double rmz = 1.0 / mzd;
+            const double u0x = mx * rmz, u0y = my * rmz;
             const double cxp = (double)vi.fx * u0x + vi.cx, cyp = (double)vi.fy * u0y + vi.cy;
             const double hx = rint(cxp), hy = rint(cyp);
             const float v0[3] = {
@@ -313,28 +314,29 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                     G00 += ak0 * ak0; G01 += ak0 * ak1; G11 += ak1 * ak1;
                     g0 += ak0 * vk; g1 += ak1 * vk; V += vk * vk;
                 }
-                const double mz2 = mzd * mzd, den = Dp * V;
-                const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) / den;
-                const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) / den;
-                const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) / den;
+                const double mz2 = mzd * mzd, rV = 1.0 / V, rden = rV / Dp;
+                const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) * rden;
+                const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) * rden;
+                const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) * rden;
                 const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
                 const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
                 const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
                 if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
-                    const double el0 = -g0 / V, el1 = -g1 / V;
+                    const double el0 = -g0 * rV, el1 = -g1 * rV, rdet = 1.0 / det;
                     Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
                     l0 = (float)el0; l1 = (float)el1;
                     // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
-                    const double dx0 = -(q11 * el0 - q01 * el1) / det;
-                    const double dy0 = -(q00 * el1 - q01 * el0) / det;
+                    const double dx0 = -(q11 * el0 - q01 * el1) * rdet;
+                    const double dy0 = -(q00 * el1 - q01 * el0) * rdet;
                     const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
                     cr.cx = (float)(cxp + dx0 - 0.5);
                     cr.cy = (float)(cyp + dy0 - 0.5);
-                    cr.a = (float)(-q01 / q00);
-                    cr.P = (float)(rho / q00);
-                    cr.R = (float)(det / (q00 * q00));
-                    cr.ymax = (float)sqrt(rho * q00 / det);
-                    cr.yl = (float)(q01 * sqrt(rho / (det * q11)));
+                    const double rq00 = 1.0 / q00;
+                    cr.a = (float)(-q01 * rq00);
+                    cr.P = (float)(rho * rq00);
+                    cr.R = (float)(det * rq00 * rq00);
+                    cr.ymax = (float)sqrt(rho * q00 * rdet);
+                    cr.yl = (float)(q01 * sqrt(rho * rdet / q11));
                     cr.on = 1.0f;
                 }
             }
@@ -378,11 +380,31 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
         b.counts[item] = count;
         b.rect[item] = rect;
     }
-    // total instance count K, for sizing the instance lists before the scan
+    // total instance count K, for sizing the instance lists before the scan:
+    // one partial sum per block (count_total_kernel adds them; one atomic per
+    // wave on a single address would serialise thousands of updates)
+    __shared__ uint32_t s_wsum[4];
     uint32_t wsum = count;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(b.d_total + 4, wsum);
+    if ((threadIdx.x & 63) == 0) s_wsum[threadIdx.x >> 6] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        b.blk_counts[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] =
+            s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+}
+
+__global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__restrict__ parts,
+                                                           int64_t n, uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t s_part[4];
+    uint32_t acc = 0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) acc += parts[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = s_part[0] + s_part[1] + s_part[2] + s_part[3];
 }
 
 __global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
@@ -501,8 +523,13 @@ __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, in
                 uint32_t k = s_rbeg[lo];
                 const uint32_t kend = s_rbeg[lo + 1];
                 while (k + 1 < kend && s_rstart[k + 1] <= (uint32_t)local) ++k;
-                ty = (int)(s_rtile[k] >> 16);
-                tx = (int)(s_rtile[k] & 0xFFFFu) + local - (int)s_rstart[k];
+                if (k < kend) {
+                    ty = (int)(s_rtile[k] >> 16);
+                    tx = (int)(s_rtile[k] & 0xFFFFu) + local - (int)s_rstart[k];
+                } else {
+                    tx = s_rect[lo].x;
+                    ty = s_rect[lo].y;
+                }
             } else {
                 // the local-th tile of the culled rectangle, row by row (the
                 // same row intervals the preprocess counted)
@@ -521,6 +548,11 @@ __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, in
                     local -= t1 - t0 + 1;
                 }
             }
+            // the preprocess counted exactly these tiles; the clamp only keeps
+            // a miscount (none is expected) inside the Gaussian's own rectangle
+            const ushort4 rr = s_rect[lo];
+            tx = min(max(tx, (int)rr.x), (int)rr.z);
+            ty = min(max(ty, (int)rr.y), (int)rr.w);
             const int64_t pos = (int64_t)base + e;
             if (pos < capacity) {
                 b.inst_key[pos] = (uint32_t)(s_toff[lo] + ty * s_tx[lo] + tx);
@@ -530,13 +562,17 @@ __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, in
     }
 }
 
+// Per-tile [start, end) of the tile-sorted instance list.  Keys at or past
+// n_tiles (none are emitted; the check keeps a bad key from writing outside
+// the ranges array) are ignored.
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ d_total,
-                              uint2 *__restrict__ ranges, int64_t bound)
+                              uint2 *__restrict__ ranges, int64_t bound, uint32_t n_tiles)
 {
     const int64_t K = d_total[0];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K && j < bound;
          j += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t k = keys[j];
+        if (k >= n_tiles) continue;
         if (j == 0 || keys[j - 1] != k) ranges[k].x = (uint32_t)j;
         if (j == K - 1 || keys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
     }
@@ -756,7 +792,15 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
     case 2: preprocess_kernel<2><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
     default: preprocess_kernel<3><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid.x * grid.y, b.d_total + 4);
     return hipGetLastError();
+}
+
+int64_t preprocess_blocks(int64_t n, int32_t n_views)
+{
+    return (int64_t)grid_for(n, 256) * n_views;
 }
 
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)
@@ -786,7 +830,7 @@ hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, h
     if (bound <= 0) return hipSuccess;
     unsigned g = grid_for(bound, 256);
     if (g > 16384) g = 16384;
-    ranges_kernel<<<g, 256, 0, s>>>(b.inst_key, b.d_total, b.ranges, bound);
+    ranges_kernel<<<g, 256, 0, s>>>(b.inst_key, b.d_total, b.ranges, bound, (uint32_t)total_tiles);
     return hipGetLastError();
 }
 

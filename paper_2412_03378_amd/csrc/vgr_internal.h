@@ -115,8 +115,9 @@ struct Buffers {
     int32_t *last_pos;   // total pixels: list position of last blended (-1)
     int32_t *last_id;    // total pixels: Gaussian index of last blended (-1)
     float4 *rgrad;       // n_views * n * 4 float4 (record gradients)
+    uint32_t *blk_counts;// preprocess blocks: instances per block
     uint32_t *d_total;   // [0] = instance count K, [1] overflow flag
-    unsigned long long *counters;  // pair counters: forward [0..2], backward [3..5]
+    unsigned long long *counters;  // pair and visit counters: forward [0..4], backward [8..12]
     const ViewInfo *views;
 };
 
@@ -127,6 +128,8 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const float *means,
                              const float *quats, const float *scales, const float *dens,
                              const float *sh, hipStream_t s);
+// Number of preprocess blocks (size of Buffers::blk_counts).
+int64_t preprocess_blocks(int64_t n, int32_t n_views);
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s);
 hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s);
 hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
