@@ -686,7 +686,7 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         gauss_view(vi, mu, q, s, g);
         for (int k = 0; k < 4; ++k) qn[k] = g.qn[k];
         qlen = g.qlen;
-        gk += gr[9] * (kSqrt2Pi * kLog2e);
+        gk += gr[9];   // sum t = K' dL/dK' = kappa dL/dkappa
         // Sigma^-1 = Rc diag(s^-2) Rc^T with dL/dSigma^-1 = -1/2 L^-1 M L^-T, L^-1 = Rc diag(s),
         // so dL/dRc = -Rc diag(s) M diag(1/s):
         //   scales: dL/ds_k = M_kk / s_k;
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         d_quats[4 * i + 3] += c * (w * gth[2] + x * gth[1] - y * gth[0]);
     }
     for (int k = 0; k < 3; ++k) d_scales[3 * i + k] += gs[k];
-    d_dens[i] += gk;
+    d_dens[i] += gk / dens[i];
     if (rp.mode == VGR_MODE_COLOR && d_sh) {
 #pragma unroll
         for (int k = 0; k < NB * 3; ++k) d_sh[i * NB * 3 + k] += gsh[k];

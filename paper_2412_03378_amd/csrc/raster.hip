@@ -229,6 +229,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                 const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
                 if constexpr (COLOR) {
+                    if (!__any(bl)) continue;            // wave-uniform
                     const float om = fast_exp2(-fminf(y, ymax));
                     const float Tn = T[k] * om;
                     const bool stop = bl && Tn < Tmin;
@@ -435,6 +436,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
                 if (COUNT) n.blend += bl ? 1u : 0u;
+                if (!__any(bl)) continue;                // wave-uniform
                 float dy_;
                 if constexpr (COLOR) {
                     const bool clamped = y > ymax;
@@ -458,10 +460,11 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     dy_ = bl ? g[k][0] * kLn2 : 0.0f;
                 }
                 touched |= bl;
-                // t = dL/d(ln x) = dL/dy * y;  dL/dK' = dy |u| r exp2(-e)
-                // (selected, not multiplied, to zero for lanes that do not blend)
+                // t = dL/d(ln x) = dL/dy * y (selected, not multiplied, to zero
+                // for lanes that do not blend); since ln x is ln K' plus terms
+                // free of K', the sum of t is K' dL/dK'
                 const float t = bl ? dy_ * y : 0.0f;
-                acc[9] += bl ? dy_ * (un[k] * rq * ex) : 0.0f;
+                acc[9] += t;
                 // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|
                 const float cz = bl ? fr.mz * rq2 : 0.0f;
                 const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);

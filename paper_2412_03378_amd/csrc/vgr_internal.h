@@ -59,7 +59,8 @@ constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 //                      = -1/2 L^-1 (w w^T / |w|^2 + z z^T) L^-T,
 // so the sums  M = sum t (w w^T/|w|^2 + z z^T)  (symmetric) and  Z = sum t z
 // carry the whole geometric gradient:
-//   [0..5] M00 M01 M02 M11 M12 M22, [6..8] Z, [9] dL/dK', [10..12] dL/dc, [13..15] 0.
+//   [0..5] M00 M01 M02 M11 M12 M22, [6..8] Z, [9] sum t (= K' dL/dK'), [10..12] dL/dc,
+//   [13..15] 0.
 
 struct ViewInfo {
     float R[9];
