@@ -6,10 +6,12 @@
 //
 // Radix pass = histogram kernel + per-digit exclusive scan of the digit-major
 // table of per-block counts (one block per digit) + scatter kernel, which adds
-// the digit starts (a scan of the 256 digit totals) itself.  The scatter ranks keys stably inside a 4096-key
-// tile: each wave owns 1024 consecutive keys, ranks 64 keys at a time by
-// matching digits with one ballot per digit bit, and keeps running per-digit
-// counters in LDS; wave and block offsets are added afterwards.
+// the digit starts (a scan of the 256 digit totals) itself.  The scatter ranks
+// keys stably inside a 4096-key tile: each wave owns 1024 consecutive keys,
+// ranks 64 keys at a time by matching digits with one ballot per digit bit,
+// and keeps running per-digit counters in LDS.  The tile is then reordered by
+// digit in LDS and written out run by run, so that neighbouring threads write
+// neighbouring addresses.
 #include "vgr_internal.h"
 
 namespace vgr {
@@ -197,6 +199,8 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ tot, int nb)
 {
     __shared__ uint32_t cnt[kWaves][256];
+    __shared__ uint32_t gdelta[256];   // global start minus block-local start
+    __shared__ uint32_t sk[kTile], sv[kTile];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t mask = (1u << dbits) - 1u;
     const int64_t n = *d_n;
@@ -237,8 +241,17 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     }
     __syncthreads();
     {
+        // per digit: block-local start (scan over digits of the block's counts),
+        // then each wave's start inside it; global start from the digit-major
+        // table of block offsets
         const int d = threadIdx.x;
-        uint32_t run = digit_start + offs[(int64_t)d * nb + blockIdx.x];
+        uint32_t c_d = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < kWaves; ++k2) c_d += cnt[k2][d];
+        uint32_t blk_count;
+        const uint32_t ls = block_exclusive_scan(c_d, &blk_count);
+        gdelta[d] = digit_start + offs[(int64_t)d * nb + blockIdx.x] - ls;
+        uint32_t run = ls;
 #pragma unroll
         for (int k2 = 0; k2 < kWaves; ++k2) {
             uint32_t c = cnt[k2][d];
@@ -247,15 +260,27 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
         }
     }
     __syncthreads();
+    // reorder the tile by digit in LDS ...
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         int64_t idx = wbase + i * 64 + lane;
         if (idx < n) {
             uint32_t d = (k[i] >> shift) & mask;
-            uint32_t pos = cnt[w][d] + r[i];
-            keys_out[pos] = k[i];
-            vals_out[pos] = v[i];
+            uint32_t lp = cnt[w][d] + r[i];
+            sk[lp] = k[i];
+            sv[lp] = v[i];
         }
+    }
+    __syncthreads();
+    // ... and write it out in order: consecutive threads write consecutive
+    // positions of the same digit run
+    const int64_t cnt_blk = min((int64_t)kTile, n - blk_base);
+    for (int e = threadIdx.x; e < cnt_blk; e += kThreads) {
+        const uint32_t key = sk[e];
+        const uint32_t d = (key >> shift) & mask;
+        const uint32_t pos = gdelta[d] + (uint32_t)e;
+        keys_out[pos] = key;
+        vals_out[pos] = sv[e];
     }
 }
 
