@@ -23,22 +23,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic FP32 work per (pixel, Gaussian) pair of the rasteriser, counted
-# from its operation list (FMA = 2 flops; add, mul, compare, min = 1; each
-# rsq / exp2 / rcp = 1):
-#   bound test of every visited pair: d_y, a = A d, w = v0 + a, n = v0 x a,
-#     |n|^2, |w|^2, the comparison                                   34
-#   per lane and Gaussian, shared by the lane's pixels (d_x, A d_x,
-#     v0 + A d_x)                                                     7 / pixels-per-lane
-#   closed-form integral of pairs past the bound test (rsq, r^2, exponent,
-#     exp2, K'|u| r exp2, skip compare)                               9
+# from its operation list (FMA = 2 flops; add, sub, mul, compare, min = 1;
+# each rsq / exp2 / rcp = 1):
+#   bound pre-test of every visited pair: row offset d_y (2), the form
+#     f = d_y (Q11 d_y + f1) + f0 (4), the comparison (1)              7
+#   per lane and Gaussian, shared by the lane's pixels: column offset d_x
+#     (2), f0 = d_x (Q00 d_x + 2 l0) - 1 (4), f1 = 2 Q01 d_x + 2 l1 (2)  8 / pixels-per-lane
+#   closed-form integral of pairs past the pre-test: a = A d, w = v0 + a,
+#     n = v0 x a, |n|^2, |w|^2 (37), rsq (1), exponent and exp2 (4),
+#     K' |u| r exp2 (3), skip compare (1)                              46
 #   forward compositing of blended pairs (clamp, exp2, T(1-a), stop test,
-#     alpha, weight, colour FMAs)                                     12   (X-ray sum: 1)
-#   backward of blended pairs: compositing replay (clamp, exp2, rcp, T, dL/dalpha,
-#     colour gradient, colour-behind update)                         32   (X-ray: 1)
-#     moment accumulation (t, dK', z, w/|w|, Z, M)                   57
-F_TEST, F_SHARED, F_FULL = 34, 7, 9
+#     alpha, weight, colour FMAs)                                      12   (X-ray sum: 1)
+#   backward of blended pairs: compositing replay (clamp, exp2, rcp, T,
+#     dL/dalpha, colour gradient, colour-behind update) 35 (X-ray: 1), moment
+#     accumulation (t, sum t, z = mz (w x n)/|w|^2, w/|w|, Z, M)       54
+F_TEST, F_SHARED, F_FULL = 7, 8, 46
 F_BLEND_FWD = {"color": 12, "xray": 1}
-F_BLEND_BWD = {"color": 32 + 57, "xray": 1 + 57}
+F_BLEND_BWD = {"color": 35 + 54, "xray": 1 + 54}
 PEAK_FP32 = 157.3e12    # MI355X published FP32 vector peak (FLOP/s)
 CALIB_COPY_BYTES = 1 << 28   # plain device copy used to calibrate the HBM byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_raster_8x8_1M_1080p.json")
@@ -124,62 +125,92 @@ def bench_headline(args, torch, dev):
                     "color", "fwd")
     fl_bwd = _flops(stats["bwd_pairs_tested"], stats["bwd_pairs_full"],
                     stats["bwd_pairs_blended"], ppl, "color", "bwd")
+    # the same step captured once in a hipGraph and replayed (no host work)
+    outs = [torch.empty((3, c.height, c.width), device=dev) for c in cams]
+    r.graph_capture(params, cams, st, outs, dLs, grads, capacity_factor=1.05, zero_grads=True)
+    graph_ms = _graph_time(r, args.steps, torch) * 1e3
     kern = {"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}
     dom = max(kern, key=lambda k: stages.get(k, 0.0))
     achieved = kern[dom] / (stages[dom] * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": _traffic(dom),
                 "flops_per_launch": kern[dom], "launch_ms": stages[dom]}
-    return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl,
+    return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
                 flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd})
 
 
+def _graph_time(r, steps, torch):
+    for _ in range(2):
+        r.graph_launch()
+    r.graph_check()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.graph_launch()
+    r.graph_check()
+    return (time.perf_counter() - t0) / steps
+
+
 def bench_batched(args, torch, dev):
+    """16 mixed-resolution views: the tile shape picked by the autotuner, then
+    forward + backward of all views captured in one hipGraph and replayed,
+    against the same views rendered by separate single-view calls."""
     from paper_2412_03378_amd import Renderer, Settings, scenes
     _log("generating the 3M-Gaussian 16-view scene")
     wl = scenes.config3()
     params = _device_scene(wl.scene, dev, torch)
     dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
     grads = [torch.zeros_like(p) for p in params]
-    st = Settings(sh_degree=3, tile=tuple(args.tile))
+    outs = [torch.empty((3, c.height, c.width), device=dev) for c in wl.cams]
     r = Renderer(0)
     nv = len(wl.cams)
-    res = {}
-    for mode in ("batched", "single"):
-        _log(f"{mode} views")
+    _log("autotuning the tile shape")
+    tile, tune_ms = r.autotune(params, wl.cams, Settings(sh_degree=3), outs, dLs, grads, iters=2)
+    st = Settings(sh_degree=3, tile=tile)
+    res = {"tile": list(tile), "autotune_ms": [round(x, 3) for x in tune_ms]}
+    _log("batched views, one captured graph")
+    r.graph_capture(params, wl.cams, st, outs, dLs, grads, capacity_factor=1.1, zero_grads=True)
+    res["batched"] = nv / _graph_time(r, args.batched_steps, torch)
+    _log("single-view calls")
+    # single-view calls get their own tuned tile (tuned on the largest view)
+    big = max(range(nv), key=lambda k: wl.cams[k].width * wl.cams[k].height)
+    tile1, _ = r.autotune(params, [wl.cams[big]], Settings(sh_degree=3), [outs[big]], [dLs[big]],
+                          grads, iters=2)
+    st1 = Settings(sh_degree=3, tile=tile1)
+    res["tile_single"] = list(tile1)
 
-        def run():
-            if mode == "batched":
-                _step(r, params, grads, wl.cams, st, dLs)
-            else:
-                for g in grads:
-                    g.zero_()
-                for c, d in zip(wl.cams, dLs):
-                    r.forward(*params, [c], st)
-                    r.backward([d], *grads)
-        for _ in range(max(1, args.warmup // 2)):
-            run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.batched_steps):
-            run()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.batched_steps
-        res[mode] = nv / dt
-    del params, grads, dLs
+    def run():
+        for g in grads:
+            g.zero_()
+        for c, d in zip(wl.cams, dLs):
+            r.forward(*params, [c], st1)
+            r.backward([d], *grads)
+    for _ in range(max(1, args.warmup // 2)):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        run()
+    torch.cuda.synchronize()
+    res["single"] = nv / ((time.perf_counter() - t0) / args.batched_steps)
+    del params, grads, dLs, outs
     return res, wl
 
 
 def bench_xray(args, torch, dev):
-    """64 cone-beam projections of a 500k-Gaussian volume, fwd+bwd in one call."""
+    """64 cone-beam projections of a 500k-Gaussian volume, fwd+bwd of all views
+    in one call: autotuned tile, stage times from eager calls, throughput from
+    a captured hipGraph."""
     from paper_2412_03378_amd import Renderer, Settings, scenes
     _log("generating the 500k-Gaussian X-ray scene")
     wl = scenes.config4()
     params = _device_scene(wl.scene, dev, torch)
     dLs = [torch.from_numpy(d[0]).to(dev) for d in wl.dL]
     grads = [torch.zeros_like(p) for p in params[:4]] + [None]
-    st = Settings(mode="xray", tile=tuple(args.tile))
+    outs = [torch.empty((c.height, c.width), device=dev) for c in wl.cams]
     r = Renderer(0)
+    _log("autotuning the tile shape (X-ray)")
+    tile, tune_ms = r.autotune(params, wl.cams, Settings(mode="xray"), outs, dLs, grads, iters=1)
+    st = Settings(mode="xray", tile=tile)
     for _ in range(max(1, args.warmup // 2)):
         _step(r, params, grads, wl.cams, st, dLs)
     torch.cuda.synchronize()
@@ -195,18 +226,23 @@ def bench_xray(args, torch, dev):
     _step(r, params, grads, wl.cams, st, dLs)
     stats = r.stats()
     r.set_counting(False)
-    ppl = args.tile[0] * args.tile[1] / 64.0
+    _log("X-ray views, one captured graph")
+    r.graph_capture(params, wl.cams, st, outs, dLs, grads, capacity_factor=1.05, zero_grads=True)
+    dtg = _graph_time(r, args.batched_steps, torch)
+    ppl = tile[0] * tile[1] / 64.0
     fl = {"raster_fwd": _flops(stats["pairs_tested"], stats["pairs_full"], stats["pairs_blended"],
                                ppl, "xray", "fwd"),
           "raster_bwd": _flops(stats["bwd_pairs_tested"], stats["bwd_pairs_full"],
                                stats["bwd_pairs_blended"], ppl, "xray", "bwd")}
     out = {"workload": "X-ray: 64 cone-beam views 512x512, 500k Gaussians, fwd+bwd in one call",
-           "ms_per_step": round(dt * 1e3, 3), "views_per_s": round(len(wl.cams) / dt, 1),
+           "tile": list(tile), "autotune_ms": [round(x, 2) for x in tune_ms],
+           "ms_per_step": round(dtg * 1e3, 3), "views_per_s": round(len(wl.cams) / dtg, 1),
+           "eager_ms_per_step": round(dt * 1e3, 3),
            "instances": stats["instances"],
            "stages_ms": {k: round(v, 4) for k, v in stages.items()},
            "tflops": {k: round(v / (stages[k] * 1e-3) / 1e12, 2) for k, v in fl.items()
                       if stages.get(k)}}
-    del params, grads, dLs
+    del params, grads, dLs, outs
     return out
 
 
@@ -219,9 +255,14 @@ def bench_train(args, torch, dev, views_per_call=16):
     params = _device_scene(wl.scene, dev, torch)
     dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
     grads = [torch.zeros_like(p) for p in params]
-    st = Settings(sh_degree=3, tile=tuple(args.tile))
     r = Renderer(0)
     nv = len(wl.cams)
+    _log("autotuning the tile shape (training calls)")
+    outs = [torch.empty((3, c.height, c.width), device=dev) for c in wl.cams[:views_per_call]]
+    tile, _ = r.autotune(params, wl.cams[:views_per_call], Settings(sh_degree=3), outs,
+                         dLs[:views_per_call], grads, iters=1)
+    del outs
+    st = Settings(sh_degree=3, tile=tile)
 
     def step():
         for g in grads:
@@ -240,7 +281,7 @@ def bench_train(args, torch, dev, views_per_call=16):
     dt = (time.perf_counter() - t0) / args.train_steps
     out = {"workload": "training step: 6M Gaussians (1024 clusters), SH3, 64 views 1920x1080, "
                        "fwd+bwd accumulated into FP32 parameter gradients, 16 views per call",
-           "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1)}
+           "tile": list(tile), "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1)}
     del params, grads, dLs
     return out
 
@@ -370,6 +411,7 @@ def main():
         "config": {"workload": "single view 1920x1080, 1M clustered Gaussians (64 clusters), "
                                "SH degree 3, fwd+bwd, upstream N(0,1)",
                    "tile": list(args.tile), "instances": h["stats"]["instances"]},
+        "graph_ms_per_step": round(h["graph_ms"], 4),
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "pairs": {k: h["stats"][k] for k in ("pairs_tested", "pairs_full", "pairs_blended",
                                              "visits", "visits_full", "bwd_pairs_tested",
@@ -381,7 +423,10 @@ def main():
         torch.cuda.empty_cache()
         res, wl3 = bench_batched(args, torch, dev)
         out["batched"] = {"workload": "16 views mixed resolution (640x480..1920x1080), 3M "
-                                      "Gaussians, SH3, fwd+bwd",
+                                      "Gaussians, SH3, fwd+bwd; batched = one hipGraph "
+                                      "replay of all views, single = one call per view",
+                          "tile": res["tile"], "autotune_ms": res["autotune_ms"],
+                          "tile_single": res["tile_single"],
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3)}
