@@ -4,8 +4,8 @@ Headline workload: one 1920x1080 view of a 1M-Gaussian clustered scene with
 SH degree 3 (the single-view configuration of the paper's method at the scale
 of its scenes), inputs resident in HBM.  One step = vgr_render_forward +
 vgr_render_backward (preprocess, depth sort, binning, tile sort, ranges,
-rasteriser forward, rasteriser backward, preprocess backward) plus zeroing
-the parameter gradients.  Also reported: batched multi-view throughput (16
+rasteriser forward, rasteriser backward, preprocess backward), the backward
+writing the parameter gradients (no separate zeroing).  Also reported: batched multi-view throughput (16
 mixed-resolution views of a 3M-Gaussian scene in one call) against the same
 16 views rendered by separate single-view calls, and the FP64 oracle timed
 on a bounded pixel sample of the headline frame on the host cores.
@@ -78,11 +78,8 @@ def _device_scene(sc, dev, torch):
 
 
 def _step(r, params, grads, cams, st, dLs):
-    for g in grads:
-        if g is not None:
-            g.zero_()
     r.forward(*params, cams, st)
-    r.backward(dLs, *grads)
+    r.backward(dLs, *grads, accumulate=False)   # overwrites: no zeroing needed
 
 
 def _log(msg):
@@ -179,11 +176,9 @@ def bench_batched(args, torch, dev):
     res["tile_single"] = list(tile1)
 
     def run():
-        for g in grads:
-            g.zero_()
-        for c, d in zip(wl.cams, dLs):
+        for k, (c, d) in enumerate(zip(wl.cams, dLs)):
             r.forward(*params, [c], st1)
-            r.backward([d], *grads)
+            r.backward([d], *grads, accumulate=k > 0)
     for _ in range(max(1, args.warmup // 2)):
         run()
     torch.cuda.synchronize()
@@ -265,12 +260,10 @@ def bench_train(args, torch, dev, views_per_call=16):
     st = Settings(sh_degree=3, tile=tile)
 
     def step():
-        for g in grads:
-            g.zero_()
         for v0 in range(0, nv, views_per_call):
             cams = wl.cams[v0:v0 + views_per_call]
             r.forward(*params, cams, st)
-            r.backward(dLs[v0:v0 + views_per_call], *grads)
+            r.backward(dLs[v0:v0 + views_per_call], *grads, accumulate=v0 > 0)
 
     step()
     torch.cuda.synchronize()

@@ -157,15 +157,18 @@ int vgr_render_forward(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
                        const vgr_camera *cams, float *const *out);
 
 /* Backward of the last forward on this context: given dL/d(out) (host array
- * of n_views device pointers, same shapes as `out`), ADD the gradients to
- * d_means (n x 3), d_quats (n x 4), d_scales (n x 3), d_dens (n) and d_sh
- * (same shape as sh; may be NULL in XRAY mode).  Gradients flow through the
+ * of n_views device pointers, same shapes as `out`), the gradients with
+ * respect to d_means (n x 3), d_quats (n x 4), d_scales (n x 3), d_dens (n)
+ * and d_sh (same shape as sh; may be NULL in XRAY mode).  accumulate = 1:
+ * ADD them to the arrays; accumulate = 0: overwrite every element (the
+ * arrays are not read, so they need no zeroing).  Gradients flow through the
  * quaternion normalisation; clamped, skipped and unblended (Gaussian, pixel)
  * pairs contribute zero.  The parameter arrays given to the forward must
  * still hold the same values.  Errors: VGR_ERR_NO_FORWARD,
  * VGR_ERR_INVALID_ARG, VGR_ERR_HIP. */
 int vgr_render_backward(vgr_ctx *ctx, const float *const *dL_dout, float *d_means,
-                        float *d_quats, float *d_scales, float *d_dens, float *d_sh);
+                        float *d_quats, float *d_scales, float *d_dens, float *d_sh,
+                        int32_t accumulate);
 
 /* Per-pixel state of view `view` of the last forward, copied (on the
  * stream) into caller arrays of H x W: final transmittance T_final (may be
@@ -192,11 +195,12 @@ int vgr_set_counting(vgr_ctx *ctx, int enable);
 int vgr_set_timing(vgr_ctx *ctx, int enable);
 int vgr_get_timing(vgr_ctx *ctx, int32_t cap, const char **names, float *ms, int32_t *count);
 
-/* Capture one whole training step - optional zeroing of the parameter
- * gradients, the forward of all n_views views and the backward - into a HIP
- * graph, for callers that replay the same step (same pointers, sizes and
- * cameras; new values in the arrays) without per-call host work.  Arguments
- * are those of vgr_render_forward and vgr_render_backward together; the
+/* Capture one whole training step - the forward of all n_views views and the
+ * backward - into a HIP graph, for callers that replay the same step (same
+ * pointers, sizes and cameras; new values in the arrays) without per-call
+ * host work.  Arguments are those of vgr_render_forward and
+ * vgr_render_backward together; zero_grads = 1 makes the backward overwrite
+ * the gradient arrays (accumulate = 0), 0 makes it add to them.  The
  * pointers are recorded and must stay valid while the graph is used.
  * The call first runs the step once eagerly (its results are valid), then
  * captures with instance lists of capacity_factor (>= 1; default 1.25) times

@@ -67,7 +67,7 @@ _SIGNATURES = {
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int32, C.POINTER(vgr_camera), C.POINTER(C.c_void_p)]),
     "vgr_render_backward": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p,
-                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "vgr_get_aux": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "vgr_get_stats": (C.c_int, [C.c_void_p, C.POINTER(vgr_stats)]),
     "vgr_set_counting": (C.c_int, [C.c_void_p, C.c_int]),

@@ -552,7 +552,8 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
 int enqueue_backward(vgr_ctx *c, const RenderParams &rp, const Buffers &b_fwd,
                      const ViewInfo *views_dev, const float *means, const float *quats,
                      const float *scales, const float *dens, const float *sh, float *d_means,
-                     float *d_quats, float *d_scales, float *d_dens, float *d_sh, hipStream_t s)
+                     float *d_quats, float *d_scales, float *d_dens, float *d_sh, bool accumulate,
+                     hipStream_t s)
 {
     const int64_t m = rp.n * rp.n_views;
     if (m == 0) return VGR_OK;
@@ -569,7 +570,7 @@ int enqueue_backward(vgr_ctx *c, const RenderParams &rp, const Buffers &b_fwd,
     mark_end(c, ST_RASTER_BWD);
     mark(c, ST_PREPROCESS_BWD);
     HIP_TRY(c, launch_preprocess_bwd(rp, b, means, quats, scales, dens, sh, d_means, d_quats,
-                                     d_scales, d_dens, d_sh, s));
+                                     d_scales, d_dens, d_sh, accumulate, s));
     mark_end(c, ST_PREPROCESS_BWD);
     return VGR_OK;
 }
@@ -621,7 +622,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
 }
 
 int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, float *d_quats,
-                        float *d_scales, float *d_dens, float *d_sh)
+                        float *d_scales, float *d_dens, float *d_sh, int32_t accumulate)
 {
     if (!c) return VGR_ERR_INVALID_ARG;
     c->err.clear();
@@ -640,7 +641,8 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     if ((rc = upload_views(c, 1, c->vinfo))) return rc;
     if ((rc = timing_begin(c))) return rc;
     return enqueue_backward(c, rp, c->buf, ptr<ViewInfo>(c->views), c->means, c->quats, c->scales,
-                            c->dens, c->sh, d_means, d_quats, d_scales, d_dens, d_sh, c->stream);
+                            c->dens, c->sh, d_means, d_quats, d_scales, d_dens, d_sh,
+                            accumulate != 0, c->stream);
 }
 
 int vgr_get_aux(vgr_ctx *c, int32_t view, float *T_final, int32_t *last_index)
@@ -736,7 +738,7 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     c->timing = false;
     c->cur = nullptr;
     rc = vgr_render_forward(c, st, n, means, quats, scales, dens, sh, n_views, cams, out);
-    if (!rc) rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh);
+    if (!rc) rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh, zero_grads ? 0 : 1);
     c->counting = counting;
     c->timing = timing;
     if (rc) return rc;
@@ -775,20 +777,11 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     Buffers b;
     int64_t K;
     rc = VGR_OK;
-    if (zero_grads && n > 0) {
-        hipError_t e = launch_fill_f32(d_means, 0.f, 3 * n, s);
-        if (e == hipSuccess) e = launch_fill_f32(d_quats, 0.f, 4 * n, s);
-        if (e == hipSuccess) e = launch_fill_f32(d_scales, 0.f, 3 * n, s);
-        if (e == hipSuccess) e = launch_fill_f32(d_dens, 0.f, n, s);
-        if (e == hipSuccess && p.rp.mode == VGR_MODE_COLOR && d_sh)
-            e = launch_fill_f32(d_sh, 0.f, 3 * n * (p.rp.sh_degree + 1) * (p.rp.sh_degree + 1), s);
-        if (e != hipSuccess) rc = fail(c, VGR_ERR_HIP, "capture: %s", hipGetErrorString(e));
-    }
     const ViewInfo *vg = ptr<ViewInfo>(c->views_graph);
     if (!rc) rc = enqueue_forward(c, p, means, quats, scales, dens, sh, vg, cap, s, b, K);
     if (!rc)
         rc = enqueue_backward(c, p.rp, b, vg, means, quats, scales, dens, sh, d_means, d_quats,
-                              d_scales, d_dens, d_sh, s);
+                              d_scales, d_dens, d_sh, zero_grads == 0, s);
     c->counting = counting2;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -870,7 +863,7 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
             if (it == 1) (void)hipEventRecord(e0, c->stream);
             rc = vgr_render_forward(c, &s2, n, means, quats, scales, dens, sh, n_views, cams, out);
             if (!rc && dL)
-                rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh);
+                rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh, 1);
         }
         if (rc) break;
         (void)hipEventRecord(e1, c->stream);

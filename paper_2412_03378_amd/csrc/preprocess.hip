@@ -655,20 +655,31 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     RenderParams rp, Buffers b, const float *__restrict__ means, const float *__restrict__ quats,
     const float *__restrict__ scales, const float *__restrict__ dens, const float *__restrict__ sh,
     float *__restrict__ d_means, float *__restrict__ d_quats, float *__restrict__ d_scales,
-    float *__restrict__ d_dens, float *__restrict__ d_sh)
+    float *__restrict__ d_dens, float *__restrict__ d_sh, int acc)
 {
     constexpr int NB = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rp.n) return;
+    constexpr int NF = 3 * NB, LS = NF + 1;   // floats per Gaussian, LDS row stride
+    // The block's SH gradients leave through LDS, so that HBM sees whole
+    // lines written (a thread's own coefficients are NF floats apart from its
+    // neighbours'; scattered partial-line stores without a prior read of the
+    // lines are slow).
+    __shared__ float s_sh[128 * LS];
+    const int64_t blk0 = (int64_t)blockIdx.x * 128;
+    const int64_t i = blk0 + threadIdx.x;
+    const bool valid = i < rp.n;
+    const bool color = rp.mode == VGR_MODE_COLOR && sh != nullptr;   // uniform
+    // floats of the block's SH span that belong to real Gaussians
+    const int64_t nvalid = (rp.n - blk0 < 128 ? rp.n - blk0 : 128) * NF;
+    float gsh[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) gsh[k] = 0.f;
+    bool any = false;
+    if (valid) {
     const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
     const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
     float gmu[3] = { 0.f, 0.f, 0.f }, gth[3] = { 0.f, 0.f, 0.f }, gs[3] = { 0.f, 0.f, 0.f };
     float gk = 0.f;
-    float gsh[NB * 3];
-#pragma unroll
-    for (int k = 0; k < NB * 3; ++k) gsh[k] = 0.f;
-    bool any = false;
     float qn[4] = { 0.f, 0.f, 0.f, 0.f }, qlen = 1.f;
     for (int v = 0; v < rp.n_views; ++v) {
         const int64_t item = (int64_t)v * rp.n + i;
@@ -713,7 +724,7 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
             float3 G[16];
             sh_basis(DEG, vx, vy, vz, Y);
             sh_basis_grad(DEG, vx, vy, vz, G);
-            const float *c3 = sh + i * NB * 3;
+            const float *c3 = sh + i * NF;
             float gv[3] = { 0.f, 0.f, 0.f };
             for (int ch = 0; ch < 3; ++ch) {
                 float raw = 0.5f;
@@ -735,23 +746,89 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
             gmu[2] += (gv[2] - vz * vg) * il;
         }
     }
-    if (!any) return;
-    for (int j = 0; j < 3; ++j) d_means[3 * i + j] += gmu[j];
+    // acc: add to the caller's arrays; otherwise overwrite them (no read)
+    auto put = [acc](float *p, float v) {
+        if (acc) *p += v;
+        else *p = v;
+    };
+    if (!any) {
+        if (!acc) {   // nothing reached this Gaussian: its gradients are zero
+            for (int j = 0; j < 3; ++j) d_means[3 * i + j] = 0.f;
+            for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = 0.f;
+            for (int j = 0; j < 3; ++j) d_scales[3 * i + j] = 0.f;
+            d_dens[i] = 0.f;
+        }
+    } else {
+    for (int j = 0; j < 3; ++j) put(d_means + 3 * i + j, gmu[j]);
     // body-frame rotation gradient -> quaternion: q -> q (x) (1, dtheta/2), so
     // dL/dq = 2 q (x) (0, dL/dtheta) / |q| (already orthogonal to q)
     {
         const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
         const float c = 2.0f / qlen;
-        d_quats[4 * i + 0] += c * -(x * gth[0] + y * gth[1] + z * gth[2]);
-        d_quats[4 * i + 1] += c * (w * gth[0] + y * gth[2] - z * gth[1]);
-        d_quats[4 * i + 2] += c * (w * gth[1] + z * gth[0] - x * gth[2]);
-        d_quats[4 * i + 3] += c * (w * gth[2] + x * gth[1] - y * gth[0]);
+        put(d_quats + 4 * i + 0, c * -(x * gth[0] + y * gth[1] + z * gth[2]));
+        put(d_quats + 4 * i + 1, c * (w * gth[0] + y * gth[2] - z * gth[1]));
+        put(d_quats + 4 * i + 2, c * (w * gth[1] + z * gth[0] - x * gth[2]));
+        put(d_quats + 4 * i + 3, c * (w * gth[2] + x * gth[1] - y * gth[0]));
     }
-    for (int k = 0; k < 3; ++k) d_scales[3 * i + k] += gs[k];
-    d_dens[i] += gk / dens[i];
-    if (rp.mode == VGR_MODE_COLOR && d_sh) {
+    for (int k = 0; k < 3; ++k) put(d_scales + 3 * i + k, gs[k]);
+    put(d_dens + i, gk / dens[i]);
+    }
+    }   // valid
+    if (color && d_sh) {
 #pragma unroll
-        for (int k = 0; k < NB * 3; ++k) d_sh[i * NB * 3 + k] += gsh[k];
+        for (int k = 0; k < NF; ++k) s_sh[threadIdx.x * LS + k] = gsh[k];
+        __syncthreads();
+        float4 o4[NF / 4 > 0 ? NF / 4 : 1];
+#pragma unroll
+        for (int r = 0; r < NF / 4; ++r) {
+            const int e = 4 * (r * 128 + threadIdx.x);
+            float f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int g = (e + c) / NF;
+                f[c] = s_sh[g * LS + (e + c - g * NF)];
+            }
+            o4[r] = make_float4(f[0], f[1], f[2], f[3]);
+        }
+        if (acc) {   // uniform: add the caller's values, all loads in flight first
+            float4 a4[NF / 4 > 0 ? NF / 4 : 1];
+#pragma unroll
+            for (int r = 0; r < NF / 4; ++r) {
+                const int64_t e = 4 * ((int64_t)r * 128 + threadIdx.x);
+                a4[r] = e + 3 < nvalid ? *reinterpret_cast<const float4 *>(d_sh + blk0 * NF + e)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (e + 3 >= nvalid) {
+                    if (e < nvalid) a4[r].x = d_sh[blk0 * NF + e];
+                    if (e + 1 < nvalid) a4[r].y = d_sh[blk0 * NF + e + 1];
+                    if (e + 2 < nvalid) a4[r].z = d_sh[blk0 * NF + e + 2];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NF / 4; ++r) {
+                o4[r].x += a4[r].x; o4[r].y += a4[r].y; o4[r].z += a4[r].z; o4[r].w += a4[r].w;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NF / 4; ++r) {
+            const int64_t e = 4 * ((int64_t)r * 128 + threadIdx.x);
+            float *dst = d_sh + blk0 * NF + e;
+            if (e + 3 < nvalid) {
+                *reinterpret_cast<float4 *>(dst) = o4[r];
+            } else {
+                if (e < nvalid) dst[0] = o4[r].x;
+                if (e + 1 < nvalid) dst[1] = o4[r].y;
+                if (e + 2 < nvalid) dst[2] = o4[r].z;
+            }
+        }
+        for (int e = 4 * (NF / 4) * 128 + threadIdx.x; e < 128 * NF; e += 128) {
+            if (e < nvalid) {
+                const int g = e / NF;
+                float *p = d_sh + blk0 * NF + e;
+                const float v = s_sh[g * LS + (e - g * NF)];
+                if (acc) *p += v;
+                else *p = v;
+            }
+        }
     }
 }
 
@@ -851,14 +928,15 @@ hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *so
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
                                  const float *quats, const float *scales, const float *dens,
                                  const float *sh, float *d_means, float *d_quats,
-                                 float *d_scales, float *d_dens, float *d_sh, hipStream_t s)
+                                 float *d_scales, float *d_dens, float *d_sh, bool accumulate,
+                                 hipStream_t s)
 {
     const unsigned g = grid_for(rp.n, 128);
     switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
-    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
-    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
-    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
-    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh); break;
+    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
+    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
+    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
+    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
     }
     return hipGetLastError();
 }

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t *__r
 
 // ---------------------------------------------------------------- radix ---
 
+template <int IPT>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                               const uint32_t *__restrict__ d_n,
                                                               int shift, uint32_t mask,
@@ -147,10 +148,10 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__
     for (int k = 0; k < kWaves; ++k) h[k][threadIdx.x] = 0;
     __syncthreads();
     const int64_t n = *d_n;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * IPT);
     if (base < n) {
 #pragma unroll 4
-        for (int i = 0; i < kItems; ++i) {
+        for (int i = 0; i < IPT; ++i) {
             int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
             if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
         }
@@ -192,6 +193,7 @@ __global__ __launch_bounds__(kThreads) void radix_rowscan_kernel(uint32_t *__res
     if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
+template <int IPT>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
@@ -200,11 +202,12 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
 {
     __shared__ uint32_t cnt[kWaves][256];
     __shared__ uint32_t gdelta[256];   // global start minus block-local start
-    __shared__ uint32_t sk[kTile], sv[kTile];
+    constexpr int TILE = kThreads * IPT;
+    __shared__ uint32_t sk[TILE], sv[TILE];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t mask = (1u << dbits) - 1u;
     const int64_t n = *d_n;
-    const int64_t blk_base = (int64_t)blockIdx.x * kTile;
+    const int64_t blk_base = (int64_t)blockIdx.x * TILE;
     if (blk_base >= n) return;   // uniform across the block
     // start of each digit = exclusive scan of the digit totals
     uint32_t tot_all;
@@ -213,18 +216,18 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     for (int k = 0; k < kWaves; ++k) cnt[k][threadIdx.x] = 0;
     __syncthreads();
 
-    const int64_t wbase = blk_base + (int64_t)w * (kTile / kWaves);
+    const int64_t wbase = blk_base + (int64_t)w * (TILE / kWaves);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t k[kItems], v[kItems], r[kItems];
+    uint32_t k[IPT], v[IPT], r[IPT];
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         int64_t idx = wbase + i * 64 + lane;
         bool valid = idx < n;
         k[i] = valid ? keys[idx] : 0u;
         v[i] = valid ? vals[idx] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         int64_t idx = wbase + i * 64 + lane;
         bool valid = idx < n;
         uint32_t d = (k[i] >> shift) & mask;
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __syncthreads();
     // reorder the tile by digit in LDS ...
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
+    for (int i = 0; i < IPT; ++i) {
         int64_t idx = wbase + i * 64 + lane;
         if (idx < n) {
             uint32_t d = (k[i] >> shift) & mask;
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __syncthreads();
     // ... and write it out in order: consecutive threads write consecutive
     // positions of the same digit run
-    const int64_t cnt_blk = min((int64_t)kTile, n - blk_base);
+    const int64_t cnt_blk = min((int64_t)TILE, n - blk_base);
     for (int e = threadIdx.x; e < cnt_blk; e += kThreads) {
         const uint32_t key = sk[e];
         const uint32_t d = (key >> shift) & mask;
@@ -319,10 +322,20 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
     return hipGetLastError();
 }
 
+// Keys per thread of a radix pass: 4 (1024-key tiles) below 4M keys, so that
+// smaller sorts still spread over all CUs, else 16 (4096-key tiles).
+constexpr int64_t kSmallSort = 1 << 22;
+
+inline int64_t radix_blocks(int64_t n, int ipt) { return (n + kThreads * ipt - 1) / (kThreads * ipt); }
+
+// Enough for a sort of any n <= n_bound (a smaller sort may use the smaller
+// tiles and so more blocks).
 int64_t radix_tmp_words(int64_t n_bound)
 {
-    const int64_t nb = blocks_for(n_bound > 0 ? n_bound : 1);
-    return 256 * nb + 256;
+    const int64_t n = n_bound > 0 ? n_bound : 1;
+    const int64_t nb_own = radix_blocks(n, n <= kSmallSort ? 4 : kItems);
+    const int64_t nb_small = radix_blocks(n < kSmallSort ? n : kSmallSort, 4);
+    return 256 * (nb_own > nb_small ? nb_own : nb_small) + 256;
 }
 
 hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2,
@@ -330,7 +343,8 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
                              hipStream_t s)
 {
     if (n_bound <= 0 || bits <= 0) return hipSuccess;
-    const int64_t nb = blocks_for(n_bound);
+    const bool small = n_bound <= kSmallSort;
+    const int64_t nb = radix_blocks(n_bound, small ? 4 : kItems);
     const int64_t table = 256 * nb;
     uint32_t *hist = tmp;            // digit-major per-block counts, then their row scans
     uint32_t *tot = tmp + table;     // per-digit totals
@@ -341,15 +355,20 @@ hipError_t launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, ui
     for (int p = 0; p < passes; ++p) {
         const int dbits = (bits - shift + (passes - p) - 1) / (passes - p);
         const uint32_t mask = (1u << dbits) - 1u;
-        radix_hist_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(ki, d_n, shift, mask, hist,
-                                                                        (int)nb);
+        const dim3 g((unsigned)nb), t(kThreads);
+        if (small) radix_hist_kernel<4><<<g, t, 0, s>>>(ki, d_n, shift, mask, hist, (int)nb);
+        else radix_hist_kernel<kItems><<<g, t, 0, s>>>(ki, d_n, shift, mask, hist, (int)nb);
         radix_rowscan_kernel<<<256, kThreads, 0, s>>>(hist, (int)nb, tot);
-        radix_scatter_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(
-            ki, vi, ko, vo, d_n, shift, dbits, hist, tot, (int)nb);
+        if (small)
+            radix_scatter_kernel<4><<<g, t, 0, s>>>(ki, vi, ko, vo, d_n, shift, dbits, hist, tot,
+                                                     (int)nb);
+        else
+            radix_scatter_kernel<kItems><<<g, t, 0, s>>>(ki, vi, ko, vo, d_n, shift, dbits, hist,
+                                                          tot, (int)nb);
         shift += dbits;
-        uint32_t *t;
-        t = ki; ki = ko; ko = t;
-        t = vi; vi = vo; vo = t;
+        uint32_t *tt;
+        tt = ki; ki = ko; ko = tt;
+        tt = vi; vi = vo; vo = tt;
     }
     if (ki != keys) {
         const int64_t grid = (n_bound + 255) / 256 < 65536 ? (n_bound + 255) / 256 : 65536;

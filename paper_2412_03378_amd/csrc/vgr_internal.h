@@ -144,10 +144,12 @@ hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool coun
                              hipStream_t s);
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
+// accumulate: add to the gradient arrays; otherwise overwrite every element.
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
                                  const float *quats, const float *scales, const float *dens,
                                  const float *sh, float *d_means, float *d_quats,
-                                 float *d_scales, float *d_dens, float *d_sh, hipStream_t s);
+                                 float *d_scales, float *d_dens, float *d_sh, bool accumulate,
+                                 hipStream_t s);
 
 // Exclusive scan of n u32 values (n host-known), out may alias nothing;
 // out[n] receives the total when write_total.  tmp: scan_tmp_words(n) u32.

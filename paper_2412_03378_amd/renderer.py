@@ -123,14 +123,16 @@ class Renderer:
         self.mode = settings.mode
         return outs
 
-    def backward(self, dL: Sequence[torch.Tensor], d_means, d_quats, d_scales, d_dens, d_sh):
-        """Add the gradients of the last forward to the given tensors."""
+    def backward(self, dL: Sequence[torch.Tensor], d_means, d_quats, d_scales, d_dens, d_sh,
+                 accumulate: bool = True):
+        """Gradients of the last forward: added to the given tensors, or written
+        over them (no zeroing needed) when accumulate is False."""
         self._sync_stream()
         dLc = [g.contiguous().float() for g in dL]
         ptrs = (C.c_void_p * len(dLc))(*[g.data_ptr() for g in dLc])
         rc = self._lib.vgr_render_backward(self._h, ptrs, _dev_ptr(d_means), _dev_ptr(d_quats),
                                            _dev_ptr(d_scales), _dev_ptr(d_dens),
-                                           _dev_ptr(d_sh))
+                                           _dev_ptr(d_sh), int(bool(accumulate)))
         L.check(rc, self._h)
 
     def aux(self, view: int, height: int, width: int, device=None):
@@ -182,7 +184,9 @@ class Renderer:
     def graph_capture(self, params, cams, settings, outs, dL, grads, capacity_factor=1.25,
                       zero_grads=True):
         """Capture forward + backward of these exact tensors into a HIP graph
-        (see vgr_graph_capture).  The tensors must stay alive and in place."""
+        (see vgr_graph_capture; zero_grads: the backward overwrites the
+        gradients instead of adding to them).  The tensors must stay alive and
+        in place."""
         self._sync_stream()
         keep, args = self._step_args(params, cams, settings, outs, dL, grads)
         self._graph_keep = (keep, params, outs, dL, grads)
@@ -230,14 +234,14 @@ class _VolRender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *gouts):
         means, quats, scales, dens, sh = ctx.saved_tensors
-        gm = torch.zeros_like(means)
-        gq = torch.zeros_like(quats)
-        gs = torch.zeros_like(scales)
-        gd = torch.zeros_like(dens)
-        gsh = torch.zeros_like(sh) if ctx.has_sh else None
+        gm = torch.empty_like(means)
+        gq = torch.empty_like(quats)
+        gs = torch.empty_like(scales)
+        gd = torch.empty_like(dens)
+        gsh = torch.empty_like(sh) if ctx.has_sh else None
         gl = [g if g is not None else torch.zeros(s, device=means.device)
               for g, s in zip(gouts, ctx.renderer.shapes)]
-        ctx.renderer.backward(gl, gm, gq, gs, gd, gsh)
+        ctx.renderer.backward(gl, gm, gq, gs, gd, gsh, accumulate=False)
         return None, None, None, gm, gq, gs, gd, gsh
 
 

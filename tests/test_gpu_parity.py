@@ -44,7 +44,8 @@ def _oset(st):
 @pytest.mark.parametrize("n,bits,kind", [
     (1, 8, "random"), (4095, 13, "random"), (4096, 13, "random"), (100003, 13, "random"),
     (262144, 32, "random"), (50000, 20, "equal"), (70001, 16, "sorted"),
-    (70001, 16, "reversed"), (33333, 32, "max"), (65536, 7, "random"), (0, 8, "random")])
+    (70001, 16, "reversed"), (33333, 32, "max"), (65536, 7, "random"), (0, 8, "random"),
+    (4194304, 15, "random"), (4194305, 15, "random")])
 def test_radix_sort_stable(R, dev, n, bits, kind):
     rng = np.random.default_rng(n + bits)
     hi = (1 << bits) - 1
@@ -194,6 +195,33 @@ def test_batched_equals_single(R, dev):
     for v, cam in enumerate(cams):
         one = R.forward(*t, [cam], st)[0].cpu().numpy()
         assert np.array_equal(one, many[v])
+
+
+def test_backward_overwrite_equals_accumulate_into_zeros(R, dev, cfg1):
+    """accumulate=False writes every gradient element (stale values in the
+    arrays do not leak through, Gaussians nothing reached get 0) and equals
+    accumulating into zeroed arrays; accumulating twice doubles."""
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    st = _settings(act="softplus", tile=(8, 8))
+    t = G.device_scene(sc, dev)
+    rng = np.random.default_rng(17)
+    dL = torch.from_numpy(rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)).to(dev)
+    R.forward(*t, [cam], st)
+    acc = [torch.zeros_like(x) for x in t]
+    R.backward([dL], *acc)
+    over = [torch.full_like(x, 7.0) for x in t]
+    R.backward([dL], *over, accumulate=False)
+    twice = [x.clone() for x in acc]
+    R.backward([dL], *twice)
+    torch.cuda.synchronize()
+    for a, o, w in zip(acc, over, twice):
+        a, o, w = a.cpu().numpy(), o.cpu().numpy(), w.cpu().numpy()
+        scale = np.abs(a).max() + 1e-30
+        # record gradients are summed with FP32 atomics: equal up to their order
+        assert np.abs(o - a).max() <= 1e-5 * scale
+        assert np.abs(w - 2 * a).max() <= 2e-5 * scale
+    untouched = np.all(acc[0].cpu().numpy() == 0, axis=1)
+    assert np.all(over[0].cpu().numpy()[untouched] == 0)
 
 
 def test_empty_and_degenerate(R, dev):
