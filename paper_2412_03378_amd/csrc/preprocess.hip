@@ -18,6 +18,10 @@
 // tangent lines x = const give the exact screen bounding box used for binning
 // (a conservative replacement of the 3-sigma screen-space heuristic that the
 // paper notes should be adjusted for this rendering model, Sec. 8, future work).
+// A second pass replaces s_max by an upper bound of beta over the rays of that
+// box (see beta_bound), which shrinks the box of anisotropic Gaussians seen
+// along a short axis; the bound pre-test and the tile culling use the same
+// D2max.
 #include "vgr_internal.h"
 
 namespace vgr {
@@ -183,6 +187,63 @@ __device__ inline void pixel_span(bool ok, float lo, float hi, float f, float c,
     p1 = min(p1, size - 1);
 }
 
+// Pixel box of the ellipsoid {(x-m)^T Sigma^-1 (x-m) <= D2} (all rays that
+// pass within Mahalanobis distance sqrt(D2) of the mean).
+__device__ inline void screen_box(const GaussView &g, const float *s2, float D2,
+                                  const ViewInfo &vi, int &x0, int &x1, int &y0, int &y1)
+{
+    // S = D2 Sigma_view, Sigma_view = Rc diag(s^2) Rc^T
+    float S[9];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            S[a * 3 + c] = D2 * (g.Rc[a * 3] * g.Rc[c * 3] * s2[0] +
+                                 g.Rc[a * 3 + 1] * g.Rc[c * 3 + 1] * s2[1] +
+                                 g.Rc[a * 3 + 2] * g.Rc[c * 3 + 2] * s2[2]);
+    // 2x2 minors (rows a and 2) by Cauchy-Binet, free of cancellation
+    float minor[2];
+    for (int a = 0; a < 2; ++a) {
+        float acc = 0.0f;
+        for (int k = 0; k < 3; ++k)
+            for (int l = k + 1; l < 3; ++l) {
+                const float det = g.Rc[a * 3 + k] * g.Rc[6 + l] - g.Rc[a * 3 + l] * g.Rc[6 + k];
+                acc += s2[k] * s2[l] * det * det;
+            }
+        minor[a] = D2 * D2 * acc;
+    }
+    float lo, hi;
+    const bool okx = axis_extent(S[0], S[2], S[8], minor[0], g.m[0], g.m[2], lo, hi);
+    pixel_span(okx, lo, hi, vi.fx, vi.cx, vi.width, x0, x1);
+    const bool oky = axis_extent(S[4], S[5], S[8], minor[1], g.m[1], g.m[2], lo, hi);
+    pixel_span(oky, lo, hi, vi.fy, vi.cy, vi.height, y0, y1);
+}
+
+// Upper bound of beta = 1 / |L u| (u unit) over the rays through the pixel box
+// [x0, x1 + 1] x [y0, y1 + 1]: with u_c the direction of the mean,
+// |L u| >= |L u_c| - |u - u_c| / s_min (the largest singular value of L is
+// 1 / s_min), and the chord |u - u_c| over the box is largest at a corner (the
+// angle to u_c is quasi-convex on the image plane).  Returns smax when the
+// bound is not smaller.
+__device__ inline float beta_bound(const GaussView &g, const float *s, float smax,
+                                   const ViewInfo &vi, int x0, int x1, int y0, int y1)
+{
+    const float mlen = sqrtf(g.m[0] * g.m[0] + g.m[1] * g.m[1] + g.m[2] * g.m[2]);
+    const float im = 1.0f / mlen;
+    const float c0 = g.m[0] * im, c1 = g.m[1] * im, c2 = g.m[2] * im;
+    float chord = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+        const float X = (float)((k & 1) ? x1 + 1 : x0), Y = (float)((k & 2) ? y1 + 1 : y0);
+        const float u0 = (X - vi.cx) / vi.fx, u1 = (Y - vi.cy) / vi.fy;
+        const float il = 1.0f / sqrtf(u0 * u0 + u1 * u1 + 1.0f);
+        const float d0 = u0 * il - c0, d1 = u1 * il - c1, d2 = il - c2;
+        chord = fmaxf(chord, sqrtf(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    const float smin = fminf(s[0], fminf(s[1], s[2]));
+    const float lu = sqrtf(g.p[0] * g.p[0] + g.p[1] * g.p[1] + g.p[2] * g.p[2]) * im;
+    const float den = lu - chord / smin;
+    if (!(den > 0.0f)) return smax;
+    return fminf(smax, 1.0001f / den);   // small slack for FP32 rounding
+}
+
 // Tile culling.  The bound pre-test rejects a pixel when f(d) > kConicMargin;
 // a tile of the Gaussian's rectangle is emitted only if the larger ellipse
 // {f <= kCullLevel} meets the pixel-centre span of the tile, so that every
@@ -252,32 +313,25 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     if (valid && z > vi.znear && K * smax > rp.tau) {
         GaussView g;
         gauss_view(vi, mu, q, s, g);
-        const float D2max = 2.0f * logf(K * smax / rp.tau);
-        // S = D2max Sigma_view, Sigma_view = Rc diag(s^2) Rc^T
+        // alpha >= alpha_min needs D^2 <= 2 ln(K beta / tau) with beta the
+        // ray's standard deviation; beta <= smax gives a first box ...
+        float D2max = 2.0f * logf(K * smax / rp.tau);
         const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
-        float S[9];
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c)
-                S[a * 3 + c] = D2max * (g.Rc[a * 3] * g.Rc[c * 3] * s2[0] +
-                                        g.Rc[a * 3 + 1] * g.Rc[c * 3 + 1] * s2[1] +
-                                        g.Rc[a * 3 + 2] * g.Rc[c * 3 + 2] * s2[2]);
-        // 2x2 minors (rows a and 2) by Cauchy-Binet, free of cancellation
-        float minor[2];
-        for (int a = 0; a < 2; ++a) {
-            float acc = 0.0f;
-            for (int k = 0; k < 3; ++k)
-                for (int l = k + 1; l < 3; ++l) {
-                    const float det = g.Rc[a * 3 + k] * g.Rc[6 + l] - g.Rc[a * 3 + l] * g.Rc[6 + k];
-                    acc += s2[k] * s2[l] * det * det;
-                }
-            minor[a] = D2max * D2max * acc;
-        }
-        float lo, hi;
         int x0, x1, y0, y1;
-        bool okx = axis_extent(S[0], S[2], S[8], minor[0], g.m[0], g.m[2], lo, hi);
-        pixel_span(okx, lo, hi, vi.fx, vi.cx, vi.width, x0, x1);
-        bool oky = axis_extent(S[4], S[5], S[8], minor[1], g.m[1], g.m[2], lo, hi);
-        pixel_span(oky, lo, hi, vi.fy, vi.cy, vi.height, y0, y1);
+        screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
+        // ... and beta over the rays of that box bounds it tighter (tight for
+        // anisotropic Gaussians seen along a short axis)
+        if (x0 <= x1 && y0 <= y1) {
+            const float beta = beta_bound(g, s, smax, vi, x0, x1, y0, y1);
+            if (beta < smax) {
+                if (K * beta > rp.tau) {
+                    D2max = 2.0f * logf(K * beta / rp.tau);
+                    screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
+                } else {
+                    x1 = x0 - 1;   // alpha < alpha_min on every ray of the box
+                }
+            }
+        }
         if (x0 <= x1 && y0 <= y1) {
             const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
             const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;

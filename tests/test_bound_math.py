@@ -146,3 +146,59 @@ def test_culling_row_interval_is_the_strip_extent(seed):
         assert X[inside].min() >= iv[0] - 1e-9 and X[inside].max() <= iv[1] + 1e-9
         assert X[inside].min() <= iv[0] + 2 * step + 0.05 * ext / 60
         assert X[inside].max() >= iv[1] - 2 * step - 0.05 * ext / 60
+
+
+def _beta_bound(cam, m, Rc, s, box):
+    """Upper bound of beta = 1/|L u| over the rays of the pixel box, written
+    from the derivation: |L u| >= |L u_c| - |u - u_c| / s_min, with the chord
+    |u - u_c| largest at a corner of the box."""
+    L = (Rc / s[None, :]).T
+    uc = m / np.linalg.norm(m)
+    chord = 0.0
+    for X in (box[0], box[1]):
+        for Y in (box[2], box[3]):
+            u = np.array([(X - cam.cx) / cam.fx, (Y - cam.cy) / cam.fy, 1.0])
+            chord = max(chord, np.linalg.norm(u / np.linalg.norm(u) - uc))
+    den = np.linalg.norm(L @ uc) - chord / s.min()
+    return s.max() if den <= 0 else min(s.max(), 1.0 / den)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_beta_bound_contains_every_visible_pixel(seed):
+    """The tighter bound D2max = 2 ln(kappa sqrt(2 pi) beta_bound / tau) still
+    contains every pixel where the oracle finds x >= tau, beta_bound is never
+    above s_max, and it is strictly below it for a Gaussian seen along its
+    short axis."""
+    rng = np.random.default_rng(300 + seed)
+    cam = scenes.look_at([0.2, -0.3, -3.0], (0, 0, 0), 64, 48, 45.0)
+    tau = -math.log1p(-1.0 / 255.0)
+    tighter = 0
+    for _ in range(25):
+        mu = np.float32(rng.uniform(-0.4, 0.4, 3))
+        q = np.float32(rng.standard_normal(4))
+        s = np.float32(np.exp(rng.uniform(np.log(0.01), np.log(0.12), 3)))
+        kappa = float(np.float32(np.exp(rng.uniform(np.log(0.5), np.log(40)))))
+        m, Rc, s64 = _view(cam, mu, q, s)
+        Kk = kappa * math.sqrt(2 * math.pi)
+        if Kk * s64.max() <= tau:
+            continue
+        box = _bbox(cam, m, Rc, s64, 2 * math.log(Kk * s64.max() / tau))
+        if box is None:
+            continue
+        beta = _beta_bound(cam, m, Rc, s64, box)
+        assert beta <= s64.max() * (1 + 1e-12)
+        tighter += beta < 0.9 * s64.max()
+        sc = H.scene([mu], [s], kappa, quats=[q])
+        x = -np.log(oracle.render(sc, cam, oracle.Settings.no_thresholds())["T"])
+        ys, xs = np.nonzero(x >= tau)
+        if not len(xs):
+            continue
+        L = (Rc / s64[None, :]).T
+        pm = L @ m
+        for px, py in zip(xs, ys):
+            u = np.array([(px + 0.5 - cam.cx) / cam.fx, (py + 0.5 - cam.cy) / cam.fy, 1.0])
+            w = L @ u
+            D2 = np.sum(np.cross(pm, w) ** 2) / (w @ w)
+            assert Kk * beta > tau
+            assert D2 <= 2 * math.log(Kk * beta / tau) + 1e-9
+    assert tighter > 0
