@@ -76,6 +76,42 @@ __device__ __forceinline__ FullRec load_full(const Stage &st, int q)
     return r;
 }
 
+// One staged record in registers, read at a per-lane index.
+struct RecRegs {
+    float4 g[kStageVec];
+};
+
+__device__ __forceinline__ RecRegs load_regs(const Stage &st, int q)
+{
+    RecRegs r;
+#pragma unroll
+    for (int v = 0; v < kStageVec; ++v) r.g[v] = st.g[v][q];
+    return r;
+}
+
+__device__ __forceinline__ PreRec pre_of4(const float4 &a, const float4 &b, const float4 &c)
+{
+    PreRec r;
+    r.hx = a.x; r.hy = a.y; r.lx = a.z; r.ly = a.w;
+    r.Q00 = b.x; r.Q01x2 = b.y; r.l0x2 = b.z; r.l1x2 = b.w;
+    r.Q11 = c.x; r.A00 = c.y; r.A10 = c.z; r.A20 = c.w;
+    return r;
+}
+
+__device__ __forceinline__ PreRec pre_of(const RecRegs &x)
+{
+    return pre_of4(x.g[0], x.g[1], x.g[2]);
+}
+
+__device__ __forceinline__ FullRec full_of(const RecRegs &x)
+{
+    FullRec r;
+    r.A01 = x.g[3].x; r.A11 = x.g[3].y; r.A21 = x.g[3].z; r.v0x = x.g[3].w;
+    r.v0y = x.g[4].x; r.v0z = x.g[4].y; r.K = x.g[4].z; r.se = x.g[4].w;
+    r.c0 = x.g[5].x; r.c1 = x.g[5].y; r.c2 = x.g[5].z; r.mz = x.g[5].w;
+    return r;
+}
+
 __device__ __forceinline__ void stage_record(Stage &st, const Buffers &b, int lane, uint32_t item)
 {
     const float4 *gp = b.geom + (size_t)item * kRecVec;
@@ -194,42 +230,54 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         if (j < range.y) stage_record(st, b, lane, b.inst_val[j]);
         __syncthreads();
         const int nb = (int)min(64u, range.y - bs);
-        bool alive = true;
-        for (int qi = 0; qi < nb; ++qi) {
-            if (COLOR) {
-                bool any = false;
+        // Phase 1: bound pre-test of the whole batch (broadcast records);
+        // bit q of mask[k] marks record q as passing for the lane's slot k.
+        uint64_t mask[PPL];
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) any |= act[k];
-                if (!__any(any)) {
-                    alive = false;
-                    break;
-                }
-            }
-            const PreRec pr = load_pre(st, qi);
+        for (int k = 0; k < PPL; ++k) mask[k] = 0;
+        for (int qi = 0; qi < nb; ++qi) {
+            const float4 g0 = st.g[0][qi], g1 = st.g[1][qi], g2 = st.g[2][qi];
+            const PreRec pr = pre_of4(g0, g1, g2);
             const ColTerms ct = col_terms(pr, pxc);
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 float dy;
-                const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
-                const bool pass = act[k] && near;
-                const bool anyp = __any(pass);
+                const bool pass = act[k] && pre_test(pr, ct, pyc[k], dy);
+                mask[k] |= (uint64_t)(pass ? 1u : 0u) << qi;
                 if (COUNT) {
                     n.test += act[k] ? 1u : 0u;
                     const bool anyl = __any(act[k]);
                     n.visits += (lane == 0 && anyl) ? 1u : 0u;
-                    n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
                 }
-                if (!anyp) continue;                  // wave-uniform
-                if (COUNT) n.full += pass ? 1u : 0u;
-                const FullRec fr = load_full(st, qi);
+            }
+        }
+        // Phase 2: every lane evaluates and blends its own passing records in
+        // list order, one per step (records read from LDS at per-lane
+        // addresses), so a step does useful work on every lane that still has
+        // a record left instead of only on those that pass one shared record.
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            uint64_t mk = mask[k];
+            while (__any(mk != 0 && act[k])) {           // wave-uniform loop
+                const bool has = mk != 0 && act[k];
+                const int qi = has ? (int)__builtin_ctzll(mk) : 0;
+                mk &= mk - 1;
+                if (COUNT) {
+                    n.full += has ? 1u : 0u;
+                    n.visits_full += lane == 0 ? 1u : 0u;
+                }
+                const RecRegs rr = load_regs(st, qi);
+                const PreRec pr = pre_of(rr);
+                const FullRec fr = full_of(rr);
+                const float dx = (pxc - pr.hx) - pr.lx;
+                const float dy = (pyc[k] - pr.hy) - pr.ly;
                 PairGeom g;
-                pair_geom(pr, fr, ct.dx, dy, g);
+                pair_geom(pr, fr, dx, dy, g);
                 const float rq = fast_rsq(g.qw);
                 const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
                 const float y = fr.K * un[k] * rq * ex;
-                const bool bl = pass && !(y < tau2);
+                const bool bl = has && !(y < tau2);
                 if constexpr (COLOR) {
-                    if (!__any(bl)) continue;            // wave-uniform
                     const float om = fast_exp2(-fminf(y, ymax));
                     const float Tn = T[k] * om;
                     const bool stop = bl && Tn < Tmin;
@@ -250,7 +298,12 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
             }
         }
         __syncthreads();
-        if (!alive) break;
+        if (COLOR) {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) any |= act[k];
+            if (!__any(any)) break;                    // every pixel has stopped
+        }
     }
 
     const int64_t HW = (int64_t)W * H;
