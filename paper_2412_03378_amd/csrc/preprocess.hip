@@ -164,8 +164,10 @@ __device__ inline bool axis_extent(float Saa, float Sa2, float S22, float minor,
     float disc = Saa * mz * mz - 2.0f * Sa2 * ma * mz + S22 * ma * ma - minor;
     disc = fmaxf(disc, 0.0f);
     const float sq = sqrtf(disc);
-    lo = (B - sq) / A;
-    hi = (B + sq) / A;
+    // a 1-ulp reciprocal: the pixel span adds a pixel of margin
+    const float rA = __builtin_amdgcn_rcpf(A);
+    lo = (B - sq) * rA;
+    hi = (B + sq) * rA;
     return true;
 }
 
@@ -226,22 +228,27 @@ __device__ inline void screen_box(const GaussView &g, const float *s2, float D2,
 __device__ inline float beta_bound(const GaussView &g, const float *s, float smax,
                                    const ViewInfo &vi, int x0, int x1, int y0, int y1)
 {
-    const float mlen = sqrtf(g.m[0] * g.m[0] + g.m[1] * g.m[1] + g.m[2] * g.m[2]);
-    const float im = 1.0f / mlen;
+    // 1-ulp reciprocals and square roots throughout; the returned bound
+    // carries a relative slack of 1e-3, far above their rounding
+    const float im = __builtin_amdgcn_rsqf(g.m[0] * g.m[0] + g.m[1] * g.m[1] + g.m[2] * g.m[2]);
     const float c0 = g.m[0] * im, c1 = g.m[1] * im, c2 = g.m[2] * im;
-    float chord = 0.0f;
+    const float ifx = __builtin_amdgcn_rcpf(vi.fx), ify = __builtin_amdgcn_rcpf(vi.fy);
+    float chord2 = 0.0f;
     for (int k = 0; k < 4; ++k) {
         const float X = (float)((k & 1) ? x1 + 1 : x0), Y = (float)((k & 2) ? y1 + 1 : y0);
-        const float u0 = (X - vi.cx) / vi.fx, u1 = (Y - vi.cy) / vi.fy;
-        const float il = 1.0f / sqrtf(u0 * u0 + u1 * u1 + 1.0f);
+        const float u0 = (X - vi.cx) * ifx, u1 = (Y - vi.cy) * ify;
+        const float il = __builtin_amdgcn_rsqf(u0 * u0 + u1 * u1 + 1.0f);
         const float d0 = u0 * il - c0, d1 = u1 * il - c1, d2 = il - c2;
-        chord = fmaxf(chord, sqrtf(d0 * d0 + d1 * d1 + d2 * d2));
+        chord2 = fmaxf(chord2, d0 * d0 + d1 * d1 + d2 * d2);
     }
     const float smin = fminf(s[0], fminf(s[1], s[2]));
-    const float lu = sqrtf(g.p[0] * g.p[0] + g.p[1] * g.p[1] + g.p[2] * g.p[2]) * im;
-    const float den = lu - chord / smin;
+    // the relative rounding of den grows like smax / smin (the cancellation
+    // in lu - chord / smin); past 1e3 the slack below would not cover it
+    if (!(smax < 1.0e3f * smin)) return smax;
+    const float lu = __builtin_sqrtf(g.p[0] * g.p[0] + g.p[1] * g.p[1] + g.p[2] * g.p[2]) * im;
+    const float den = lu - __builtin_sqrtf(chord2) * __builtin_amdgcn_rcpf(smin);
     if (!(den > 0.0f)) return smax;
-    return fminf(smax, 1.0001f / den);   // small slack for FP32 rounding
+    return fminf(smax, 1.001f * __builtin_amdgcn_rcpf(den));
 }
 
 // Tile culling.  The bound pre-test rejects a pixel when f(d) > kConicMargin;
@@ -490,8 +497,9 @@ __global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int6
 // row list.  A block whose row lists do not fit in LDS walks the rows per
 // instance instead.
 constexpr int kEmitRows = 1024;
+constexpr int kEmitThreads = 256;   // wave 0 builds the row lists, all waves write
 
-__global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
+__global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
                                                   int64_t capacity)
 {
     __shared__ uint32_t s_off[64];
@@ -502,65 +510,70 @@ __global__ __launch_bounds__(64) void emit_kernel(RenderParams rp, Buffers b, in
     __shared__ uint32_t s_rbeg[65];
     __shared__ uint32_t s_rstart[kEmitRows];   // first local instance of the row
     __shared__ uint32_t s_rtile[kEmitRows];    // row << 16 | first tile column
+    __shared__ uint32_t s_table;
     const int lane = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
     const int64_t j = j0 + lane;
     const int64_t jend = min(j0 + 64, m);
     const uint32_t base = b.offsets[j0];
     const uint32_t total = b.offsets[jend] - base;
-    CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
-    ushort4 rect = make_ushort4(0, 0, 0, 0);
-    uint32_t my_off = total;
-    if (j < m) {
-        const uint32_t item = b.item_ids[j];
-        my_off = b.offsets[j] - base;
-        rect = b.rect[item];
-        const float4 c6 = b.geom[(size_t)item * kRecVec + 6];
-        const float4 c7 = b.geom[(size_t)item * kRecVec + 7];
-        cr = CullRows{ c6.x, c6.y, c6.z, c6.w, c7.x, c7.y, c7.z, c7.w };
-        const ViewInfo &vi = b.views[(int)(item / (uint64_t)rp.n)];
-        s_item[lane] = item;
-        s_toff[lane] = vi.tile_off;
-        s_tx[lane] = vi.tiles_x;
-    } else {
-        s_item[lane] = 0;
-        s_toff[lane] = 0;
-        s_tx[lane] = 0;
-    }
-    s_off[lane] = my_off;
-    s_rect[lane] = rect;
-    s_cull[lane] = cr;
-    const bool has = j < m && (j + 1 < jend ? b.offsets[j + 1] - base : total) > my_off;
-    // non-empty rows of this lane's Gaussian, and their prefix over the wave
-    uint32_t nrows = 0;
-    if (has)
-        for (int row = rect.y; row <= rect.w; ++row) {
-            int t0, t1;
-            nrows += cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1) ? 1u : 0u;
+    if (lane < 64) {   // wave 0: the Gaussians' row lists
+        CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
+        ushort4 rect = make_ushort4(0, 0, 0, 0);
+        uint32_t my_off = total;
+        if (j < m) {
+            const uint32_t item = b.item_ids[j];
+            my_off = b.offsets[j] - base;
+            rect = b.rect[item];
+            const float4 c6 = b.geom[(size_t)item * kRecVec + 6];
+            const float4 c7 = b.geom[(size_t)item * kRecVec + 7];
+            cr = CullRows{ c6.x, c6.y, c6.z, c6.w, c7.x, c7.y, c7.z, c7.w };
+            const ViewInfo &vi = b.views[(int)(item / (uint64_t)rp.n)];
+            s_item[lane] = item;
+            s_toff[lane] = vi.tile_off;
+            s_tx[lane] = vi.tiles_x;
+        } else {
+            s_item[lane] = 0;
+            s_toff[lane] = 0;
+            s_tx[lane] = 0;
         }
-    uint32_t incl = nrows;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    const uint32_t rows_total = __shfl(incl, 63, 64);
-    const bool table = rows_total <= (uint32_t)kEmitRows;   // wave-uniform
-    s_rbeg[lane] = incl - nrows;
-    if (lane == 63) s_rbeg[64] = incl;
-    if (table && has) {
-        uint32_t k = incl - nrows, acc = 0;
-        for (int row = rect.y; row <= rect.w; ++row) {
-            int t0, t1;
-            if (!cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1)) continue;
-            s_rstart[k] = acc;
-            s_rtile[k] = ((uint32_t)row << 16) | (uint32_t)t0;
-            acc += (uint32_t)(t1 - t0 + 1);
-            ++k;
+        s_off[lane] = my_off;
+        s_rect[lane] = rect;
+        s_cull[lane] = cr;
+        const bool has = j < m && (j + 1 < jend ? b.offsets[j + 1] - base : total) > my_off;
+        // non-empty rows of this lane's Gaussian, and their prefix over the wave
+        uint32_t nrows = 0;
+        if (has)
+            for (int row = rect.y; row <= rect.w; ++row) {
+                int t0, t1;
+                nrows += cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1) ? 1u : 0u;
+            }
+        uint32_t incl = nrows;
+    #pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
         }
+        const uint32_t rows_total = __shfl(incl, 63, 64);
+        const bool table = rows_total <= (uint32_t)kEmitRows;   // wave-uniform
+        s_rbeg[lane] = incl - nrows;
+        if (lane == 63) s_rbeg[64] = incl;
+        if (table && has) {
+            uint32_t k = incl - nrows, acc = 0;
+            for (int row = rect.y; row <= rect.w; ++row) {
+                int t0, t1;
+                if (!cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1)) continue;
+                s_rstart[k] = acc;
+                s_rtile[k] = ((uint32_t)row << 16) | (uint32_t)t0;
+                acc += (uint32_t)(t1 - t0 + 1);
+                ++k;
+            }
+        }
+        if (lane == 0) s_table = table ? 1u : 0u;
     }
     __syncthreads();
-    for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+    const bool table = s_table != 0;
+    for (uint32_t e0 = 0; e0 < total; e0 += kEmitThreads) {
         const uint32_t e = e0 + lane;
         if (e < total) {
             // largest g with s_off[g] <= e (entries with no instances share the
@@ -949,7 +962,7 @@ hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, 
 hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
                        hipStream_t s)
 {
-    emit_kernel<<<grid_for(m, 64), 64, 0, s>>>(rp, b, m, capacity);   // one wave per 64 Gaussians
+    emit_kernel<<<grid_for(m, 64), kEmitThreads, 0, s>>>(rp, b, m, capacity);   // 64 Gaussians per block
     return hipGetLastError();
 }
 
