@@ -35,11 +35,11 @@ if ROOT not in sys.path:
 #   forward compositing of blended pairs (clamp, exp2, T(1-a), stop test,
 #     alpha, weight, colour FMAs)                                      12   (X-ray sum: 1)
 #   backward of blended pairs: compositing replay (clamp, exp2, rcp, T,
-#     dL/dalpha, colour gradient, colour-behind update) 35 (X-ray: 1), moment
-#     accumulation (t, sum t, z = mz (w x n)/|w|^2, w/|w|, Z, M)       54
+#     g.c, dL/dalpha, colour gradient, g.(colour behind) update) 25 (X-ray:
+#     1), moment accumulation (t, sum t, z = mz (w x n)/|w|^2, w/|w|, Z, M) 54
 F_TEST, F_SHARED, F_FULL = 7, 8, 46
 F_BLEND_FWD = {"color": 12, "xray": 1}
-F_BLEND_BWD = {"color": 35 + 54, "xray": 1 + 54}
+F_BLEND_BWD = {"color": 25 + 54, "xray": 1 + 54}
 PEAK_FP32 = 157.3e12    # MI355X published FP32 vector peak (FLOP/s)
 CALIB_COPY_BYTES = 1 << 28   # plain device copy used to calibrate the HBM byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_raster_8x8_1M_1080p.json")

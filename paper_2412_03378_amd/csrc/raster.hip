@@ -25,8 +25,9 @@
 //
 // The backward walks each pixel's list in reverse from its last blended
 // Gaussian, recovering T in front of Gaussian i as T_after / (1 - alpha_i)
-// from the stored final transmittance, and the colour behind it as a running
-// sum starting at T_final * bg.  The geometric gradient of each pair is kept
+// from the stored final transmittance, and the colour behind it (through its
+// dot product with dL/dC, which is all the replay needs) as a running sum
+// starting at T_final * bg.  The geometric gradient of each pair is kept
 // as moments in the Gaussian's L-frame (see the record-gradient layout in
 // vgr_internal.h).  Per Gaussian, the 16 partial sums of the wave are reduced
 // with a transpose-reduce (lane-swap and DPP moves, no LDS) and added with one
@@ -425,7 +426,9 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     const float ux = (pxc - vi.cx) / vi.fx;
     const uint2 range = b.ranges[gt];
 
-    float pyc[PPL], un[PPL], T[PPL], g[PPL][NCH], B[PPL][NCH];
+    // GB: dL/dC . (colour composited behind the current Gaussian); the replay
+    // needs the colour behind only through this dot product
+    float pyc[PPL], un[PPL], T[PPL], g[PPL][NCH], GB[PPL];
     int last[PPL];
     int maxlast = -1;
     Counts n;
@@ -439,11 +442,13 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
         const int64_t idx = (int64_t)py * W + px;
         last[k] = inside ? b.last_pos[vi.pix_off + idx] : -1;
         T[k] = inside ? b.T_final[vi.pix_off + idx] : 1.0f;
+        float gbg = 0.0f;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             g[k][c] = inside ? vi.dL[c * HW + idx] : 0.0f;
-            B[k][c] = T[k] * rp.bg[c];
+            gbg = __fmaf_rn(g[k][c], rp.bg[c], gbg);
         }
+        GB[k] = T[k] * gbg;
         maxlast = max(maxlast, last[k]);
     }
 #pragma unroll
@@ -497,16 +502,15 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     const float inv = fast_rcp(om);
                     const float alpha = 1.0f - om;
                     const float Tb = T[k] * inv;
-                    const float da = g[k][0] * (fr.c0 * Tb - B[k][0] * inv) +
-                                     g[k][1] * (fr.c1 * Tb - B[k][1] * inv) +
-                                     g[k][2] * (fr.c2 * Tb - B[k][2] * inv);
+                    // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
+                    const float gc = __fmaf_rn(g[k][0], fr.c0,
+                                               __fmaf_rn(g[k][1], fr.c1, g[k][2] * fr.c2));
+                    const float da = __fmaf_rn(Tb, gc, -(inv * GB[k]));
                     const float wgt = bl ? alpha * Tb : 0.0f;
                     acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
                     acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
                     acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
-                    B[k][0] = __fmaf_rn(fr.c0, wgt, B[k][0]);
-                    B[k][1] = __fmaf_rn(fr.c1, wgt, B[k][1]);
-                    B[k][2] = __fmaf_rn(fr.c2, wgt, B[k][2]);
+                    GB[k] = __fmaf_rn(gc, wgt, GB[k]);
                     T[k] = bl ? Tb : T[k];
                     dy_ = (bl && !clamped) ? da * kLn2 * om : 0.0f;
                 } else {
