@@ -4,9 +4,14 @@
 // TW*TH/64 pixels of column l % TW, rows l / TW + k * (64 / TW) ("slot" k).
 // Tiles are launched in the order of b.tile_order (heaviest lists first).
 // The tile's depth-sorted Gaussian list is walked in batches of 64 records
-// staged in LDS (structure of arrays; every lane reads the same record, a
-// broadcast).  A step reads the three float4 of the bound pre-test first and
-// the other three only when some pixel of the slot passes it.
+// staged in LDS (structure of arrays).  The colour forward (and the X-ray
+// forward with one pixel per lane) pre-tests the whole batch with broadcast
+// reads and then lets every lane evaluate its own passing records in order
+// (per-lane reads), so that an evaluation step is not spent on lanes whose
+// pixel the record misses; the X-ray forward with several pixels per lane,
+// and the backward (whose per-Gaussian reduction needs the wave on one
+// record), walk the batch together, reading the three float4 of the bound
+// pre-test first and the other three only when some pixel of the slot passes.
 //
 // Per (pixel, Gaussian) pair, with the record (centre h + l, A, v0, mz, K',
 // bound form Q, l; see vgr_internal.h) and d = pixel centre - h - l:
@@ -231,70 +236,128 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         if (j < range.y) stage_record(st, b, lane, b.inst_val[j]);
         __syncthreads();
         const int nb = (int)min(64u, range.y - bs);
-        // Phase 1: bound pre-test of the whole batch (broadcast records);
-        // bit q of mask[k] marks record q as passing for the lane's slot k.
-        uint64_t mask[PPL];
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) mask[k] = 0;
-        for (int qi = 0; qi < nb; ++qi) {
-            const float4 g0 = st.g[0][qi], g1 = st.g[1][qi], g2 = st.g[2][qi];
-            const PreRec pr = pre_of4(g0, g1, g2);
-            const ColTerms ct = col_terms(pr, pxc);
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                float dy;
-                const bool pass = act[k] && pre_test(pr, ct, pyc[k], dy);
-                mask[k] |= (uint64_t)(pass ? 1u : 0u) << qi;
-                if (COUNT) {
-                    n.test += act[k] ? 1u : 0u;
-                    const bool anyl = __any(act[k]);
-                    n.visits += (lane == 0 && anyl) ? 1u : 0u;
+        if constexpr (PPL == 1 || COLOR) {
+            // Phase 1: bound pre-test of the whole batch (broadcast records);
+            // bit q of mask[k] marks record q as passing for the lane's slot k.
+            uint64_t mask[PPL];
+    #pragma unroll
+            for (int k = 0; k < PPL; ++k) mask[k] = 0;
+            for (int qi = 0; qi < nb; ++qi) {
+                const float4 g0 = st.g[0][qi], g1 = st.g[1][qi], g2 = st.g[2][qi];
+                const PreRec pr = pre_of4(g0, g1, g2);
+                const ColTerms ct = col_terms(pr, pxc);
+    #pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    float dy;
+                    const bool pass = act[k] && pre_test(pr, ct, pyc[k], dy);
+                    mask[k] |= (uint64_t)(pass ? 1u : 0u) << qi;
+                    if (COUNT) {
+                        n.test += act[k] ? 1u : 0u;
+                        const bool anyl = __any(act[k]);
+                        n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                    }
                 }
             }
-        }
-        // Phase 2: every lane evaluates and blends its own passing records in
-        // list order, one per step (records read from LDS at per-lane
-        // addresses), so a step does useful work on every lane that still has
-        // a record left instead of only on those that pass one shared record.
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            uint64_t mk = mask[k];
-            while (__any(mk != 0 && act[k])) {           // wave-uniform loop
-                const bool has = mk != 0 && act[k];
-                const int qi = has ? (int)__builtin_ctzll(mk) : 0;
-                mk &= mk - 1;
-                if (COUNT) {
-                    n.full += has ? 1u : 0u;
-                    n.visits_full += lane == 0 ? 1u : 0u;
+            // Phase 2: every lane evaluates and blends its own passing records in
+            // list order, one per step (records read from LDS at per-lane
+            // addresses), so a step does useful work on every lane that still has
+            // a record left instead of only on those that pass one shared record.
+    #pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                uint64_t mk = mask[k];
+                while (__any(mk != 0 && act[k])) {           // wave-uniform loop
+                    const bool has = mk != 0 && act[k];
+                    const int qi = has ? (int)__builtin_ctzll(mk) : 0;
+                    mk &= mk - 1;
+                    if (COUNT) {
+                        n.full += has ? 1u : 0u;
+                        n.visits_full += lane == 0 ? 1u : 0u;
+                    }
+                    const RecRegs rr = load_regs(st, qi);
+                    const PreRec pr = pre_of(rr);
+                    const FullRec fr = full_of(rr);
+                    const float dx = (pxc - pr.hx) - pr.lx;
+                    const float dy = (pyc[k] - pr.hy) - pr.ly;
+                    PairGeom g;
+                    pair_geom(pr, fr, dx, dy, g);
+                    const float rq = fast_rsq(g.qw);
+                    const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                    const float y = fr.K * un[k] * rq * ex;
+                    const bool bl = has && !(y < tau2);
+                    if constexpr (COLOR) {
+                        const float om = fast_exp2(-fminf(y, ymax));
+                        const float Tn = T[k] * om;
+                        const bool stop = bl && Tn < Tmin;
+                        const bool dob = bl && !stop;
+                        const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
+                        C0[k] = __fmaf_rn(fr.c0, wgt, C0[k]);
+                        C1[k] = __fmaf_rn(fr.c1, wgt, C1[k]);
+                        C2[k] = __fmaf_rn(fr.c2, wgt, C2[k]);
+                        T[k] = dob ? Tn : T[k];
+                        last[k] = dob ? (int)(bs + qi) : last[k];
+                        act[k] = act[k] && !stop;
+                        if (COUNT) n.blend += dob ? 1u : 0u;
+                    } else {
+                        C0[k] += bl ? y : 0.0f;
+                        last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
+                        if (COUNT) n.blend += bl ? 1u : 0u;
+                    }
                 }
-                const RecRegs rr = load_regs(st, qi);
-                const PreRec pr = pre_of(rr);
-                const FullRec fr = full_of(rr);
-                const float dx = (pxc - pr.hx) - pr.lx;
-                const float dy = (pyc[k] - pr.hy) - pr.ly;
-                PairGeom g;
-                pair_geom(pr, fr, dx, dy, g);
-                const float rq = fast_rsq(g.qw);
-                const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
-                const float y = fr.K * un[k] * rq * ex;
-                const bool bl = has && !(y < tau2);
-                if constexpr (COLOR) {
-                    const float om = fast_exp2(-fminf(y, ymax));
-                    const float Tn = T[k] * om;
-                    const bool stop = bl && Tn < Tmin;
-                    const bool dob = bl && !stop;
-                    const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
-                    C0[k] = __fmaf_rn(fr.c0, wgt, C0[k]);
-                    C1[k] = __fmaf_rn(fr.c1, wgt, C1[k]);
-                    C2[k] = __fmaf_rn(fr.c2, wgt, C2[k]);
-                    T[k] = dob ? Tn : T[k];
-                    last[k] = dob ? (int)(bs + qi) : last[k];
-                    act[k] = act[k] && !stop;
-                    if (COUNT) n.blend += dob ? 1u : 0u;
-                } else {
-                    C0[k] += bl ? y : 0.0f;
-                    last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
-                    if (COUNT) n.blend += bl ? 1u : 0u;
+            }
+        } else {
+            // X-ray with several pixels per lane: every record of the list is
+            // summed (no early stop), and one broadcast read per step is
+            // shared by the lane's pixels, which measured faster than a
+            // per-lane walk that re-reads the record for each pixel.
+            for (int qi = 0; qi < nb; ++qi) {
+                if (COLOR) {
+                    bool any = false;
+    #pragma unroll
+                    for (int k = 0; k < PPL; ++k) any |= act[k];
+                    if (!__any(any)) break;              // every pixel has stopped
+                }
+                const PreRec pr = load_pre(st, qi);
+                const ColTerms ct = col_terms(pr, pxc);
+    #pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    float dy;
+                    const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
+                    const bool pass = act[k] && near;
+                    const bool anyp = __any(pass);
+                    if (COUNT) {
+                        n.test += act[k] ? 1u : 0u;
+                        const bool anyl = __any(act[k]);
+                        n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                        n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
+                    }
+                    if (!anyp) continue;                  // wave-uniform
+                    if (COUNT) n.full += pass ? 1u : 0u;
+                    const FullRec fr = load_full(st, qi);
+                    PairGeom g;
+                    pair_geom(pr, fr, ct.dx, dy, g);
+                    const float rq = fast_rsq(g.qw);
+                    const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                    const float y = fr.K * un[k] * rq * ex;
+                    const bool bl = pass && !(y < tau2);
+                    if constexpr (COLOR) {
+                        if (!__any(bl)) continue;            // wave-uniform
+                        const float om = fast_exp2(-fminf(y, ymax));
+                        const float Tn = T[k] * om;
+                        const bool stop = bl && Tn < Tmin;
+                        const bool dob = bl && !stop;
+                        const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
+                        C0[k] = __fmaf_rn(fr.c0, wgt, C0[k]);
+                        C1[k] = __fmaf_rn(fr.c1, wgt, C1[k]);
+                        C2[k] = __fmaf_rn(fr.c2, wgt, C2[k]);
+                        T[k] = dob ? Tn : T[k];
+                        last[k] = dob ? (int)(bs + qi) : last[k];
+                        act[k] = act[k] && !stop;
+                        if (COUNT) n.blend += dob ? 1u : 0u;
+                    } else {
+                        C0[k] += bl ? y : 0.0f;
+                        last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
+                        if (COUNT) n.blend += bl ? 1u : 0u;
+                    }
                 }
             }
         }
