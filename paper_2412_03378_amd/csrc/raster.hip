@@ -49,6 +49,10 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// True if p holds on any active lane: a ballot of the predicate's lane mask,
+// which the branch tests directly.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 struct Stage {
     float4 g[kStageVec][64];
     uint32_t item[64];
@@ -156,14 +160,12 @@ struct PairGeom {
 __device__ __forceinline__ void pair_geom(const PreRec &p, const FullRec &r, float dx, float dy,
                                           PairGeom &g)
 {
-    const float ax0 = p.A00 * dx, ax1 = p.A10 * dx, ax2 = p.A20 * dx;
-    const float wx0 = r.v0x + ax0, wx1 = r.v0y + ax1, wx2 = r.v0z + ax2;
-    g.a0 = __fmaf_rn(r.A01, dy, ax0);
-    g.a1 = __fmaf_rn(r.A11, dy, ax1);
-    g.a2 = __fmaf_rn(r.A21, dy, ax2);
-    g.w0 = __fmaf_rn(r.A01, dy, wx0);
-    g.w1 = __fmaf_rn(r.A11, dy, wx1);
-    g.w2 = __fmaf_rn(r.A21, dy, wx2);
+    g.a0 = __fmaf_rn(r.A01, dy, p.A00 * dx);
+    g.a1 = __fmaf_rn(r.A11, dy, p.A10 * dx);
+    g.a2 = __fmaf_rn(r.A21, dy, p.A20 * dx);
+    g.w0 = r.v0x + g.a0;
+    g.w1 = r.v0y + g.a1;
+    g.w2 = r.v0z + g.a2;
     g.n0 = __fmaf_rn(r.v0y, g.a2, -r.v0z * g.a1);
     g.n1 = __fmaf_rn(r.v0z, g.a0, -r.v0x * g.a2);
     g.n2 = __fmaf_rn(r.v0x, g.a1, -r.v0y * g.a0);
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     mask[k] |= (uint64_t)(pass ? 1u : 0u) << qi;
                     if (COUNT) {
                         n.test += act[k] ? 1u : 0u;
-                        const bool anyl = __any(act[k]);
+                        const bool anyl = wave_any(act[k]);
                         n.visits += (lane == 0 && anyl) ? 1u : 0u;
                     }
                 }
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 uint64_t mk = mask[k];
-                while (__any(mk != 0 && act[k])) {           // wave-uniform loop
+                while (wave_any(mk != 0 && act[k])) {           // wave-uniform loop
                     const bool has = mk != 0 && act[k];
                     const int qi = has ? (int)__builtin_ctzll(mk) : 0;
                     mk &= mk - 1;
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     const float y = fr.K * un[k] * rq * ex;
                     const bool bl = has && !(y < tau2);
                     if constexpr (COLOR) {
-                        const float om = fast_exp2(-fminf(y, ymax));
+                        const float om = fast_exp2(-(y > ymax ? ymax : y));
                         const float Tn = T[k] * om;
                         const bool stop = bl && Tn < Tmin;
                         const bool dob = bl && !stop;
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     bool any = false;
     #pragma unroll
                     for (int k = 0; k < PPL; ++k) any |= act[k];
-                    if (!__any(any)) break;              // every pixel has stopped
+                    if (!wave_any(any)) break;              // every pixel has stopped
                 }
                 const PreRec pr = load_pre(st, qi);
                 const ColTerms ct = col_terms(pr, pxc);
@@ -323,10 +325,10 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     float dy;
                     const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
                     const bool pass = act[k] && near;
-                    const bool anyp = __any(pass);
+                    const bool anyp = wave_any(pass);
                     if (COUNT) {
                         n.test += act[k] ? 1u : 0u;
-                        const bool anyl = __any(act[k]);
+                        const bool anyl = wave_any(act[k]);
                         n.visits += (lane == 0 && anyl) ? 1u : 0u;
                         n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
                     }
@@ -340,8 +342,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     const float y = fr.K * un[k] * rq * ex;
                     const bool bl = pass && !(y < tau2);
                     if constexpr (COLOR) {
-                        if (!__any(bl)) continue;            // wave-uniform
-                        const float om = fast_exp2(-fminf(y, ymax));
+                        if (!wave_any(bl)) continue;            // wave-uniform
+                        const float om = fast_exp2(-(y > ymax ? ymax : y));
                         const float Tn = T[k] * om;
                         const bool stop = bl && Tn < Tmin;
                         const bool dob = bl && !stop;
@@ -366,7 +368,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) any |= act[k];
-            if (!__any(any)) break;                    // every pixel has stopped
+            if (!wave_any(any)) break;                    // every pixel has stopped
         }
     }
 
@@ -529,9 +531,11 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const int jpos = bs + qi;
             const PreRec pr = load_pre(st, qi);
             const ColTerms ct = col_terms(pr, pxc);
+            // -0 is the exact identity of addition, so the first term of each
+            // sum needs no add
             float acc[16];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+            for (int e = 0; e < 16; ++e) acc[e] = e < 13 ? -0.0f : 0.0f;
             bool touched = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
@@ -539,10 +543,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const bool inl = jpos <= last[k];
                 const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
                 const bool pass = inl && near;
-                const bool anyp = __any(pass);
+                const bool anyp = wave_any(pass);
                 if (COUNT) {
                     n.test += inl ? 1u : 0u;
-                    const bool anyl = __any(inl);
+                    const bool anyl = wave_any(inl);
                     n.visits += (lane == 0 && anyl) ? 1u : 0u;
                     n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
                 }
@@ -557,11 +561,11 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
                 if (COUNT) n.blend += bl ? 1u : 0u;
-                if (!__any(bl)) continue;                // wave-uniform
+                if (!wave_any(bl)) continue;                // wave-uniform
                 float dy_;
                 if constexpr (COLOR) {
                     const bool clamped = y > ymax;
-                    const float om = fast_exp2(-fminf(y, ymax));
+                    const float om = fast_exp2(-(clamped ? ymax : y));
                     const float inv = fast_rcp(om);
                     const float alpha = 1.0f - om;
                     const float Tb = T[k] * inv;
@@ -585,23 +589,27 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 // free of K', the sum of t is K' dL/dK'
                 const float t = bl ? dy_ * y : 0.0f;
                 acc[9] += t;
-                // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|
-                const float cz = bl ? fr.mz * rq2 : 0.0f;
+                // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|;
+                // M += t (w' w'^T + z z^T) as (t w') w'^T + (t z) z^T (t is zero,
+                // and z finite, on lanes that do not blend)
+                const float cz = fr.mz * rq2;
                 const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);
                 const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
                 const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
                 const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
-                acc[6] = __fmaf_rn(t, z0, acc[6]);
-                acc[7] = __fmaf_rn(t, z1, acc[7]);
-                acc[8] = __fmaf_rn(t, z2, acc[8]);
-                acc[0] = __fmaf_rn(t, __fmaf_rn(p0, p0, z0 * z0), acc[0]);
-                acc[1] = __fmaf_rn(t, __fmaf_rn(p0, p1, z0 * z1), acc[1]);
-                acc[2] = __fmaf_rn(t, __fmaf_rn(p0, p2, z0 * z2), acc[2]);
-                acc[3] = __fmaf_rn(t, __fmaf_rn(p1, p1, z1 * z1), acc[3]);
-                acc[4] = __fmaf_rn(t, __fmaf_rn(p1, p2, z1 * z2), acc[4]);
-                acc[5] = __fmaf_rn(t, __fmaf_rn(p2, p2, z2 * z2), acc[5]);
+                const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
+                const float tp0 = t * p0, tp1 = t * p1, tp2 = t * p2;
+                acc[6] += tz0;
+                acc[7] += tz1;
+                acc[8] += tz2;
+                acc[0] += __fmaf_rn(tp0, p0, tz0 * z0);
+                acc[1] += __fmaf_rn(tp0, p1, tz0 * z1);
+                acc[2] += __fmaf_rn(tp0, p2, tz0 * z2);
+                acc[3] += __fmaf_rn(tp1, p1, tz1 * z1);
+                acc[4] += __fmaf_rn(tp1, p2, tz1 * z2);
+                acc[5] += __fmaf_rn(tp2, p2, tz2 * z2);
             }
-            if (__any(touched)) {
+            if (wave_any(touched)) {
                 const float tot = wave_reduce16(acc, lane);
                 if ((lane & 3) == 0)
                     atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
