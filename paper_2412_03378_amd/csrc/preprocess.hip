@@ -513,144 +513,156 @@ __global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int6
     }
 }
 
-// Emission of the (tile, Gaussian) pairs in depth order.  Each one-wave block
-// owns 64 consecutive depth-sorted Gaussians; their instance ranges are
-// contiguous.  Each lane first lists its Gaussian's non-empty tile rows (the
-// culled row intervals, in LDS); then the lanes write 64 consecutive instances
-// at a time, each lane finding the Gaussian that owns its instance by binary
-// search over the 64 offsets, and the row by a short scan of that Gaussian's
-// row list.  A block whose row lists do not fit in LDS walks the rows per
-// instance instead.
+// Emission of the (tile, Gaussian) pairs in depth order.  Each 256-thread
+// block owns 64 consecutive depth-sorted Gaussians, whose instance ranges are
+// contiguous.  Their candidate tile rows (the rows of each rectangle, in
+// Gaussian then row order) are processed 1024 at a time, four consecutive
+// rows per thread: each thread finds the owning Gaussian by binary search
+// over the 64 row prefixes and culls its rows to tile intervals (the same
+// intervals the preprocess counted); a block scan of the interval lengths
+// gives each row its first instance; then each thread writes instances
+// e, e + 256, ..., finding the row of instance e by binary search over the
+// row starts.
 constexpr int kEmitRows = 1024;
-constexpr int kEmitThreads = 256;   // wave 0 builds the row lists, all waves write
+constexpr int kEmitThreads = 256;
+constexpr int kEmitRowsPerThread = kEmitRows / kEmitThreads;
+
+// Exclusive scan over the 256 threads of an emission block; *total gets the sum.
+__device__ __forceinline__ uint32_t emit_block_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kEmitThreads / 64; ++i) {
+        const uint32_t ws = wsum[i];
+        off += i < w ? ws : 0u;
+        tot += ws;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
                                                   int64_t capacity)
 {
-    __shared__ uint32_t s_off[64];
     __shared__ uint32_t s_item[64];
     __shared__ ushort4 s_rect[64];
     __shared__ CullRows s_cull[64];
     __shared__ int32_t s_toff[64], s_tx[64];
-    __shared__ uint32_t s_rbeg[65];
-    __shared__ uint32_t s_rstart[kEmitRows];   // first local instance of the row
-    __shared__ uint32_t s_rtile[kEmitRows];    // row << 16 | first tile column
-    __shared__ uint32_t s_table;
-    const int lane = threadIdx.x;
+    __shared__ uint32_t s_rowbeg[65];              // first candidate row of each Gaussian
+    __shared__ uint32_t s_rstart[kEmitRows + 1];   // first instance of each row of the chunk
+    __shared__ uint32_t s_rtile[kEmitRows];        // tile row << 16 | first tile column
+    __shared__ uint8_t s_rg[kEmitRows];            // owning Gaussian (0..63)
+    __shared__ uint32_t s_wsum[kEmitThreads / 64];
+    const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
-    const int64_t j = j0 + lane;
     const int64_t jend = min(j0 + 64, m);
     const uint32_t base = b.offsets[j0];
-    const uint32_t total = b.offsets[jend] - base;
-    if (lane < 64) {   // wave 0: the Gaussians' row lists
+    if (tid < 64) {   // wave 0: the block's Gaussians and their candidate row counts
+        const int64_t j = j0 + tid;
         CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
         ushort4 rect = make_ushort4(0, 0, 0, 0);
-        uint32_t my_off = total;
-        if (j < m) {
-            const uint32_t item = b.item_ids[j];
-            my_off = b.offsets[j] - base;
+        uint32_t item = 0, rows = 0;
+        int32_t toff = 0, txs = 0;
+        if (j < m && b.offsets[j + 1] > b.offsets[j]) {   // a Gaussian with instances
+            item = b.item_ids[j];
             rect = b.rect[item];
             const float4 c6 = b.geom[(size_t)item * kRecVec + 6];
             const float4 c7 = b.geom[(size_t)item * kRecVec + 7];
             cr = CullRows{ c6.x, c6.y, c6.z, c6.w, c7.x, c7.y, c7.z, c7.w };
             const ViewInfo &vi = b.views[(int)(item / (uint64_t)rp.n)];
-            s_item[lane] = item;
-            s_toff[lane] = vi.tile_off;
-            s_tx[lane] = vi.tiles_x;
-        } else {
-            s_item[lane] = 0;
-            s_toff[lane] = 0;
-            s_tx[lane] = 0;
+            toff = vi.tile_off;
+            txs = vi.tiles_x;
+            rows = (uint32_t)rect.w - (uint32_t)rect.y + 1u;
         }
-        s_off[lane] = my_off;
-        s_rect[lane] = rect;
-        s_cull[lane] = cr;
-        const bool has = j < m && (j + 1 < jend ? b.offsets[j + 1] - base : total) > my_off;
-        // non-empty rows of this lane's Gaussian, and their prefix over the wave
-        uint32_t nrows = 0;
-        if (has)
-            for (int row = rect.y; row <= rect.w; ++row) {
-                int t0, t1;
-                nrows += cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1) ? 1u : 0u;
-            }
-        uint32_t incl = nrows;
-    #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
+        s_item[tid] = item;
+        s_rect[tid] = rect;
+        s_cull[tid] = cr;
+        s_toff[tid] = toff;
+        s_tx[tid] = txs;
+        uint32_t inc = rows;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, 64);
+            if (tid >= d) inc += t;
         }
-        const uint32_t rows_total = __shfl(incl, 63, 64);
-        const bool table = rows_total <= (uint32_t)kEmitRows;   // wave-uniform
-        s_rbeg[lane] = incl - nrows;
-        if (lane == 63) s_rbeg[64] = incl;
-        if (table && has) {
-            uint32_t k = incl - nrows, acc = 0;
-            for (int row = rect.y; row <= rect.w; ++row) {
-                int t0, t1;
-                if (!cull_row(cr, row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1)) continue;
-                s_rstart[k] = acc;
-                s_rtile[k] = ((uint32_t)row << 16) | (uint32_t)t0;
-                acc += (uint32_t)(t1 - t0 + 1);
-                ++k;
-            }
-        }
-        if (lane == 0) s_table = table ? 1u : 0u;
+        s_rowbeg[tid] = inc - rows;
+        if (tid == 63) s_rowbeg[64] = inc;
     }
     __syncthreads();
-    const bool table = s_table != 0;
-    for (uint32_t e0 = 0; e0 < total; e0 += kEmitThreads) {
-        const uint32_t e = e0 + lane;
-        if (e < total) {
-            // largest g with s_off[g] <= e (entries with no instances share the
-            // offset of the next owner, which the search prefers)
-            int lo = 0, hi = 63;
+    const uint32_t nrows = s_rowbeg[64];
+    uint32_t done = 0;   // instances of the earlier chunks
+    for (uint32_t c0 = 0; c0 < nrows; c0 += kEmitRows) {
+        const uint32_t cn = min((uint32_t)kEmitRows, nrows - c0);
+        uint32_t cnt[kEmitRowsPerThread];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kEmitRowsPerThread; ++i) {
+            const uint32_t rl = (uint32_t)(tid * kEmitRowsPerThread + i);
+            cnt[i] = 0;
+            if (rl < cn) {
+                const uint32_t r = c0 + rl;
+                // largest g with s_rowbeg[g] <= r: Gaussians without rows share
+                // their prefix with the next one, which the search prefers
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_rowbeg[mid] <= r) lo = mid;
+                    else hi = mid - 1;
+                }
+                const ushort4 rect = s_rect[lo];
+                const int row = (int)rect.y + (int)(r - s_rowbeg[lo]);
+                int t0 = 0, t1 = -1;
+                if (cull_row(s_cull[lo], row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1))
+                    cnt[i] = (uint32_t)(t1 - t0 + 1);
+                s_rtile[rl] = ((uint32_t)row << 16) | (uint32_t)(t0 & 0xFFFF);
+                s_rg[rl] = (uint8_t)lo;
+            }
+            sum += cnt[i];
+        }
+        uint32_t chunk;
+        uint32_t run = done + emit_block_scan(sum, s_wsum, &chunk);
+#pragma unroll
+        for (int i = 0; i < kEmitRowsPerThread; ++i) {
+            const uint32_t rl = (uint32_t)(tid * kEmitRowsPerThread + i);
+            if (rl < cn) s_rstart[rl] = run;
+            run += cnt[i];
+        }
+        if (tid == 0) s_rstart[cn] = done + chunk;
+        __syncthreads();
+        for (uint32_t e = done + (uint32_t)tid; e < done + chunk; e += kEmitThreads) {
+            // largest k with s_rstart[k] <= e (rows without instances share the
+            // start of the next row, which the search prefers)
+            int lo = 0, hi = (int)cn - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= e) lo = mid;
+                if (s_rstart[mid] <= e) lo = mid;
                 else hi = mid - 1;
             }
-            int local = (int)(e - s_off[lo]);
-            int tx, ty;
-            if (table) {
-                uint32_t k = s_rbeg[lo];
-                const uint32_t kend = s_rbeg[lo + 1];
-                while (k + 1 < kend && s_rstart[k + 1] <= (uint32_t)local) ++k;
-                if (k < kend) {
-                    ty = (int)(s_rtile[k] >> 16);
-                    tx = (int)(s_rtile[k] & 0xFFFFu) + local - (int)s_rstart[k];
-                } else {
-                    tx = s_rect[lo].x;
-                    ty = s_rect[lo].y;
-                }
-            } else {
-                // the local-th tile of the culled rectangle, row by row (the
-                // same row intervals the preprocess counted)
-                const ushort4 r = s_rect[lo];
-                const CullRows c = s_cull[lo];
-                tx = r.x;
-                ty = r.y;
-                for (int row = r.y; row <= r.w; ++row) {
-                    int t0, t1;
-                    if (!cull_row(c, row, rp.tile_w, rp.tile_h, r.x, r.z, t0, t1)) continue;
-                    if (local <= t1 - t0) {
-                        tx = t0 + local;
-                        ty = row;
-                        break;
-                    }
-                    local -= t1 - t0 + 1;
-                }
-            }
+            const int g = s_rg[lo];
+            const ushort4 rr = s_rect[g];
             // the preprocess counted exactly these tiles; the clamp only keeps
             // a miscount (none is expected) inside the Gaussian's own rectangle
-            const ushort4 rr = s_rect[lo];
-            tx = min(max(tx, (int)rr.x), (int)rr.z);
-            ty = min(max(ty, (int)rr.y), (int)rr.w);
+            const int ty = min(max((int)(s_rtile[lo] >> 16), (int)rr.y), (int)rr.w);
+            const int tx = min(max((int)(s_rtile[lo] & 0xFFFFu) + (int)(e - s_rstart[lo]),
+                                   (int)rr.x), (int)rr.z);
             const int64_t pos = (int64_t)base + e;
             if (pos < capacity) {
-                b.inst_key[pos] = (uint32_t)(s_toff[lo] + ty * s_tx[lo] + tx);
-                b.inst_val[pos] = s_item[lo];
+                b.inst_key[pos] = (uint32_t)(s_toff[g] + ty * s_tx[g] + tx);
+                b.inst_val[pos] = s_item[g];
             }
         }
+        done += chunk;
+        __syncthreads();   // the next chunk rewrites the row tables
     }
 }
 

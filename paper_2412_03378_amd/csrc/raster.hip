@@ -536,14 +536,17 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             float acc[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[e] = e < 13 ? -0.0f : 0.0f;
-            bool touched = false;
+            // lane masks (wave-uniform) of the slot's passing and blending
+            // pixels; the branches test them directly
+            uint64_t touched = 0;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 float dy;
                 const bool inl = jpos <= last[k];
                 const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
                 const bool pass = inl && near;
-                const bool anyp = wave_any(pass);
+                const uint64_t pm = __builtin_amdgcn_ballot_w64(pass);
+                const bool anyp = pm != 0;
                 if (COUNT) {
                     n.test += inl ? 1u : 0u;
                     const bool anyl = wave_any(inl);
@@ -561,7 +564,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const float y = fr.K * un[k] * rq * ex;
                 const bool bl = pass && !(y < tau2);
                 if (COUNT) n.blend += bl ? 1u : 0u;
-                if (!wave_any(bl)) continue;                // wave-uniform
+                const uint64_t bm = __builtin_amdgcn_ballot_w64(!(y < tau2)) & pm;
+                if (bm == 0) continue;                      // wave-uniform
                 float dy_;
                 if constexpr (COLOR) {
                     const bool clamped = y > ymax;
@@ -583,7 +587,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 } else {
                     dy_ = bl ? g[k][0] * kLn2 : 0.0f;
                 }
-                touched |= bl;
+                touched |= bm;
                 // t = dL/d(ln x) = dL/dy * y (selected, not multiplied, to zero
                 // for lanes that do not blend); since ln x is ln K' plus terms
                 // free of K', the sum of t is K' dL/dK'
@@ -609,7 +613,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 acc[4] += __fmaf_rn(tp1, p2, tz1 * z2);
                 acc[5] += __fmaf_rn(tp2, p2, tz2 * z2);
             }
-            if (wave_any(touched)) {
+            if (touched != 0) {
                 const float tot = wave_reduce16(acc, lane);
                 if ((lane & 3) == 0)
                     atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
