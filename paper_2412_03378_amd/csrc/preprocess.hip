@@ -64,34 +64,41 @@ __device__ inline void sh_basis(int deg, float x, float y, float z, float *Y)
 }
 
 // Gradient of the same polynomials: G[k] = (dY/dx, dY/dy, dY/dz).
-__device__ inline void sh_basis_grad(int deg, float x, float y, float z, float3 *G)
+// sum_k w[k] grad Y_k at (x, y, z): the gradient of sum_k w[k] Y_k, from the
+// derivatives of the Cartesian polynomials of sh_basis, without forming the
+// 16 gradients.
+__device__ inline float3 sh_grad_dot(int deg, float x, float y, float z, const float *w)
 {
-    G[0] = make_float3(0.f, 0.f, 0.f);
-    if (deg < 1) return;
-    const float c1 = SHC(3.0f, 4.0f);
-    G[1] = make_float3(0.f, -c1, 0.f);
-    G[2] = make_float3(0.f, 0.f, c1);
-    G[3] = make_float3(-c1, 0.f, 0.f);
-    if (deg < 2) return;
-    const float a = 0.5f * SHC(15.0f, 1.0f), b = 0.25f * SHC(5.0f, 1.0f),
-                c = 0.25f * SHC(15.0f, 1.0f);
-    G[4] = make_float3(a * y, a * x, 0.f);
-    G[5] = make_float3(0.f, -a * z, -a * y);
-    G[6] = make_float3(-2.f * b * x, -2.f * b * y, 4.f * b * z);
-    G[7] = make_float3(-a * z, 0.f, -a * x);
-    G[8] = make_float3(2.f * c * x, -2.f * c * y, 0.f);
-    if (deg < 3) return;
-    const float d = 0.25f * SHC(35.0f, 2.0f), e = 0.5f * SHC(105.0f, 1.0f),
-                f = 0.25f * SHC(21.0f, 2.0f), g = 0.25f * SHC(7.0f, 1.0f),
-                h = 0.25f * SHC(105.0f, 1.0f);
-    const float xx = x * x, yy = y * y, zz = z * z;
-    G[9] = make_float3(-6.f * d * x * y, -3.f * d * (xx - yy), 0.f);
-    G[10] = make_float3(e * y * z, e * x * z, e * x * y);
-    G[11] = make_float3(2.f * f * x * y, -f * (4.f * zz - xx - 3.f * yy), -8.f * f * y * z);
-    G[12] = make_float3(-6.f * g * x * z, -6.f * g * y * z, g * (6.f * zz - 3.f * xx - 3.f * yy));
-    G[13] = make_float3(-f * (4.f * zz - 3.f * xx - yy), 2.f * f * x * y, -8.f * f * x * z);
-    G[14] = make_float3(2.f * h * x * z, -2.f * h * y * z, h * (xx - yy));
-    G[15] = make_float3(-3.f * d * (xx - yy), 6.f * d * x * y, 0.f);
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (deg >= 1) {
+        const float c1 = SHC(3.0f, 4.0f);
+        gy -= c1 * w[1];
+        gz += c1 * w[2];
+        gx -= c1 * w[3];
+    }
+    if (deg >= 2) {
+        const float a = 0.5f * SHC(15.0f, 1.0f), b = 0.25f * SHC(5.0f, 1.0f),
+                    c = 0.25f * SHC(15.0f, 1.0f);
+        const float a4 = a * w[4], a5 = a * w[5], b6 = b * w[6], a7 = a * w[7], c8 = c * w[8];
+        gx += a4 * y - 2.f * b6 * x - a7 * z + 2.f * c8 * x;
+        gy += a4 * x - a5 * z - 2.f * b6 * y - 2.f * c8 * y;
+        gz += -a5 * y + 4.f * b6 * z - a7 * x;
+    }
+    if (deg >= 3) {
+        const float d = 0.25f * SHC(35.0f, 2.0f), e = 0.5f * SHC(105.0f, 1.0f),
+                    f = 0.25f * SHC(21.0f, 2.0f), g = 0.25f * SHC(7.0f, 1.0f),
+                    h = 0.25f * SHC(105.0f, 1.0f);
+        const float xx = x * x, yy = y * y, zz = z * z;
+        const float d9 = d * w[9], e10 = e * w[10], f11 = f * w[11], g12 = g * w[12],
+                    f13 = f * w[13], h14 = h * w[14], d15 = d * w[15];
+        gx += -6.f * d9 * x * y + e10 * y * z + 2.f * f11 * x * y - 6.f * g12 * x * z -
+              f13 * (4.f * zz - 3.f * xx - yy) + 2.f * h14 * x * z - 3.f * d15 * (xx - yy);
+        gy += -3.f * d9 * (xx - yy) + e10 * x * z - f11 * (4.f * zz - xx - 3.f * yy) -
+              6.f * g12 * y * z + 2.f * f13 * x * y - 2.f * h14 * y * z + 6.f * d15 * x * y;
+        gz += e10 * x * y - 8.f * f11 * y * z + g12 * (6.f * zz - 3.f * xx - 3.f * yy) -
+              8.f * f13 * x * z + h14 * (xx - yy);
+    }
+    return make_float3(gx, gy, gz);
 }
 #undef SHC
 
@@ -825,30 +832,30 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
             const float il = 1.0f / len;
             vx *= il; vy *= il; vz *= il;
             float Y[16];
-            float3 G[16];
             sh_basis(DEG, vx, vy, vz, Y);
-            sh_basis_grad(DEG, vx, vy, vz, G);
             float c3[NF];
             load_sh_row<NF>(sh, i, ((uintptr_t)sh & 15) == 0, c3);
-            float gv[3] = { 0.f, 0.f, 0.f };
+            float graw[3];
+#pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float raw = 0.5f;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) raw = fmaf(c3[k * 3 + ch], Y[k], raw);
-                const float graw = gr[10 + ch] * act_grad(rp.act, raw);
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    gsh[k * 3 + ch] += graw * Y[k];
-                    const float w = graw * c3[k * 3 + ch];
-                    gv[0] += w * G[k].x;
-                    gv[1] += w * G[k].y;
-                    gv[2] += w * G[k].z;
-                }
+                graw[ch] = gr[10 + ch] * act_grad(rp.act, raw);
             }
-            const float vg = vx * gv[0] + vy * gv[1] + vz * gv[2];
-            gmu[0] += (gv[0] - vx * vg) * il;
-            gmu[1] += (gv[1] - vy * vg) * il;
-            gmu[2] += (gv[2] - vz * vg) * il;
+            // the direction gradient is sum_k w_k grad Y_k with w_k = sum_ch graw c_k
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                wk[k] = graw[0] * c3[k * 3] + graw[1] * c3[k * 3 + 1] + graw[2] * c3[k * 3 + 2];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) gsh[k * 3 + ch] += graw[ch] * Y[k];
+            }
+            const float3 gv = sh_grad_dot(DEG, vx, vy, vz, wk);
+            const float vg = vx * gv.x + vy * gv.y + vz * gv.z;
+            gmu[0] += (gv.x - vx * vg) * il;
+            gmu[1] += (gv.y - vy * vg) * il;
+            gmu[2] += (gv.z - vz * vg) * il;
         }
     }
     // acc: add to the caller's arrays; otherwise overwrite them (no read)
