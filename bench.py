@@ -37,7 +37,10 @@ if ROOT not in sys.path:
 #   backward of blended pairs: compositing replay (clamp, exp2, rcp, T,
 #     g.c, dL/dalpha, colour gradient, g.(colour behind) update) 25 (X-ray:
 #     1), moment accumulation (t, sum t, z = mz (w x n)/|w|^2, w/|w|, Z, M) 54
-F_TEST, F_SHARED, F_FULL = 7, 8, 46
+#   a backward that reuses the forward's pre-test masks (colour mode, or one
+#     pixel per lane) tests nothing and recomputes d_x, d_y (4) per pair past
+#     the pre-test                                                      4
+F_TEST, F_SHARED, F_FULL, F_OFFSETS = 7, 8, 46, 4
 F_BLEND_FWD = {"color": 12, "xray": 1}
 F_BLEND_BWD = {"color": 25 + 54, "xray": 1 + 54}
 PEAK_FP32 = 157.3e12    # MI355X published FP32 vector peak (FLOP/s)
@@ -67,7 +70,8 @@ def _traffic(kernel):
 
 def _flops(tested, full, blended, ppl, mode, direction):
     fb = F_BLEND_FWD[mode] if direction == "fwd" else F_BLEND_BWD[mode]
-    return tested * (F_TEST + F_SHARED / ppl) + full * F_FULL + blended * fb
+    offs = F_OFFSETS if direction == "bwd" and (mode == "color" or ppl == 1) else 0
+    return tested * (F_TEST + F_SHARED / ppl) + full * (F_FULL + offs) + blended * fb
 
 
 def _device_scene(sc, dev, torch):

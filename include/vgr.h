@@ -104,7 +104,11 @@ typedef struct {
     int64_t visits_full;     /*   steps, and those that took the evaluation   */
                              /*   branch (some pixel passed the bound test)   */
     int64_t bwd_pairs_tested;   /* the same five counts for the backward   */
-    int64_t bwd_pairs_full;     /*   rasteriser of the last backward       */
+    int64_t bwd_pairs_full;     /*   rasteriser of the last backward (no    */
+                                /*   pairs tested, and visits = evaluation */
+                                /*   steps, where it reuses the forward's  */
+                                /*   bound-test masks: colour mode, or one */
+                                /*   pixel per lane)                       */
     int64_t bwd_pairs_blended;
     int64_t bwd_visits;
     int64_t bwd_visits_full;

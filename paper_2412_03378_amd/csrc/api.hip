@@ -36,7 +36,7 @@ struct vgr_ctx {
 
     // workspace
     DevBuf geom, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
-    DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id;
+    DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id, pmask;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts;
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
@@ -216,6 +216,7 @@ Buffers make_buffers(vgr_ctx *c)
     b.inst_val = ptr<uint32_t>(c->inst_val);
     b.inst_key2 = ptr<uint32_t>(c->inst_key2);
     b.inst_val2 = ptr<uint32_t>(c->inst_val2);
+    b.pmask = ptr<uint64_t>(c->pmask);
     b.ranges = ptr<uint2>(c->ranges);
     b.tile_key = ptr<uint32_t>(c->tile_key);
     b.tile_order = ptr<uint32_t>(c->tile_order);
@@ -295,7 +296,7 @@ void vgr_destroy(vgr_ctx *c)
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     DevBuf *all[] = { &c->views_graph, &c->geom, &c->depth_key, &c->item_ids, &c->key2, &c->item2,
                       &c->counts, &c->cnt_sorted, &c->offsets, &c->rect, &c->inst_key,
-                      &c->inst_val, &c->inst_key2, &c->inst_val2, &c->ranges, &c->T_final,
+                      &c->inst_val, &c->inst_key2, &c->inst_val2, &c->pmask, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
                       &c->words, &c->counters, &c->views, &c->blk_counts };
@@ -539,6 +540,13 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     HIP_TRY(c, launch_ranges(b, K, rp.total_tiles, s));
     HIP_TRY(c, launch_tile_order(b, rp.total_tiles, ptr<uint32_t>(c->sort_tmp), s));
     mark_end(c, ST_RANGES);
+    if (cap < 0 && raster_keeps_masks(rp.mode, rp.tile_w, rp.tile_h)) {
+        // (a capture sizes this buffer for its capacity before it starts)
+        if ((rc = ensure(c, c->pmask,
+                         8 * (size_t)pmask_words(K, rp.total_tiles, rp.tile_w, rp.tile_h))))
+            return rc;
+        b.pmask = ptr<uint64_t>(c->pmask);
+    }
     if (c->counting)
         HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
     mark(c, ST_RASTER_FWD);
@@ -752,6 +760,10 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
         (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(cap > p.sort_n ? cap : p.sort_n))) ||
         (rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1))) ||
         (rc = ensure(c, c->views_graph, sizeof(ViewInfo) * kMaxViews)))
+        return rc;
+    if (raster_keeps_masks(p.rp.mode, p.rp.tile_w, p.rp.tile_h) &&
+        (rc = ensure(c, c->pmask,
+                     8 * (size_t)pmask_words(cap, p.rp.total_tiles, p.rp.tile_w, p.rp.tile_h))))
         return rc;
     c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
     for (int v = 0; v < n_views; ++v) {

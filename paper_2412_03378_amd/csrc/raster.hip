@@ -8,10 +8,14 @@
 // forward with one pixel per lane) pre-tests the whole batch with broadcast
 // reads and then lets every lane evaluate its own passing records in order
 // (per-lane reads), so that an evaluation step is not spent on lanes whose
-// pixel the record misses; the X-ray forward with several pixels per lane,
-// and the backward (whose per-Gaussian reduction needs the wave on one
-// record), walk the batch together, reading the three float4 of the bound
-// pre-test first and the other three only when some pixel of the slot passes.
+// pixel the record misses; it keeps each lane's pass mask of the batch for
+// the backward.  The X-ray forward with several pixels per lane walks the
+// batch together, reading the three float4 of the bound pre-test first and
+// the other three only when some pixel of the slot passes.  The backward
+// (whose per-Gaussian reduction needs the wave on one record) walks the
+// batch together too: where the forward kept its masks, it visits only the
+// records that the union of the lanes' masks names; otherwise it pre-tests
+// each record as the X-ray forward does.
 //
 // Per (pixel, Gaussian) pair, with the record (centre h + l, A, v0, mz, K',
 // bound form Q, l; see vgr_internal.h) and d = pixel centre - h - l:
@@ -260,6 +264,10 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     }
                 }
             }
+            // kept for the backward (layout: raster_keeps_masks)
+    #pragma unroll
+            for (int k = 0; k < PPL; ++k)
+                b.pmask[((size_t)bs + 64 * (size_t)gt + lane) * PPL + k] = mask[k];
             // Phase 2: every lane evaluates and blends its own passing records in
             // list order, one per step (records read from LDS at per-lane
             // addresses), so a step does useful work on every lane that still has
@@ -436,10 +444,20 @@ constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor2 = 0x4E;
 constexpr int kDppQuadXor1 = 0xB1;
 
+constexpr int kDppRowRor4 = 0x124;
+constexpr int kDppRowRor2 = 0x122;
+constexpr int kDppRowRor1 = 0x121;
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_move_u(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
@@ -475,6 +493,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     constexpr int RS = TileMap<TW, TH>::RS;
     constexpr bool COLOR = MODE == VGR_MODE_COLOR;
     constexpr int NCH = COLOR ? 3 : 1;
+    // the forward kept its pre-test masks for this shape and mode
+    constexpr bool KEEP = COLOR || PPL == 1;
     __shared__ Stage st;
 
     const int gt = (int)b.tile_order[blockIdx.x];
@@ -522,104 +542,165 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     const float tau2 = rp.tau2, ymax = rp.ymax;
     float *rg = reinterpret_cast<float *>(b.rgrad);
 
-    for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
-        const int bs = max((int)range.x, be - 64);
-        const int j = bs + lane;
-        if (j < be) stage_record(st, b, lane, b.inst_val[j]);
-        __syncthreads();
-        for (int qi = be - 1 - bs; qi >= 0; --qi) {
-            const int jpos = bs + qi;
-            const PreRec pr = load_pre(st, qi);
-            const ColTerms ct = col_terms(pr, pxc);
-            // -0 is the exact identity of addition, so the first term of each
-            // sum needs no add
-            float acc[16];
+    // One record of the batch against the lane's pixels: pass[k] marks the
+    // slots whose pixel the bound pre-test admits (dy is recomputed here).
+    auto record = [&](int qi, const PreRec &pr, float dx, const bool (&pass)[PPL]) {
+        float acc[16];
+        // -0 is the exact identity of addition, so the first term of each
+        // sum needs no add
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[e] = e < 13 ? -0.0f : 0.0f;
-            // lane masks (wave-uniform) of the slot's passing and blending
-            // pixels; the branches test them directly
-            uint64_t touched = 0;
+        for (int e = 0; e < 16; ++e) acc[e] = e < 13 ? -0.0f : 0.0f;
+        // lane masks (wave-uniform) of the slot's passing and blending
+        // pixels; the branches test them directly
+        uint64_t touched = 0;
+        const FullRec fr = load_full(st, qi);
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const uint64_t pm = __builtin_amdgcn_ballot_w64(pass[k]);
+            if (COUNT) n.visits_full += (lane == 0 && pm != 0) ? 1u : 0u;
+            if (pm == 0) continue;                  // wave-uniform
+            if (COUNT) n.full += pass[k] ? 1u : 0u;
+            const float dy = (pyc[k] - pr.hy) - pr.ly;
+            PairGeom pg;
+            pair_geom(pr, fr, dx, dy, pg);
+            const float rq = fast_rsq(pg.qw);
+            const float rq2 = rq * rq;
+            const float ex = fast_exp2(-(fr.se * pg.num * rq2));
+            const float y = fr.K * un[k] * rq * ex;
+            const bool bl = pass[k] && !(y < tau2);
+            if (COUNT) n.blend += bl ? 1u : 0u;
+            const uint64_t bm = __builtin_amdgcn_ballot_w64(!(y < tau2)) & pm;
+            if (bm == 0) continue;                      // wave-uniform
+            float dy_;
+            if constexpr (COLOR) {
+                const bool clamped = y > ymax;
+                const float om = fast_exp2(-(clamped ? ymax : y));
+                const float inv = fast_rcp(om);
+                const float alpha = 1.0f - om;
+                const float Tb = T[k] * inv;
+                // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
+                const float gc = __fmaf_rn(g[k][0], fr.c0,
+                                           __fmaf_rn(g[k][1], fr.c1, g[k][2] * fr.c2));
+                const float da = __fmaf_rn(Tb, gc, -(inv * GB[k]));
+                const float wgt = bl ? alpha * Tb : 0.0f;
+                acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
+                acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
+                acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
+                GB[k] = __fmaf_rn(gc, wgt, GB[k]);
+                T[k] = bl ? Tb : T[k];
+                dy_ = (bl && !clamped) ? da * kLn2 * om : 0.0f;
+            } else {
+                dy_ = bl ? g[k][0] * kLn2 : 0.0f;
+            }
+            touched |= bm;
+            // t = dL/d(ln x) = dL/dy * y (selected, not multiplied, to zero
+            // for lanes that do not blend); since ln x is ln K' plus terms
+            // free of K', the sum of t is K' dL/dK'
+            const float t = bl ? dy_ * y : 0.0f;
+            acc[9] += t;
+            // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|;
+            // M += t (w' w'^T + z z^T) as (t w') w'^T + (t z) z^T (t is zero,
+            // and z finite, on lanes that do not blend)
+            const float cz = fr.mz * rq2;
+            const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);
+            const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
+            const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
+            const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
+            const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
+            const float tp0 = t * p0, tp1 = t * p1, tp2 = t * p2;
+            acc[6] += tz0;
+            acc[7] += tz1;
+            acc[8] += tz2;
+            acc[0] += __fmaf_rn(tp0, p0, tz0 * z0);
+            acc[1] += __fmaf_rn(tp0, p1, tz0 * z1);
+            acc[2] += __fmaf_rn(tp0, p2, tz0 * z2);
+            acc[3] += __fmaf_rn(tp1, p1, tz1 * z1);
+            acc[4] += __fmaf_rn(tp1, p2, tz1 * z2);
+            acc[5] += __fmaf_rn(tp2, p2, tz2 * z2);
+        }
+        if (touched != 0) {
+            const float tot = wave_reduce16(acc, lane);
+            if ((lane & 3) == 0)
+                atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
+        }
+    };
+
+    if constexpr (KEEP) {
+        // Batches aligned as in the forward, whose pre-test masks are reused:
+        // the walk visits only records some pixel of the tile admits.
+        for (int bs = (int)range.x + ((maxlast - (int)range.x) & ~63); bs >= (int)range.x;
+             bs -= 64) {
+            const int j = bs + lane;
+            if (j <= maxlast) stage_record(st, b, lane, b.inst_val[j]);
+            uint64_t mask[PPL];
+            uint64_t any = 0;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                float dy;
-                const bool inl = jpos <= last[k];
-                const bool near = pre_test(pr, ct, pyc[k], dy);   // always evaluated: sets dy
-                const bool pass = inl && near;
-                const uint64_t pm = __builtin_amdgcn_ballot_w64(pass);
-                const bool anyp = pm != 0;
-                if (COUNT) {
-                    n.test += inl ? 1u : 0u;
-                    const bool anyl = wave_any(inl);
-                    n.visits += (lane == 0 && anyl) ? 1u : 0u;
-                    n.visits_full += (lane == 0 && anyp) ? 1u : 0u;
-                }
-                if (!anyp) continue;                  // wave-uniform
-                if (COUNT) n.full += pass ? 1u : 0u;
-                const FullRec fr = load_full(st, qi);
-                PairGeom pg;
-                pair_geom(pr, fr, ct.dx, dy, pg);
-                const float rq = fast_rsq(pg.qw);
-                const float rq2 = rq * rq;
-                const float ex = fast_exp2(-(fr.se * pg.num * rq2));
-                const float y = fr.K * un[k] * rq * ex;
-                const bool bl = pass && !(y < tau2);
-                if (COUNT) n.blend += bl ? 1u : 0u;
-                const uint64_t bm = __builtin_amdgcn_ballot_w64(!(y < tau2)) & pm;
-                if (bm == 0) continue;                      // wave-uniform
-                float dy_;
-                if constexpr (COLOR) {
-                    const bool clamped = y > ymax;
-                    const float om = fast_exp2(-(clamped ? ymax : y));
-                    const float inv = fast_rcp(om);
-                    const float alpha = 1.0f - om;
-                    const float Tb = T[k] * inv;
-                    // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
-                    const float gc = __fmaf_rn(g[k][0], fr.c0,
-                                               __fmaf_rn(g[k][1], fr.c1, g[k][2] * fr.c2));
-                    const float da = __fmaf_rn(Tb, gc, -(inv * GB[k]));
-                    const float wgt = bl ? alpha * Tb : 0.0f;
-                    acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
-                    acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
-                    acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
-                    GB[k] = __fmaf_rn(gc, wgt, GB[k]);
-                    T[k] = bl ? Tb : T[k];
-                    dy_ = (bl && !clamped) ? da * kLn2 * om : 0.0f;
-                } else {
-                    dy_ = bl ? g[k][0] * kLn2 : 0.0f;
-                }
-                touched |= bm;
-                // t = dL/d(ln x) = dL/dy * y (selected, not multiplied, to zero
-                // for lanes that do not blend); since ln x is ln K' plus terms
-                // free of K', the sum of t is K' dL/dK'
-                const float t = bl ? dy_ * y : 0.0f;
-                acc[9] += t;
-                // z = mz (w x n) / |w|^2 = L (m - gamma u);  w' = w / |w|;
-                // M += t (w' w'^T + z z^T) as (t w') w'^T + (t z) z^T (t is zero,
-                // and z finite, on lanes that do not blend)
-                const float cz = fr.mz * rq2;
-                const float z0 = cz * (pg.w1 * pg.n2 - pg.w2 * pg.n1);
-                const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
-                const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
-                const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
-                const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
-                const float tp0 = t * p0, tp1 = t * p1, tp2 = t * p2;
-                acc[6] += tz0;
-                acc[7] += tz1;
-                acc[8] += tz2;
-                acc[0] += __fmaf_rn(tp0, p0, tz0 * z0);
-                acc[1] += __fmaf_rn(tp0, p1, tz0 * z1);
-                acc[2] += __fmaf_rn(tp0, p2, tz0 * z2);
-                acc[3] += __fmaf_rn(tp1, p1, tz1 * z1);
-                acc[4] += __fmaf_rn(tp1, p2, tz1 * z2);
-                acc[5] += __fmaf_rn(tp2, p2, tz2 * z2);
+                // records of the batch up to the pixel's last blended one
+                const int d = last[k] - bs;
+                const uint64_t lim = d < 0 ? 0ull : (d >= 63 ? ~0ull : (2ull << d) - 1ull);
+                mask[k] = b.pmask[((size_t)bs + 64 * (size_t)gt + lane) * PPL + k] & lim;
+                any |= mask[k];
             }
-            if (touched != 0) {
-                const float tot = wave_reduce16(acc, lane);
-                if ((lane & 3) == 0)
-                    atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
+            // union over the wave: OR within each row of 16 lanes, then of the rows
+            uint32_t lo = (uint32_t)any, hi = (uint32_t)(any >> 32);
+            lo |= dpp_move_u<kDppRowRor8>(lo);
+            hi |= dpp_move_u<kDppRowRor8>(hi);
+            lo |= dpp_move_u<kDppRowRor4>(lo);
+            hi |= dpp_move_u<kDppRowRor4>(hi);
+            lo |= dpp_move_u<kDppRowRor2>(lo);
+            hi |= dpp_move_u<kDppRowRor2>(hi);
+            lo |= dpp_move_u<kDppRowRor1>(lo);
+            hi |= dpp_move_u<kDppRowRor1>(hi);
+            const uint32_t ulo = __builtin_amdgcn_readlane(lo, 0) | __builtin_amdgcn_readlane(lo, 16) |
+                                 __builtin_amdgcn_readlane(lo, 32) | __builtin_amdgcn_readlane(lo, 48);
+            const uint32_t uhi = __builtin_amdgcn_readlane(hi, 0) | __builtin_amdgcn_readlane(hi, 16) |
+                                 __builtin_amdgcn_readlane(hi, 32) | __builtin_amdgcn_readlane(hi, 48);
+            uint64_t u = ((uint64_t)uhi << 32) | ulo;   // wave-uniform
+            __syncthreads();
+            while (u != 0) {
+                const int qi = 63 - __builtin_clzll(u);
+                u &= ~(1ull << qi);
+                if (COUNT) n.visits += lane == 0 ? 1u : 0u;
+                const RecRegs rr = load_regs(st, qi);
+                const PreRec pr = pre_of(rr);
+                const float dx = (pxc - pr.hx) - pr.lx;
+                bool pass[PPL];
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) pass[k] = (mask[k] >> qi) & 1u;
+                record(qi, pr, dx, pass);
             }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
+            const int bs = max((int)range.x, be - 64);
+            const int j = bs + lane;
+            if (j < be) stage_record(st, b, lane, b.inst_val[j]);
+            __syncthreads();
+            for (int qi = be - 1 - bs; qi >= 0; --qi) {
+                const int jpos = bs + qi;
+                const PreRec pr = load_pre(st, qi);
+                const ColTerms ct = col_terms(pr, pxc);
+                bool pass[PPL];
+                bool anyp = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    float dy;
+                    const bool inl = jpos <= last[k];
+                    pass[k] = inl && pre_test(pr, ct, pyc[k], dy);
+                    anyp |= pass[k];
+                    if (COUNT) {
+                        n.test += inl ? 1u : 0u;
+                        const bool anyl = wave_any(inl);
+                        n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                    }
+                }
+                if (!wave_any(anyp)) continue;             // wave-uniform
+                record(qi, pr, ct.dx, pass);
+            }
+            __syncthreads();
+        }
     }
     if (COUNT) {
         atomicAdd(&b.counters[8], (unsigned long long)n.test);

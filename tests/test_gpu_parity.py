@@ -120,7 +120,7 @@ def test_forward_deterministic(R, dev, cfg1):
 
 # ------------------------------------------------------ config 1 backward ---
 
-@pytest.mark.parametrize("act,tile", [("clamp", (16, 16)), ("softplus", (8, 8))])
+@pytest.mark.parametrize("act,tile", [("clamp", (16, 16)), ("softplus", (8, 8)), ("clamp", (32, 8))])
 def test_config1_backward(R, dev, cfg1, act, tile):
     sc, cam = cfg1.scene, cfg1.cams[0]
     st = _settings(act=act, tile=tile, bg=(0.1, 0.2, 0.3))
@@ -148,9 +148,12 @@ def _xray_small(n=3000, size=96, views=3, seed=4):
     return wl.scene, [wl.cams[k] for k in (0, 16, 40)][:views]
 
 
-def test_xray_forward_backward(R, dev):
+# 8x8 tiles: the backward reuses the forward's pre-test masks (one pixel per
+# lane); 16x16: it runs its own pre-test
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_xray_forward_backward(R, dev, tile):
     sc, cams = _xray_small()
-    st = _settings(mode="xray")
+    st = _settings(mode="xray", tile=tile)
     ost = _oset(st)
     t = G.device_scene(sc, dev)
     imgs = R.forward(*t, cams, st)
