@@ -245,25 +245,35 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         if constexpr (PPL == 1 || COLOR) {
             // Phase 1: bound pre-test of the whole batch (broadcast records);
             // bit q of mask[k] marks record q as passing for the lane's slot k.
-            uint64_t mask[PPL];
+            // The two 32-record halves fill 32-bit words, each bit set by one
+            // select of a wave-uniform constant.
+            uint32_t mhalf[2][PPL];
     #pragma unroll
-            for (int k = 0; k < PPL; ++k) mask[k] = 0;
-            for (int qi = 0; qi < nb; ++qi) {
-                const float4 g0 = st.g[0][qi], g1 = st.g[1][qi], g2 = st.g[2][qi];
-                const PreRec pr = pre_of4(g0, g1, g2);
-                const ColTerms ct = col_terms(pr, pxc);
+            for (int h = 0; h < 2; ++h) {
     #pragma unroll
-                for (int k = 0; k < PPL; ++k) {
-                    float dy;
-                    const bool pass = act[k] && pre_test(pr, ct, pyc[k], dy);
-                    mask[k] |= (uint64_t)(pass ? 1u : 0u) << qi;
-                    if (COUNT) {
-                        n.test += act[k] ? 1u : 0u;
-                        const bool anyl = wave_any(act[k]);
-                        n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                for (int k = 0; k < PPL; ++k) mhalf[h][k] = 0u;
+                const int qend = min(nb, 32 * h + 32);
+                for (int qi = 32 * h; qi < qend; ++qi) {
+                    const float4 g0 = st.g[0][qi], g1 = st.g[1][qi], g2 = st.g[2][qi];
+                    const PreRec pr = pre_of4(g0, g1, g2);
+                    const ColTerms ct = col_terms(pr, pxc);
+                    const uint32_t bit = 1u << (qi & 31);
+    #pragma unroll
+                    for (int k = 0; k < PPL; ++k) {
+                        float dy;
+                        const bool pass = act[k] && pre_test(pr, ct, pyc[k], dy);
+                        mhalf[h][k] |= pass ? bit : 0u;
+                        if (COUNT) {
+                            n.test += act[k] ? 1u : 0u;
+                            const bool anyl = wave_any(act[k]);
+                            n.visits += (lane == 0 && anyl) ? 1u : 0u;
+                        }
                     }
                 }
             }
+            uint64_t mask[PPL];
+    #pragma unroll
+            for (int k = 0; k < PPL; ++k) mask[k] = ((uint64_t)mhalf[1][k] << 32) | mhalf[0][k];
             // kept for the backward (layout: raster_keeps_masks)
     #pragma unroll
             for (int k = 0; k < PPL; ++k)
