@@ -172,6 +172,14 @@ def bench_batched(args, torch, dev):
     st = Settings(sh_degree=3, tile=tile)
     res = {"tile": list(tile), "autotune_ms": [round(x, 3) for x in tune_ms]}
     _log("batched views, one captured graph")
+    # load balance over the compute units (instrumented kernels, one eager call)
+    r.set_counting(True)
+    r.forward(*params, wl.cams, st)
+    r.backward(dLs, *grads, accumulate=False)
+    s = r.stats()
+    r.set_counting(False)
+    res["load_balance"] = {"raster_fwd": round(s["load_balance_fwd"], 3),
+                           "raster_bwd": round(s["load_balance_bwd"], 3)}
     r.graph_capture(params, wl.cams, st, outs, dLs, grads, capacity_factor=1.1, zero_grads=True)
     res["batched"] = nv / _graph_time(r, args.batched_steps, torch)
     _log("single-view calls")
@@ -418,6 +426,9 @@ def main():
                                              "bwd_pairs_full", "bwd_pairs_blended", "bwd_visits",
                                              "bwd_visits_full")},
         "roofline": h["roofline"],
+        # per compute unit: summed workgroup durations of each rasteriser, max / mean
+        "load_balance": {"raster_fwd": round(h["stats"]["load_balance_fwd"], 3),
+                         "raster_bwd": round(h["stats"]["load_balance_bwd"], 3)},
     }
     if not args.no_batched:
         torch.cuda.empty_cache()
@@ -429,7 +440,8 @@ def main():
                           "tile_single": res["tile_single"],
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
-                          "speedup": round(res["batched"] / res["single"], 3)}
+                          "speedup": round(res["batched"] / res["single"], 3),
+                          "load_balance": res["load_balance"]}
     if not args.no_xray:
         torch.cuda.empty_cache()
         out["xray"] = bench_xray(args, torch, dev)

@@ -115,6 +115,10 @@ typedef struct {
     int32_t overflow;        /* 1 if a fixed-capacity run dropped instances */
     int32_t tile_w, tile_h;  /* tile used */
     int32_t n_views;
+    double load_balance_fwd; /* filled when pair counting is on: per compute */
+    double load_balance_bwd; /*   unit, the summed durations of its raster   */
+                             /*   workgroups; max over mean (1 = balanced;    */
+                             /*   0 if that rasteriser has not run counting)  */
 } vgr_stats;
 
 typedef struct vgr_ctx vgr_ctx;

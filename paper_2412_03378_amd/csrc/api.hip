@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "vgr_internal.h"
@@ -38,7 +39,7 @@ struct vgr_ctx {
     DevBuf geom, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id, pmask;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
-    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts;
+    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts, wg_time;
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
@@ -229,6 +230,7 @@ Buffers make_buffers(vgr_ctx *c)
     b.d_total = ptr<uint32_t>(c->words);
     b.blk_counts = ptr<uint32_t>(c->blk_counts);
     b.counters = ptr<unsigned long long>(c->counters);
+    b.wg_time = ptr<uint2>(c->wg_time);
     b.views = ptr<ViewInfo>(c->views);
     return b;
 }
@@ -299,7 +301,7 @@ void vgr_destroy(vgr_ctx *c)
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->pmask, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
-                      &c->words, &c->counters, &c->views, &c->blk_counts };
+                      &c->words, &c->counters, &c->views, &c->blk_counts, &c->wg_time };
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (c->h_views) (void)hipHostFree(c->h_views);
@@ -547,8 +549,14 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
             return rc;
         b.pmask = ptr<uint64_t>(c->pmask);
     }
-    if (c->counting)
+    if (c->counting) {
+        if ((rc = ensure(c, c->wg_time, 16 * (size_t)(rp.total_tiles > 0 ? rp.total_tiles : 1))))
+            return rc;
+        b.wg_time = ptr<uint2>(c->wg_time);
         HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.wg_time), 0u,
+                                   4 * (int64_t)rp.total_tiles, s));
+    }
     mark(c, ST_RASTER_FWD);
     HIP_TRY(c, launch_raster_fwd(rp, b, c->counting, s));
     mark_end(c, ST_RASTER_FWD);
@@ -695,6 +703,28 @@ int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
     out->tile_w = c->rp.tile_w;
     out->tile_h = c->rp.tile_h;
     out->n_views = c->rp.n_views;
+    // load balance of the rasterisers: per compute unit, the summed durations
+    // of its workgroups; max over mean
+    const int32_t T = c->rp.total_tiles;
+    if (c->counting && T > 0 && c->wg_time.bytes >= 16 * (size_t)T) {
+        std::vector<uint32_t> wt(4 * (size_t)T);
+        HIP_TRY(c, hipMemcpy(wt.data(), c->wg_time.p, 16 * (size_t)T, hipMemcpyDeviceToHost));
+        for (int dir = 0; dir < 2; ++dir) {
+            std::map<uint32_t, double> busy;
+            for (int32_t k = 0; k < T; ++k) {
+                const uint32_t key = wt[2 * ((size_t)dir * T + k)];
+                const uint32_t dur = wt[2 * ((size_t)dir * T + k) + 1];
+                if (dur) busy[key] += dur;
+            }
+            double mx = 0.0, sum = 0.0;
+            for (const auto &kv : busy) {
+                mx = kv.second > mx ? kv.second : mx;
+                sum += kv.second;
+            }
+            const double lb = busy.empty() || sum <= 0.0 ? 0.0 : mx / (sum / busy.size());
+            (dir == 0 ? out->load_balance_fwd : out->load_balance_bwd) = lb;
+        }
+    }
     // visible (Gaussian, view) items = items with a nonzero tile count
     const int64_t m = c->rp.n * c->rp.n_views;
     if (m > 0) {

@@ -53,6 +53,18 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Counting runs time each workgroup: the constant-rate realtime counter at
+// start and end, and a key of the compute unit it ran on (XCC id, then the
+// shader engine, array and CU fields of HW_ID), so that the host can sum the
+// busy time per compute unit (load balance).
+__device__ __forceinline__ uint64_t wg_clock() { return __builtin_amdgcn_s_memrealtime(); }
+__device__ __forceinline__ uint32_t cu_key()
+{
+    const uint32_t hw = __builtin_amdgcn_s_getreg(4 | (31 << 11));    // HW_ID
+    const uint32_t xcc = __builtin_amdgcn_s_getreg(20 | (3 << 11));   // XCC_ID[3:0]
+    return (xcc << 8) | ((hw >> 8) & 0xFFu);
+}
+
 // True if p holds on any active lane: a ballot of the predicate's lane mask,
 // which the branch tests directly.
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
@@ -207,6 +219,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     constexpr bool COLOR = MODE == VGR_MODE_COLOR;
     __shared__ Stage st;
 
+    const uint64_t t_start = COUNT ? wg_clock() : 0;
     const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
@@ -419,6 +432,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         atomicAdd(&b.counters[2], (unsigned long long)n.blend);
         atomicAdd(&b.counters[3], (unsigned long long)n.visits);
         atomicAdd(&b.counters[4], (unsigned long long)n.visits_full);
+        if (lane == 0)
+            b.wg_time[blockIdx.x] = make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
     }
 }
 
@@ -507,6 +522,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     constexpr bool KEEP = COLOR || PPL == 1;
     __shared__ Stage st;
 
+    const uint64_t t_start = COUNT ? wg_clock() : 0;
     const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
@@ -548,7 +564,12 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off, 64));
-    if (maxlast < (int)range.x) return;   // uniform: no pixel of this tile blended anything
+    if (maxlast < (int)range.x) {   // uniform: no pixel of this tile blended anything
+        if (COUNT && lane == 0)
+            b.wg_time[rp.total_tiles + blockIdx.x] =
+                make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
+        return;
+    }
     const float tau2 = rp.tau2, ymax = rp.ymax;
     float *rg = reinterpret_cast<float *>(b.rgrad);
 
@@ -718,6 +739,9 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
         atomicAdd(&b.counters[10], (unsigned long long)n.blend);
         atomicAdd(&b.counters[11], (unsigned long long)n.visits);
         atomicAdd(&b.counters[12], (unsigned long long)n.visits_full);
+        if (lane == 0)
+            b.wg_time[rp.total_tiles + blockIdx.x] =
+                make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
     }
 }
 
