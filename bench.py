@@ -123,6 +123,10 @@ def bench_headline(args, torch, dev):
     r.set_counting(True)
     _step(r, params, grads, cams, st, dLs)
     stats = r.stats()
+    r.set_counting(False, wg_timing=True)
+    _step(r, params, grads, cams, st, dLs)
+    lb = r.stats()
+    stats["load_balance_fwd"], stats["load_balance_bwd"] = lb["load_balance_fwd"], lb["load_balance_bwd"]
     r.set_counting(False)
     ppl = tile[0] * tile[1] / 64.0
     fl_fwd = _flops(stats["pairs_tested"], stats["pairs_full"], stats["pairs_blended"], ppl,
@@ -172,8 +176,8 @@ def bench_batched(args, torch, dev):
     st = Settings(sh_degree=3, tile=tile)
     res = {"tile": list(tile), "autotune_ms": [round(x, 3) for x in tune_ms]}
     _log("batched views, one captured graph")
-    # load balance over the compute units (instrumented kernels, one eager call)
-    r.set_counting(True)
+    # load balance over the compute units (workgroup timing, one eager call)
+    r.set_counting(False, wg_timing=True)
     r.forward(*params, wl.cams, st)
     r.backward(dLs, *grads, accumulate=False)
     s = r.stats()

@@ -115,10 +115,10 @@ typedef struct {
     int32_t overflow;        /* 1 if a fixed-capacity run dropped instances */
     int32_t tile_w, tile_h;  /* tile used */
     int32_t n_views;
-    double load_balance_fwd; /* filled when pair counting is on: per compute */
-    double load_balance_bwd; /*   unit, the summed durations of its raster   */
-                             /*   workgroups; max over mean (1 = balanced;    */
-                             /*   0 if that rasteriser has not run counting)  */
+    double load_balance_fwd; /* after a forward timed by vgr_set_counting bit */
+    double load_balance_bwd; /*   1: per compute unit, the summed durations  */
+                             /*   of its raster workgroups, max over mean    */
+                             /*   (1 = balanced; 0 if not timed)             */
 } vgr_stats;
 
 typedef struct vgr_ctx vgr_ctx;
@@ -189,8 +189,11 @@ int vgr_get_aux(vgr_ctx *ctx, int32_t view, float *T_final, int32_t *last_index)
  * (vgr_set_counting) the pair counters of the rasteriser are filled. */
 int vgr_get_stats(vgr_ctx *ctx, vgr_stats *out);
 
-/* Turn pair counting in the rasterisers on (1) or off (0).  Counting runs
- * separate instrumented kernel variants; timing runs keep it off. */
+/* Bit 0: pair counting in the rasterisers (separate instrumented kernel
+ * variants; timing runs keep it off).  Bit 1: the rasterisers of eager calls
+ * record each workgroup's duration and compute unit, for the load balance in
+ * vgr_stats (the production kernels, two clock reads and one store per
+ * workgroup).  0 turns both off. */
 int vgr_set_counting(vgr_ctx *ctx, int enable);
 
 /* Stage timing with HIP events recorded on the context's stream around each

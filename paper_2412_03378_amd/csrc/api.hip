@@ -58,6 +58,8 @@ struct vgr_ctx {
                 *sh = nullptr;
 
     bool counting = false;
+    bool wg_timing = false;     // time each rasteriser workgroup (load balance)
+    bool wg_timed = false;      // the last forward was timed so
     bool timing = false;
     // timing: one set of events per forward / backward call since timing was
     // switched on; stage st spans events [st] .. [st + 1] of its set
@@ -230,7 +232,7 @@ Buffers make_buffers(vgr_ctx *c)
     b.d_total = ptr<uint32_t>(c->words);
     b.blk_counts = ptr<uint32_t>(c->blk_counts);
     b.counters = ptr<unsigned long long>(c->counters);
-    b.wg_time = ptr<uint2>(c->wg_time);
+    b.wg_time = nullptr;   // set by a forward that times its workgroups
     b.views = ptr<ViewInfo>(c->views);
     return b;
 }
@@ -329,7 +331,8 @@ const char *vgr_last_error(const vgr_ctx *c)
 int vgr_set_counting(vgr_ctx *c, int enable)
 {
     if (!c) return VGR_ERR_INVALID_ARG;
-    c->counting = enable != 0;
+    c->counting = (enable & 1) != 0;
+    c->wg_timing = (enable & 2) != 0;
     return VGR_OK;
 }
 
@@ -549,13 +552,17 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
             return rc;
         b.pmask = ptr<uint64_t>(c->pmask);
     }
-    if (c->counting) {
+    if (c->counting)
+        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
+    b.wg_time = nullptr;
+    c->wg_timed = false;
+    if (c->wg_timing && cap < 0) {
         if ((rc = ensure(c, c->wg_time, 16 * (size_t)(rp.total_tiles > 0 ? rp.total_tiles : 1))))
             return rc;
         b.wg_time = ptr<uint2>(c->wg_time);
-        HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
         HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.wg_time), 0u,
                                    4 * (int64_t)rp.total_tiles, s));
+        c->wg_timed = true;
     }
     mark(c, ST_RASTER_FWD);
     HIP_TRY(c, launch_raster_fwd(rp, b, c->counting, s));
@@ -706,7 +713,7 @@ int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
     // load balance of the rasterisers: per compute unit, the summed durations
     // of its workgroups; max over mean
     const int32_t T = c->rp.total_tiles;
-    if (c->counting && T > 0 && c->wg_time.bytes >= 16 * (size_t)T) {
+    if (c->wg_timed && T > 0 && c->wg_time.bytes >= 16 * (size_t)T) {
         std::vector<uint32_t> wt(4 * (size_t)T);
         HIP_TRY(c, hipMemcpy(wt.data(), c->wg_time.p, 16 * (size_t)T, hipMemcpyDeviceToHost));
         for (int dir = 0; dir < 2; ++dir) {

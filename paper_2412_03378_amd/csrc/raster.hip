@@ -53,8 +53,8 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Counting runs time each workgroup: the constant-rate realtime counter at
-// start and end, and a key of the compute unit it ran on (XCC id, then the
+// Timed runs (b.wg_time set) record for each workgroup the constant-rate
+// realtime counter difference between start and end, and a key of the compute unit it ran on (XCC id, then the
 // shader engine, array and CU fields of HW_ID), so that the host can sum the
 // busy time per compute unit (load balance).
 __device__ __forceinline__ uint64_t wg_clock() { return __builtin_amdgcn_s_memrealtime(); }
@@ -219,7 +219,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     constexpr bool COLOR = MODE == VGR_MODE_COLOR;
     __shared__ Stage st;
 
-    const uint64_t t_start = COUNT ? wg_clock() : 0;
+    const bool timed = b.wg_time != nullptr;   // uniform
+    const uint64_t t_start = timed ? wg_clock() : 0;
     const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
@@ -432,9 +433,9 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
         atomicAdd(&b.counters[2], (unsigned long long)n.blend);
         atomicAdd(&b.counters[3], (unsigned long long)n.visits);
         atomicAdd(&b.counters[4], (unsigned long long)n.visits_full);
-        if (lane == 0)
-            b.wg_time[blockIdx.x] = make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
     }
+    if (timed && lane == 0)
+        b.wg_time[blockIdx.x] = make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
 }
 
 // Sum v[0..15] over the 64 lanes (transpose-reduce).  Afterwards lane l with
@@ -522,7 +523,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     constexpr bool KEEP = COLOR || PPL == 1;
     __shared__ Stage st;
 
-    const uint64_t t_start = COUNT ? wg_clock() : 0;
+    const bool timed = b.wg_time != nullptr;   // uniform
+    const uint64_t t_start = timed ? wg_clock() : 0;
     const int gt = (int)b.tile_order[blockIdx.x];
     const int v = find_view(b.views, rp.n_views, gt);
     const ViewInfo &vi = b.views[v];
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off, 64));
     if (maxlast < (int)range.x) {   // uniform: no pixel of this tile blended anything
-        if (COUNT && lane == 0)
+        if (timed && lane == 0)
             b.wg_time[rp.total_tiles + blockIdx.x] =
                 make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
         return;
@@ -739,10 +741,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
         atomicAdd(&b.counters[10], (unsigned long long)n.blend);
         atomicAdd(&b.counters[11], (unsigned long long)n.visits);
         atomicAdd(&b.counters[12], (unsigned long long)n.visits_full);
-        if (lane == 0)
-            b.wg_time[rp.total_tiles + blockIdx.x] =
-                make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
     }
+    if (timed && lane == 0)
+        b.wg_time[rp.total_tiles + blockIdx.x] =
+            make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
 }
 
 template <int TW, int TH>

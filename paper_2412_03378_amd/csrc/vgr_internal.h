@@ -122,7 +122,7 @@ struct Buffers {
     uint32_t *blk_counts;// preprocess blocks: instances per block
     uint32_t *d_total;   // [0] = instance count K, [1] overflow flag
     unsigned long long *counters;  // pair and visit counters: forward [0..4], backward [8..12]
-    uint2 *wg_time;      // counting runs: per rasteriser workgroup (launch slot) the
+    uint2 *wg_time;      // timed runs (else null): per rasteriser workgroup (launch slot) the
                          // compute unit key and its duration in clock ticks, forward
                          // at [0, total tiles), backward at [total tiles, 2 total tiles)
     const ViewInfo *views;

@@ -149,8 +149,11 @@ class Renderer:
         L.check(self._lib.vgr_get_stats(self._h, C.byref(s)), self._h)
         return {k: getattr(s, k) for k, _ in L.vgr_stats._fields_}
 
-    def set_counting(self, on: bool):
-        L.check(self._lib.vgr_set_counting(self._h, int(bool(on))), self._h)
+    def set_counting(self, on: bool, wg_timing: bool = False):
+        """on: pair counting (instrumented kernels); wg_timing: per-workgroup
+        timing of the production rasterisers (load balance in stats())."""
+        L.check(self._lib.vgr_set_counting(self._h, int(bool(on)) | (2 if wg_timing else 0)),
+                self._h)
 
     def set_timing(self, on: bool):
         L.check(self._lib.vgr_set_timing(self._h, int(bool(on))), self._h)
