@@ -373,3 +373,24 @@ def test_isotropic_gaussian_has_zero_rotation_gradient(R, dev):
     scale_mag = np.abs(gref["scales"]).max()
     assert scale_mag > 0
     assert np.abs(gref["quats"]).max() <= 1e-9 * scale_mag
+
+
+def test_emission_of_long_row_lists(R, dev):
+    """Large Gaussians on a tall image: every block of 64 depth-sorted
+    Gaussians lists far more than 1024 candidate tile rows, so the emission
+    walks its rows in several chunks; images and gradients against the
+    oracle."""
+    rng = np.random.default_rng(61)
+    n = 150
+    cam = scenes.Camera(np.eye(3, dtype=np.float32), np.array([0.0, 0.0, 4.0], np.float32),
+                        300.0, 300.0, 8.0, 1200.0, 16, 2400, 0.2)
+    means = np.c_[rng.uniform(-0.3, 0.3, (n, 2)), rng.uniform(-1.0, 1.0, n)]
+    scales = np.exp(rng.uniform(np.log(0.8), np.log(2.5), (n, 3)))
+    dens = np.exp(rng.uniform(np.log(0.02), np.log(0.2), n))
+    sc = H.scene(means, scales, dens, quats=rng.standard_normal((n, 4)),
+                 rgb=rng.uniform(0, 1, (n, 3)))
+    st = _settings(act="softplus", tile=(8, 8))
+    img, ref = _fwd_bwd_check(R, dev, sc, cam, st, seed=62)
+    stats = R.stats()
+    # the lists really are long: about one instance per Gaussian and tile row
+    assert stats["instances"] > 64 * 1024
