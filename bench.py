@@ -74,6 +74,32 @@ def _flops(tested, full, blended, ppl, mode, direction):
     return tested * (F_TEST + F_SHARED / ppl) + full * (F_FULL + offs) + blended * fb
 
 
+def _raster_rates(r, call, ppl, mode):
+    """TFLOP/s of algorithmic work and fraction of PEAK_FP32 for both
+    rasterisers over one eager call: stage times from HIP events on the
+    library stream, pair counts from the instrumented kernels on the same
+    inputs."""
+    r.set_timing(True)
+    call()
+    stages = r.timing()
+    r.set_timing(False)
+    r.set_counting(True)
+    call()
+    st = r.stats()
+    r.set_counting(False)
+    fl = {"raster_fwd": _flops(st["pairs_tested"], st["pairs_full"], st["pairs_blended"], ppl,
+                               mode, "fwd"),
+          "raster_bwd": _flops(st["bwd_pairs_tested"], st["bwd_pairs_full"],
+                               st["bwd_pairs_blended"], ppl, mode, "bwd")}
+    out = {}
+    for k, f in fl.items():
+        if stages.get(k):
+            rate = f / (stages[k] * 1e-3)
+            out[k] = {"ms": round(stages[k], 4), "tflops": round(rate / 1e12, 2),
+                      "frac": round(rate / PEAK_FP32, 4)}
+    return out
+
+
 def _device_scene(sc, dev, torch):
     import numpy as np
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
@@ -184,6 +210,11 @@ def bench_batched(args, torch, dev):
     r.set_counting(False)
     res["load_balance"] = {"raster_fwd": round(s["load_balance_fwd"], 3),
                            "raster_bwd": round(s["load_balance_bwd"], 3)}
+
+    def call_all():
+        r.forward(*params, wl.cams, st)
+        r.backward(dLs, *grads, accumulate=False)
+    res["rasterisers"] = _raster_rates(r, call_all, tile[0] * tile[1] / 64.0, "color")
     r.graph_capture(params, wl.cams, st, outs, dLs, grads, capacity_factor=1.1, zero_grads=True)
     res["batched"] = nv / _graph_time(r, args.batched_steps, torch)
     _log("single-view calls")
@@ -207,6 +238,11 @@ def bench_batched(args, torch, dev):
     torch.cuda.synchronize()
     res["single"] = nv / ((time.perf_counter() - t0) / args.batched_steps)
     del params, grads, dLs, outs
+    if not args.no_cpu_baseline:
+        import oracle
+        _log("oracle on one batched view")
+        res["oracle"] = oracle_per_view(wl.scene, wl.cams[0], wl.dL[0], 64,
+                                        oracle.Settings())
     return res, wl
 
 
@@ -255,8 +291,15 @@ def bench_xray(args, torch, dev):
            "instances": stats["instances"],
            "stages_ms": {k: round(v, 4) for k, v in stages.items()},
            "tflops": {k: round(v / (stages[k] * 1e-3) / 1e12, 2) for k, v in fl.items()
-                      if stages.get(k)}}
+                      if stages.get(k)},
+           "frac": {k: round(v / (stages[k] * 1e-3) / PEAK_FP32, 4) for k, v in fl.items()
+                    if stages.get(k)}}
     del params, grads, dLs, outs
+    if not args.no_cpu_baseline:
+        import oracle
+        _log("oracle on one X-ray view")
+        out["oracle"] = oracle_per_view(wl.scene, wl.cams[0], wl.dL[0], 128,
+                                        oracle.Settings(mode="xray"))
     return out
 
 
@@ -291,38 +334,72 @@ def bench_train(args, torch, dev, views_per_call=16):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.train_steps
+    def call_one():
+        r.forward(*params, wl.cams[:views_per_call], st)
+        r.backward(dLs[:views_per_call], *grads, accumulate=True)
     out = {"workload": "training step: 6M Gaussians (1024 clusters), SH3, 64 views 1920x1080, "
                        "fwd+bwd accumulated into FP32 parameter gradients, 16 views per call",
-           "tile": list(tile), "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1)}
+           "tile": list(tile), "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1),
+           "rasterisers_one_call": _raster_rates(r, call_one, tile[0] * tile[1] / 64.0, "color")}
     del params, grads, dLs
+    if not args.no_cpu_baseline:
+        import oracle
+        _log("oracle on one training view")
+        out["oracle"] = oracle_per_view(wl.scene, wl.cams[0], wl.dL[0], 64, oracle.Settings())
     return out
+
+
+def _oracle_view_ms(scene, cam, dL, n_pix, st, seed=0):
+    """FP64 oracle, forward + backward of one view over all Gaussians,
+    extrapolated to the whole view from two random pixel samples (n_pix / 2
+    and n_pix pixels, both at least twice the host threads so that the
+    per-pixel loop runs on all of them): per pixel (t2 - t1) / (n2 - n1), plus
+    the per-view set-up t1 - n1 * per pixel.  dL: (C, H, W).  Returns
+    (ms, seconds spent)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(seed)
+    n1 = max(n_pix // 2, 1)
+
+    def run(k):
+        pix = np.stack([rng.integers(0, cam.width, k), rng.integers(0, cam.height, k)], 1)
+        dLp = np.asarray(dL)[:, pix[:, 1], pix[:, 0]].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.render(scene, cam, st, pixels=pix)
+        oracle.render_backward(scene, cam, st, dLp, pixels=pix, with_abs=False)
+        return time.perf_counter() - t0
+
+    t1 = run(n1)
+    t2 = run(n_pix)
+    per_pix = max(t2 - t1, 1e-9) / max(n_pix - n1, 1)
+    setup = max(t1 - n1 * per_pix, 0.0)
+    return (setup + per_pix * cam.width * cam.height) * 1e3, t1 + t2
 
 
 def cpu_baseline(wl, n_pix):
     """FP64 oracle, forward + backward on n_pix pixels of the headline frame
     (all Gaussians per pixel), extrapolated to the whole frame."""
-    import numpy as np
     import oracle
     cam = wl.cams[0]
-    rng = np.random.default_rng(0)
-    pix = np.stack([rng.integers(0, cam.width, n_pix), rng.integers(0, cam.height, n_pix)], 1)
-    dL = wl.dL[0][:, pix[:, 1], pix[:, 0]].astype(np.float64)
-    st = oracle.Settings()
-    # per-view set-up alone (depth order, precision matrices, colours): one pixel
-    t0 = time.perf_counter()
-    oracle.render(wl.scene, cam, st, pixels=pix[:1])
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.render(wl.scene, cam, st, pixels=pix)
-    oracle.render_backward(wl.scene, cam, st, dL, pixels=pix, with_abs=False)
-    t_all = time.perf_counter() - t0
-    per_pix = max(t_all - 2 * t_setup, 1e-9) / n_pix
-    total_ms = (2 * t_setup + per_pix * cam.width * cam.height) * 1e3
+    total_ms, t_all = _oracle_view_ms(wl.scene, cam, wl.dL[0], n_pix, oracle.Settings())
     return {"value": total_ms, "unit": "ms per fwd+bwd (extrapolated)",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"fwd+bwd of {n_pix} random pixels of the 1920x1080 frame over all "
-                      f"{wl.scene.n} Gaussians in FP64 ({t_all:.1f} s), scaled to "
+            "sample": f"fwd+bwd of {n_pix // 2} and then {n_pix} random pixels of the "
+                      f"1920x1080 frame over all {wl.scene.n} Gaussians in FP64 ({t_all:.1f} s); "
+                      f"per-pixel cost from the difference, scaled to "
                       f"{cam.width * cam.height} pixels plus the per-view set-up"}
+
+
+def oracle_per_view(scene, cam, dL, n_pix, st):
+    """The oracle beside a multi-view workload: one view, extrapolated, as
+    views/s on the host cores."""
+    import oracle
+    ms, t_all = _oracle_view_ms(scene, cam, dL, n_pix, st)
+    return {"views_per_s": round(1e3 / ms, 6), "ms_per_view": round(ms, 1),
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"fwd+bwd of {n_pix // 2} and then {n_pix} random pixels of one "
+                      f"{cam.width}x{cam.height} view over all {scene.n} Gaussians in FP64 "
+                      f"({t_all:.1f} s), extrapolated as for the headline"}
 
 
 def write_traffic(fetch_csv, write_csv, out_path=TRAFFIC_FILE):
@@ -445,7 +522,10 @@ def main():
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3),
-                          "load_balance": res["load_balance"]}
+                          "load_balance": res["load_balance"],
+                          "rasterisers": res["rasterisers"]}
+        if "oracle" in res:
+            out["batched"]["oracle"] = res["oracle"]
     if not args.no_xray:
         torch.cuda.empty_cache()
         out["xray"] = bench_xray(args, torch, dev)
