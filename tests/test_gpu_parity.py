@@ -394,3 +394,30 @@ def test_emission_of_long_row_lists(R, dev):
     stats = R.stats()
     # the lists really are long: about one instance per Gaussian and tile row
     assert stats["instances"] > 64 * 1024
+
+
+def test_workgroup_timing_and_pair_counts(R, dev, cfg1):
+    """Workgroup timing (production kernels) yields a finite per-CU load
+    balance >= 1 without changing the image; pair counting reports blended
+    pairs equal in forward and backward (the backward replays exactly the
+    forward's blends) and no backward pre-tests."""
+    sc, cam = cfg1.scene, cfg1.cams[0]
+    st = _settings(tile=(8, 8))
+    t = G.device_scene(sc, dev)
+    ref = R.forward(*t, [cam], st)[0].cpu().numpy()
+    R.set_counting(False, wg_timing=True)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    grads = [torch.zeros_like(x) for x in t]
+    R.backward([torch.ones((3, cam.height, cam.width), device=dev)], *grads)
+    s = R.stats()
+    R.set_counting(False)
+    assert np.array_equal(img, ref)
+    assert 1.0 <= s["load_balance_fwd"] < 100.0 and 1.0 <= s["load_balance_bwd"] < 100.0
+    R.set_counting(True)
+    R.forward(*t, [cam], st)
+    R.backward([torch.ones((3, cam.height, cam.width), device=dev)], *grads)
+    s = R.stats()
+    R.set_counting(False)
+    assert s["pairs_blended"] > 0 and s["pairs_blended"] == s["bwd_pairs_blended"]
+    assert s["bwd_pairs_tested"] == 0
+    assert s["pairs_full"] >= s["pairs_blended"] and s["pairs_tested"] >= s["pairs_full"]
