@@ -11,8 +11,10 @@ sh, sh_degree`` and ``R, t, fx, fy, cx, cy, width, height, znear``).
 
 Passages followed (arXiv 2412.03378): the density mixture and Gaussian
 (Sec. 3.2), the alpha-blend without splatting (Sec. 4.1), the 1D Gaussian on
-a ray and its boxed full-line integral (Sec. 4.2, Supp. B), tomography as a
-sum of line integrals (Sec. 6.2).
+a ray and its boxed full-line integral (Sec. 4.2, Supp. B), the density
+reparameterisation (Sec. 5, eq. density_reparam), tomography as a sum of line
+integrals (Sec. 6.2), and the world-space positional gradient norms that
+drive densification (Supp. D).
 """
 from __future__ import annotations
 
@@ -50,7 +52,7 @@ class _Cam(C.Structure):
 
 class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
-                ("pad", C.c_int32), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("density", C.c_int32), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
 
 
@@ -65,11 +67,12 @@ class Settings:
     x_min_xray: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
     act: str = "clamp"             # "clamp" | "softplus"
+    density: str = "kappa"         # "kappa" | "theta" (eq. density_reparam)
 
     @staticmethod
-    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0)):
+    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa"):
         return Settings(mode=mode, alpha_min=1e-300, alpha_max=1.0 - 1e-12, T_min=0.0,
-                        x_min_xray=1e-300, bg=bg, act=act)
+                        x_min_xray=1e-300, bg=bg, act=act, density=density)
 
 
 def _load():
@@ -120,6 +123,7 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     s.mode = 1 if st.mode == "xray" else 0
     s.sh_degree = int(sh_degree)
     s.act = 1 if st.act == "softplus" else 0
+    s.density = 1 if st.density == "theta" else 0
     s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
     s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
     s.bg[:] = [float(v) for v in st.bg]
@@ -255,3 +259,50 @@ def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=Tr
             res["abs_" + k] = absg[k]
             res["err_" + k] = errg[k]
     return res
+
+
+def densify_stats(scene, cams, settings: Settings, dLs):
+    """Densification statistics of one multi-view step (Supp. D: world-space
+    positional gradients): per Gaussian, the sum over views of the norm of
+    that view's dL/dmu, with the loss of view v being sum(dLs[v] * image_v).
+
+    Which views count a Gaussian as visible depends on the tile bound of an
+    implementation, so two bounds are returned: ``visible_lo`` counts the
+    views where it contributes to some pixel (blended or summed), ``visible_hi``
+    the views where it survives the near-plane and opacity culls
+    (kappa sqrt(2 pi) s_max >= the skip threshold, the largest x any ray can
+    reach, since beta <= s_max).  Also returned: the per-view gradients and
+    their sums of absolute contributions and error scales, for tolerances."""
+    st = settings or Settings()
+    xray = st.mode == "xray"
+    n = int(np.asarray(scene.means).shape[0])
+    norm_sum = np.zeros(n)
+    lo = np.zeros(n, np.int64)
+    hi = np.zeros(n, np.int64)
+    per_view = []
+    s32 = _f32(scene.scales)
+    dens = _f32(scene.dens)
+    if st.density == "theta":
+        th = np.clip(dens.astype(np.float64), 0.0, 1.0)
+        kappa = -np.log1p(-0.99 * th) * (1.0 / s32.astype(np.float64)).sum(1) / 3.0
+    else:
+        kappa = dens.astype(np.float64)
+    tau = st.x_min_xray if xray else -math.log1p(-st.alpha_min)
+    reach = kappa * math.sqrt(2.0 * math.pi) * s32.max(1).astype(np.float64)
+    means = _f32(scene.means)
+    for cam, dL in zip(cams, dLs):
+        r = render_backward(scene, cam, st, dL, with_abs=True)
+        per_view.append(r)
+        norm_sum += np.linalg.norm(r["means"], axis=1)
+        touched = (r["abs_dens"] > 0) | (r["abs_means"].max(1) > 0)
+        if not xray:
+            touched |= r["abs_sh"].reshape(n, -1).max(1) > 0
+        lo += touched
+        # view-space depth of the mean in FP64; the FP32 depth key that decides
+        # the near cull differs by rounding only, so the bound is relaxed by 1e-6
+        R = np.asarray(cam.R, np.float32).reshape(3, 3).astype(np.float64)
+        t = np.asarray(cam.t, np.float32).reshape(3).astype(np.float64)
+        z = means.astype(np.float64) @ R[2] + t[2]
+        znear = float(getattr(cam, "znear", 0.2))
+        hi += (z > znear - 1e-6 * max(1.0, abs(znear))) & (reach >= tau * (1.0 - 1e-5))
+    return dict(norm_sum=norm_sum, visible_lo=lo, visible_hi=hi, per_view=per_view)

@@ -32,6 +32,10 @@
  *   - colour c = act(sum_k sh_k Y_k(v) + 0.5), v = normalize(mu - o), with
  *     real orthonormal spherical harmonics (Condon-Shortley phase), act =
  *     max(.,0) or softplus with sharpness 10 (Supp. D).
+ *   - the density input is kappa itself, or theta with the reparameterisation
+ *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
+ *     density_reparam); theta outside the paper's range [0, 1] is clamped to
+ *     it, with zero gradient outside.
  *
  * Decision margins: for every threshold test that decides the output (skip,
  * clamp, terminate) the oracle reports the smallest relative distance to the
@@ -64,7 +68,7 @@ typedef struct {
     int32_t mode;       /* 0 colour, 1 X-ray */
     int32_t sh_degree;  /* 0..3 */
     int32_t act;        /* 0 max(.,0), 1 softplus(10 y)/10 */
-    int32_t pad;
+    int32_t density;    /* 0: dens holds kappa; 1: dens holds theta (kappa_of) */
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
 } orc_settings;
@@ -243,6 +247,7 @@ typedef struct {
     double *P;           /* n x 9 world-space Sigma^-1 */
     double *rgb;         /* n x 3 colour for this view */
     double *raw;         /* n x 3 colour before activation */
+    double *kappa;       /* n densities kappa */
     double o[3];
 } view_state;
 
@@ -319,9 +324,40 @@ static float depth_key(const orc_camera *cam, const float *mu)
     return fmaf(R[6], mu[0], fmaf(R[7], mu[1], fmaf(R[8], mu[2], cam->t[2])));
 }
 
+/* Density kappa of a Gaussian from its density input and scales: the input
+   itself, or, for the reparameterisation of Sec. 5 (eq. density_reparam),
+   kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 with theta in [0, 1]. */
+static double theta_clamped(float th)
+{
+    return th < 0.0f ? 0.0 : (th > 1.0f ? 1.0 : (double)th);
+}
+
+static double kappa_of(const orc_settings *st, float dens, const float s[3])
+{
+    if (st->density == 0) return (double)dens;
+    double h = (1.0 / s[0] + 1.0 / s[1] + 1.0 / s[2]) / 3.0;
+    return -log1p(-0.99 * theta_clamped(dens)) * h;
+}
+
+/* d kappa / d(input) and d kappa / d s_k of kappa_of. */
+static void kappa_grad(const orc_settings *st, float dens, const float s[3], double *dk_din,
+                       double dk_ds[3])
+{
+    if (st->density == 0) {
+        *dk_din = 1.0;
+        dk_ds[0] = dk_ds[1] = dk_ds[2] = 0.0;
+        return;
+    }
+    double th = theta_clamped(dens);
+    double h = (1.0 / s[0] + 1.0 / s[1] + 1.0 / s[2]) / 3.0;
+    double phi = -log1p(-0.99 * th);
+    *dk_din = (dens < 0.0f || dens > 1.0f) ? 0.0 : 0.99 / (1.0 - 0.99 * th) * h;
+    for (int k = 0; k < 3; ++k) dk_ds[k] = -phi / (3.0 * (double)s[k] * (double)s[k]);
+}
+
 static int view_setup(view_state *vs, int64_t n, const float *means, const float *quats,
-                      const float *scales, const float *sh, const orc_camera *cam,
-                      const orc_settings *st)
+                      const float *scales, const float *dens, const float *sh,
+                      const orc_camera *cam, const orc_settings *st)
 {
     memset(vs, 0, sizeof *vs);
     vs->n = n;
@@ -330,7 +366,8 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
     vs->P = (double *)malloc(sizeof(double) * 9 * (size_t)(n > 0 ? n : 1));
     vs->rgb = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     vs->raw = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-    if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw) return -3;
+    vs->kappa = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw || !vs->kappa) return -3;
     camera_origin(cam, vs->o);
     int nb = (st->sh_degree + 1) * (st->sh_degree + 1);
     int64_t nvis = 0;
@@ -339,6 +376,7 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
         double R[9];
         quat_rotation(quats + 4 * i, R, NULL, NULL);
         precision_matrix(R, scales + 3 * i, vs->P + 9 * i);
+        vs->kappa[i] = kappa_of(st, dens[i], scales + 3 * i);
         vs->key[i] = depth_key(cam, means + 3 * i);
         if (st->mode == 0) {
             double v[3], len = 0, Y[(ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)];
@@ -364,7 +402,7 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
 
 static void view_free(view_state *vs)
 {
-    free(vs->order); free(vs->key); free(vs->P); free(vs->rgb); free(vs->raw);
+    free(vs->order); free(vs->key); free(vs->P); free(vs->rgb); free(vs->raw); free(vs->kappa);
 }
 
 static double rel_margin(double v, double thr)
@@ -396,8 +434,7 @@ static void list_push(blend_list *bl, blend_rec r)
 }
 
 /* Composite one pixel; fills out[3] (colour) or out[0] (X-ray). */
-static void shade_pixel(const view_state *vs, const float *means, const float *dens,
-                        const orc_settings *st, const double d[3], double *out,
+static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st, const double d[3], double *out,
                         double *T_out, int64_t *last_out, int32_t *nblend_out,
                         double *margin_out, double *untrunc_out, blend_list *bl)
 {
@@ -410,7 +447,7 @@ static void shade_pixel(const view_state *vs, const float *means, const float *d
             int64_t i = vs->order[r];
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_terms rt;
-            ray_integral(mu, vs->P + 9 * i, (double)dens[i], vs->o, d, &rt);
+            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
             full += rt.x;
             double m = rel_margin(rt.x, st->x_min_xray);
             if (m < margin) margin = m;
@@ -440,7 +477,7 @@ static void shade_pixel(const view_state *vs, const float *means, const float *d
         int64_t i = vs->order[r];
         double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
         ray_terms rt;
-        ray_integral(mu, vs->P + 9 * i, (double)dens[i], vs->o, d, &rt);
+        ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
         double m = rel_margin(rt.x, tau);
         if (m < margin) margin = m;
         if (rt.x < tau) continue;                      /* alpha < alpha_min */
@@ -481,14 +518,14 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
     view_state vs;
-    int rc = view_setup(&vs, n, means, quats, scales, sh, cam, st);
+    int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
     int C = st->mode == 1 ? 1 : 3;
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < npix; ++p) {
         double d[3];
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
-        shade_pixel(&vs, means, dens, st, d, out + C * p, T_out ? T_out + p : NULL,
+        shade_pixel(&vs, means, st, d, out + C * p, T_out ? T_out + p : NULL,
                     last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
                     margin_out ? margin_out + p : NULL, untrunc_out ? untrunc_out + p : NULL,
                     NULL);
@@ -539,19 +576,20 @@ static void add3(double *g, double *a, double *e, int64_t off, double unit, doub
     if (e) atomic_add(e + off, fabs(ge * unit));
 }
 
-/* Chain dL/dx = gx (line integral of Gaussian i on ray (o, d)) to mu, q, s,
-   kappa.  For the error scale (see grad_out), gabs is |gx| formed without
+/* Chain dL/dx = gx (line integral of Gaussian i on ray (o, d)) to mu, q, s
+   and the density input (kappa, or theta with its path into s).  For the error scale (see grad_out), gabs is |gx| formed without
    cancellation and the weight is 1 + D^2/2 + w_extra: a relative error e in
    D^2 becomes D^2 e / 2 in x = ... exp(-D^2/2). */
 static void chain_integral(int64_t i, double gx, double gabs, double w_extra, const float *means,
                            const float *quats, const float *scales, const float *dens,
-                           const double o[3], const double d[3], grad_out *go)
+                           const orc_settings *st, const double o[3], const double d[3],
+                           grad_out *go)
 {
     double R[9], qn[4], qlen, P[9];
     quat_rotation(quats + 4 * i, R, qn, &qlen);
     precision_matrix(R, scales + 3 * i, P);
     double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
-    double kappa = dens[i];
+    double kappa = kappa_of(st, dens[i], scales + 3 * i);
     ray_terms rt;
     ray_integral(mu, P, kappa, o, d, &rt);
     /* x = kappa sqrt(2pi) a^-1/2 exp(-D^2/2),  D^2 = v^T P v, v = mu - o - gamma d
@@ -565,7 +603,13 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
         D2 += rt.v[r] * Pv[r];
     }
     const double ge = gabs * (1.0 + 0.5 * D2 + w_extra);
-    add3(go->g_dens, go->a_dens, go->e_dens, i, sqrt(2 * ORC_PI) * rt.beta * rt.Gmax, gx, ge);
+    const double dx_dk = sqrt(2 * ORC_PI) * rt.beta * rt.Gmax;
+    double dk_din, dk_ds[3];
+    kappa_grad(st, dens[i], scales + 3 * i, &dk_din, dk_ds);
+    add3(go->g_dens, go->a_dens, go->e_dens, i, dx_dk * dk_din, gx, ge);
+    if (st->density != 0)
+        for (int k = 0; k < 3; ++k)
+            add3(go->g_scales, go->a_scales, go->e_scales, 3 * i + k, dx_dk * dk_ds[k], gx, ge);
     double G[9];   /* dx/dP per unit gx */
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
@@ -631,14 +675,14 @@ static void chain_colour(int64_t i, const double gc[3], double w, const view_sta
 
 /* Squared Mahalanobis distance of Gaussian i from the ray (o, d). */
 static double pair_D2(int64_t i, const float *means, const float *quats, const float *scales,
-                      const float *dens, const double o[3], const double d[3])
+                      const double o[3], const double d[3])
 {
     double R[9], qn[4], qlen, P[9];
     quat_rotation(quats + 4 * i, R, qn, &qlen);
     precision_matrix(R, scales + 3 * i, P);
     double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     ray_terms rt;
-    ray_integral(mu, P, dens[i], o, d, &rt);
+    ray_integral(mu, P, 1.0, o, d, &rt);   /* D^2 does not depend on kappa */
     double D2 = 0;
     for (int r = 0; r < 3; ++r)
         D2 += rt.v[r] * (P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2]);
@@ -662,7 +706,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
     view_state vs;
-    int rc = view_setup(&vs, n, means, quats, scales, sh, cam, st);
+    int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
     grad_out go = { g_means, g_quats, g_scales, g_dens, g_sh,
                     a_means, a_quats, a_scales, a_dens, a_sh,
@@ -675,11 +719,11 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         double d[3], out[3];
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
         blend_list bl = { NULL, 0, 0 };
-        shade_pixel(&vs, means, dens, st, d, out, NULL, NULL, NULL, NULL, NULL, &bl);
+        shade_pixel(&vs, means, st, d, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
                 chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,
-                               vs.o, d, &go);
+                               st, vs.o, d, &go);
         } else {
             /* S: colour composited behind the current Gaussian, ending in bg */
             double S[3] = { st->bg[0], st->bg[1], st->bg[2] };
@@ -697,10 +741,10 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                 const double ex = exp(-br->x);
                 if (!br->clamped)
                     chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales, dens,
-                                   vs.o, d, &go);
+                                   st, vs.o, d, &go);
                 double w = 1.0 + steps;
                 if (go.e_means || go.e_sh)
-                    w += 0.5 * pair_D2(i, means, quats, scales, dens, vs.o, d);
+                    w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d);
                 chain_colour(i, gc, w, &vs, means, sh, st, &go);
                 for (int ch = 0; ch < 3; ++ch)
                     S[ch] = vs.rgb[3 * i + ch] * br->alpha + (1.0 - br->alpha) * S[ch];

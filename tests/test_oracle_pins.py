@@ -526,3 +526,121 @@ def test_error_scale_weights():
     g = oracle.render_backward(wl.scene, wl.cams[0], oracle.Settings(), dL)
     for k in ("means", "quats", "scales", "dens", "sh"):
         assert np.all(g["err_" + k] >= g["abs_" + k] * (1 - 1e-12)), k
+
+
+# ------------------------------------ Sec. 5 density reparameterisation ---
+
+def _theta_x(theta):
+    """Centre-ray integral of an isotropic Gaussian under eq. density_reparam:
+    kappa = -ln(1 - 0.99 theta) / s and x = kappa sqrt(2 pi) s (Sec. 4.2), so
+    x = -sqrt(2 pi) ln(1 - 0.99 theta) whatever s is (peak opacity
+    1 - (1 - 0.99 theta)^sqrt(2 pi))."""
+    return -H.SQRT2PI * math.log1p(-0.99 * theta)
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.5, 0.9, 1.0])
+def test_density_reparam_isotropic_opacity_is_scale_free(theta):
+    """With theta as the density input, an isotropic Gaussian seen through its
+    centre has the same line integral (so opacity) at every scale, the closed
+    form above."""
+    cam = H.odd_camera(9, 30.0, 4.0)
+    st = oracle.Settings.no_thresholds(mode="xray", density="theta")
+    vals = []
+    for s in (0.02, 0.1, 0.4):
+        sc = H.scene([[0.0, 0.0, 0.0]], [f32(s)] * 3, theta)
+        vals.append(oracle.render(sc, cam, st, pixels=[_centre(cam)])["image"][0, 0])
+    assert vals == pytest.approx([_theta_x(f32(theta))] * 3, rel=1e-12)
+
+
+def test_density_reparam_anisotropic_mean_inverse_scale():
+    """Axis-aligned anisotropic Gaussian seen along z: beta = s_z (eq.
+    betagamma), so x = kappa sqrt(2 pi) s_z with kappa the mean inverse scale
+    times -ln(1 - 0.99 theta) (eq. density_reparam)."""
+    cam = H.odd_camera(9, 30.0, 4.0)
+    s = [f32(0.03), f32(0.11), f32(0.07)]
+    theta = f32(0.6)
+    sc = H.scene([[0.0, 0.0, 0.0]], [s], theta, rgb=[[1.0, 1.0, 1.0]])
+    st = oracle.Settings.no_thresholds(mode="xray", density="theta")
+    x = oracle.render(sc, cam, st, pixels=[_centre(cam)])["image"][0, 0]
+    kappa = -math.log(1.0 - 0.99 * theta) * (1 / s[0] + 1 / s[1] + 1 / s[2]) / 3.0
+    assert x == pytest.approx(kappa * H.SQRT2PI * s[2], rel=1e-12)
+
+
+def test_density_reparam_range():
+    """theta = 0 is empty space; inputs outside [0, 1] act as the nearest end
+    of the range, with zero gradient."""
+    cam = H.odd_camera(9, 30.0, 4.0)
+    st = oracle.Settings(act="clamp", bg=(0.2, 0.4, 0.6), density="theta")
+    img = lambda th: oracle.render(H.scene([[0.0, 0.0, 0.0]], [0.1] * 3, th), cam, st)["image"]
+    assert np.array_equal(img(0.0), np.broadcast_to(np.array([0.2, 0.4, 0.6])[:, None, None],
+                                                     (3, 9, 9)))
+    assert np.array_equal(img(-0.3), img(0.0))
+    assert np.array_equal(img(1.7), img(1.0))
+    dL = np.ones((3, 9, 9))
+    for th in (-0.3, 1.7):
+        g = oracle.render_backward(H.scene([[0.0, 0.0, 0.0]], [0.1] * 3, th), cam, st, dL)
+        assert g["dens"][0] == 0.0
+
+
+@pytest.mark.parametrize("mode", ["color", "xray"])
+def test_fd_gradients_density_reparam(mode):
+    """dL/dtheta and the extra path of the scales through kappa against
+    central finite differences (thresholds off; a smaller step than the other
+    checks, since kappa grows as 1/s and the scales are small)."""
+    rng = np.random.default_rng(14)
+    n = 6
+    cam = scenes.look_at([0.5, -0.3, -3.0], (0, 0, 0), 13, 11, 35.0)
+    means = np.c_[rng.uniform(-0.3, 0.3, (n, 2)), np.linspace(-0.6, 0.6, n)]
+    sc = H.scene(means, np.exp(rng.uniform(np.log(0.05), np.log(0.2), (n, 3))),
+                 rng.uniform(0.05, 0.95, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    st = oracle.Settings.no_thresholds(mode=mode, act="softplus", bg=(0.2, 0.3, 0.1),
+                                       density="theta")
+    assert _fd_check(sc, cam, st, rng, n_checks=60, rel_h=3e-6, xray=mode == "xray") < 1e-6
+
+
+# -------------------------------- Supp. D world-space gradient norms ---
+
+def test_densify_norms_match_finite_differences():
+    """Per Gaussian, the sum over views of |dL_v/dmu| (each view's own loss)
+    equals the same sum built from finite differences of the forward."""
+    rng = np.random.default_rng(15)
+    n = 4
+    sc = H.scene(np.c_[rng.uniform(-0.3, 0.3, (n, 2)), np.linspace(-0.5, 0.5, n)],
+                 np.exp(rng.uniform(np.log(0.06), np.log(0.2), (n, 3))), rng.uniform(1, 6, n),
+                 quats=rng.standard_normal((n, 4)), sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    cams = [scenes.look_at([0.4, -0.2, -3.0], (0, 0, 0), 11, 9, 35.0),
+            scenes.look_at([-2.5, 0.3, -1.5], (0, 0, 0), 9, 11, 35.0)]
+    st = oracle.Settings.no_thresholds(act="softplus")
+    dLs = [rng.standard_normal((3, c.height, c.width)) for c in cams]
+    ds = oracle.densify_stats(sc, cams, st, dLs)
+    fd_norm = np.zeros(n)
+    for cam, dL in zip(cams, dLs):
+        for i in range(n):
+            g = np.zeros(3)
+            for k in range(3):
+                v = float(sc.means[i, k])
+                h = 2e-5 * max(1.0, abs(v))
+                vals = []
+                for sgn in (1, -1):
+                    m2 = sc.means.copy()
+                    m2[i, k] = np.float32(v + sgn * h)
+                    s2 = scenes.Scene(m2, sc.quats, sc.scales, sc.dens, sc.sh, sc.sh_degree)
+                    vals.append((float(m2[i, k]),
+                                 float(np.sum(oracle.render(s2, cam, st)["image"] * dL))))
+                g[k] = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+            fd_norm[i] += np.linalg.norm(g)
+    assert ds["norm_sum"] == pytest.approx(fd_norm, rel=1e-6)
+    assert np.all(ds["visible_lo"] == 2) and np.all(ds["visible_hi"] == 2)
+
+
+def test_densify_visibility_bounds():
+    """A Gaussian behind the camera, one too faint for any ray to reach the
+    skip threshold, and one outside the image are in neither count or only
+    in the upper one; a Gaussian in front of the camera is in both."""
+    cam = H.odd_camera(9, 30.0, 4.0)
+    sc = H.scene([[0.0, 0.0, 0.0], [0.0, 0.0, -6.0], [0.05, 0.0, 0.5], [30.0, 0.0, 0.0]],
+                 [[0.1] * 3, [0.1] * 3, [0.01] * 3, [0.1] * 3], [3.0, 3.0, 0.01, 3.0])
+    ds = oracle.densify_stats(sc, [cam], oracle.Settings(), [np.ones((3, 9, 9))])
+    assert list(ds["visible_lo"]) == [1, 0, 0, 0]
+    assert list(ds["visible_hi"]) == [1, 0, 0, 1]
