@@ -61,6 +61,7 @@ typedef struct {
 
 enum { VGR_MODE_COLOR = 0, VGR_MODE_XRAY = 1 };
 enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
+enum { VGR_DENSITY_KAPPA = 0, VGR_DENSITY_THETA = 1 };
 
 /* Rendering rules.  Defaults in brackets (vgr_default_settings).
  *   mode        colour compositing or X-ray line integrals [COLOR]
@@ -78,6 +79,12 @@ enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
  *               softplus(10 y)/10 (Supp. D) [CLAMP0]
  *   tile_w/h    screen tile in pixels, one of 8x8, 16x8, 16x16, 32x8;
  *               0 = the context's tuned choice (8x8 until vgr_autotune) [0, 0]
+ *   density     what the `dens` input holds: KAPPA, the density kappa >= 0
+ *               itself, or THETA, the paper's density parameter theta, with
+ *               kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3
+ *               computed inside the preprocess (Sec. 5, eq. density_reparam);
+ *               theta is clamped to its range [0, 1], with zero gradient
+ *               outside it [KAPPA]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -89,7 +96,8 @@ typedef struct {
     float bg[3];
     int32_t act;
     int32_t tile_w, tile_h;
-    int32_t reserved[2];
+    int32_t density;
+    int32_t reserved;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */
@@ -147,7 +155,8 @@ const char *vgr_last_error(const vgr_ctx *ctx);
  *   quats  n x 4, rotation (w, x, y, z); normalised inside, need not be unit
  *   scales n x 3, standard deviations along the rotated axes, > 0
  *          (Sigma_i = R_i diag(s_i^2) R_i^T)
- *   dens   n, density kappa_i >= 0 (units 1/length)
+ *   dens   n, density kappa_i >= 0 (units 1/length), or theta_i in [0, 1]
+ *          (settings->density)
  *   sh     n x (sh_degree+1)^2 x 3 colour coefficients (COLOR); may be NULL
  *          in XRAY mode
  *   cams   host array of n_views cameras (1 <= n_views <= 64)
@@ -167,7 +176,9 @@ int vgr_render_forward(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
 /* Backward of the last forward on this context: given dL/d(out) (host array
  * of n_views device pointers, same shapes as `out`), the gradients with
  * respect to d_means (n x 3), d_quats (n x 4), d_scales (n x 3), d_dens (n)
- * and d_sh (same shape as sh; may be NULL in XRAY mode).  accumulate = 1:
+ * and d_sh (same shape as sh; may be NULL in XRAY mode); d_dens is the
+ * gradient with respect to the forward's `dens` input (kappa or theta, and
+ * with theta the scales receive the path through kappa too).  accumulate = 1:
  * ADD them to the arrays; accumulate = 0: overwrite every element (the
  * arrays are not read, so they need no zeroing).  Gradients flow through the
  * quaternion normalisation; clamped, skipped and unblended (Gaussian, pixel)
@@ -177,6 +188,24 @@ int vgr_render_forward(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
 int vgr_render_backward(vgr_ctx *ctx, const float *const *dL_dout, float *d_means,
                         float *d_quats, float *d_scales, float *d_dens, float *d_sh,
                         int32_t accumulate);
+
+/* Densification statistics (Supp. D: the paper thresholds the world-space
+ * positional gradient of each Gaussian to decide where to densify).  After
+ * this call every backward on the context, and every replay of a graph
+ * captured after it (the eager steps that vgr_graph_capture and vgr_autotune
+ * run included), ADDS for each Gaussian i
+ *   grad_norm_sum[i] += sum over the call's views v of |dL_v/dmu_i|, the
+ *                       Euclidean norm of view v's share of d_means[i];
+ *   view_count[i]    += the number of those views in which Gaussian i was
+ *                       handed to the rasteriser (at least one tile).
+ * Both are device arrays owned by the caller (n floats, n int32), either may
+ * be NULL; both NULL turns the statistics off.  `capacity` is their length:
+ * a later backward with n > capacity fails with VGR_ERR_INVALID_ARG.  The
+ * caller clears them (e.g. at each densification step).  Adds one pass over
+ * the per-view tile counts (4 bytes per Gaussian and view) to the backward.
+ * VGR_ERR_INVALID_ARG for a negative capacity. */
+int vgr_set_densify_stats(vgr_ctx *ctx, float *grad_norm_sum, int32_t *view_count,
+                          int64_t capacity);
 
 /* Per-pixel state of view `view` of the last forward, copied (on the
  * stream) into caller arrays of H x W: final transmittance T_final (may be

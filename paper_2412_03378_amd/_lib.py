@@ -23,6 +23,8 @@ VGR_MODE_COLOR = 0
 VGR_MODE_XRAY = 1
 VGR_ACT_CLAMP0 = 0
 VGR_ACT_SOFTPLUS10 = 1
+VGR_DENSITY_KAPPA = 0
+VGR_DENSITY_THETA = 1
 
 
 class vgr_camera(C.Structure):
@@ -35,7 +37,7 @@ class vgr_settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("tile_h", C.c_int32), ("density", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vgr_stats(C.Structure):
@@ -73,6 +75,7 @@ _SIGNATURES = {
     "vgr_get_stats": (C.c_int, [C.c_void_p, C.POINTER(vgr_stats)]),
     "vgr_set_counting": (C.c_int, [C.c_void_p, C.c_int]),
     "vgr_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "vgr_set_densify_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "vgr_get_timing": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                  C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "vgr_sort_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),

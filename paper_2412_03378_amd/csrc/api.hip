@@ -57,6 +57,11 @@ struct vgr_ctx {
     const float *means = nullptr, *quats = nullptr, *scales = nullptr, *dens = nullptr,
                 *sh = nullptr;
 
+    // densification statistics (vgr_set_densify_stats)
+    float *dn_norm = nullptr;
+    int32_t *dn_count = nullptr;
+    int64_t dn_cap = 0;
+
     bool counting = false;
     bool wg_timing = false;     // time each rasteriser workgroup (load balance)
     bool wg_timed = false;      // the last forward was timed so
@@ -336,6 +341,18 @@ int vgr_set_counting(vgr_ctx *c, int enable)
     return VGR_OK;
 }
 
+int vgr_set_densify_stats(vgr_ctx *c, float *grad_norm_sum, int32_t *view_count,
+                          int64_t capacity)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (capacity < 0) return fail(c, VGR_ERR_INVALID_ARG, "negative capacity");
+    c->dn_norm = grad_norm_sum;
+    c->dn_count = view_count;
+    c->dn_cap = (grad_norm_sum || view_count) ? capacity : 0;
+    return VGR_OK;
+}
+
 int vgr_set_timing(vgr_ctx *c, int enable)
 {
     if (!c) return VGR_ERR_INVALID_ARG;
@@ -402,6 +419,8 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
         return fail(c, VGR_ERR_INVALID_ARG, "sh_degree must be 0..3");
     if (st->act != VGR_ACT_CLAMP0 && st->act != VGR_ACT_SOFTPLUS10)
         return fail(c, VGR_ERR_INVALID_ARG, "bad act");
+    if (st->density != VGR_DENSITY_KAPPA && st->density != VGR_DENSITY_THETA)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad density");
     if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
         !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
         return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
@@ -421,6 +440,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.mode = st->mode;
     rp.sh_degree = st->mode == VGR_MODE_COLOR ? st->sh_degree : 0;
     rp.act = st->act;
+    rp.density = st->density;
     rp.n_views = n_views;
     rp.n = n;
     rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;
@@ -593,7 +613,8 @@ int enqueue_backward(vgr_ctx *c, const RenderParams &rp, const Buffers &b_fwd,
     mark_end(c, ST_RASTER_BWD);
     mark(c, ST_PREPROCESS_BWD);
     HIP_TRY(c, launch_preprocess_bwd(rp, b, means, quats, scales, dens, sh, d_means, d_quats,
-                                     d_scales, d_dens, d_sh, accumulate, s));
+                                     d_scales, d_dens, d_sh, accumulate, c->dn_norm,
+                                     c->dn_count, s));
     mark_end(c, ST_PREPROCESS_BWD);
     return VGR_OK;
 }
@@ -608,6 +629,9 @@ int check_grads(vgr_ctx *c, const RenderParams &rp, float *d_means, float *d_qua
             return rc;
         if (rp.mode == VGR_MODE_COLOR && (rc = check_ptr(c, d_sh, "d_sh"))) return rc;
     }
+    if ((c->dn_norm || c->dn_count) && rp.n > c->dn_cap)
+        return fail(c, VGR_ERR_INVALID_ARG, "n = %lld exceeds the densification arrays (%lld)",
+                    (long long)rp.n, (long long)c->dn_cap);
     return VGR_OK;
 }
 

@@ -324,6 +324,19 @@ __device__ __forceinline__ bool cull_row(const CullRows &c, int ty, int tw, int 
     return t0 <= t1;
 }
 
+// Density kappa from the density input: the input itself, or the paper's
+// reparameterisation kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3
+// (Sec. 5, eq. density_reparam) with theta clamped to [0, 1].
+__device__ inline float theta_log(float theta)   // -ln(1 - 0.99 theta)
+{
+    return -log1pf(-0.99f * fminf(fmaxf(theta, 0.0f), 1.0f));
+}
+__device__ inline float density_of(int density, float in, const float *s)
+{
+    if (density != VGR_DENSITY_THETA) return in;
+    return theta_log(in) * ((1.0f / s[0] + 1.0f / s[1] + 1.0f / s[2]) * (1.0f / 3.0f));
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
                                                          const float *__restrict__ means,
@@ -341,7 +354,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
     const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
-    const float kappa = dens[i];
+    const float kappa = density_of(rp.density, dens[i], s);
 
     uint32_t key = 0xFFFFFFFFu, count = 0;
     ushort4 rect = make_ushort4(0, 0, 0, 0);
@@ -766,7 +779,8 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     RenderParams rp, Buffers b, const float *__restrict__ means, const float *__restrict__ quats,
     const float *__restrict__ scales, const float *__restrict__ dens, const float *__restrict__ sh,
     float *__restrict__ d_means, float *__restrict__ d_quats, float *__restrict__ d_scales,
-    float *__restrict__ d_dens, float *__restrict__ d_sh, int acc)
+    float *__restrict__ d_dens, float *__restrict__ d_sh, int acc, float *__restrict__ gnorm,
+    int32_t *__restrict__ vcount)
 {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     constexpr int NF = 3 * NB, LS = NF + 1;   // floats per Gaussian, LDS row stride
@@ -792,8 +806,14 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     float gmu[3] = { 0.f, 0.f, 0.f }, gth[3] = { 0.f, 0.f, 0.f }, gs[3] = { 0.f, 0.f, 0.f };
     float gk = 0.f;
     float qn[4] = { 0.f, 0.f, 0.f, 0.f }, qlen = 1.f;
+    // densification statistics: sum over views of |dL_v/dmu| and the views
+    // in which the Gaussian had tiles
+    const bool stats = gnorm != nullptr || vcount != nullptr;   // uniform
+    float nsum = 0.f;
+    int32_t nvis = 0;
     for (int v = 0; v < rp.n_views; ++v) {
         const int64_t item = (int64_t)v * rp.n + i;
+        if (stats) nvis += b.counts[item] > 0u ? 1 : 0;
         const float4 *rg = b.rgrad + item * 4;
         const float4 r0 = rg[0], r1 = rg[1], r2 = rg[2], r3 = rg[3];
         const float gr[16] = { r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
@@ -824,8 +844,9 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         for (int j = 0; j < 3; ++j)
             dm[j] = -(g.L[j] * gr[6] + g.L[3 + j] * gr[7] + g.L[6 + j] * gr[8]);
         // m = R_view mu + t
+        float gmv[3];   // this view's dL/dmu
         for (int j = 0; j < 3; ++j)
-            gmu[j] += vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];
+            gmv[j] = vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];
         if (rp.mode == VGR_MODE_COLOR) {
             float vx = mu[0] - vi.o[0], vy = mu[1] - vi.o[1], vz = mu[2] - vi.o[2];
             const float len = sqrtf(vx * vx + vy * vy + vz * vz);
@@ -853,11 +874,15 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
             }
             const float3 gv = sh_grad_dot(DEG, vx, vy, vz, wk);
             const float vg = vx * gv.x + vy * gv.y + vz * gv.z;
-            gmu[0] += (gv.x - vx * vg) * il;
-            gmu[1] += (gv.y - vy * vg) * il;
-            gmu[2] += (gv.z - vz * vg) * il;
+            gmv[0] += (gv.x - vx * vg) * il;
+            gmv[1] += (gv.y - vy * vg) * il;
+            gmv[2] += (gv.z - vz * vg) * il;
         }
+        for (int j = 0; j < 3; ++j) gmu[j] += gmv[j];
+        if (stats) nsum += sqrtf(gmv[0] * gmv[0] + gmv[1] * gmv[1] + gmv[2] * gmv[2]);
     }
+    if (gnorm) gnorm[i] += nsum;
+    if (vcount) vcount[i] += nvis;
     // acc: add to the caller's arrays; otherwise overwrite them (no read)
     auto put = [acc](float *p, float v) {
         if (acc) *p += v;
@@ -882,8 +907,23 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         put(d_quats + 4 * i + 2, c * (w * gth[1] + z * gth[0] - x * gth[2]));
         put(d_quats + 4 * i + 3, c * (w * gth[2] + x * gth[1] - y * gth[0]));
     }
+    // gk = kappa dL/dkappa.  Density input kappa: dL/dkappa = gk / kappa.
+    // Input theta, kappa = phi(theta) h(s) with phi = -ln(1 - 0.99 theta) and
+    // h = mean of 1/s_k: dL/dtheta = gk phi'/phi and dL/ds_k gains
+    // gk d ln h / ds_k = -gk / (s_k^2 sum_j 1/s_j).
+    if (rp.density == VGR_DENSITY_THETA) {
+        const float th = dens[i];
+        const float dth = (th < 0.0f || th > 1.0f)
+                              ? 0.0f
+                              : gk * (0.99f / (fmaf(-0.99f, th, 1.0f) * theta_log(th)));
+        put(d_dens + i, dth);
+        const float is[3] = { 1.0f / s[0], 1.0f / s[1], 1.0f / s[2] };
+        const float r = gk / (is[0] + is[1] + is[2]);
+        for (int k = 0; k < 3; ++k) gs[k] -= r * (is[k] * is[k]);
+    } else {
+        put(d_dens + i, gk / dens[i]);
+    }
     for (int k = 0; k < 3; ++k) put(d_scales + 3 * i + k, gs[k]);
-    put(d_dens + i, gk / dens[i]);
     }
     }   // valid
     if (color && d_sh) {
@@ -1041,14 +1081,15 @@ hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const
                                  const float *quats, const float *scales, const float *dens,
                                  const float *sh, float *d_means, float *d_quats,
                                  float *d_scales, float *d_dens, float *d_sh, bool accumulate,
-                                 hipStream_t s)
+                                 float *gnorm, int32_t *vcount, hipStream_t s)
 {
     const unsigned g = grid_for(rp.n, 128);
+    const int acc = accumulate ? 1 : 0;
     switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
-    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
-    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
-    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
-    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, accumulate ? 1 : 0); break;
+    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
+    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
+    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
+    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
     }
     return hipGetLastError();
 }

@@ -90,6 +90,7 @@ struct RenderParams {
     float bg[3];
     int32_t tile_w, tile_h;
     int32_t total_tiles;
+    int32_t density;     // VGR_DENSITY_KAPPA or VGR_DENSITY_THETA
 };
 
 // Device workspace views handed to kernels.
@@ -167,11 +168,12 @@ hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool coun
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
 // accumulate: add to the gradient arrays; otherwise overwrite every element.
+// gnorm / vcount (may be null): densification statistics, always added to.
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
                                  const float *quats, const float *scales, const float *dens,
                                  const float *sh, float *d_means, float *d_quats,
                                  float *d_scales, float *d_dens, float *d_sh, bool accumulate,
-                                 hipStream_t s);
+                                 float *gnorm, int32_t *vcount, hipStream_t s);
 
 // Exclusive scan of n u32 values (n host-known), out may alias nothing;
 // out[n] receives the total when write_total.  tmp: scan_tmp_words(n) u32.

@@ -25,6 +25,7 @@ class Settings:
     bg: tuple = (0.0, 0.0, 0.0)
     act: str = "clamp"               # "clamp" | "softplus"
     tile: tuple = (0, 0)             # (0, 0): the context's tuned tile
+    density: str = "kappa"           # "kappa" | "theta": what `dens` holds
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -35,13 +36,15 @@ class Settings:
         s.bg[:] = [float(v) for v in self.bg]
         s.act = L.VGR_ACT_SOFTPLUS10 if self.act == "softplus" else L.VGR_ACT_CLAMP0
         s.tile_w, s.tile_h = int(self.tile[0]), int(self.tile[1])
+        s.density = L.VGR_DENSITY_THETA if self.density == "theta" else L.VGR_DENSITY_KAPPA
         return s
 
     @staticmethod
-    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), sh_degree=0):
+    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), sh_degree=0,
+                      density="kappa"):
         """Smallest thresholds FP32 allows (for finite-difference checks)."""
         return Settings(mode=mode, sh_degree=sh_degree, alpha_min=1e-30, alpha_max=1 - 2 ** -20,
-                        T_min=0.0, x_min_xray=1e-30, bg=bg, act=act)
+                        T_min=0.0, x_min_xray=1e-30, bg=bg, act=act, density=density)
 
 
 def camera_struct(cam) -> L.vgr_camera:
@@ -154,6 +157,22 @@ class Renderer:
         timing of the production rasterisers (load balance in stats())."""
         L.check(self._lib.vgr_set_counting(self._h, int(bool(on)) | (2 if wg_timing else 0)),
                 self._h)
+
+    def set_densify_stats(self, grad_norm_sum: Optional[torch.Tensor],
+                          view_count: Optional[torch.Tensor]):
+        """Make every later backward add, per Gaussian, the sum over views of
+        |dL_v/dmu| to grad_norm_sum (float32, n) and the number of views that
+        saw it to view_count (int32, n); None, None turns this off.  The
+        tensors must stay alive while set."""
+        ts = [t for t in (grad_norm_sum, view_count) if t is not None]
+        if grad_norm_sum is not None and grad_norm_sum.dtype != torch.float32:
+            raise ValueError("grad_norm_sum must be float32")
+        if view_count is not None and view_count.dtype != torch.int32:
+            raise ValueError("view_count must be int32")
+        cap = min(int(t.numel()) for t in ts) if ts else 0
+        self._densify_keep = ts
+        L.check(self._lib.vgr_set_densify_stats(self._h, _dev_ptr(grad_norm_sum),
+                                                 _dev_ptr(view_count), cap), self._h)
 
     def set_timing(self, on: bool):
         L.check(self._lib.vgr_set_timing(self._h, int(bool(on))), self._h)

@@ -211,6 +211,14 @@ def config1(n=1000, width=128, height=128, seed=1) -> Workload:
                     _scene(means, scales, quats, dens, sh, 0), [cam])
 
 
+def with_theta(scene: Scene, seed: int, lo: float = 0.02, hi: float = 0.98) -> Scene:
+    """The same Gaussians with the density input replaced by the paper's
+    density parameter theta (Sec. 5), drawn uniform in [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed)
+    theta = _f32(rng.uniform(lo, hi, scene.n))
+    return Scene(scene.means, scene.quats, scene.scales, theta, scene.sh, scene.sh_degree)
+
+
 def _clustered_scene(rng, n, n_clusters, sh_degree=3):
     means = clustered_means(rng, n, n_clusters)
     scales = np.exp(rng.normal(math.log(0.01), 0.7, (n, 3)))
