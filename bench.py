@@ -321,19 +321,27 @@ def bench_train(args, torch, dev, views_per_call=16):
     del outs
     st = Settings(sh_degree=3, tile=tile)
 
-    def step():
+    def step(p, s):
         for v0 in range(0, nv, views_per_call):
             cams = wl.cams[v0:v0 + views_per_call]
-            r.forward(*params, cams, st)
+            r.forward(*p, cams, s)
             r.backward(dLs[v0:v0 + views_per_call], *grads, accumulate=v0 > 0)
 
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.train_steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.train_steps
+    def timed(p, s):
+        step(p, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.train_steps):
+            step(p, s)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.train_steps
+        r.set_timing(True)
+        step(p, s)
+        stages = r.timing()
+        r.set_timing(False)
+        return dt, stages
+
+    dt, stages = timed(params, st)
     def call_one():
         r.forward(*params, wl.cams[:views_per_call], st)
         r.backward(dLs[:views_per_call], *grads, accumulate=True)
@@ -341,7 +349,31 @@ def bench_train(args, torch, dev, views_per_call=16):
                        "fwd+bwd accumulated into FP32 parameter gradients, 16 views per call",
            "tile": list(tile), "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1),
            "rasterisers_one_call": _raster_rates(r, call_one, tile[0] * tile[1] / 64.0, "color")}
-    del params, grads, dLs
+    # the same step with the paper's training inputs: theta as the density
+    # input (kappa computed in the preprocess) and the densification
+    # statistics accumulated by the backward
+    # theta is chosen so that kappa is the one of the step above (clamped to
+    # theta <= 1 where that kappa is out of reach), so both steps render the
+    # same scene and the difference is the cost of the two options
+    _log("training step with theta input and densification statistics")
+    import numpy as np
+    h = (1.0 / wl.scene.scales.astype(np.float64)).mean(1)
+    theta = np.clip(-np.expm1(-wl.scene.dens.astype(np.float64) / h) / 0.99, 0.0, 1.0)
+    p_theta = list(params)
+    p_theta[3] = torch.from_numpy(theta.astype(np.float32)).to(dev)
+    gnorm = torch.zeros(wl.scene.n, dtype=torch.float32, device=dev)
+    vcount = torch.zeros(wl.scene.n, dtype=torch.int32, device=dev)
+    r.set_densify_stats(gnorm, vcount)
+    dt2, stages2 = timed(p_theta, Settings(sh_degree=3, tile=tile, density="theta"))
+    r.set_densify_stats(None, None)
+    pick = lambda d: {k: round(d.get(k, 0.0) * 4, 3) for k in ("preprocess_fwd", "preprocess_bwd")}
+    out["stage_ms_per_step"] = {k: round(v * 4, 3) for k, v in stages.items()}
+    out["theta_and_densify_stats"] = {
+        "ms_per_step": round(dt2 * 1e3, 2), "views_per_s": round(nv / dt2, 1),
+        "theta_clamped": int((theta >= 1.0).sum()),
+        "stage_ms_per_step": {"kappa": pick(stages), "theta_and_stats": pick(stages2)},
+        "note": "theta gives the kappa of the plain step; stage means per call x 4 calls"}
+    del params, grads, dLs, p_theta, gnorm, vcount
     if not args.no_cpu_baseline:
         import oracle
         _log("oracle on one training view")

@@ -337,7 +337,7 @@ __device__ inline float density_of(int density, float in, const float *s)
     return theta_log(in) * ((1.0f / s[0] + 1.0f / s[1] + 1.0f / s[2]) * (1.0f / 3.0f));
 }
 
-template <int DEG>
+template <int DEG, bool MULTI>
 __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
                                                          const float *__restrict__ means,
                                                          const float *__restrict__ quats,
@@ -345,159 +345,169 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                                                          const float *__restrict__ dens,
                                                          const float *__restrict__ sh)
 {
+    // One thread per Gaussian for all views of the call: its parameters (and
+    // its SH row, from the first view that sees it) are read from HBM once.
+    // MULTI = false is the one-view form: no loop, and the SH row is not kept
+    // across iterations (fewer registers, higher occupancy).
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
     const bool valid = i0 < rp.n;
     const int64_t i = valid ? i0 : rp.n - 1;   // threads past the end mirror the last Gaussian
-    const ViewInfo &vi = b.views[v];
-    const int64_t item = (int64_t)v * rp.n + i;
     const float mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     const float q[4] = { quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3] };
     const float s[3] = { scales[3 * i], scales[3 * i + 1], scales[3 * i + 2] };
     const float kappa = density_of(rp.density, dens[i], s);
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    float c3[NB * 3];
+    bool have_sh = false;
+    uint32_t total = 0;
 
-    uint32_t key = 0xFFFFFFFFu, count = 0;
-    ushort4 rect = make_ushort4(0, 0, 0, 0);
-    const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
-    const float K = kappa * kSqrt2Pi;
-    const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
-    if (valid && z > vi.znear && K * smax > rp.tau) {
-        GaussView g;
-        gauss_view(vi, mu, q, s, g);
-        // alpha >= alpha_min needs D^2 <= 2 ln(K beta / tau) with beta the
-        // ray's standard deviation; beta <= smax gives a first box ...
-        float D2max = 2.0f * logf(K * smax / rp.tau);
-        const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
-        int x0, x1, y0, y1;
-        screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
-        // ... and beta over the rays of that box bounds it tighter (tight for
-        // anisotropic Gaussians seen along a short axis)
-        if (x0 <= x1 && y0 <= y1) {
-            const float beta = beta_bound(g, s, smax, vi, x0, x1, y0, y1);
-            if (beta < smax) {
-                if (K * beta > rp.tau) {
-                    D2max = 2.0f * logf(K * beta / rp.tau);
-                    screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
-                } else {
-                    x1 = x0 - 1;   // alpha < alpha_min on every ray of the box
+    const int n_views = MULTI ? rp.n_views : 1;
+    for (int v = 0; v < n_views; ++v) {
+        const ViewInfo &vi = b.views[v];
+        const int64_t item = (int64_t)v * rp.n + i;
+        uint32_t key = 0xFFFFFFFFu, count = 0;
+        ushort4 rect = make_ushort4(0, 0, 0, 0);
+        const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
+        const float K = kappa * kSqrt2Pi;
+        const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
+        if (valid && z > vi.znear && K * smax > rp.tau) {
+            GaussView g;
+            gauss_view(vi, mu, q, s, g);
+            // alpha >= alpha_min needs D^2 <= 2 ln(K beta / tau) with beta the
+            // ray's standard deviation; beta <= smax gives a first box ...
+            float D2max = 2.0f * logf(K * smax / rp.tau);
+            const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
+            int x0, x1, y0, y1;
+            screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
+            // ... and beta over the rays of that box bounds it tighter (tight for
+            // anisotropic Gaussians seen along a short axis)
+            if (x0 <= x1 && y0 <= y1) {
+                const float beta = beta_bound(g, s, smax, vi, x0, x1, y0, y1);
+                if (beta < smax) {
+                    if (K * beta > rp.tau) {
+                        D2max = 2.0f * logf(K * beta / rp.tau);
+                        screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
+                    } else {
+                        x1 = x0 - 1;   // alpha < alpha_min on every ray of the box
+                    }
                 }
             }
-        }
-        if (x0 <= x1 && y0 <= y1) {
-            const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
-            const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;
-            rect = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,
-                                (unsigned short)ty1);
-            key = __float_as_uint(z);
-            // view-space mean and projected centre in FP64: their rounding sets
-            // how precisely the pixel offsets of small, distant Gaussians are known
-            const double mx = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
-            const double my = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
-            const double mzd = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
-            const double rmz = 1.0 / mzd;
-            const double u0x = mx * rmz, u0y = my * rmz;
-            const double cxp = (double)vi.fx * u0x + vi.cx, cyp = (double)vi.fy * u0y + vi.cy;
-            const double hx = rint(cxp), hy = rint(cyp);
-            const float v0[3] = {
-                (float)(g.L[0] * u0x + g.L[1] * u0y + g.L[2]),
-                (float)(g.L[3] * u0x + g.L[4] * u0y + g.L[5]),
-                (float)(g.L[6] * u0x + g.L[7] * u0y + g.L[8]) };
-            const float mz = (float)mzd;
-            const float ifx = 1.0f / vi.fx, ify = 1.0f / vi.fy;
-            const float A[6] = { g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify,
-                                 g.L[6] * ifx, g.L[7] * ify };
-            // bound pre-test form (FP64): with G = A^T A, gv = A^T v0, V = |v0|^2,
-            // D' = D2max (1 + 1e-4):  Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V),
-            // l = -gv / V
-            float Q00 = 0.f, Q01 = 0.f, Q11 = 0.f, l0 = 0.f, l1 = 0.f;
-            CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
-            {
-                const double Dp = (double)D2max * (1.0 + 1e-4);
-                double G00 = 0, G01 = 0, G11 = 0, g0 = 0, g1 = 0, V = 0;
-                for (int k = 0; k < 3; ++k) {
-                    const double ak0 = A[2 * k], ak1 = A[2 * k + 1], vk = v0[k];
-                    G00 += ak0 * ak0; G01 += ak0 * ak1; G11 += ak1 * ak1;
-                    g0 += ak0 * vk; g1 += ak1 * vk; V += vk * vk;
+            if (x0 <= x1 && y0 <= y1) {
+                const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
+                const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;
+                rect = make_ushort4((unsigned short)tx0, (unsigned short)ty0, (unsigned short)tx1,
+                                    (unsigned short)ty1);
+                key = __float_as_uint(z);
+                // view-space mean and projected centre in FP64: their rounding sets
+                // how precisely the pixel offsets of small, distant Gaussians are known
+                const double mx = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
+                const double my = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
+                const double mzd = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
+                const double rmz = 1.0 / mzd;
+                const double u0x = mx * rmz, u0y = my * rmz;
+                const double cxp = (double)vi.fx * u0x + vi.cx, cyp = (double)vi.fy * u0y + vi.cy;
+                const double hx = rint(cxp), hy = rint(cyp);
+                const float v0[3] = {
+                    (float)(g.L[0] * u0x + g.L[1] * u0y + g.L[2]),
+                    (float)(g.L[3] * u0x + g.L[4] * u0y + g.L[5]),
+                    (float)(g.L[6] * u0x + g.L[7] * u0y + g.L[8]) };
+                const float mz = (float)mzd;
+                const float ifx = 1.0f / vi.fx, ify = 1.0f / vi.fy;
+                const float A[6] = { g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify,
+                                     g.L[6] * ifx, g.L[7] * ify };
+                // bound pre-test form (FP64): with G = A^T A, gv = A^T v0, V = |v0|^2,
+                // D' = D2max (1 + 1e-4):  Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V),
+                // l = -gv / V
+                float Q00 = 0.f, Q01 = 0.f, Q11 = 0.f, l0 = 0.f, l1 = 0.f;
+                CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
+                {
+                    const double Dp = (double)D2max * (1.0 + 1e-4);
+                    double G00 = 0, G01 = 0, G11 = 0, g0 = 0, g1 = 0, V = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        const double ak0 = A[2 * k], ak1 = A[2 * k + 1], vk = v0[k];
+                        G00 += ak0 * ak0; G01 += ak0 * ak1; G11 += ak1 * ak1;
+                        g0 += ak0 * vk; g1 += ak1 * vk; V += vk * vk;
+                    }
+                    const double mz2 = mzd * mzd, rV = 1.0 / V, rden = rV / Dp;
+                    const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) * rden;
+                    const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) * rden;
+                    const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) * rden;
+                    const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
+                    const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
+                    const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
+                    if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
+                        const double el0 = -g0 * rV, el1 = -g1 * rV, rdet = 1.0 / det;
+                        Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
+                        l0 = (float)el0; l1 = (float)el1;
+                        // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
+                        const double dx0 = -(q11 * el0 - q01 * el1) * rdet;
+                        const double dy0 = -(q00 * el1 - q01 * el0) * rdet;
+                        const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
+                        cr.cx = (float)(cxp + dx0 - 0.5);
+                        cr.cy = (float)(cyp + dy0 - 0.5);
+                        const double rq00 = 1.0 / q00;
+                        cr.a = (float)(-q01 * rq00);
+                        cr.P = (float)(rho * rq00);
+                        cr.R = (float)(det * rq00 * rq00);
+                        cr.ymax = (float)sqrt(rho * q00 * rdet);
+                        cr.yl = (float)(q01 * sqrt(rho * rdet / q11));
+                        cr.on = 1.0f;
+                    }
                 }
-                const double mz2 = mzd * mzd, rV = 1.0 / V, rden = rV / Dp;
-                const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) * rden;
-                const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) * rden;
-                const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) * rden;
-                const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
-                const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
-                const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
-                if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
-                    const double el0 = -g0 * rV, el1 = -g1 * rV, rdet = 1.0 / det;
-                    Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
-                    l0 = (float)el0; l1 = (float)el1;
-                    // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
-                    const double dx0 = -(q11 * el0 - q01 * el1) * rdet;
-                    const double dy0 = -(q00 * el1 - q01 * el0) * rdet;
-                    const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
-                    cr.cx = (float)(cxp + dx0 - 0.5);
-                    cr.cy = (float)(cyp + dy0 - 0.5);
-                    const double rq00 = 1.0 / q00;
-                    cr.a = (float)(-q01 * rq00);
-                    cr.P = (float)(rho * rq00);
-                    cr.R = (float)(det * rq00 * rq00);
-                    cr.ymax = (float)sqrt(rho * q00 * rdet);
-                    cr.yl = (float)(q01 * sqrt(rho * rdet / q11));
-                    cr.on = 1.0f;
+                // tiles of the rectangle that the bound ellipse reaches, row by row
+                for (int ty = ty0; ty <= ty1; ++ty) {
+                    int t0, t1;
+                    if (cull_row(cr, ty, rp.tile_w, rp.tile_h, tx0, tx1, t0, t1))
+                        count += (uint32_t)(t1 - t0 + 1);
                 }
-            }
-            // tiles of the rectangle that the bound ellipse reaches, row by row
-            for (int ty = ty0; ty <= ty1; ++ty) {
-                int t0, t1;
-                if (cull_row(cr, ty, rp.tile_w, rp.tile_h, tx0, tx1, t0, t1))
-                    count += (uint32_t)(t1 - t0 + 1);
-            }
-            float4 *gp = b.geom + item * kRecVec;
-            gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
-            gp[1] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
-            gp[2] = make_float4(Q11, A[0], A[2], A[4]);
-            gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
-            gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
-            gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
-            gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);
-            float rgb[3] = { 0.0f, 0.0f, 0.0f };
-            if (rp.mode == VGR_MODE_COLOR) {
-                float dx = mu[0] - vi.o[0], dy = mu[1] - vi.o[1], dz = mu[2] - vi.o[2];
-                const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-                dx *= il; dy *= il; dz *= il;
-                float Y[16];
-                sh_basis(DEG, dx, dy, dz, Y);
-                constexpr int NB = (DEG + 1) * (DEG + 1);
-                float c3[NB * 3];
-                load_sh_row<NB * 3>(sh, i, ((uintptr_t)sh & 15) == 0, c3);
-                for (int ch = 0; ch < 3; ++ch) {
-                    float acc = 0.5f;
+                float4 *gp = b.geom + item * kRecVec;
+                gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
+                gp[1] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
+                gp[2] = make_float4(Q11, A[0], A[2], A[4]);
+                gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
+                gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
+                gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
+                gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);
+                float rgb[3] = { 0.0f, 0.0f, 0.0f };
+                if (rp.mode == VGR_MODE_COLOR) {
+                    float dx = mu[0] - vi.o[0], dy = mu[1] - vi.o[1], dz = mu[2] - vi.o[2];
+                    const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                    dx *= il; dy *= il; dz *= il;
+                    float Y[16];
+                    sh_basis(DEG, dx, dy, dz, Y);
+                    if (!have_sh) {
+                        load_sh_row<NB * 3>(sh, i, ((uintptr_t)sh & 15) == 0, c3);
+                        have_sh = true;
+                    }
+                    for (int ch = 0; ch < 3; ++ch) {
+                        float acc = 0.5f;
 #pragma unroll
-                    for (int k = 0; k < NB; ++k) acc = fmaf(c3[k * 3 + ch], Y[k], acc);
-                    rgb[ch] = act_fwd(rp.act, acc);
+                        for (int k = 0; k < NB; ++k) acc = fmaf(c3[k * 3 + ch], Y[k], acc);
+                        rgb[ch] = act_fwd(rp.act, acc);
+                    }
                 }
+                gp[5] = make_float4(rgb[0], rgb[1], rgb[2], mz);
             }
-            gp[5] = make_float4(rgb[0], rgb[1], rgb[2], mz);
         }
-    }
-    if (count == 0) key = 0xFFFFFFFFu;
-    if (valid) {
-        b.depth_key[item] = key;
-        b.item_ids[item] = (uint32_t)item;
-        b.counts[item] = count;
-        b.rect[item] = rect;
+        if (count == 0) key = 0xFFFFFFFFu;
+        if (valid) {
+            b.depth_key[item] = key;
+            b.item_ids[item] = (uint32_t)item;
+            b.counts[item] = count;
+            b.rect[item] = rect;
+            total += count;
+        }
     }
     // total instance count K, for sizing the instance lists before the scan:
     // one partial sum per block (count_total_kernel adds them; one atomic per
     // wave on a single address would serialise thousands of updates)
     __shared__ uint32_t s_wsum[4];
-    uint32_t wsum = count;
+    uint32_t wsum = total;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
     if ((threadIdx.x & 63) == 0) s_wsum[threadIdx.x >> 6] = wsum;
     __syncthreads();
-    if (threadIdx.x == 0)
-        b.blk_counts[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] =
-            s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    if (threadIdx.x == 0) b.blk_counts[blockIdx.x] = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
 }
 
 __global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__restrict__ parts,
@@ -1014,22 +1024,33 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
                              const float *quats, const float *scales, const float *dens,
                              const float *sh, hipStream_t s)
 {
-    dim3 grid(grid_for(rp.n, 256), rp.n_views);
-    switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
-    case 0: preprocess_kernel<0><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-    case 1: preprocess_kernel<1><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-    case 2: preprocess_kernel<2><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-    default: preprocess_kernel<3><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+    const unsigned grid = grid_for(rp.n, 256);
+    const int deg = rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0;
+    if (rp.n_views > 1) {
+        switch (deg) {
+        case 0: preprocess_kernel<0, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        case 1: preprocess_kernel<1, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        case 2: preprocess_kernel<2, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        default: preprocess_kernel<3, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        }
+    } else {
+        switch (deg) {
+        case 0: preprocess_kernel<0, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        case 1: preprocess_kernel<1, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        case 2: preprocess_kernel<2, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        default: preprocess_kernel<3, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid.x * grid.y, b.d_total + 4);
+    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total + 4);
     return hipGetLastError();
 }
 
 int64_t preprocess_blocks(int64_t n, int32_t n_views)
 {
-    return (int64_t)grid_for(n, 256) * n_views;
+    (void)n_views;   // one thread per Gaussian covers all views
+    return (int64_t)grid_for(n, 256);
 }
 
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)
