@@ -10,7 +10,8 @@ duck-typed scene / camera objects (attributes ``means, quats, scales, dens,
 sh, sh_degree`` and ``R, t, fx, fy, cx, cy, width, height, znear``).
 
 Passages followed (arXiv 2412.03378): the density mixture and Gaussian
-(Sec. 3.2), the alpha-blend without splatting (Sec. 4.1), the 1D Gaussian on
+(Sec. 3.2), the 3DGS splatting opacity the paper compares against (Sec. 3,
+eq. 3dgs_alpha, eq. affine_approx), the alpha-blend without splatting (Sec. 4.1), the 1D Gaussian on
 a ray and its boxed full-line integral (Sec. 4.2, Supp. B), the density
 reparameterisation (Sec. 5, eq. density_reparam), tomography as a sum of line
 integrals (Sec. 6.2), and the world-space positional gradient norms that
@@ -52,7 +53,8 @@ class _Cam(C.Structure):
 
 class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
-                ("density", C.c_int32), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("density", C.c_int32), ("alpha_model", C.c_int32), ("pad", C.c_int32),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
 
 
@@ -68,6 +70,7 @@ class Settings:
     bg: tuple = (0.0, 0.0, 0.0)
     act: str = "clamp"             # "clamp" | "softplus"
     density: str = "kappa"         # "kappa" | "theta" (eq. density_reparam)
+    alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS, eq. 3dgs_alpha)
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa"):
@@ -124,6 +127,7 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     s.sh_degree = int(sh_degree)
     s.act = 1 if st.act == "softplus" else 0
     s.density = 1 if st.density == "theta" else 0
+    s.alpha_model = 1 if st.alpha_model == "splat" else 0
     s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
     s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
     s.bg[:] = [float(v) for v in st.bg]

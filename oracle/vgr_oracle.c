@@ -32,6 +32,10 @@
  *   - colour c = act(sum_k sh_k Y_k(v) + 0.5), v = normalize(mu - o), with
  *     real orthonormal spherical harmonics (Condon-Shortley phase), act =
  *     max(.,0) or softplus with sharpness 10 (Supp. D).
+ *   - comparison model (alpha_model = 1): the 3DGS splatting opacity the
+ *     paper replaces (Sec. 3, eq. 3dgs_alpha, eq. affine_approx), with the
+ *     density input read as the peak opacity o in [0, 1] (clamped) and the
+ *     same compositing rules; forward only.
  *   - the density input is kappa itself, or theta with the reparameterisation
  *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
  *     density_reparam); theta outside the paper's range [0, 1] is clamped to
@@ -69,6 +73,8 @@ typedef struct {
     int32_t sh_degree;  /* 0..3 */
     int32_t act;        /* 0 max(.,0), 1 softplus(10 y)/10 */
     int32_t density;    /* 0: dens holds kappa; 1: dens holds theta (kappa_of) */
+    int32_t alpha_model;/* 0: the paper's ray integral; 1: 3DGS splatting (splat_setup) */
+    int32_t pad;
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
 } orc_settings;
@@ -248,6 +254,7 @@ typedef struct {
     double *rgb;         /* n x 3 colour for this view */
     double *raw;         /* n x 3 colour before activation */
     double *kappa;       /* n densities kappa */
+    double *splat;       /* alpha_model 1: n x 6 (mu'_x, mu'_y, C00, C01, C11, o) */
     double o[3];
 } view_state;
 
@@ -355,6 +362,59 @@ static void kappa_grad(const orc_settings *st, float dens, const float s[3], dou
     for (int k = 0; k < 3; ++k) dk_ds[k] = -phi / (3.0 * (double)s[k] * (double)s[k]);
 }
 
+/* 3DGS splatting of Gaussian (mu, R, s) in camera cam (Sec. 3, eq. 3dgs_alpha
+   and eq. affine_approx): the 2D mean mu' is the projection of the view-space
+   mean m = W mu + t, and the 2D covariance Sigma' = J W Sigma W^T J^T with W the
+   world-to-view rotation, Sigma = R diag(s^2) R^T and J the Jacobian of the
+   pinhole map (x, y, z) -> (fx x/z + cx, fy y/z + cy) at m.  out = (mu'_x,
+   mu'_y, C00, C01, C11, o) with C = Sigma'^-1 and o the peak opacity in [0, 1]. */
+static void splat_setup(const orc_camera *cam, const float *mu, const double R[9],
+                        const float s[3], float dens, double out[6])
+{
+    const float *Wf = cam->R;
+    double m[3];
+    for (int a = 0; a < 3; ++a)
+        m[a] = (double)Wf[3 * a] * mu[0] + (double)Wf[3 * a + 1] * mu[1] +
+               (double)Wf[3 * a + 2] * mu[2] + (double)cam->t[a];
+    double S[9], WS[9], V[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k)
+                acc += R[i * 3 + k] * R[j * 3 + k] * (double)s[k] * (double)s[k];
+            S[i * 3 + j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += (double)Wf[i * 3 + k] * S[k * 3 + j];
+            WS[i * 3 + j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += WS[i * 3 + k] * (double)Wf[j * 3 + k];
+            V[i * 3 + j] = acc;
+        }
+    const double fx = cam->fx, fy = cam->fy, z = m[2];
+    const double J[6] = { fx / z, 0.0, -fx * m[0] / (z * z), 0.0, fy / z, -fy * m[1] / (z * z) };
+    double Sp[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double acc = 0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) acc += J[a * 3 + i] * V[i * 3 + j] * J[b * 3 + j];
+            Sp[a * 2 + b] = acc;
+        }
+    const double det = Sp[0] * Sp[3] - Sp[1] * Sp[2];
+    out[0] = fx * m[0] / z + cam->cx;
+    out[1] = fy * m[1] / z + cam->cy;
+    out[2] = Sp[3] / det;
+    out[3] = -0.5 * (Sp[1] + Sp[2]) / det;
+    out[4] = Sp[0] / det;
+    out[5] = dens < 0.0f ? 0.0 : (dens > 1.0f ? 1.0 : (double)dens);
+}
+
 static int view_setup(view_state *vs, int64_t n, const float *means, const float *quats,
                       const float *scales, const float *dens, const float *sh,
                       const orc_camera *cam, const orc_settings *st)
@@ -368,6 +428,10 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
     vs->raw = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     vs->kappa = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw || !vs->kappa) return -3;
+    if (st->alpha_model == 1) {
+        vs->splat = (double *)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
+        if (!vs->splat) return -3;
+    }
     camera_origin(cam, vs->o);
     int nb = (st->sh_degree + 1) * (st->sh_degree + 1);
     int64_t nvis = 0;
@@ -377,6 +441,7 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
         quat_rotation(quats + 4 * i, R, NULL, NULL);
         precision_matrix(R, scales + 3 * i, vs->P + 9 * i);
         vs->kappa[i] = kappa_of(st, dens[i], scales + 3 * i);
+        if (vs->splat) splat_setup(cam, means + 3 * i, R, scales + 3 * i, dens[i], vs->splat + 6 * i);
         vs->key[i] = depth_key(cam, means + 3 * i);
         if (st->mode == 0) {
             double v[3], len = 0, Y[(ORC_MAX_DEG + 1) * (ORC_MAX_DEG + 1)];
@@ -403,6 +468,7 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
 static void view_free(view_state *vs)
 {
     free(vs->order); free(vs->key); free(vs->P); free(vs->rgb); free(vs->raw); free(vs->kappa);
+    free(vs->splat);
 }
 
 static double rel_margin(double v, double thr)
@@ -434,7 +500,8 @@ static void list_push(blend_list *bl, blend_rec r)
 }
 
 /* Composite one pixel; fills out[3] (colour) or out[0] (X-ray). */
-static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st, const double d[3], double *out,
+static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st,
+                        const double d[3], const double pc[2], double *out,
                         double *T_out, int64_t *last_out, int32_t *nblend_out,
                         double *margin_out, double *untrunc_out, blend_list *bl)
 {
@@ -475,16 +542,30 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
     int32_t cnt = 0;
     for (int64_t r = 0; r < vs->nvis; ++r) {
         int64_t i = vs->order[r];
-        double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+        double alpha, m;
         ray_terms rt;
-        ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
-        double m = rel_margin(rt.x, tau);
-        if (m < margin) margin = m;
-        if (rt.x < tau) continue;                      /* alpha < alpha_min */
-        double alpha = -expm1(-rt.x);
+        if (vs->splat) {
+            /* alpha = o exp(-1/2 dp^T C dp), dp = pixel centre - mu' */
+            const double *sp = vs->splat + 6 * i;
+            const double dx = pc[0] - sp[0], dy = pc[1] - sp[1];
+            alpha = sp[5] * exp(-0.5 * (sp[2] * dx * dx + 2.0 * sp[3] * dx * dy + sp[4] * dy * dy));
+            rt.x = -log1p(-alpha);
+            m = rel_margin(alpha, st->alpha_min);
+            if (m < margin) margin = m;
+            if (alpha < st->alpha_min) continue;
+            m = rel_margin(alpha, st->alpha_max);
+            if (m < margin) margin = m;
+        } else {
+            double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+            m = rel_margin(rt.x, tau);
+            if (m < margin) margin = m;
+            if (rt.x < tau) continue;                  /* alpha < alpha_min */
+            alpha = -expm1(-rt.x);
+            m = rel_margin(rt.x, xmax);
+            if (m < margin) margin = m;
+        }
         int clamped = 0;
-        m = rel_margin(rt.x, xmax);
-        if (m < margin) margin = m;
         if (alpha > st->alpha_max) { alpha = st->alpha_max; clamped = 1; }
         double Tn = T * (1.0 - alpha);
         if (st->T_min > 0) {
@@ -517,6 +598,7 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
+    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -524,8 +606,9 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < npix; ++p) {
         double d[3];
+        const double pc[2] = { pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5 };
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
-        shade_pixel(&vs, means, st, d, out + C * p, T_out ? T_out + p : NULL,
+        shade_pixel(&vs, means, st, d, pc, out + C * p, T_out ? T_out + p : NULL,
                     last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
                     margin_out ? margin_out + p : NULL, untrunc_out ? untrunc_out + p : NULL,
                     NULL);
@@ -705,6 +788,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
+    if (st->alpha_model != 0) return -2;   /* the splatting model is forward only */
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -719,7 +803,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         double d[3], out[3];
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
         blend_list bl = { NULL, 0, 0 };
-        shade_pixel(&vs, means, st, d, out, NULL, NULL, NULL, NULL, NULL, &bl);
+        shade_pixel(&vs, means, st, d, NULL, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
                 chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,

@@ -644,3 +644,91 @@ def test_densify_visibility_bounds():
     ds = oracle.densify_stats(sc, [cam], oracle.Settings(), [np.ones((3, 9, 9))])
     assert list(ds["visible_lo"]) == [1, 0, 0, 0]
     assert list(ds["visible_hi"]) == [1, 0, 0, 1]
+
+
+# --------------------------------- Sec. 3 comparison model: 3DGS splatting ---
+
+def _splat_settings():
+    return oracle.Settings(act="clamp", alpha_min=1e-30, alpha_max=1.0 - 1e-12, T_min=0.0,
+                           alpha_model="splat")
+
+
+def test_splat_isotropic_on_axis():
+    """An isotropic Gaussian on the optical axis splats to a circular 2D
+    Gaussian of pixel standard deviation f s / z (eq. affine_approx with
+    J = diag(f/z, f/z) there): alpha = o exp(-r^2 / (2 (f s / z)^2)) at r pixels
+    from the centre (eq. 3dgs_alpha)."""
+    cam = H.odd_camera(65, 40.0, 4.0)
+    s, o = f32(0.05), f32(0.7)
+    sc = H.scene([[0.0, 0.0, 0.0]], [s] * 3, o, rgb=[[1.0, 1.0, 1.0]])
+    c = _centre(cam)
+    pix = [(c[0] + k, c[1]) for k in range(0, 8)] + [(c[0] + 3, c[1] - 4)]
+    img = oracle.render(sc, cam, _splat_settings(), pixels=pix)["image"][0]
+    sig = float(cam.fx) * s / 4.0
+    for (px, py), a in zip(pix, img):
+        r2 = (px - c[0]) ** 2 + (py - c[1]) ** 2
+        assert a == pytest.approx(o * math.exp(-0.5 * r2 / sig ** 2), rel=1e-6)
+
+
+def test_splat_off_axis_jacobian():
+    """Axis-aligned Gaussian at (x0, 0, 0) seen from (0, 0, -4): the
+    projection's Jacobian at m = (x0, 0, 4) has the row (f/z, 0, -f x0/z^2), so
+    Sigma'_00 = (f/z)^2 s_x^2 + (f x0/z^2)^2 s_z^2, Sigma'_11 = (f/z)^2 s_y^2,
+    Sigma'_01 = 0, around mu' = (f x0/z + c_x, c_y)."""
+    cam = H.odd_camera(65, 40.0, 4.0)
+    x0 = f32(0.6)
+    s = [f32(0.03), f32(0.05), f32(0.4)]
+    o = f32(0.9)
+    sc = H.scene([[x0, 0.0, 0.0]], [s], o, rgb=[[1.0, 1.0, 1.0]])
+    f, z = float(cam.fx), 4.0
+    s00 = (f / z) ** 2 * s[0] ** 2 + (f * x0 / z ** 2) ** 2 * s[2] ** 2
+    s11 = (f / z) ** 2 * s[1] ** 2
+    mx, my = f * x0 / z + float(cam.cx), float(cam.cy)
+    pix = [(int(mx) + dx, int(my) + dy) for dx in (-3, 0, 2) for dy in (-2, 0, 1)]
+    img = oracle.render(sc, cam, _splat_settings(), pixels=pix)["image"][0]
+    for (px, py), a in zip(pix, img):
+        dx, dy = px + 0.5 - mx, py + 0.5 - my
+        assert a == pytest.approx(o * math.exp(-0.5 * (dx * dx / s00 + dy * dy / s11)), rel=1e-6)
+
+
+def test_splat_rotation_about_view_axis():
+    """Rotating the Gaussian by phi about the optical axis rotates its splat
+    by phi: Sigma' = (f/z)^2 Rz diag(sx^2, sy^2) Rz^T for a Gaussian on the
+    axis (W = I, J = [f/z I2 | 0] there)."""
+    cam = H.odd_camera(65, 40.0, 4.0)
+    phi = 0.6
+    q = [math.cos(phi / 2), 0.0, 0.0, math.sin(phi / 2)]
+    s = [f32(0.08), f32(0.02), f32(0.05)]
+    sc = H.scene([[0.0, 0.0, 0.0]], [s], 1.0, quats=[q], rgb=[[1.0, 1.0, 1.0]])
+    f, z = float(cam.fx), 4.0
+    Rz = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+    Sp = (f / z) ** 2 * Rz @ np.diag([s[0] ** 2, s[1] ** 2]) @ Rz.T
+    Ci = np.linalg.inv(Sp)
+    c = _centre(cam)
+    pix = [(c[0] + dx, c[1] + dy) for dx in (-4, -1, 0, 3) for dy in (-3, 0, 2)]
+    img = oracle.render(sc, cam, _splat_settings(), pixels=pix)["image"][0]
+    for (px, py), a in zip(pix, img):
+        d = np.array([px - c[0], py - c[1]], np.float64)
+        assert a == pytest.approx(math.exp(-0.5 * d @ Ci @ d), rel=1e-6, abs=1e-300)
+
+
+def test_splat_compositing_and_limits():
+    """Two splats on the axis composite with eq. 3dgs_alpha_blend; opacity is
+    clamped to [0, 1] and alpha to alpha_max; the splatting model has no
+    backward in the oracle."""
+    cam = H.odd_camera(9, 30.0, 4.0)
+    st = oracle.Settings(act="clamp", bg=(0.2, 0.4, 0.6), alpha_model="splat")
+    c1, c2 = np.array([1.0, 0.2, 0.1]), np.array([0.1, 0.9, 0.3])
+    sc = H.scene([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]], [[0.1] * 3, [0.1] * 3], [0.6, 0.5],
+                 rgb=np.stack([c1, c2]))
+    out = oracle.render(sc, cam, st, pixels=[_centre(cam)])["image"][:, 0]
+    bg = np.array([0.2, 0.4, 0.6])
+    cf = 0.5 + sc.sh[:, 0, :].astype(np.float64) * scenes.Y00
+    expect = cf[0] * 0.6 + cf[1] * 0.5 * 0.4 + bg * 0.4 * 0.5
+    assert np.allclose(out, expect, rtol=1e-6)
+    one = lambda o: oracle.render(H.scene([[0.0, 0.0, 0.0]], [0.1] * 3, o, rgb=[[1.0, 1.0, 1.0]]),
+                                  cam, st, pixels=[_centre(cam)])["image"][0, 0]
+    assert one(1.7) == one(1.0) == pytest.approx(0.99 * 1.0 + 0.01 * 0.2, rel=1e-6)
+    assert one(-0.5) == pytest.approx(0.2, rel=1e-12)
+    with pytest.raises(RuntimeError):
+        oracle.render_backward(sc, cam, st, np.ones((3, 9, 9)))
