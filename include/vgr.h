@@ -62,6 +62,7 @@ typedef struct {
 enum { VGR_MODE_COLOR = 0, VGR_MODE_XRAY = 1 };
 enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
 enum { VGR_DENSITY_KAPPA = 0, VGR_DENSITY_THETA = 1 };
+enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
 
 /* Rendering rules.  Defaults in brackets (vgr_default_settings).
  *   mode        colour compositing or X-ray line integrals [COLOR]
@@ -85,6 +86,17 @@ enum { VGR_DENSITY_KAPPA = 0, VGR_DENSITY_THETA = 1 };
  *               computed inside the preprocess (Sec. 5, eq. density_reparam);
  *               theta is clamped to its range [0, 1], with zero gradient
  *               outside it [KAPPA]
+ *   alpha_model VOLUMETRIC: the paper's opacity from the ray integral (above).
+ *               SPLAT: the 3DGS splatting opacity the paper compares against
+ *               (Sec. 3, eq. 3dgs_alpha, eq. affine_approx), for A/B runs on
+ *               the same pipeline: alpha = o exp(-1/2 dp^T Sigma'^-1 dp) with
+ *               dp = pixel centre - projected mean, Sigma' = J W Sigma W^T J^T
+ *               (W the world-to-view rotation, J the pinhole Jacobian at the
+ *               view-space mean) and o = `dens` read as the peak opacity,
+ *               clamped to [0, 1]; the same skip, clamp, stop and background
+ *               rules; tiles from the exact alpha >= alpha_min ellipse.  Colour
+ *               mode with density KAPPA only; forward only (a backward after
+ *               it fails with VGR_ERR_INVALID_ARG) [VOLUMETRIC]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -97,7 +109,7 @@ typedef struct {
     int32_t act;
     int32_t tile_w, tile_h;
     int32_t density;
-    int32_t reserved;
+    int32_t alpha_model;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */

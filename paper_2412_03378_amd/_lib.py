@@ -25,6 +25,8 @@ VGR_ACT_CLAMP0 = 0
 VGR_ACT_SOFTPLUS10 = 1
 VGR_DENSITY_KAPPA = 0
 VGR_DENSITY_THETA = 1
+VGR_ALPHA_VOLUMETRIC = 0
+VGR_ALPHA_SPLAT = 1
 
 
 class vgr_camera(C.Structure):
@@ -37,7 +39,7 @@ class vgr_settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("density", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32)]
 
 
 class vgr_stats(C.Structure):

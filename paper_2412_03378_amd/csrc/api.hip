@@ -421,6 +421,12 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
         return fail(c, VGR_ERR_INVALID_ARG, "bad act");
     if (st->density != VGR_DENSITY_KAPPA && st->density != VGR_DENSITY_THETA)
         return fail(c, VGR_ERR_INVALID_ARG, "bad density");
+    if (st->alpha_model != VGR_ALPHA_VOLUMETRIC && st->alpha_model != VGR_ALPHA_SPLAT)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad alpha_model");
+    if (st->alpha_model == VGR_ALPHA_SPLAT &&
+        (st->mode != VGR_MODE_COLOR || st->density != VGR_DENSITY_KAPPA))
+        return fail(c, VGR_ERR_INVALID_ARG,
+                    "the splatting model needs colour mode and the plain density input");
     if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
         !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
         return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
@@ -441,6 +447,9 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.sh_degree = st->mode == VGR_MODE_COLOR ? st->sh_degree : 0;
     rp.act = st->act;
     rp.density = st->density;
+    rp.alpha_model = st->alpha_model;
+    rp.amin = st->alpha_min;
+    rp.amax = st->alpha_max;
     rp.n_views = n_views;
     rp.n = n;
     rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;
@@ -676,6 +685,8 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward to differentiate");
     if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
     const RenderParams &rp = c->rp;
+    if (rp.alpha_model == VGR_ALPHA_SPLAT)
+        return fail(c, VGR_ERR_INVALID_ARG, "the splatting model has no backward");
     int rc;
     if ((rc = check_grads(c, rp, d_means, d_quats, d_scales, d_dens, d_sh))) return rc;
     for (int v = 0; v < rp.n_views; ++v) {

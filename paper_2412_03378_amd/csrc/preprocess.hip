@@ -324,6 +324,65 @@ __device__ __forceinline__ bool cull_row(const CullRows &c, int ty, int tw, int 
     return t0 <= t1;
 }
 
+// Bound pre-test form f(d) = d^T Q d + 2 l^T d - 1 of a record (FP64 in,
+// FP32 out) and the tile-culling ellipse {f <= kCullLevel}, kept only when Q
+// is positive definite with condition number <= 1e4 (otherwise Q = l = 0:
+// no pixel is rejected early and no tile is culled).  (cxp, cyp): projected
+// centre in pixels.
+__device__ inline void bound_form(double q00, double q01, double q11, double el0, double el1,
+                                  double cxp, double cyp, float &Q00, float &Q01, float &Q11,
+                                  float &l0, float &l1, CullRows &cr)
+{
+    Q00 = Q01 = Q11 = l0 = l1 = 0.f;
+    cr = CullRows{ 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
+    const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
+    const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
+    const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
+    if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
+        const double rdet = 1.0 / det;
+        Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
+        l0 = (float)el0; l1 = (float)el1;
+        // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
+        const double dx0 = -(q11 * el0 - q01 * el1) * rdet;
+        const double dy0 = -(q00 * el1 - q01 * el0) * rdet;
+        const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
+        cr.cx = (float)(cxp + dx0 - 0.5);
+        cr.cy = (float)(cyp + dy0 - 0.5);
+        const double rq00 = 1.0 / q00;
+        cr.a = (float)(-q01 * rq00);
+        cr.P = (float)(rho * rq00);
+        cr.R = (float)(det * rq00 * rq00);
+        cr.ymax = (float)sqrt(rho * q00 * rdet);
+        cr.yl = (float)(q01 * sqrt(rho * rdet / q11));
+        cr.on = 1.0f;
+    }
+}
+
+// 3DGS splat of one Gaussian (Sec. 3, eq. affine_approx), FP64: the 2D
+// covariance Sigma' = J Sigma_v J^T in pixels^2, with Sigma_v = Rc diag(s^2)
+// Rc^T the view-space covariance and J the Jacobian of the pinhole map at the
+// view-space mean (mx, my, mz).
+__device__ inline void splat_cov(const GaussView &g, const float *s, const ViewInfo &vi,
+                                 double mx, double my, double mz, double &S00, double &S01,
+                                 double &S11)
+{
+    double V[6];   // V00 V01 V02 V11 V12 V22
+    const int ia[6] = { 0, 0, 0, 1, 1, 2 }, ib[6] = { 0, 1, 2, 1, 2, 2 };
+    for (int e = 0; e < 6; ++e) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+            acc += (double)g.Rc[ia[e] * 3 + k] * (double)g.Rc[ib[e] * 3 + k] * (double)s[k] *
+                   (double)s[k];
+        V[e] = acc;
+    }
+    const double rz = 1.0 / mz;
+    const double j00 = vi.fx * rz, j02 = -vi.fx * mx * rz * rz;
+    const double j11 = vi.fy * rz, j12 = -vi.fy * my * rz * rz;
+    S00 = j00 * j00 * V[0] + 2.0 * j00 * j02 * V[2] + j02 * j02 * V[5];
+    S01 = j00 * j11 * V[1] + j00 * j12 * V[2] + j02 * j11 * V[4] + j02 * j12 * V[5];
+    S11 = j11 * j11 * V[3] + 2.0 * j11 * j12 * V[4] + j12 * j12 * V[5];
+}
+
 // Density kappa from the density input: the input itself, or the paper's
 // reparameterisation kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3
 // (Sec. 5, eq. density_reparam) with theta clamped to [0, 1].
@@ -337,7 +396,7 @@ __device__ inline float density_of(int density, float in, const float *s)
     return theta_log(in) * ((1.0f / s[0] + 1.0f / s[1] + 1.0f / s[2]) * (1.0f / 3.0f));
 }
 
-template <int DEG, bool MULTI>
+template <int DEG, bool MULTI, bool SPLAT>
 __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
                                                          const float *__restrict__ means,
                                                          const float *__restrict__ quats,
@@ -348,7 +407,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     // One thread per Gaussian for all views of the call: its parameters (and
     // its SH row, from the first view that sees it) are read from HBM once.
     // MULTI = false is the one-view form: no loop, and the SH row is not kept
-    // across iterations (fewer registers, higher occupancy).
+    // across iterations (fewer registers, higher occupancy).  SPLAT: the record
+    // of the 3DGS splatting model (the density input is the peak opacity).
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i0 < rp.n;
     const int64_t i = valid ? i0 : rp.n - 1;   // threads past the end mirror the last Gaussian
@@ -370,14 +430,37 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
         const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
         const float K = kappa * kSqrt2Pi;
         const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
-        if (valid && z > vi.znear && K * smax > rp.tau) {
+        const float op = fminf(fmaxf(kappa, 0.0f), 1.0f);   // splat: peak opacity
+        if (SPLAT ? (valid && z > vi.znear && op >= rp.amin)
+                  : (valid && z > vi.znear && K * smax > rp.tau)) {
             GaussView g;
             gauss_view(vi, mu, q, s, g);
+            int x0, x1, y0, y1;
+            float D2max = 0.0f;
+            double S00 = 0.0, S01 = 0.0, S11 = 0.0, E2 = 0.0;
+            if constexpr (SPLAT) {
+                // alpha = o exp(-1/2 d^T Sigma'^-1 d) >= alpha_min inside the ellipse
+                // d^T Sigma'^-1 d <= E2 = 2 ln(o / alpha_min); its box is
+                // |dx| <= sqrt(E2 S00), |dy| <= sqrt(E2 S11)
+                const double mxs = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
+                const double mys = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
+                const double mzs = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
+                splat_cov(g, s, vi, mxs, mys, mzs, S00, S01, S11);
+                E2 = 2.0 * log((double)op / (double)rp.amin);
+                const double cxs = (double)vi.fx * (mxs / mzs) + vi.cx;
+                const double cys = (double)vi.fy * (mys / mzs) + vi.cy;
+                const double hwx = sqrt(E2 * S00), hwy = sqrt(E2 * S11);
+                if (S00 * S11 - S01 * S01 > 0.0) {
+                    pixel_span(true, (float)(cxs - hwx), (float)(cxs + hwx), 1.0f, 0.0f, vi.width, x0, x1);
+                    pixel_span(true, (float)(cys - hwy), (float)(cys + hwy), 1.0f, 0.0f, vi.height, y0, y1);
+                } else {
+                    x0 = y0 = 0; x1 = y1 = -1;   // degenerate splat: no area
+                }
+            } else {
             // alpha >= alpha_min needs D^2 <= 2 ln(K beta / tau) with beta the
             // ray's standard deviation; beta <= smax gives a first box ...
-            float D2max = 2.0f * logf(K * smax / rp.tau);
+            D2max = 2.0f * logf(K * smax / rp.tau);
             const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
-            int x0, x1, y0, y1;
             screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
             // ... and beta over the rays of that box bounds it tighter (tight for
             // anisotropic Gaussians seen along a short axis)
@@ -392,6 +475,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                     }
                 }
             }
+            }   // volumetric bound
             if (x0 <= x1 && y0 <= y1) {
                 const int tx0 = x0 / rp.tile_w, tx1 = x1 / rp.tile_w;
                 const int ty0 = y0 / rp.tile_h, ty1 = y1 / rp.tile_h;
@@ -415,12 +499,20 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 const float ifx = 1.0f / vi.fx, ify = 1.0f / vi.fy;
                 const float A[6] = { g.L[0] * ifx, g.L[1] * ify, g.L[3] * ifx, g.L[4] * ify,
                                      g.L[6] * ifx, g.L[7] * ify };
-                // bound pre-test form (FP64): with G = A^T A, gv = A^T v0, V = |v0|^2,
-                // D' = D2max (1 + 1e-4):  Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V),
-                // l = -gv / V
-                float Q00 = 0.f, Q01 = 0.f, Q11 = 0.f, l0 = 0.f, l1 = 0.f;
-                CullRows cr = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
-                {
+                // bound pre-test form (FP64).  Volumetric: with G = A^T A, gv = A^T v0,
+                // V = |v0|^2, D' = D2max (1 + 1e-4):
+                // Q = (mz^2 (V G - gv gv^T) - D' G) / (D' V), l = -gv / V.
+                // Splat: Q = Sigma'^-1 / (E2 (1 + 1e-4)), l = 0.
+                float Q00, Q01, Q11, l0, l1;
+                CullRows cr;
+                double C00 = 0.0, C01 = 0.0, C11 = 0.0;
+                if constexpr (SPLAT) {
+                    const double rdet = 1.0 / (S00 * S11 - S01 * S01);
+                    C00 = S11 * rdet; C01 = -S01 * rdet; C11 = S00 * rdet;
+                    const double rE = 1.0 / (E2 * (1.0 + 1e-4));
+                    bound_form(C00 * rE, C01 * rE, C11 * rE, 0.0, 0.0, cxp, cyp, Q00, Q01, Q11, l0,
+                               l1, cr);
+                } else {
                     const double Dp = (double)D2max * (1.0 + 1e-4);
                     double G00 = 0, G01 = 0, G11 = 0, g0 = 0, g1 = 0, V = 0;
                     for (int k = 0; k < 3; ++k) {
@@ -432,27 +524,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                     const double q00 = (mz2 * (V * G00 - g0 * g0) - Dp * G00) * rden;
                     const double q01 = (mz2 * (V * G01 - g0 * g1) - Dp * G01) * rden;
                     const double q11 = (mz2 * (V * G11 - g1 * g1) - Dp * G11) * rden;
-                    const double tr = q00 + q11, det = q00 * q11 - q01 * q01;
-                    const double disc = sqrt(fmax(0.25 * tr * tr - det, 0.0));
-                    const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
-                    if (q00 > 0 && det > 0 && lmin > 0 && lmax <= 1e4 * lmin) {
-                        const double el0 = -g0 * rV, el1 = -g1 * rV, rdet = 1.0 / det;
-                        Q00 = (float)q00; Q01 = (float)q01; Q11 = (float)q11;
-                        l0 = (float)el0; l1 = (float)el1;
-                        // ellipse {f <= kCullLevel}: centre d0 = -Q^-1 l, (d-d0)^T Q (d-d0) <= rho
-                        const double dx0 = -(q11 * el0 - q01 * el1) * rdet;
-                        const double dy0 = -(q00 * el1 - q01 * el0) * rdet;
-                        const double rho = 1.0 + kCullLevel - (el0 * dx0 + el1 * dy0);
-                        cr.cx = (float)(cxp + dx0 - 0.5);
-                        cr.cy = (float)(cyp + dy0 - 0.5);
-                        const double rq00 = 1.0 / q00;
-                        cr.a = (float)(-q01 * rq00);
-                        cr.P = (float)(rho * rq00);
-                        cr.R = (float)(det * rq00 * rq00);
-                        cr.ymax = (float)sqrt(rho * q00 * rdet);
-                        cr.yl = (float)(q01 * sqrt(rho * rdet / q11));
-                        cr.on = 1.0f;
-                    }
+                    bound_form(q00, q01, q11, -g0 * rV, -g1 * rV, cxp, cyp, Q00, Q01, Q11, l0, l1, cr);
                 }
                 // tiles of the rectangle that the bound ellipse reaches, row by row
                 for (int ty = ty0; ty <= ty1; ++ty) {
@@ -463,9 +535,16 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 float4 *gp = b.geom + item * kRecVec;
                 gp[0] = make_float4((float)hx, (float)hy, (float)(cxp - hx), (float)(cyp - hy));
                 gp[1] = make_float4(Q00, 2.0f * Q01, 2.0f * l0, 2.0f * l1);
-                gp[2] = make_float4(Q11, A[0], A[2], A[4]);
-                gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
-                gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
+                if constexpr (SPLAT) {
+                    gp[2] = make_float4(Q11, 0.0f, 0.0f, 0.0f);
+                    gp[3] = make_float4((float)(0.5 * kLog2e * C00), (float)(kLog2e * C01),
+                                        (float)(0.5 * kLog2e * C11), 0.0f);
+                    gp[4] = make_float4(0.0f, 0.0f, op, 0.0f);
+                } else {
+                    gp[2] = make_float4(Q11, A[0], A[2], A[4]);
+                    gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
+                    gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
+                }
                 gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
                 gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);
                 float rgb[3] = { 0.0f, 0.0f, 0.0f };
@@ -1026,21 +1105,22 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
 {
     const unsigned grid = grid_for(rp.n, 256);
     const int deg = rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0;
-    if (rp.n_views > 1) {
-        switch (deg) {
-        case 0: preprocess_kernel<0, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        case 1: preprocess_kernel<1, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        case 2: preprocess_kernel<2, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        default: preprocess_kernel<3, true><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        }
-    } else {
-        switch (deg) {
-        case 0: preprocess_kernel<0, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        case 1: preprocess_kernel<1, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        case 2: preprocess_kernel<2, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        default: preprocess_kernel<3, false><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh); break;
-        }
+    const bool multi = rp.n_views > 1, splat = rp.alpha_model == VGR_ALPHA_SPLAT;
+#define VGR_PRE(D, M, S) preprocess_kernel<D, M, S><<<grid, 256, 0, s>>>(rp, b, means, quats, scales, dens, sh)
+#define VGR_PRE_DEG(M, S)            \
+    switch (deg) {                   \
+    case 0: VGR_PRE(0, M, S); break; \
+    case 1: VGR_PRE(1, M, S); break; \
+    case 2: VGR_PRE(2, M, S); break; \
+    default: VGR_PRE(3, M, S); break; \
     }
+    if (splat) {
+        if (multi) { VGR_PRE_DEG(true, true) } else { VGR_PRE_DEG(false, true) }
+    } else {
+        if (multi) { VGR_PRE_DEG(true, false) } else { VGR_PRE_DEG(false, false) }
+    }
+#undef VGR_PRE_DEG
+#undef VGR_PRE
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total + 4);

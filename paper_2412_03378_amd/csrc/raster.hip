@@ -216,7 +216,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE == VGR_MODE_COLOR;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY;
+    constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
     __shared__ Stage st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
@@ -250,6 +251,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     }
     const uint2 range = b.ranges[gt];
     const float tau2 = rp.tau2, ymax = rp.ymax, Tmin = rp.T_min;
+    const float amin = rp.amin, amax = rp.amax;
 
     for (uint32_t bs = range.x; bs < range.y; bs += 64) {
         const uint32_t j = bs + lane;
@@ -312,18 +314,32 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     const FullRec fr = full_of(rr);
                     const float dx = (pxc - pr.hx) - pr.lx;
                     const float dy = (pyc[k] - pr.hy) - pr.ly;
-                    PairGeom g;
-                    pair_geom(pr, fr, dx, dy, g);
-                    const float rq = fast_rsq(g.qw);
-                    const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
-                    const float y = fr.K * un[k] * rq * ex;
-                    const bool bl = has && !(y < tau2);
+                    float y, om, wa;   // log2(e) x (volumetric), 1 - alpha, alpha
+                    bool bl;
+                    if constexpr (SPLAT) {
+                        // alpha = o exp(-1/2 d^T C d) (the 3DGS splat)
+                        const float e = __fmaf_rn(dx, __fmaf_rn(fr.A01, dx, fr.A11 * dy),
+                                                  fr.A21 * (dy * dy));
+                        const float al = fr.K * fast_exp2(-e);
+                        bl = has && !(al < amin);
+                        wa = al > amax ? amax : al;
+                        om = 1.0f - wa;
+                        y = 0.0f;
+                    } else {
+                        PairGeom g;
+                        pair_geom(pr, fr, dx, dy, g);
+                        const float rq = fast_rsq(g.qw);
+                        const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                        y = fr.K * un[k] * rq * ex;
+                        bl = has && !(y < tau2);
+                        om = fast_exp2(-(y > ymax ? ymax : y));
+                        wa = 1.0f - om;
+                    }
                     if constexpr (COLOR) {
-                        const float om = fast_exp2(-(y > ymax ? ymax : y));
                         const float Tn = T[k] * om;
                         const bool stop = bl && Tn < Tmin;
                         const bool dob = bl && !stop;
-                        const float wgt = dob ? (1.0f - om) * T[k] : 0.0f;
+                        const float wgt = dob ? wa * T[k] : 0.0f;
                         C0[k] = __fmaf_rn(fr.c0, wgt, C0[k]);
                         C1[k] = __fmaf_rn(fr.c1, wgt, C1[k]);
                         C2[k] = __fmaf_rn(fr.c2, wgt, C2[k]);
@@ -751,7 +767,10 @@ template <int TW, int TH>
 hipError_t fwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     const dim3 grid(rp.total_tiles), block(64);
-    if (rp.mode == VGR_MODE_COLOR) {
+    if (rp.alpha_model == VGR_ALPHA_SPLAT) {
+        if (count) raster_fwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
+        else raster_fwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.mode == VGR_MODE_COLOR) {
         if (count) raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
         else raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);
     } else {

@@ -21,6 +21,7 @@ constexpr float kConicMargin = 0.05f;
 constexpr float kCullLevel = 0.1f;   // tile culling level of the bound form (> kConicMargin)
 constexpr float kCullPad = 0.02f;    // pixels added on both ends of a culled row span
 constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
+constexpr int kModeSplat = 2;     // rasteriser template mode: colour with the splatting alpha
 
 // Rasteriser record of one (Gaussian, view), 128 bytes (8 float4, one cache
 // line), in the Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view
@@ -38,6 +39,10 @@ constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 //   g5 = (r, g, b, mz)          colour after the activation (0 in X-ray mode)
 //   g6 = (cx, cy, a, P)         tile-culling ellipse (see cull_row in the
 //   g7 = (R, ymax, yl, on)        preprocess source); on = 0: no culling
+// With the splatting model (VGR_ALPHA_SPLAT) g0, g1, g5, g6, g7 keep their
+// meaning (l = 0) and g2 = (Q11, 0, 0, 0), g3 = (c00, c01, c11, 0),
+// g4 = (0, 0, o, 0) with c = log2(e) (C00/2, C01, C11/2), C = Sigma'^-1:
+// alpha = o exp2(-(c00 dx^2 + c01 dx dy + c11 dy^2)).
 // For the pixel with centre (px + 0.5, py + 0.5), ray u = (ux, uy, 1), and
 // pixel offset d = (px + 0.5, py + 0.5) - h - l:
 //   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)
@@ -91,6 +96,8 @@ struct RenderParams {
     int32_t tile_w, tile_h;
     int32_t total_tiles;
     int32_t density;     // VGR_DENSITY_KAPPA or VGR_DENSITY_THETA
+    int32_t alpha_model; // VGR_ALPHA_VOLUMETRIC or VGR_ALPHA_SPLAT
+    float amin, amax;    // alpha_min, alpha_max (splatting model)
 };
 
 // Device workspace views handed to kernels.

@@ -26,6 +26,7 @@ class Settings:
     act: str = "clamp"               # "clamp" | "softplus"
     tile: tuple = (0, 0)             # (0, 0): the context's tuned tile
     density: str = "kappa"           # "kappa" | "theta": what `dens` holds
+    alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS comparison, forward only)
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -37,6 +38,7 @@ class Settings:
         s.act = L.VGR_ACT_SOFTPLUS10 if self.act == "softplus" else L.VGR_ACT_CLAMP0
         s.tile_w, s.tile_h = int(self.tile[0]), int(self.tile[1])
         s.density = L.VGR_DENSITY_THETA if self.density == "theta" else L.VGR_DENSITY_KAPPA
+        s.alpha_model = L.VGR_ALPHA_SPLAT if self.alpha_model == "splat" else L.VGR_ALPHA_VOLUMETRIC
         return s
 
     @staticmethod

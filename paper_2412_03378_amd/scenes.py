@@ -219,6 +219,14 @@ def with_theta(scene: Scene, seed: int, lo: float = 0.02, hi: float = 0.98) -> S
     return Scene(scene.means, scene.quats, scene.scales, theta, scene.sh, scene.sh_degree)
 
 
+def with_opacity(scene: Scene, seed: int, lo: float = 0.05, hi: float = 1.0) -> Scene:
+    """The same Gaussians with the density input replaced by a peak opacity
+    in [lo, hi] (seeded), the input of the 3DGS splatting model (Sec. 3)."""
+    rng = np.random.default_rng(seed)
+    o = _f32(rng.uniform(lo, hi, scene.n))
+    return Scene(scene.means, scene.quats, scene.scales, o, scene.sh, scene.sh_degree)
+
+
 def _clustered_scene(rng, n, n_clusters, sh_degree=3):
     means = clustered_means(rng, n, n_clusters)
     scales = np.exp(rng.normal(math.log(0.01), 0.7, (n, 3)))
