@@ -14,6 +14,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -169,8 +170,56 @@ def bench_headline(args, torch, dev):
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": _traffic(dom),
                 "flops_per_launch": kern[dom], "launch_ms": stages[dom]}
+    splat_ab = None if args.no_splat else _splat_ab(r, params, wl, tile, args.steps, torch, dev)
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
-                flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd})
+                flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab)
+
+
+def _fwd_only(r, params, cams, st, steps, torch):
+    for _ in range(3):
+        r.forward(*params, cams, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.forward(*params, cams, st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    r.set_timing(True)
+    for _ in range(steps):
+        r.forward(*params, cams, st)
+    stages = r.timing()
+    r.set_timing(False)
+    r.set_counting(True)
+    r.forward(*params, cams, st)
+    stats = r.stats()
+    r.set_counting(False)
+    return {"fwd_ms": round(ms, 4), "raster_fwd_ms": round(stages["raster_fwd"], 4),
+            "preprocess_ms": round(stages["preprocess_fwd"], 4), "instances": stats["instances"],
+            "pairs_tested": stats["pairs_tested"], "pairs_blended": stats["pairs_blended"]}
+
+
+def _splat_ab(r, params, wl, tile, steps, torch, dev):
+    """Forward of the headline scene with the paper's volumetric opacity and
+    with the 3DGS splatting opacity it replaces (same pipeline, same GPU).  The
+    splats' peak opacity is that of the volumetric model for an isotropic
+    Gaussian of the same volume seen through its centre,
+    o = 1 - exp(-kappa sqrt(2 pi) (s_x s_y s_z)^(1/3)), so that both scenes are
+    about equally opaque."""
+    import numpy as np
+    from paper_2412_03378_amd import Settings
+    _log("forward A/B: volumetric vs splatting opacity")
+    sc = wl.scene
+    sg = np.cbrt(np.prod(sc.scales.astype(np.float64), axis=1))
+    o = -np.expm1(-sc.dens.astype(np.float64) * math.sqrt(2.0 * math.pi) * sg)
+    p_splat = list(params)
+    p_splat[3] = torch.from_numpy(o.astype(np.float32)).to(dev)
+    vol = _fwd_only(r, params, wl.cams, Settings(sh_degree=3, tile=tile), steps, torch)
+    spl = _fwd_only(r, p_splat, wl.cams, Settings(sh_degree=3, tile=tile, alpha_model="splat"),
+                    steps, torch)
+    return {"workload": "forward only, single view 1920x1080, 1M Gaussians, SH3",
+            "volumetric": vol, "splat": spl,
+            "fwd_ratio": round(vol["fwd_ms"] / spl["fwd_ms"], 3),
+            "raster_fwd_ratio": round(vol["raster_fwd_ms"] / spl["raster_fwd_ms"], 3)}
 
 
 def _graph_time(r, steps, torch):
@@ -485,6 +534,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-xray", action="store_true")
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-splat", action="store_true")
     ap.add_argument("--train-steps", type=int, default=2)
     ap.add_argument("--cpu-pixels", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -500,7 +550,7 @@ def main():
         return
     if args.profile:
         args.no_batched = args.no_xray = args.no_train = True
-        args.no_cpu_baseline = True
+        args.no_cpu_baseline = args.no_splat = True
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(views would shard across GPUs with an all-reduce of parameter "
@@ -543,6 +593,8 @@ def main():
         "load_balance": {"raster_fwd": round(h["stats"]["load_balance_fwd"], 3),
                          "raster_bwd": round(h["stats"]["load_balance_bwd"], 3)},
     }
+    if h["splat_ab"] is not None:
+        out["splat_ab"] = h["splat_ab"]
     if not args.no_batched:
         torch.cuda.empty_cache()
         res, wl3 = bench_batched(args, torch, dev)
