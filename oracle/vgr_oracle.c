@@ -756,6 +756,151 @@ static void chain_colour(int64_t i, const double gc[3], double w, const view_sta
     }
 }
 
+/* Chain dL/dalpha = ga (the splatting alpha of Gaussian i at the pixel centre
+   pc, unclamped) to mu, q, s and the opacity input.  With d = pc - mu',
+   alpha = o exp(-1/2 d^T C d), C = Sigma'^-1, Sigma' = J V J^T, V = W R D R^T W^T,
+   D = diag(s^2):
+     dalpha/do = G,  dalpha/dC = -1/2 alpha d d^T,  dalpha/dmu' = alpha C d,
+     dL/dSigma' = -C (dL/dC) C,  dL/dV = J^T (dL/dSigma') J,
+     dL/dJ = 2 (dL/dSigma') J V,  dL/dR = 2 W^T (dL/dV) W R D,
+     dL/ds_k = 2 s_k (R^T W^T (dL/dV) W R)_kk,
+   and J, mu' depend on the view-space mean m = W mu + t.  The error-scale
+   weight is 1 + q/2 + w_extra, q = d^T C d (a relative error e in q becomes
+   q e / 2 in alpha).  Returns q. */
+static double chain_splat(int64_t i, double ga, double gabs, double w_extra, const float *means,
+                          const float *quats, const float *scales, const float *dens,
+                          const orc_camera *cam, const double pc[2], grad_out *go)
+{
+    double R[9], qn[4], qlen;
+    quat_rotation(quats + 4 * i, R, qn, &qlen);
+    const float *s = scales + 3 * i;
+    const float *Wf = cam->R;
+    double W[9], m[3], WR[9], V[9];
+    for (int k = 0; k < 9; ++k) W[k] = Wf[k];
+    for (int a = 0; a < 3; ++a)
+        m[a] = W[3 * a] * means[3 * i] + W[3 * a + 1] * means[3 * i + 1] +
+               W[3 * a + 2] * means[3 * i + 2] + (double)cam->t[a];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += W[a * 3 + k] * R[k * 3 + b];
+            WR[a * 3 + b] = acc;
+        }
+    double D[3];
+    for (int k = 0; k < 3; ++k) D[k] = (double)s[k] * (double)s[k];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += WR[a * 3 + k] * D[k] * WR[b * 3 + k];
+            V[a * 3 + b] = acc;
+        }
+    const double fx = cam->fx, fy = cam->fy, x = m[0], y = m[1], z = m[2];
+    double J[6] = { fx / z, 0.0, -fx * x / (z * z), 0.0, fy / z, -fy * y / (z * z) };
+    double Sp[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc += J[a * 3 + k] * V[k * 3 + l] * J[b * 3 + l];
+            Sp[a * 2 + b] = acc;
+        }
+    const double det = Sp[0] * Sp[3] - Sp[1] * Sp[2];
+    const double Cm[4] = { Sp[3] / det, -Sp[1] / det, -Sp[2] / det, Sp[0] / det };
+    const double dx = pc[0] - (fx * x / z + cam->cx), dy = pc[1] - (fy * y / z + cam->cy);
+    const double Cd[2] = { Cm[0] * dx + Cm[1] * dy, Cm[2] * dx + Cm[3] * dy };
+    const double q = dx * Cd[0] + dy * Cd[1];
+    const double G = exp(-0.5 * q);
+    const float di = dens[i];
+    const double o = di < 0.0f ? 0.0 : (di > 1.0f ? 1.0 : (double)di);
+    const double alpha = o * G;
+    const double ge = gabs * (1.0 + 0.5 * q + w_extra);
+    /* opacity (zero gradient where the input was clamped) */
+    add3(go->g_dens, go->a_dens, go->e_dens, i, (di < 0.0f || di > 1.0f) ? 0.0 : G, ga, ge);
+    /* per unit ga: dL/dC (full symmetric) and dL/dSigma' = -C GC C */
+    const double GC[4] = { -0.5 * alpha * dx * dx, -0.5 * alpha * dx * dy,
+                           -0.5 * alpha * dx * dy, -0.5 * alpha * dy * dy };
+    double T1[4], GS[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            T1[a * 2 + b] = Cm[a * 2] * GC[b] + Cm[a * 2 + 1] * GC[2 + b];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            GS[a * 2 + b] = -(T1[a * 2] * Cm[b] + T1[a * 2 + 1] * Cm[2 + b]);
+    /* dL/dV = J^T GS J, dL/dJ = 2 GS J V */
+    double GV[9], GJ[6], JV[6];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            double acc = 0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) acc += J[a * 3 + k] * GS[a * 2 + b] * J[b * 3 + l];
+            GV[k * 3 + l] = acc;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int l = 0; l < 3; ++l) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += J[a * 3 + k] * V[k * 3 + l];
+            JV[a * 3 + l] = acc;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int l = 0; l < 3; ++l)
+            GJ[a * 3 + l] = 2.0 * (GS[a * 2] * JV[l] + GS[a * 2 + 1] * JV[3 + l]);
+    /* view-space mean: through J and through mu' (dL/dmu' = alpha C d) */
+    const double gmu_p[2] = { alpha * Cd[0], alpha * Cd[1] };
+    double gm[3];
+    gm[0] = GJ[2] * (-fx / (z * z)) + gmu_p[0] * fx / z;
+    gm[1] = GJ[5] * (-fy / (z * z)) + gmu_p[1] * fy / z;
+    gm[2] = GJ[0] * (-fx / (z * z)) + GJ[2] * (2.0 * fx * x / (z * z * z)) +
+            GJ[4] * (-fy / (z * z)) + GJ[5] * (2.0 * fy * y / (z * z * z)) -
+            gmu_p[0] * fx * x / (z * z) - gmu_p[1] * fy * y / (z * z);
+    for (int r = 0; r < 3; ++r)
+        add3(go->g_means, go->a_means, go->e_means, 3 * i + r,
+             W[r] * gm[0] + W[3 + r] * gm[1] + W[6 + r] * gm[2], ga, ge);
+    /* H = (W R)^T GV (W R): scales dL/ds_k = 2 s_k H_kk; rotation via
+       dL/dR = 2 W^T GV W R D */
+    double GVW[9], H[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += GV[a * 3 + k] * WR[k * 3 + b];
+            GVW[a * 3 + b] = acc;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += WR[k * 3 + a] * GVW[k * 3 + b];
+            H[a * 3 + b] = acc;
+        }
+    for (int k = 0; k < 3; ++k)
+        add3(go->g_scales, go->a_scales, go->e_scales, 3 * i + k, 2.0 * (double)s[k] * H[k * 4],
+             ga, ge);
+    double dR[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += W[k * 3 + a] * GVW[k * 3 + b];
+            dR[a * 3 + b] = 2.0 * acc * D[b];
+        }
+    double Jq[4][9], dqn[4];
+    rot_jacobian(qn, Jq);
+    for (int c = 0; c < 4; ++c) {
+        double acc = 0;
+        for (int e = 0; e < 9; ++e) acc += dR[e] * Jq[c][e];
+        dqn[c] = acc;
+    }
+    double dot = qn[0] * dqn[0] + qn[1] * dqn[1] + qn[2] * dqn[2] + qn[3] * dqn[3];
+    for (int c = 0; c < 4; ++c)
+        add3(go->g_quats, go->a_quats, go->e_quats, 4 * i + c, (dqn[c] - qn[c] * dot) / qlen, ga, ge);
+    return q;
+}
+
+/* q = dp^T C dp of Gaussian i's splat at the pixel centre pc. */
+static double splat_q(const view_state *vs, int64_t i, const double pc[2])
+{
+    const double *sp = vs->splat + 6 * i;
+    const double dx = pc[0] - sp[0], dy = pc[1] - sp[1];
+    return sp[2] * dx * dx + 2.0 * sp[3] * dx * dy + sp[4] * dy * dy;
+}
+
 /* Squared Mahalanobis distance of Gaussian i from the ray (o, d). */
 static double pair_D2(int64_t i, const float *means, const float *quats, const float *scales,
                       const double o[3], const double d[3])
@@ -788,7 +933,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
-    if (st->alpha_model != 0) return -2;   /* the splatting model is forward only */
+    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -803,7 +948,8 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         double d[3], out[3];
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
         blend_list bl = { NULL, 0, 0 };
-        shade_pixel(&vs, means, st, d, NULL, out, NULL, NULL, NULL, NULL, NULL, &bl);
+        const double pc[2] = { pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5 };
+        shade_pixel(&vs, means, st, d, pc, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
                 chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,
@@ -822,13 +968,22 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                     gc[ch] = g[ch] * br->alpha * br->T;
                 }
                 const double steps = (double)(bl.cnt - 1 - r);
-                const double ex = exp(-br->x);
-                if (!br->clamped)
-                    chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales, dens,
-                                   st, vs.o, d, &go);
                 double w = 1.0 + steps;
-                if (go.e_means || go.e_sh)
-                    w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d);
+                if (vs.splat) {
+                    /* splatting model: the chain starts at dL/dalpha; the
+                       colour's error weight uses q = d^T C d in place of D^2 */
+                    const double q = br->clamped ? splat_q(&vs, i, pc)
+                                                 : chain_splat(i, galpha, gabs, steps, means,
+                                                               quats, scales, dens, cam, pc, &go);
+                    w += 0.5 * q;
+                } else {
+                    const double ex = exp(-br->x);
+                    if (!br->clamped)
+                        chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales,
+                                       dens, st, vs.o, d, &go);
+                    if (go.e_means || go.e_sh)
+                        w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d);
+                }
                 chain_colour(i, gc, w, &vs, means, sh, st, &go);
                 for (int ch = 0; ch < 3; ++ch)
                     S[ch] = vs.rgb[3 * i + ch] * br->alpha + (1.0 - br->alpha) * S[ch];

@@ -730,5 +730,27 @@ def test_splat_compositing_and_limits():
                                   cam, st, pixels=[_centre(cam)])["image"][0, 0]
     assert one(1.7) == one(1.0) == pytest.approx(0.99 * 1.0 + 0.01 * 0.2, rel=1e-6)
     assert one(-0.5) == pytest.approx(0.2, rel=1e-12)
-    with pytest.raises(RuntimeError):
-        oracle.render_backward(sc, cam, st, np.ones((3, 9, 9)))
+    for o in (1.7, -0.5):
+        g = oracle.render_backward(H.scene([[0.0, 0.0, 0.0]], [0.1] * 3, o), cam, st,
+                                   np.ones((3, 9, 9)))
+        assert g["dens"][0] == 0.0
+
+
+@pytest.mark.parametrize("seed", [16, 17])
+def test_fd_gradients_splat(seed):
+    """The splatting model's analytic backward (through Sigma'^-1, the
+    projection Jacobian, the rotation, scales, opacity and SH) against central
+    finite differences of its forward (thresholds off)."""
+    rng = np.random.default_rng(seed)
+    n = 6
+    cam = scenes.look_at([0.7, -0.4, -3.0], (0, 0, 0), 13, 11, 45.0)
+    means = np.c_[rng.uniform(-0.5, 0.5, (n, 2)), np.linspace(-0.6, 0.6, n)]
+    sc = H.scene(means, np.exp(rng.uniform(np.log(0.08), np.log(0.3), (n, 3))),
+                 rng.uniform(0.05, 0.95, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    st = oracle.Settings(act="softplus", alpha_min=1e-300, alpha_max=1.0 - 1e-12, T_min=0.0,
+                         bg=(0.2, 0.3, 0.1), alpha_model="splat")
+    assert _fd_check(sc, cam, st, rng, n_checks=80, rel_h=3e-6) < 1e-6
+    g = oracle.render_backward(sc, cam, st, rng.standard_normal((3, cam.height, cam.width)))
+    for k in ("means", "quats", "scales", "dens", "sh"):
+        assert np.all(g["err_" + k] >= g["abs_" + k] * (1 - 1e-12)), k
