@@ -94,9 +94,9 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               (W the world-to-view rotation, J the pinhole Jacobian at the
  *               view-space mean) and o = `dens` read as the peak opacity,
  *               clamped to [0, 1]; the same skip, clamp, stop and background
- *               rules; tiles from the exact alpha >= alpha_min ellipse.  Colour
- *               mode with density KAPPA only; forward only (a backward after
- *               it fails with VGR_ERR_INVALID_ARG) [VOLUMETRIC]
+ *               rules; tiles from the exact alpha >= alpha_min ellipse; the
+ *               backward returns d_dens = dL/do (zero where o was clamped).
+ *               Colour mode with density KAPPA only [VOLUMETRIC]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:

@@ -685,8 +685,6 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward to differentiate");
     if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
     const RenderParams &rp = c->rp;
-    if (rp.alpha_model == VGR_ALPHA_SPLAT)
-        return fail(c, VGR_ERR_INVALID_ARG, "the splatting model has no backward");
     int rc;
     if ((rc = check_grads(c, rp, d_means, d_quats, d_scales, d_dens, d_sh))) return rc;
     for (int v = 0; v < rp.n_views; ++v) {

@@ -863,7 +863,91 @@ __global__ void fill_f32_kernel(float *__restrict__ p, float v, int64_t n)
 
 // ------------------------------------------------------------ backward ---
 
-template <int DEG>
+// Gradient of one view's splatting record (Sec. 3, eq. 3dgs_alpha, eq.
+// affine_approx), FP64.  gr: sum tau dx^2, sum tau dx dy, sum tau dy^2,
+// sum tau dx, sum tau dy (tau = dL/dalpha alpha, d = pixel - mu').  With
+// C = Sigma'^-1, Sigma' = J V J^T, V = Rc D Rc^T, D = diag(s^2):
+//   dL/dC = -1/2 [[A, B], [B, Cq]],  dL/dSigma' = -C (dL/dC) C,
+//   dL/dmu' = C (Px, Py),  dL/dV = J^T (dL/dSigma') J,  dL/dJ = 2 (dL/dSigma') J V,
+//   H = Rc^T (dL/dV) Rc:  dL/ds_k = 2 s_k H_kk,  body-frame rotation
+//   dL/dtheta = 2 (H12 (D1 - D2), H20 (D2 - D0), H01 (D0 - D1)),
+// and the view-space mean through J and mu'.  Adds the world-space mean
+// gradient to gmw, the scales' to gs and the rotation's to gth.
+__device__ inline void splat_view_grad(const GaussView &g, const float *s, const float *mu,
+                                       const ViewInfo &vi, const float *gr, float *gmw,
+                                       float *gs, float *gth)
+{
+    const double mx = (double)vi.R[0] * mu[0] + (double)vi.R[1] * mu[1] + (double)vi.R[2] * mu[2] + vi.t[0];
+    const double my = (double)vi.R[3] * mu[0] + (double)vi.R[4] * mu[1] + (double)vi.R[5] * mu[2] + vi.t[1];
+    const double mz = (double)vi.R[6] * mu[0] + (double)vi.R[7] * mu[1] + (double)vi.R[8] * mu[2] + vi.t[2];
+    double Rc[9], D[3], V[9];
+    for (int k = 0; k < 9; ++k) Rc[k] = g.Rc[k];
+    for (int k = 0; k < 3; ++k) D[k] = (double)s[k] * (double)s[k];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            V[a * 3 + c] = Rc[a * 3] * Rc[c * 3] * D[0] + Rc[a * 3 + 1] * Rc[c * 3 + 1] * D[1] +
+                           Rc[a * 3 + 2] * Rc[c * 3 + 2] * D[2];
+    const double rz = 1.0 / mz;
+    // J = [[j00, 0, j02], [0, j11, j12]]
+    const double j00 = vi.fx * rz, j02 = -vi.fx * mx * rz * rz;
+    const double j11 = vi.fy * rz, j12 = -vi.fy * my * rz * rz;
+    const double J[6] = { j00, 0.0, j02, 0.0, j11, j12 };
+    double JV[6];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c)
+            JV[a * 3 + c] = J[a * 3] * V[c] + J[a * 3 + 1] * V[3 + c] + J[a * 3 + 2] * V[6 + c];
+    const double S00 = JV[0] * J[0] + JV[1] * J[1] + JV[2] * J[2];
+    const double S01 = JV[0] * J[3] + JV[1] * J[4] + JV[2] * J[5];
+    const double S11 = JV[3] * J[3] + JV[4] * J[4] + JV[5] * J[5];
+    const double rdet = 1.0 / (S00 * S11 - S01 * S01);
+    const double C00 = S11 * rdet, C01 = -S01 * rdet, C11 = S00 * rdet;
+    // dL/dSigma' = C N C / 2 with N = [[A, B], [B, Cq]]
+    const double A = gr[0], B = gr[1], Cq = gr[2];
+    const double T00 = C00 * A + C01 * B, T01 = C00 * B + C01 * Cq;
+    const double T10 = C01 * A + C11 * B, T11 = C01 * B + C11 * Cq;
+    const double G00 = 0.5 * (T00 * C00 + T01 * C01);
+    const double G01 = 0.5 * (T00 * C01 + T01 * C11);
+    const double G11 = 0.5 * (T10 * C01 + T11 * C11);
+    const double GS[4] = { G00, G01, G01, G11 };
+    // dL/dmu' = C (Px, Py)
+    const double gpx = C00 * gr[3] + C01 * gr[4], gpy = C01 * gr[3] + C11 * gr[4];
+    // dL/dV = J^T GS J;  dL/dJ = 2 GS J V
+    double GV[9];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            double acc = 0.0;
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 2; ++c) acc += J[a * 3 + k] * GS[a * 2 + c] * J[c * 3 + l];
+            GV[k * 3 + l] = acc;
+        }
+    double GJ[6];
+    for (int a = 0; a < 2; ++a)
+        for (int l = 0; l < 3; ++l)
+            GJ[a * 3 + l] = 2.0 * (GS[a * 2] * JV[l] + GS[a * 2 + 1] * JV[3 + l]);
+    // view-space mean: J(m) and mu' = (fx mx / mz + cx, fy my / mz + cy)
+    const double rz2 = rz * rz, rz3 = rz2 * rz;
+    double gm[3];
+    gm[0] = -vi.fx * rz2 * GJ[2] + vi.fx * rz * gpx;
+    gm[1] = -vi.fy * rz2 * GJ[5] + vi.fy * rz * gpy;
+    gm[2] = -vi.fx * rz2 * GJ[0] + 2.0 * vi.fx * mx * rz3 * GJ[2] - vi.fy * rz2 * GJ[4] +
+            2.0 * vi.fy * my * rz3 * GJ[5] - vi.fx * mx * rz2 * gpx - vi.fy * my * rz2 * gpy;
+    for (int j = 0; j < 3; ++j)
+        gmw[j] += (float)(vi.R[j] * gm[0] + vi.R[3 + j] * gm[1] + vi.R[6 + j] * gm[2]);
+    // H = Rc^T GV Rc
+    double GR[9], H[9];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            GR[a * 3 + c] = GV[a * 3] * Rc[c] + GV[a * 3 + 1] * Rc[3 + c] + GV[a * 3 + 2] * Rc[6 + c];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            H[a * 3 + c] = Rc[a] * GR[c] + Rc[3 + a] * GR[3 + c] + Rc[6 + a] * GR[6 + c];
+    for (int k = 0; k < 3; ++k) gs[k] += (float)(2.0 * s[k] * H[k * 4]);
+    gth[0] += (float)(2.0 * H[5] * (D[1] - D[2]));
+    gth[1] += (float)(2.0 * H[2] * (D[2] - D[0]));
+    gth[2] += (float)(2.0 * H[1] * (D[0] - D[1]));
+}
+
+template <int DEG, bool SPLAT>
 __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     RenderParams rp, Buffers b, const float *__restrict__ means, const float *__restrict__ quats,
     const float *__restrict__ scales, const float *__restrict__ dens, const float *__restrict__ sh,
@@ -917,7 +1001,11 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         gauss_view(vi, mu, q, s, g);
         for (int k = 0; k < 4; ++k) qn[k] = g.qn[k];
         qlen = g.qlen;
-        gk += gr[9];   // sum t = K' dL/dK' = kappa dL/dkappa
+        gk += gr[9];   // sum t = K' dL/dK' = kappa dL/dkappa (splat: sum tau = o dL/do)
+        float gmv[3] = { 0.f, 0.f, 0.f };   // this view's dL/dmu
+        if constexpr (SPLAT) {
+            splat_view_grad(g, s, mu, vi, gr, gmv, gs, gth);
+        } else {
         // Sigma^-1 = Rc diag(s^-2) Rc^T with dL/dSigma^-1 = -1/2 L^-1 M L^-T, L^-1 = Rc diag(s),
         // so dL/dRc = -Rc diag(s) M diag(1/s):
         //   scales: dL/ds_k = M_kk / s_k;
@@ -933,9 +1021,9 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         for (int j = 0; j < 3; ++j)
             dm[j] = -(g.L[j] * gr[6] + g.L[3 + j] * gr[7] + g.L[6 + j] * gr[8]);
         // m = R_view mu + t
-        float gmv[3];   // this view's dL/dmu
         for (int j = 0; j < 3; ++j)
             gmv[j] = vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];
+        }   // volumetric record
         if (rp.mode == VGR_MODE_COLOR) {
             float vx = mu[0] - vi.o[0], vy = mu[1] - vi.o[1], vz = mu[2] - vi.o[2];
             const float len = sqrtf(vx * vx + vy * vy + vz * vz);
@@ -1000,7 +1088,11 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     // Input theta, kappa = phi(theta) h(s) with phi = -ln(1 - 0.99 theta) and
     // h = mean of 1/s_k: dL/dtheta = gk phi'/phi and dL/ds_k gains
     // gk d ln h / ds_k = -gk / (s_k^2 sum_j 1/s_j).
-    if (rp.density == VGR_DENSITY_THETA) {
+    if constexpr (SPLAT) {
+        // opacity o = clamp(input, 0, 1): dL/do = sum tau / o
+        const float o = dens[i];
+        put(d_dens + i, (o < 0.0f || o > 1.0f) ? 0.0f : gk / o);
+    } else if (rp.density == VGR_DENSITY_THETA) {
         const float th = dens[i];
         const float dth = (th < 0.0f || th > 1.0f)
                               ? 0.0f
@@ -1186,12 +1278,22 @@ hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const
 {
     const unsigned g = grid_for(rp.n, 128);
     const int acc = accumulate ? 1 : 0;
-    switch (rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0) {
-    case 0: preprocess_bwd_kernel<0><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
-    case 1: preprocess_bwd_kernel<1><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
-    case 2: preprocess_bwd_kernel<2><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
-    default: preprocess_bwd_kernel<3><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount); break;
+    const int deg = rp.mode == VGR_MODE_COLOR ? rp.sh_degree : 0;
+#define VGR_PBW(D, S) preprocess_bwd_kernel<D, S><<<g, 128, 0, s>>>(rp, b, means, quats, scales, dens, sh, d_means, d_quats, d_scales, d_dens, d_sh, acc, gnorm, vcount)
+#define VGR_PBW_DEG(S)            \
+    switch (deg) {                \
+    case 0: VGR_PBW(0, S); break; \
+    case 1: VGR_PBW(1, S); break; \
+    case 2: VGR_PBW(2, S); break; \
+    default: VGR_PBW(3, S); break; \
     }
+    if (rp.alpha_model == VGR_ALPHA_SPLAT) {
+        VGR_PBW_DEG(true)
+    } else {
+        VGR_PBW_DEG(false)
+    }
+#undef VGR_PBW_DEG
+#undef VGR_PBW
     return hipGetLastError();
 }
 

@@ -533,7 +533,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE == VGR_MODE_COLOR;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY;
+    constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
     constexpr int NCH = COLOR ? 3 : 1;
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
@@ -589,6 +590,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
         return;
     }
     const float tau2 = rp.tau2, ymax = rp.ymax;
+    const float amin = rp.amin, amax = rp.amax;
     float *rg = reinterpret_cast<float *>(b.rgrad);
 
     // One record of the batch against the lane's pixels: pass[k] marks the
@@ -610,6 +612,42 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             if (pm == 0) continue;                  // wave-uniform
             if (COUNT) n.full += pass[k] ? 1u : 0u;
             const float dy = (pyc[k] - pr.hy) - pr.ly;
+            if constexpr (SPLAT) {
+                // alpha = o exp2(-e); with tau = dL/dalpha alpha the record
+                // gradient keeps sum tau (d d^T, d) and sum tau: dL/do =
+                // sum tau / o, dL/dC = -1/2 sum tau d d^T, dL/dmu' = C sum tau d
+                const float e = __fmaf_rn(dx, __fmaf_rn(fr.A01, dx, fr.A11 * dy),
+                                          fr.A21 * (dy * dy));
+                const float al = fr.K * fast_exp2(-e);
+                const bool bl = pass[k] && !(al < amin);
+                if (COUNT) n.blend += bl ? 1u : 0u;
+                const uint64_t bm = __builtin_amdgcn_ballot_w64(!(al < amin)) & pm;
+                if (bm == 0) continue;                      // wave-uniform
+                const bool clamped = al > amax;
+                const float a = clamped ? amax : al;
+                const float om = 1.0f - a;
+                const float inv = fast_rcp(om);
+                const float Tb = T[k] * inv;
+                const float gc = __fmaf_rn(g[k][0], fr.c0,
+                                           __fmaf_rn(g[k][1], fr.c1, g[k][2] * fr.c2));
+                const float da = __fmaf_rn(Tb, gc, -(inv * GB[k]));
+                const float wgt = bl ? a * Tb : 0.0f;
+                acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
+                acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
+                acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
+                GB[k] = __fmaf_rn(gc, wgt, GB[k]);
+                T[k] = bl ? Tb : T[k];
+                touched |= bm;
+                const float tau = (bl && !clamped) ? da * al : 0.0f;
+                const float tdx = tau * dx, tdy = tau * dy;
+                acc[9] += tau;
+                acc[3] += tdx;
+                acc[4] += tdy;
+                acc[0] += tdx * dx;
+                acc[1] += tdx * dy;
+                acc[2] += tdy * dy;
+                continue;
+            }
             PairGeom pg;
             pair_geom(pr, fr, dx, dy, pg);
             const float rq = fast_rsq(pg.qw);
@@ -784,7 +822,10 @@ template <int TW, int TH>
 hipError_t bwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     const dim3 grid(rp.total_tiles), block(64);
-    if (rp.mode == VGR_MODE_COLOR) {
+    if (rp.alpha_model == VGR_ALPHA_SPLAT) {
+        if (count) raster_bwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
+        else raster_bwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.mode == VGR_MODE_COLOR) {
         if (count) raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
         else raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);
     } else {

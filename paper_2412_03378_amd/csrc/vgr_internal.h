@@ -42,7 +42,10 @@ constexpr int kModeSplat = 2;     // rasteriser template mode: colour with the s
 // With the splatting model (VGR_ALPHA_SPLAT) g0, g1, g5, g6, g7 keep their
 // meaning (l = 0) and g2 = (Q11, 0, 0, 0), g3 = (c00, c01, c11, 0),
 // g4 = (0, 0, o, 0) with c = log2(e) (C00/2, C01, C11/2), C = Sigma'^-1:
-// alpha = o exp2(-(c00 dx^2 + c01 dx dy + c11 dy^2)).
+// alpha = o exp2(-(c00 dx^2 + c01 dx dy + c11 dy^2)).  Its record gradient,
+// with tau = dL/dalpha alpha summed over the pixels that blend it: [0..2]
+// sum tau (dx^2, dx dy, dy^2), [3..4] sum tau (dx, dy), [9] sum tau,
+// [10..12] dL/dc.
 // For the pixel with centre (px + 0.5, py + 0.5), ray u = (ux, uy, 1), and
 // pixel offset d = (px + 0.5, py + 0.5) - h - l:
 //   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)

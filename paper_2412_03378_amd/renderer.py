@@ -26,7 +26,7 @@ class Settings:
     act: str = "clamp"               # "clamp" | "softplus"
     tile: tuple = (0, 0)             # (0, 0): the context's tuned tile
     density: str = "kappa"           # "kappa" | "theta": what `dens` holds
-    alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS comparison, forward only)
+    alpha_model: str = "volumetric"  # "volumetric" | "splat" (the 3DGS comparison model)
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()

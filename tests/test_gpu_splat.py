@@ -98,15 +98,56 @@ def test_splat_large_off_axis(R, dev):
     _check_views(R, dev, sc, [cam], _settings(tile=(8, 8)))
 
 
-def test_splat_rejects_backward_and_other_modes(R, dev):
+def _grad_check(R, dev, sc, cams, st, seed):
+    """Backward of the sum of the views' losses against the oracle's analytic
+    splatting backward (pixels with a decision at a threshold get a zero
+    upstream gradient)."""
+    ost = _oset(st)
+    t = G.device_scene(sc, dev)
+    R.forward(*t, cams, st)
+    rng = np.random.default_rng(seed)
+    dLs, refs = [], []
+    for cam in cams:
+        ref = oracle.render(sc, cam, ost)
+        dLs.append(rng.standard_normal((3, cam.height, cam.width)) * (ref["margin"] > G.MARGIN))
+    grads = [torch.zeros_like(x) for x in t]
+    R.backward([torch.from_numpy(d.astype(np.float32)).to(dev) for d in dLs], *grads)
+    torch.cuda.synchronize()
+    keys = ("means", "quats", "scales", "dens", "sh")
+    per = [oracle.render_backward(sc, cam, ost, d) for cam, d in zip(cams, dLs)]
+    worst = {}
+    for k, g in zip(keys, grads):
+        ref = sum(p[k] for p in per)
+        absr = sum(p["abs_" + k] for p in per)
+        errr = sum(p["err_" + k] for p in per)
+        worst[k] = G.grad_errors(g.cpu().numpy(), ref, absr, errr)
+        print(k, f"ratio {worst[k]:.3g}", G.grad_worst(g.cpu().numpy(), ref, absr, errr))
+    assert max(worst.values()) <= 1.0, worst
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_splat_backward_parity(R, dev, tile):
+    """Gradients of the splatting model (through Sigma'^-1, the projection
+    Jacobian, rotation, scales, opacity and colour) on the parity workload."""
+    wl = scenes.config1()
+    sc = scenes.with_opacity(wl.scene, seed=56)
+    _grad_check(R, dev, sc, wl.cams, _settings(tile=tile, act="softplus", bg=(0.1, 0.2, 0.3)),
+                seed=57)
+
+
+def test_splat_backward_multi_view_sh3(R, dev):
+    wl = scenes.config3(n=1500, n_views=3, n_clusters=24, seed=58, with_grad=False)
+    sc = scenes.with_opacity(wl.scene, seed=59)
+    cams = [scenes.Camera(c.R, c.t, c.fx / 16, c.fy / 16, c.cx / 16, c.cy / 16,
+                          c.width // 16, c.height // 16) for c in wl.cams]
+    _grad_check(R, dev, sc, cams, _settings(sh_degree=3, act="softplus", tile=(16, 8)), seed=60)
+
+
+def test_splat_rejects_other_modes(R, dev):
     from paper_2412_03378_amd import _lib as L
     wl = scenes.config1(n=100, width=32, height=32)
     sc = scenes.with_opacity(wl.scene, seed=55)
     t = G.device_scene(sc, dev)
-    R.forward(*t, wl.cams, _settings(tile=(8, 8)))
-    with pytest.raises(L.VgrError) as ei:
-        R.backward([torch.ones((3, 32, 32), device=dev)], *[torch.zeros_like(x) for x in t])
-    assert ei.value.code == L.VGR_ERR_INVALID_ARG
     for kw in (dict(mode="xray"), dict(density="theta")):
         with pytest.raises(L.VgrError) as ei:
             R.forward(*t, wl.cams, _settings(tile=(8, 8), **kw))
