@@ -170,12 +170,15 @@ def bench_headline(args, torch, dev):
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": _traffic(dom),
                 "flops_per_launch": kern[dom], "launch_ms": stages[dom]}
-    splat_ab = None if args.no_splat else _splat_ab(r, params, wl, tile, args.steps, torch, dev)
+    splat_ab = (None if args.no_splat else
+                _splat_ab(r, params, wl, tile, args.steps, torch, dev, grads, dLs))
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
                 flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab)
 
 
-def _fwd_only(r, params, cams, st, steps, torch):
+def _ab_leg(r, params, cams, st, steps, torch, grads, dLs):
+    """Forward-only and forward+backward times of one model, with its stage
+    split (HIP events, separate steps) and counters."""
     for _ in range(3):
         r.forward(*params, cams, st)
     torch.cuda.synchronize()
@@ -183,43 +186,55 @@ def _fwd_only(r, params, cams, st, steps, torch):
     for _ in range(steps):
         r.forward(*params, cams, st)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / steps
+    for _ in range(2):
+        _step(r, params, grads, cams, st, dLs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _step(r, params, grads, cams, st, dLs)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / steps
     r.set_timing(True)
     for _ in range(steps):
-        r.forward(*params, cams, st)
+        _step(r, params, grads, cams, st, dLs)
     stages = r.timing()
     r.set_timing(False)
     r.set_counting(True)
     r.forward(*params, cams, st)
     stats = r.stats()
     r.set_counting(False)
-    return {"fwd_ms": round(ms, 4), "raster_fwd_ms": round(stages["raster_fwd"], 4),
-            "preprocess_ms": round(stages["preprocess_fwd"], 4), "instances": stats["instances"],
-            "pairs_tested": stats["pairs_tested"], "pairs_blended": stats["pairs_blended"]}
+    pick = ("preprocess_fwd", "raster_fwd", "raster_bwd", "preprocess_bwd")
+    return {"fwd_ms": round(fwd_ms, 4), "fwd_bwd_ms": round(step_ms, 4),
+            "stages_ms": {k: round(stages[k], 4) for k in pick},
+            "instances": stats["instances"], "pairs_tested": stats["pairs_tested"],
+            "pairs_blended": stats["pairs_blended"]}
 
 
-def _splat_ab(r, params, wl, tile, steps, torch, dev):
-    """Forward of the headline scene with the paper's volumetric opacity and
-    with the 3DGS splatting opacity it replaces (same pipeline, same GPU).  The
+def _splat_ab(r, params, wl, tile, steps, torch, dev, grads, dLs):
+    """The headline scene with the paper's volumetric opacity and with the
+    3DGS splatting opacity it replaces (same pipeline, same GPU).  The
     splats' peak opacity is that of the volumetric model for an isotropic
     Gaussian of the same volume seen through its centre,
     o = 1 - exp(-kappa sqrt(2 pi) (s_x s_y s_z)^(1/3)), so that both scenes are
     about equally opaque."""
     import numpy as np
     from paper_2412_03378_amd import Settings
-    _log("forward A/B: volumetric vs splatting opacity")
+    _log("A/B: volumetric vs splatting opacity")
     sc = wl.scene
     sg = np.cbrt(np.prod(sc.scales.astype(np.float64), axis=1))
     o = -np.expm1(-sc.dens.astype(np.float64) * math.sqrt(2.0 * math.pi) * sg)
     p_splat = list(params)
     p_splat[3] = torch.from_numpy(o.astype(np.float32)).to(dev)
-    vol = _fwd_only(r, params, wl.cams, Settings(sh_degree=3, tile=tile), steps, torch)
-    spl = _fwd_only(r, p_splat, wl.cams, Settings(sh_degree=3, tile=tile, alpha_model="splat"),
-                    steps, torch)
-    return {"workload": "forward only, single view 1920x1080, 1M Gaussians, SH3",
+    vol = _ab_leg(r, params, wl.cams, Settings(sh_degree=3, tile=tile), steps, torch, grads, dLs)
+    spl = _ab_leg(r, p_splat, wl.cams, Settings(sh_degree=3, tile=tile, alpha_model="splat"),
+                  steps, torch, grads, dLs)
+    ratio = lambda k: round(vol["stages_ms"][k] / spl["stages_ms"][k], 3)
+    return {"workload": "single view 1920x1080, 1M Gaussians, SH3",
             "volumetric": vol, "splat": spl,
             "fwd_ratio": round(vol["fwd_ms"] / spl["fwd_ms"], 3),
-            "raster_fwd_ratio": round(vol["raster_fwd_ms"] / spl["raster_fwd_ms"], 3)}
+            "fwd_bwd_ratio": round(vol["fwd_bwd_ms"] / spl["fwd_bwd_ms"], 3),
+            "raster_fwd_ratio": ratio("raster_fwd"), "raster_bwd_ratio": ratio("raster_bwd")}
 
 
 def _graph_time(r, steps, torch):
