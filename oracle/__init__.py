@@ -53,7 +53,7 @@ class _Cam(C.Structure):
 
 class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
-                ("density", C.c_int32), ("alpha_model", C.c_int32), ("pad", C.c_int32),
+                ("density", C.c_int32), ("alpha_model", C.c_int32), ("near_segment", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
 
@@ -71,11 +71,14 @@ class Settings:
     act: str = "clamp"             # "clamp" | "softplus"
     density: str = "kappa"         # "kappa" | "theta" (eq. density_reparam)
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS, eq. 3dgs_alpha)
+    near_segment: bool = False     # integrate each ray from the near plane on (Sec. 4.2)
 
     @staticmethod
-    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa"):
+    def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa",
+                      near_segment=False):
         return Settings(mode=mode, alpha_min=1e-300, alpha_max=1.0 - 1e-12, T_min=0.0,
-                        x_min_xray=1e-300, bg=bg, act=act, density=density)
+                        x_min_xray=1e-300, bg=bg, act=act, density=density,
+                        near_segment=near_segment)
 
 
 def _load():
@@ -128,6 +131,7 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     s.act = 1 if st.act == "softplus" else 0
     s.density = 1 if st.density == "theta" else 0
     s.alpha_model = 1 if st.alpha_model == "splat" else 0
+    s.near_segment = 1 if st.near_segment else 0
     s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
     s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
     s.bg[:] = [float(v) for v in st.bg]

@@ -36,6 +36,11 @@
  *     paper replaces (Sec. 3, eq. 3dgs_alpha, eq. affine_approx), with the
  *     density input read as the peak opacity o in [0, 1] (clamped) and the
  *     same compositing rules; forward only.
+ *   - near_segment = 1: the integral along each ray starts where the ray
+ *     crosses the near plane z = znear instead of covering the whole line,
+ *     x = kappa sqrt(2 pi) beta G(o + gamma d) Phi((gamma - t_n) / beta), Phi the
+ *     standard normal distribution function (Sec. 4.2, the finite-limit erf
+ *     form with the argument (t - gamma) / (sqrt 2 beta)).
  *   - the density input is kappa itself, or theta with the reparameterisation
  *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
  *     density_reparam); theta outside the paper's range [0, 1] is clamped to
@@ -74,7 +79,7 @@ typedef struct {
     int32_t act;        /* 0 max(.,0), 1 softplus(10 y)/10 */
     int32_t density;    /* 0: dens holds kappa; 1: dens holds theta (kappa_of) */
     int32_t alpha_model;/* 0: the paper's ray integral; 1: 3DGS splatting (splat_setup) */
-    int32_t pad;
+    int32_t near_segment;/* 1: integrate each ray from the near plane on (finite segment) */
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
 } orc_settings;
@@ -143,6 +148,17 @@ static void ray_integral(const double mu[3], const double P[9], double kappa,
     rt->a = a;
     for (int k = 0; k < 3; ++k) rt->v[k] = -diff[k];
     rt->x = kappa * sqrt(2.0 * ORC_PI) * beta * Gmax;
+}
+
+/* Standard normal distribution function and density. */
+static double norm_cdf(double e) { return 0.5 * erfc(-e / sqrt(2.0)); }
+static double norm_pdf(double e) { return exp(-0.5 * e * e) / sqrt(2.0 * ORC_PI); }
+
+/* Ray parameter t_n at which the unit ray o + t d crosses the near plane
+   z_view = znear (o is the camera centre, so z_view(t) = t zrow . d). */
+static double near_t(const double zrow[3], double znear, const double d[3])
+{
+    return znear / (zrow[0] * d[0] + zrow[1] * d[1] + zrow[2] * d[2]);
 }
 
 /* Exported for closed-form pins: out = {gamma, beta, Gmax, x}. */
@@ -256,6 +272,8 @@ typedef struct {
     double *kappa;       /* n densities kappa */
     double *splat;       /* alpha_model 1: n x 6 (mu'_x, mu'_y, C00, C01, C11, o) */
     double o[3];
+    double zrow[3];      /* view-space depth axis in world coordinates (third row of R) */
+    double znear;
 } view_state;
 
 static const float *g_sort_key;
@@ -433,6 +451,8 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
         if (!vs->splat) return -3;
     }
     camera_origin(cam, vs->o);
+    for (int k = 0; k < 3; ++k) vs->zrow[k] = cam->R[6 + k];
+    vs->znear = cam->znear;
     int nb = (st->sh_degree + 1) * (st->sh_degree + 1);
     int64_t nvis = 0;
     #pragma omp parallel for schedule(static)
@@ -515,6 +535,8 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_terms rt;
             ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+            if (st->near_segment)
+                rt.x *= norm_cdf((rt.gamma - near_t(vs->zrow, vs->znear, d)) / rt.beta);
             full += rt.x;
             double m = rel_margin(rt.x, st->x_min_xray);
             if (m < margin) margin = m;
@@ -558,6 +580,8 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
         } else {
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+            if (st->near_segment)
+                rt.x *= norm_cdf((rt.gamma - near_t(vs->zrow, vs->znear, d)) / rt.beta);
             m = rel_margin(rt.x, tau);
             if (m < margin) margin = m;
             if (rt.x < tau) continue;                  /* alpha < alpha_min */
@@ -598,7 +622,7 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
-    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0)) return -1;
+    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -665,9 +689,10 @@ static void add3(double *g, double *a, double *e, int64_t off, double unit, doub
    D^2 becomes D^2 e / 2 in x = ... exp(-D^2/2). */
 static void chain_integral(int64_t i, double gx, double gabs, double w_extra, const float *means,
                            const float *quats, const float *scales, const float *dens,
-                           const orc_settings *st, const double o[3], const double d[3],
+                           const orc_settings *st, const view_state *vs, const double d[3],
                            grad_out *go)
 {
+    const double *o = vs->o;
     double R[9], qn[4], qlen, P[9];
     quat_rotation(quats + 4 * i, R, qn, &qlen);
     precision_matrix(R, scales + 3 * i, P);
@@ -678,15 +703,26 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
     /* x = kappa sqrt(2pi) a^-1/2 exp(-D^2/2),  D^2 = v^T P v, v = mu - o - gamma d
        dx/dkappa = sqrt(2pi) beta Gmax
        dx/dP     = x (-1/2 d d^T / a - 1/2 v v^T)
-       dx/dmu    = -x P v                                                   */
+       dx/dmu    = -x P v
+       With the finite segment, x_seg = x Phi(e), e = (gamma - t_n)/beta
+       = (mu-o)^T P d a^-1/2 - t_n a^1/2:  dx_seg = Phi dx + x phi(e) de, with
+       de/dmu = P d a^-1/2 and de/dP = ((mu-o) d^T + d (mu-o)^T) a^-1/2 / 2
+       - ((mu-o)^T P d) a^-3/2 d d^T / 2 - t_n a^-1/2 d d^T / 2.            */
     double x = rt.x;
+    double Phi = 1.0, xphi = 0.0, tn = 0.0;
+    if (st->near_segment) {
+        tn = near_t(vs->zrow, vs->znear, d);
+        const double e = (rt.gamma - tn) / rt.beta;
+        Phi = norm_cdf(e);
+        xphi = x * norm_pdf(e);
+    }
     double Pv[3], D2 = 0;
     for (int r = 0; r < 3; ++r) {
         Pv[r] = P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2];
         D2 += rt.v[r] * Pv[r];
     }
     const double ge = gabs * (1.0 + 0.5 * D2 + w_extra);
-    const double dx_dk = sqrt(2 * ORC_PI) * rt.beta * rt.Gmax;
+    const double dx_dk = sqrt(2 * ORC_PI) * rt.beta * rt.Gmax * Phi;
     double dk_din, dk_ds[3];
     kappa_grad(st, dens[i], scales + 3 * i, &dk_din, dk_ds);
     add3(go->g_dens, go->a_dens, go->e_dens, i, dx_dk * dk_din, gx, ge);
@@ -696,9 +732,26 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
     double G[9];   /* dx/dP per unit gx */
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
-            G[r * 3 + c] = x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
+            G[r * 3 + c] = Phi * x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
+    double Pd[3] = { 0, 0, 0 };
+    if (st->near_segment) {
+        const double dm[3] = { mu[0] - o[0], mu[1] - o[1], mu[2] - o[2] };
+        double b = 0;
+        for (int r = 0; r < 3; ++r) {
+            Pd[r] = P[r * 3] * d[0] + P[r * 3 + 1] * d[1] + P[r * 3 + 2] * d[2];
+            b += dm[r] * Pd[r];
+        }
+        const double ra = 1.0 / sqrt(rt.a);
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                G[r * 3 + c] += xphi * (0.5 * (dm[r] * d[c] + d[r] * dm[c]) * ra -
+                                        0.5 * b * ra * ra * ra * d[r] * d[c] -
+                                        0.5 * tn * ra * d[r] * d[c]);
+        for (int r = 0; r < 3; ++r) Pd[r] *= ra;
+    }
     for (int r = 0; r < 3; ++r)
-        add3(go->g_means, go->a_means, go->e_means, 3 * i + r, -x * Pv[r], gx, ge);
+        add3(go->g_means, go->a_means, go->e_means, 3 * i + r, -Phi * x * Pv[r] + xphi * Pd[r],
+             gx, ge);
     /* P = sum_k s_k^-2 r_k r_k^T, r_k = column k of R */
     double dR[9];
     for (int k = 0; k < 3; ++k) {
@@ -933,7 +986,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
 {
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
-    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0)) return -1;
+    if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -953,7 +1006,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
                 chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,
-                               st, vs.o, d, &go);
+                               st, &vs, d, &go);
         } else {
             /* S: colour composited behind the current Gaussian, ending in bg */
             double S[3] = { st->bg[0], st->bg[1], st->bg[2] };
@@ -980,7 +1033,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                     const double ex = exp(-br->x);
                     if (!br->clamped)
                         chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales,
-                                       dens, st, vs.o, d, &go);
+                                       dens, st, &vs, d, &go);
                     if (go.e_means || go.e_sh)
                         w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d);
                 }

@@ -754,3 +754,72 @@ def test_fd_gradients_splat(seed):
     g = oracle.render_backward(sc, cam, st, rng.standard_normal((3, cam.height, cam.width)))
     for k in ("means", "quats", "scales", "dens", "sh"):
         assert np.all(g["err_" + k] >= g["abs_" + k] * (1 - 1e-12)), k
+
+
+# ------------------------- Sec. 4.2 finite segment from the near plane ---
+
+def test_near_segment_isotropic_closed_form():
+    """Along the optical axis an isotropic Gaussian at depth z0 contributes
+    kappa sqrt(2 pi) s Phi((z0 - zn) / s) when the integral starts at the near
+    plane zn (the finite-limit erf form of Sec. 4.2): half of the full-line
+    value when the mean sits on the plane."""
+    from scipy.stats import norm
+    cam = H.odd_camera(9, 30.0, 4.0)           # camera at z = -4, znear 0.2
+    s, kappa = f32(0.3), 2.0
+    zn = float(np.float32(cam.znear))
+    st = oracle.Settings.no_thresholds(mode="xray", near_segment=True)
+    for z0 in (zn - 4.0, zn - 4.0 + 0.25, zn - 4.0 - 0.4, zn - 4.0 + 2.0):
+        sc = H.scene([[0.0, 0.0, f32(z0)]], [s] * 3, kappa)
+        zv = float(np.float32(z0)) + 4.0       # view-space depth of the mean
+        x = oracle.render(sc, cam, st, pixels=[_centre(cam)])["image"][0, 0]
+        expect = kappa * H.SQRT2PI * s * norm.cdf((zv - zn) / s)
+        if zv > zn:   # means behind the plane are culled, as in the full-line model
+            assert x == pytest.approx(expect, rel=1e-10)
+    off = oracle.Settings.no_thresholds(mode="xray")
+    sc = H.scene([[0.0, 0.0, f32(zn - 4.0 + 2.0)]], [s] * 3, kappa)
+    assert (oracle.render(sc, cam, off, pixels=[_centre(cam)])["image"][0, 0]
+            == pytest.approx(kappa * H.SQRT2PI * s, rel=1e-12))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_near_segment_quadrature(seed):
+    """A random anisotropic Gaussian straddling the near plane, on an oblique
+    pixel ray: the segment integral equals adaptive quadrature of
+    kappa G(o + t d) from the plane crossing to infinity."""
+    rng = np.random.default_rng(100 + seed)
+    cam = scenes.look_at([0.3, -0.2, -3.0], (0, 0, 0), 21, 17, 50.0, znear=2.6)
+    q = rng.standard_normal(4)
+    s = np.float32(rng.uniform(0.15, 0.4, 3))
+    mu = np.float32(rng.uniform(-0.2, 0.2, 3))
+    kappa = 3.0
+    sc = H.scene([mu], [s], kappa, quats=[q])
+    px = (int(rng.integers(6, 15)), int(rng.integers(5, 12)))
+    o, d = H.pixel_ray_world(cam, *px)
+    Rv = np.asarray(cam.R, np.float64)
+    tn = float(np.float32(cam.znear)) / (Rv[2] @ d)
+    q32 = sc.quats[0].astype(np.float64)      # the stored (FP32) quaternion
+    Rq = H.rotation_matrix(q32 / np.linalg.norm(q32))
+    P = Rq @ np.diag(1.0 / s.astype(np.float64) ** 2) @ Rq.T
+    f = lambda t: kappa * math.exp(-0.5 * (o + t * d - mu) @ P @ (o + t * d - mu))
+    ref = integrate.quad(f, tn, np.inf, epsabs=0, epsrel=1e-12, limit=200)[0]
+    st = oracle.Settings.no_thresholds(mode="xray", near_segment=True)
+    x = oracle.render(sc, cam, st, pixels=[px])["image"][0, 0]
+    assert x == pytest.approx(ref, rel=1e-9)
+    full = oracle.render(sc, cam, oracle.Settings.no_thresholds(mode="xray"), pixels=[px])
+    assert x < full["image"][0, 0]
+
+
+@pytest.mark.parametrize("mode", ["color", "xray"])
+def test_fd_gradients_near_segment(mode):
+    """The segment's extra terms (through gamma, beta and t_n) against central
+    finite differences, on Gaussians straddling the near plane."""
+    rng = np.random.default_rng(18)
+    n = 6
+    cam = scenes.look_at([0.4, -0.3, -3.0], (0, 0, 0), 13, 11, 45.0, znear=2.7)
+    means = np.c_[rng.uniform(-0.3, 0.3, (n, 2)), np.linspace(-0.45, 0.3, n)]
+    sc = H.scene(means, np.exp(rng.uniform(np.log(0.1), np.log(0.3), (n, 3))),
+                 rng.uniform(1, 6, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    st = oracle.Settings.no_thresholds(mode=mode, act="softplus", bg=(0.2, 0.3, 0.1),
+                                       near_segment=True)
+    assert _fd_check(sc, cam, st, rng, n_checks=80, rel_h=3e-6, xray=mode == "xray") < 1e-6
