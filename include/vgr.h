@@ -97,6 +97,15 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               rules; tiles from the exact alpha >= alpha_min ellipse; the
  *               backward returns d_dens = dL/do (zero where o was clamped).
  *               Colour mode with density KAPPA only [VOLUMETRIC]
+ *   near_segment 0: each Gaussian's integral covers the whole line (the
+ *               boxed result of Sec. 4.2).  1: it starts where the pixel's ray
+ *               crosses the near plane z = znear, x = kappa sqrt(2 pi) beta
+ *               G(o + gamma d) Phi((gamma - t_n) / beta) with Phi the standard
+ *               normal distribution function (the finite-limit erf form of
+ *               Sec. 4.2), so Gaussians straddling the plane lose the part
+ *               behind it.  Evaluated only for records whose bound reaches
+ *               within 6 standard deviations of the plane (elsewhere Phi = 1 to
+ *               FP32 precision).  VOLUMETRIC only [0]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -110,6 +119,8 @@ typedef struct {
     int32_t tile_w, tile_h;
     int32_t density;
     int32_t alpha_model;
+    int32_t near_segment;
+    int32_t reserved;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */

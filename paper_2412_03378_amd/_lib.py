@@ -39,7 +39,8 @@ class vgr_settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32)]
+                ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32),
+                ("near_segment", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vgr_stats(C.Structure):

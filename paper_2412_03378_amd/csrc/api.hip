@@ -427,6 +427,10 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
         (st->mode != VGR_MODE_COLOR || st->density != VGR_DENSITY_KAPPA))
         return fail(c, VGR_ERR_INVALID_ARG,
                     "the splatting model needs colour mode and the plain density input");
+    if (st->near_segment != 0 && st->near_segment != 1)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad near_segment");
+    if (st->near_segment && st->alpha_model == VGR_ALPHA_SPLAT)
+        return fail(c, VGR_ERR_INVALID_ARG, "the near-plane segment needs the volumetric model");
     if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
         !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
         return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
@@ -450,6 +454,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.alpha_model = st->alpha_model;
     rp.amin = st->alpha_min;
     rp.amax = st->alpha_max;
+    rp.near_segment = st->near_segment;
     rp.n_views = n_views;
     rp.n = n;
     rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;

@@ -543,7 +543,14 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 } else {
                     gp[2] = make_float4(Q11, A[0], A[2], A[4]);
                     gp[3] = make_float4(A[1], A[3], A[5], v0[0]);
-                    gp[4] = make_float4(v0[1], v0[2], K * kLog2e, (0.5f * kLog2e) * mz * mz);
+                    // near-plane segment: every ray that can reach alpha_min passes
+                    // within sqrt(D2max) smax of the mean, so its closest point lies
+                    // beyond depth mz - sqrt(D2max) smax, and beta <= smax: with
+                    // (mz - znear) / smax - sqrt(D2max) > 6, Phi > 1 - 1e-9 there
+                    const bool near = rp.near_segment &&
+                                      (mz - vi.znear) / smax - sqrtf(D2max) <= 6.0f;
+                    gp[4] = make_float4(v0[1], v0[2], near ? -(K * kLog2e) : K * kLog2e,
+                                        (0.5f * kLog2e) * mz * mz);
                 }
                 gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
                 gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);
@@ -1012,14 +1019,27 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
         //   rotation: for the body-frame perturbation Rc -> Rc (I + [dtheta]x),
         //   dL/dtheta = vee(W - W^T) with W = Rc^T dL/dRc = -diag(s) M diag(1/s),
         //   i.e. dL/dtheta_x = M12 (s1/s2 - s2/s1) and cyclically.
-        for (int k = 0; k < 3; ++k) gs[k] += gr[k == 0 ? 0 : (k == 1 ? 3 : 5)] * g.inv_s[k];
-        gth[0] += gr[4] * ((s[1] * s[1] - s[2] * s[2]) * g.inv_s[1] * g.inv_s[2]);
-        gth[1] += gr[2] * ((s[2] * s[2] - s[0] * s[0]) * g.inv_s[2] * g.inv_s[0]);
-        gth[2] += gr[1] * ((s[0] * s[0] - s[1] * s[1]) * g.inv_s[0] * g.inv_s[1]);
+        // near-plane segment: M -= p U^T + U p^T (p = L m) and Z -= U (U = 0 elsewhere)
+        float Mm[6] = { gr[0], gr[1], gr[2], gr[3], gr[4], gr[5] };
+        float Zm[3] = { gr[6], gr[7], gr[8] };
+        if (rp.near_segment) {
+            const float *U = gr + 13;
+            Mm[0] -= 2.0f * g.p[0] * U[0];
+            Mm[1] -= g.p[0] * U[1] + U[0] * g.p[1];
+            Mm[2] -= g.p[0] * U[2] + U[0] * g.p[2];
+            Mm[3] -= 2.0f * g.p[1] * U[1];
+            Mm[4] -= g.p[1] * U[2] + U[1] * g.p[2];
+            Mm[5] -= 2.0f * g.p[2] * U[2];
+            for (int j = 0; j < 3; ++j) Zm[j] -= U[j];
+        }
+        for (int k = 0; k < 3; ++k) gs[k] += Mm[k == 0 ? 0 : (k == 1 ? 3 : 5)] * g.inv_s[k];
+        gth[0] += Mm[4] * ((s[1] * s[1] - s[2] * s[2]) * g.inv_s[1] * g.inv_s[2]);
+        gth[1] += Mm[2] * ((s[2] * s[2] - s[0] * s[0]) * g.inv_s[2] * g.inv_s[0]);
+        gth[2] += Mm[1] * ((s[0] * s[0] - s[1] * s[1]) * g.inv_s[0] * g.inv_s[1]);
         // dL/dm = -L^T Z
         float dm[3];
         for (int j = 0; j < 3; ++j)
-            dm[j] = -(g.L[j] * gr[6] + g.L[3 + j] * gr[7] + g.L[6 + j] * gr[8]);
+            dm[j] = -(g.L[j] * Zm[0] + g.L[3 + j] * Zm[1] + g.L[6 + j] * Zm[2]);
         // m = R_view mu + t
         for (int j = 0; j < 3; ++j)
             gmv[j] = vi.R[j] * dm[0] + vi.R[3 + j] * dm[1] + vi.R[6 + j] * dm[2];

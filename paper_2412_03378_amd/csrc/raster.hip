@@ -53,6 +53,18 @@ __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Near-plane segment factor Phi(eta) of a flagged record (K' < 0):
+// eta = (gamma - t_n) / beta = mz (v0 . w) / |w| - zn |w| for the pixel's
+// w = L u, t_n = zn |u| the near-plane crossing of the ray (Sec. 4.2, the
+// integral from t_n on).  qw = |w|^2, rq = 1 / |w|.
+__device__ __forceinline__ float near_eta(float v0x, float v0y, float v0z, float mz, float w0,
+                                          float w1, float w2, float qw, float rq, float zn)
+{
+    const float vw = __fmaf_rn(v0x, w0, __fmaf_rn(v0y, w1, v0z * w2));
+    return __fmaf_rn(mz, vw, -zn * qw) * rq;
+}
+__device__ __forceinline__ float norm_cdf(float e) { return 0.5f * erfcf(-0.70710678f * e); }
+
 // Timed runs (b.wg_time set) record for each workgroup the constant-rate
 // realtime counter difference between start and end, and a key of the compute unit it ran on (XCC id, then the
 // shader engine, array and CU fields of HW_ID), so that the host can sum the
@@ -216,8 +228,9 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE != VGR_MODE_XRAY;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear;
     constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
+    constexpr bool NEAR = MODE == kModeColorNear || MODE == kModeXrayNear;
     __shared__ Stage st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
@@ -252,6 +265,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     const uint2 range = b.ranges[gt];
     const float tau2 = rp.tau2, ymax = rp.ymax, Tmin = rp.T_min;
     const float amin = rp.amin, amax = rp.amax;
+    const float zn = vi.znear;
 
     for (uint32_t bs = range.x; bs < range.y; bs += 64) {
         const uint32_t j = bs + lane;
@@ -330,7 +344,12 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                         pair_geom(pr, fr, dx, dy, g);
                         const float rq = fast_rsq(g.qw);
                         const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
-                        y = fr.K * un[k] * rq * ex;
+                        y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
+                        if constexpr (NEAR) {
+                            if (fr.K < 0.0f)
+                                y *= norm_cdf(near_eta(fr.v0x, fr.v0y, fr.v0z, fr.mz, g.w0, g.w1,
+                                                       g.w2, g.qw, rq, zn));
+                        }
                         bl = has && !(y < tau2);
                         om = fast_exp2(-(y > ymax ? ymax : y));
                         wa = 1.0f - om;
@@ -387,7 +406,12 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     pair_geom(pr, fr, ct.dx, dy, g);
                     const float rq = fast_rsq(g.qw);
                     const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
-                    const float y = fr.K * un[k] * rq * ex;
+                    float y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
+                    if constexpr (NEAR) {
+                        if (fr.K < 0.0f)
+                            y *= norm_cdf(near_eta(fr.v0x, fr.v0y, fr.v0z, fr.mz, g.w0, g.w1, g.w2,
+                                                   g.qw, rq, zn));
+                    }
                     const bool bl = pass && !(y < tau2);
                     if constexpr (COLOR) {
                         if (!wave_any(bl)) continue;            // wave-uniform
@@ -533,8 +557,9 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE != VGR_MODE_XRAY;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear;
     constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
+    constexpr bool NEAR = MODE == kModeColorNear || MODE == kModeXrayNear;
     constexpr int NCH = COLOR ? 3 : 1;
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
@@ -591,6 +616,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     }
     const float tau2 = rp.tau2, ymax = rp.ymax;
     const float amin = rp.amin, amax = rp.amax;
+    const float zn = vi.znear;
     float *rg = reinterpret_cast<float *>(b.rgrad);
 
     // One record of the batch against the lane's pixels: pass[k] marks the
@@ -600,7 +626,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
         // -0 is the exact identity of addition, so the first term of each
         // sum needs no add
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = e < 13 ? -0.0f : 0.0f;
+        for (int e = 0; e < 16; ++e) acc[e] = (e < 13 || NEAR) ? -0.0f : 0.0f;
         // lane masks (wave-uniform) of the slot's passing and blending
         // pixels; the branches test them directly
         uint64_t touched = 0;
@@ -653,7 +679,24 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const float rq = fast_rsq(pg.qw);
             const float rq2 = rq * rq;
             const float ex = fast_exp2(-(fr.se * pg.num * rq2));
-            const float y = fr.K * un[k] * rq * ex;
+            float y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
+            // near-plane segment: y *= Phi(eta); hn = h (eta + 2 zn |w|) and
+            // h = phi(eta) / Phi(eta) enter the moments below
+            float hh = 0.0f, hn = 0.0f;
+            if constexpr (NEAR) {
+                if (fr.K < 0.0f) {
+                    const float eta = near_eta(fr.v0x, fr.v0y, fr.v0z, fr.mz, pg.w0, pg.w1, pg.w2,
+                                               pg.qw, rq, zn);
+                    const float Phi = norm_cdf(eta);
+                    y *= Phi;
+                    // h stays finite on every lane (lanes whose pixel does not blend
+                    // this record multiply it by t = 0): far out in the lower tail
+                    // Phi underflows, and h tends to -eta there
+                    hh = Phi > 1e-30f ? 0.39894228f * fast_exp2(-0.72134752f * eta * eta) / Phi
+                                      : -eta;
+                    hn = hh * __fmaf_rn(2.0f * zn, pg.qw * rq, eta);
+                }
+            }
             const bool bl = pass[k] && !(y < tau2);
             if (COUNT) n.blend += bl ? 1u : 0u;
             const uint64_t bm = __builtin_amdgcn_ballot_w64(!(y < tau2)) & pm;
@@ -694,7 +737,14 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
             const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
             const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
-            const float tp0 = t * p0, tp1 = t * p1, tp2 = t * p2;
+            const float tw = NEAR ? __fmaf_rn(t, hn, t) : t;   // weight of w' w'^T
+            const float tp0 = tw * p0, tp1 = tw * p1, tp2 = tw * p2;
+            if constexpr (NEAR) {
+                const float th = t * hh;
+                acc[13] += th * p0;
+                acc[14] += th * p1;
+                acc[15] += th * p2;
+            }
             acc[6] += tz0;
             acc[7] += tz1;
             acc[8] += tz2;
@@ -808,6 +858,14 @@ hipError_t fwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipSt
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
         if (count) raster_fwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
         else raster_fwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.near_segment) {
+        if (rp.mode == VGR_MODE_COLOR) {
+            if (count) raster_fwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeColorNear, false><<<grid, block, 0, s>>>(rp, b);
+        } else {
+            if (count) raster_fwd_kernel<TW, TH, kModeXrayNear, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeXrayNear, false><<<grid, block, 0, s>>>(rp, b);
+        }
     } else if (rp.mode == VGR_MODE_COLOR) {
         if (count) raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
         else raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);
@@ -825,6 +883,14 @@ hipError_t bwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipSt
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
         if (count) raster_bwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
         else raster_bwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.near_segment) {
+        if (rp.mode == VGR_MODE_COLOR) {
+            if (count) raster_bwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeColorNear, false><<<grid, block, 0, s>>>(rp, b);
+        } else {
+            if (count) raster_bwd_kernel<TW, TH, kModeXrayNear, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeXrayNear, false><<<grid, block, 0, s>>>(rp, b);
+        }
     } else if (rp.mode == VGR_MODE_COLOR) {
         if (count) raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
         else raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);

@@ -21,7 +21,9 @@ constexpr float kConicMargin = 0.05f;
 constexpr float kCullLevel = 0.1f;   // tile culling level of the bound form (> kConicMargin)
 constexpr float kCullPad = 0.02f;    // pixels added on both ends of a culled row span
 constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
-constexpr int kModeSplat = 2;     // rasteriser template mode: colour with the splatting alpha
+// rasteriser template modes beyond VGR_MODE_COLOR / VGR_MODE_XRAY: colour with
+// the splatting alpha; colour and X-ray with the near-plane segment
+constexpr int kModeSplat = 2, kModeColorNear = 3, kModeXrayNear = 4;
 
 // Rasteriser record of one (Gaussian, view), 128 bytes (8 float4, one cache
 // line), in the Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view
@@ -35,7 +37,9 @@ constexpr int kModeSplat = 2;     // rasteriser template mode: colour with the s
 //   g1 = (Q00, 2 Q01, 2 l0, 2 l1)
 //   g2 = (Q11, A00, A10, A20)   A = L[:, 0:2] diag(1/fx, 1/fy)
 //   g3 = (A01, A11, A21, v0x)   v0 = L m / mz: L applied to the ray through the mean
-//   g4 = (v0y, v0z, K', se)     K' = kappa sqrt(2 pi) log2 e,  se = (log2 e / 2) mz^2
+//   g4 = (v0y, v0z, K', se)     K' = kappa sqrt(2 pi) log2 e,  se = (log2 e / 2) mz^2;
+//                               K' < 0 (|K'| the value) flags a record that needs
+//                               the near-plane segment factor
 //   g5 = (r, g, b, mz)          colour after the activation (0 in X-ray mode)
 //   g6 = (cx, cy, a, P)         tile-culling ellipse (see cull_row in the
 //   g7 = (R, ymax, yl, on)        preprocess source); on = 0: no culling
@@ -68,7 +72,11 @@ constexpr int kModeSplat = 2;     // rasteriser template mode: colour with the s
 // so the sums  M = sum t (w w^T/|w|^2 + z z^T)  (symmetric) and  Z = sum t z
 // carry the whole geometric gradient:
 //   [0..5] M00 M01 M02 M11 M12 M22, [6..8] Z, [9] sum t (= K' dL/dK'), [10..12] dL/dc,
-//   [13..15] 0.
+//   [13..15] U = sum t h w/|w| (near-plane segment, else 0).
+// With the segment factor Phi(eta), eta = (gamma - t_n)/beta = mz (v0.w')
+// - zn |w| (w' = w/|w|) and h = phi(eta)/Phi(eta), the w' w'^T weight in M
+// becomes t (1 + h (eta + 2 zn |w|)), and the preprocess backward subtracts
+// (Lm) U^T + U (Lm)^T from M and adds L^T U to dL/dm.
 
 struct ViewInfo {
     float R[9];
@@ -101,6 +109,8 @@ struct RenderParams {
     int32_t density;     // VGR_DENSITY_KAPPA or VGR_DENSITY_THETA
     int32_t alpha_model; // VGR_ALPHA_VOLUMETRIC or VGR_ALPHA_SPLAT
     float amin, amax;    // alpha_min, alpha_max (splatting model)
+    int32_t near_segment;// integrate from the near plane (records flagged by K' < 0)
+    int32_t pad1;
 };
 
 // Device workspace views handed to kernels.

@@ -27,6 +27,7 @@ class Settings:
     tile: tuple = (0, 0)             # (0, 0): the context's tuned tile
     density: str = "kappa"           # "kappa" | "theta": what `dens` holds
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (the 3DGS comparison model)
+    near_segment: bool = False       # integrate each ray from the near plane on
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -39,14 +40,16 @@ class Settings:
         s.tile_w, s.tile_h = int(self.tile[0]), int(self.tile[1])
         s.density = L.VGR_DENSITY_THETA if self.density == "theta" else L.VGR_DENSITY_KAPPA
         s.alpha_model = L.VGR_ALPHA_SPLAT if self.alpha_model == "splat" else L.VGR_ALPHA_VOLUMETRIC
+        s.near_segment = 1 if self.near_segment else 0
         return s
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), sh_degree=0,
-                      density="kappa"):
+                      density="kappa", near_segment=False):
         """Smallest thresholds FP32 allows (for finite-difference checks)."""
         return Settings(mode=mode, sh_degree=sh_degree, alpha_min=1e-30, alpha_max=1 - 2 ** -20,
-                        T_min=0.0, x_min_xray=1e-30, bg=bg, act=act, density=density)
+                        T_min=0.0, x_min_xray=1e-30, bg=bg, act=act, density=density,
+                        near_segment=near_segment)
 
 
 def camera_struct(cam) -> L.vgr_camera:

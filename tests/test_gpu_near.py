@@ -1,0 +1,136 @@
+"""GPU parity of the near-plane segment (Sec. 4.2: the ray integral taken
+from the ray's near-plane crossing on instead of over the whole line) against
+the FP64 oracle through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import gpu_helpers as G
+import helpers as H
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def R(dev):
+    from paper_2412_03378_amd import Renderer
+    return Renderer(0)
+
+
+def _settings(**kw):
+    from paper_2412_03378_amd import Settings
+    return Settings(near_segment=True, **kw)
+
+
+def _oset(st):
+    return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
+                           T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act,
+                           near_segment=True)
+
+
+def _straddling_scene(seed, n_near=60, n_far=300, deg=1):
+    """Gaussians whose means sit just in front of the near plane (view depth
+    2.6, camera at z = -4) with scales that reach across it, and a field
+    behind them."""
+    rng = np.random.default_rng(seed)
+    near = np.c_[rng.uniform(-0.6, 0.6, (n_near, 2)), rng.uniform(-1.38, -0.9, n_near)]
+    far = np.c_[rng.uniform(-1, 1, (n_far, 2)), rng.uniform(-0.5, 1.0, n_far)]
+    means = np.r_[near, far]
+    scales = np.r_[np.exp(rng.uniform(np.log(0.05), np.log(0.3), (n_near, 3))),
+                   np.exp(rng.uniform(np.log(0.02), np.log(0.12), (n_far, 3)))]
+    n = means.shape[0]
+    sh = rng.normal(0, 0.3, (n, (deg + 1) ** 2, 3))
+    return H.scene(means, scales, np.exp(rng.uniform(np.log(0.3), np.log(6), n)),
+                   quats=rng.standard_normal((n, 4)), sh=sh, deg=deg)
+
+
+def _cam(w=48, h=40):
+    c = scenes.axis_camera(4.0, w, h, 60.0)
+    return scenes.Camera(c.R, c.t, c.fx, c.fy, c.cx, c.cy, c.width, c.height, znear=2.6)
+
+
+def _check(R, dev, sc, cams, st, seed):
+    ost = _oset(st)
+    xray = st.mode == "xray"
+    t = G.device_scene(sc, dev)
+    imgs = R.forward(*t, cams, st)
+    rng = np.random.default_rng(seed)
+    dLs = []
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc, cam, ost)
+        img = imgs[v].cpu().numpy()
+        e_ok, nflag, e_flag = G.compare_image(img[None] if xray else img, ref["image"],
+                                              ref["margin"], xray=xray)
+        print(f"view {v}: err {e_ok:.3g} flagged {nflag} ({e_flag:.3g})")
+        assert e_ok <= (G.XRAY_REL if xray else G.IMG_TOL) and e_flag <= G.FLIP_TOL
+        nch = 1 if xray else 3
+        dLs.append(rng.standard_normal((nch, cam.height, cam.width)) * (ref["margin"] > G.MARGIN))
+    keys = ("means", "quats", "scales", "dens") + (() if xray else ("sh",))
+    grads = [torch.zeros_like(x) for x in t[:len(keys)]]
+    R.backward([torch.from_numpy((d[0] if xray else d).astype(np.float32)).to(dev) for d in dLs],
+               *grads, *([None] if xray else []))
+    torch.cuda.synchronize()
+    per = [oracle.render_backward(sc, cam, ost, d) for cam, d in zip(cams, dLs)]
+    worst = {}
+    for k, g in zip(keys, grads):
+        ref = sum(p[k] for p in per)
+        absr = sum(p["abs_" + k] for p in per)
+        errr = sum(p["err_" + k] for p in per)
+        worst[k] = G.grad_errors(g.cpu().numpy(), ref, absr, errr)
+        print(k, f"ratio {worst[k]:.3g}", G.grad_worst(g.cpu().numpy(), ref, absr, errr))
+    assert max(worst.values()) <= 1.0, worst
+    return imgs
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_near_segment_colour(R, dev, tile):
+    sc = _straddling_scene(61)
+    _check(R, dev, sc, [_cam()], _settings(act="softplus", sh_degree=1, tile=tile,
+                                           bg=(0.1, 0.2, 0.3)), seed=62)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_near_segment_xray(R, dev, tile):
+    """X-ray, two views in one call (8x8: the masks kept by the forward;
+    16x16: the broadcast walk)."""
+    sc = _straddling_scene(63, deg=0)
+    cams = [_cam(), _cam(40, 32)]
+    _check(R, dev, sc, cams, _settings(mode="xray", tile=tile), seed=64)
+
+
+def test_near_segment_changes_only_straddling_gaussians(R, dev):
+    """Far from the plane the segment factor is 1 to FP32 precision: a scene
+    with no Gaussian near the plane renders the same with the option on and
+    off, while the straddling scene renders darker with it on."""
+    from paper_2412_03378_amd import Settings
+    far = scenes.config1()
+    t = G.device_scene(far.scene, dev)
+    on = R.forward(*t, far.cams, _settings(tile=(8, 8)))[0].cpu().numpy()
+    off = R.forward(*t, far.cams, Settings(tile=(8, 8)))[0].cpu().numpy()
+    assert np.abs(on - off).max() <= 1e-6
+    sc = _straddling_scene(65)
+    t = G.device_scene(sc, dev)
+    st_on = _settings(mode="xray", tile=(8, 8))
+    st_off = Settings(mode="xray", tile=(8, 8))
+    x_on = R.forward(*t, [_cam()], st_on)[0].cpu().numpy()
+    x_off = R.forward(*t, [_cam()], st_off)[0].cpu().numpy()
+    assert (x_on <= x_off * (1 + 1e-5) + 1e-12).all() and x_on.sum() < 0.99 * x_off.sum()
+
+
+def test_near_segment_rejects_splat(R, dev):
+    from paper_2412_03378_amd import _lib as L
+    wl = scenes.config1(n=100, width=32, height=32)
+    t = G.device_scene(wl.scene, dev)
+    with pytest.raises(L.VgrError) as ei:
+        R.forward(*t, wl.cams, _settings(tile=(8, 8), alpha_model="splat"))
+    assert ei.value.code == L.VGR_ERR_INVALID_ARG
