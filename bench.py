@@ -172,8 +172,20 @@ def bench_headline(args, torch, dev):
                 "flops_per_launch": kern[dom], "launch_ms": stages[dom]}
     splat_ab = (None if args.no_splat else
                 _splat_ab(r, params, wl, tile, args.steps, torch, dev, grads, dLs))
+    near_ab = None
+    if not args.no_splat:
+        _log("A/B: near-plane segment off vs on")
+        near_ab = {"workload": "single view 1920x1080, 1M Gaussians, SH3 (none near the plane: "
+                               "the cost of the option's kernels)",
+                   "off": _ab_leg(r, params, wl.cams, Settings(sh_degree=3, tile=tile),
+                                  args.steps, torch, grads, dLs),
+                   "on": _ab_leg(r, params, wl.cams,
+                                 Settings(sh_degree=3, tile=tile, near_segment=True),
+                                 args.steps, torch, grads, dLs)}
+        near_ab["fwd_bwd_ratio"] = round(near_ab["on"]["fwd_bwd_ms"] / near_ab["off"]["fwd_bwd_ms"], 3)
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
-                flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab)
+                flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab,
+                near_ab=near_ab)
 
 
 def _ab_leg(r, params, cams, st, steps, torch, grads, dLs):
@@ -610,6 +622,8 @@ def main():
     }
     if h["splat_ab"] is not None:
         out["splat_ab"] = h["splat_ab"]
+    if h["near_ab"] is not None:
+        out["near_segment_ab"] = h["near_ab"]
     if not args.no_batched:
         torch.cuda.empty_cache()
         res, wl3 = bench_batched(args, torch, dev)

@@ -737,14 +737,17 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
             const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
             const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
-            const float tw = NEAR ? __fmaf_rn(t, hn, t) : t;   // weight of w' w'^T
-            const float tp0 = tw * p0, tp1 = tw * p1, tp2 = tw * p2;
+            float tw = t;   // weight of w' w'^T
             if constexpr (NEAR) {
-                const float th = t * hh;
-                acc[13] += th * p0;
-                acc[14] += th * p1;
-                acc[15] += th * p2;
+                if (fr.K < 0.0f) {   // wave-uniform: the whole wave is on one record
+                    tw = __fmaf_rn(t, hn, t);
+                    const float th = t * hh;
+                    acc[13] += th * p0;
+                    acc[14] += th * p1;
+                    acc[15] += th * p2;
+                }
             }
+            const float tp0 = tw * p0, tp1 = tw * p1, tp2 = tw * p2;
             acc[6] += tz0;
             acc[7] += tz1;
             acc[8] += tz2;
