@@ -11,15 +11,21 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("mode", ["color", "xray"])
-def test_autograd_matches_explicit_backward(mode):
+@pytest.mark.parametrize("mode,opt", [("color", {}), ("xray", {}), ("color", {"density": "theta"}),
+                                      ("color", {"alpha_model": "splat"}),
+                                      ("xray", {"near_segment": True})])
+def test_autograd_matches_explicit_backward(mode, opt):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_2412_03378_amd import Renderer, Settings, render
     dev = torch.device("cuda", 0)
     wl = scenes.config1(n=400, width=40, height=32)
+    if opt.get("density") == "theta":
+        wl.scene = scenes.with_theta(wl.scene, seed=7)
+    if opt.get("alpha_model") == "splat":
+        wl.scene = scenes.with_opacity(wl.scene, seed=8)
     cams = [wl.cams[0], scenes.axis_camera(3.5, 24, 20, 50.0)]
-    st = Settings(mode=mode, tile=(8, 8))
+    st = Settings(mode=mode, tile=(8, 8), **opt)
     t = [x.clone().requires_grad_(True) if x is not None else None
          for x in G.device_scene(wl.scene, dev)]
     if mode == "xray":

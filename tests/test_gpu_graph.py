@@ -101,3 +101,43 @@ def test_autotune_picks_a_valid_tile(dev):
     explicit = [x.cpu().numpy() for x in r.forward(*params, cams, Settings(sh_degree=3, tile=best))]
     for a, b in zip(auto, explicit):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("opt", [{"alpha_model": "splat"}, {"near_segment": True, "density": "theta"}])
+def test_graph_replays_with_options(opt):
+    """A captured step with the training and comparison options replays to
+    the eager step's images and gradients (up to the order of the backward's
+    FP32 atomics), replay after replay."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2412_03378_amd import Renderer, Settings
+    dev = torch.device("cuda", 0)
+    wl = scenes.config1(n=600, width=48, height=40)
+    sc = wl.scene
+    if opt.get("alpha_model") == "splat":
+        sc = scenes.with_opacity(sc, seed=9)
+    if opt.get("density") == "theta":
+        sc = scenes.with_theta(sc, seed=10)
+    cam = scenes.Camera(wl.cams[0].R, wl.cams[0].t, wl.cams[0].fx, wl.cams[0].fy,
+                        wl.cams[0].cx, wl.cams[0].cy, 48, 40, znear=3.3)
+    st = Settings(act="softplus", tile=(8, 8), **opt)
+    t = G.device_scene(sc, dev)
+    dL = [torch.from_numpy(np.random.default_rng(11).standard_normal(
+        (3, 40, 48)).astype(np.float32)).to(dev)]
+    ref = Renderer(0)
+    img = ref.forward(*t, [cam], st)[0].clone()
+    g_ref = [torch.zeros_like(x) for x in t]
+    ref.backward(dL, *g_ref, accumulate=False)
+    torch.cuda.synchronize()
+    r = Renderer(0)
+    outs = [torch.empty((3, 40, 48), device=dev)]
+    grads = [torch.zeros_like(x) for x in t]
+    r.graph_capture(t, [cam], st, outs, dL, grads)
+    for _ in range(3):
+        r.graph_launch()
+        r.graph_check()
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], img)
+        for a, b in zip(grads, g_ref):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            assert np.allclose(a, b, rtol=1e-4, atol=1e-5 * float(np.abs(b).max()) + 1e-12)
