@@ -106,8 +106,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built; run paper_2412_03378_amd.build.build() "
-                          "(or __graft_entry__.build()) first")
+        raise ImportError(f"{path} is not built; run paper_2412_03378_amd.build.build() first")
     lib = C.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)
