@@ -37,7 +37,9 @@ def _settings(**kw):
 
 def _oset(st):
     return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
-                           T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act)
+                           T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act,
+                           density=st.density, alpha_model=st.alpha_model,
+                           near_segment=st.near_segment)
 
 
 def _pixels(cam, n, seed):
@@ -123,6 +125,38 @@ def test_config2_backward_sparse(R, dev, cfg2):
     wl, t = cfg2
     st = _settings(sh_degree=3, tile=TILE)
     _sparse_backward(R, dev, t, wl.scene, wl.cams, st, [_pixels(wl.cams[0], 40, 22)], 23, True)
+
+
+def test_config2_splat_sampled(R, dev, cfg2):
+    """The forward/backward A/B configuration of the benchmark: the headline
+    scene with the splatting opacity, peak opacities o = 1 - exp(-kappa
+    sqrt(2 pi) (s_x s_y s_z)^(1/3)) as the benchmark sets them."""
+    wl, t = cfg2
+    sc = wl.scene
+    sg = np.cbrt(np.prod(sc.scales.astype(np.float64), axis=1))
+    o = (-np.expm1(-sc.dens.astype(np.float64) * np.sqrt(2.0 * np.pi) * sg)).astype(np.float32)
+    sc = scenes.Scene(sc.means, sc.quats, sc.scales, o, sc.sh, sc.sh_degree)
+    ts = list(t)
+    ts[3] = torch.from_numpy(o).to(dev)
+    cam = wl.cams[0]
+    st = _settings(sh_degree=3, tile=TILE, alpha_model="splat")
+    img = R.forward(*ts, [cam], st)[0].cpu().numpy()
+    T, last = R.aux(0, cam.height, cam.width)
+    _check_forward(img, T.cpu().numpy(), last.cpu().numpy(), sc, cam, st, _pixels(cam, 64, 24))
+    _sparse_backward(R, dev, ts, sc, [cam], st, [_pixels(cam, 30, 25)], 26, True)
+
+
+def test_config2_near_segment_sampled(R, dev, cfg2):
+    """The headline scene with the near-plane segment on (the benchmark's
+    option-cost configuration: the segment kernels, no record flagged)."""
+    wl, t = cfg2
+    cam = wl.cams[0]
+    st = _settings(sh_degree=3, tile=TILE, near_segment=True)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    T, last = R.aux(0, cam.height, cam.width)
+    _check_forward(img, T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
+                   _pixels(cam, 64, 27))
+    _sparse_backward(R, dev, t, wl.scene, [cam], st, [_pixels(cam, 30, 28)], 29, True)
 
 
 def test_config4_xray_sampled(R, dev):
