@@ -279,7 +279,8 @@ def densify_stats(scene, cams, settings: Settings, dLs):
     views where it contributes to some pixel (blended or summed), ``visible_hi``
     the views where it survives the near-plane and opacity culls
     (kappa sqrt(2 pi) s_max >= the skip threshold, the largest x any ray can
-    reach, since beta <= s_max).  Also returned: the per-view gradients and
+    reach, since beta <= s_max; for the splatting model, peak opacity >=
+    alpha_min).  Also returned: the per-view gradients and
     their sums of absolute contributions and error scales, for tolerances."""
     st = settings or Settings()
     xray = st.mode == "xray"
@@ -297,6 +298,12 @@ def densify_stats(scene, cams, settings: Settings, dLs):
         kappa = dens.astype(np.float64)
     tau = st.x_min_xray if xray else -math.log1p(-st.alpha_min)
     reach = kappa * math.sqrt(2.0 * math.pi) * s32.max(1).astype(np.float64)
+    if st.alpha_model == "splat":
+        # splatting model: alpha <= o, so a Gaussian can reach alpha_min only
+        # if its peak opacity does
+        alive = np.clip(dens.astype(np.float64), 0.0, 1.0) >= st.alpha_min * (1.0 - 1e-6)
+    else:
+        alive = reach >= tau * (1.0 - 1e-5)
     means = _f32(scene.means)
     for cam, dL in zip(cams, dLs):
         r = render_backward(scene, cam, st, dL, with_abs=True)
@@ -312,5 +319,5 @@ def densify_stats(scene, cams, settings: Settings, dLs):
         t = np.asarray(cam.t, np.float32).reshape(3).astype(np.float64)
         z = means.astype(np.float64) @ R[2] + t[2]
         znear = float(getattr(cam, "znear", 0.2))
-        hi += (z > znear - 1e-6 * max(1.0, abs(znear))) & (reach >= tau * (1.0 - 1e-5))
+        hi += (z > znear - 1e-6 * max(1.0, abs(znear))) & alive
     return dict(norm_sum=norm_sum, visible_lo=lo, visible_hi=hi, per_view=per_view)

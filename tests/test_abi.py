@@ -30,7 +30,9 @@ def test_exports_every_declared_symbol():
 def test_header_structs_match_binding():
     from paper_2412_03378_amd import _lib
     assert ctypes.sizeof(_lib.vgr_camera) == 4 * (9 + 3 + 4 + 2 + 1 + 1)
-    assert ctypes.sizeof(_lib.vgr_settings) == 4 * (2 + 4 + 3 + 1 + 2 + 2)
+    # mode, sh_degree; 4 thresholds; bg; act; tile_w, tile_h; density,
+    # alpha_model, near_segment, reserved
+    assert ctypes.sizeof(_lib.vgr_settings) == 4 * (2 + 4 + 3 + 1 + 2 + 4)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -39,7 +39,8 @@ def _settings(**kw):
 def _oset(st):
     return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
                            T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act,
-                           density=st.density)
+                           density=st.density, alpha_model=st.alpha_model,
+                           near_segment=st.near_segment)
 
 
 KEYS = ("means", "quats", "scales", "dens", "sh")
@@ -109,7 +110,7 @@ def test_theta_xray_multi_view(R, dev):
     _multi_view_check(R, dev, sc, cams, st, seed=44)
 
 
-@pytest.mark.parametrize("density", ["kappa", "theta"])
+@pytest.mark.parametrize("density", ["kappa", "theta", "splat"])
 def test_densify_stats_multi_view(R, dev, density):
     """Three views of uneven size in one call: the per-Gaussian sum of
     |dL_v/dmu| matches the oracle within the gradient tolerance, the view
@@ -119,9 +120,14 @@ def test_densify_stats_multi_view(R, dev, density):
     sc = wl.scene
     if density == "theta":
         sc = scenes.with_theta(sc, seed=46)
+    if density == "splat":   # the statistics of the splatting comparison model
+        sc = scenes.with_opacity(sc, seed=46)
     cams = [scenes.Camera(c.R, c.t, c.fx / 16, c.fy / 16, c.cx / 16, c.cy / 16,
                           c.width // 16, c.height // 16) for c in wl.cams]
-    st = _settings(sh_degree=3, act="softplus", tile=(16, 8), density=density)
+    if density == "splat":
+        st = _settings(sh_degree=3, act="softplus", tile=(16, 8), alpha_model="splat")
+    else:
+        st = _settings(sh_degree=3, act="softplus", tile=(16, 8), density=density)
     n = sc.n
     gnorm = torch.zeros(n, dtype=torch.float32, device=dev)
     vcount = torch.zeros(n, dtype=torch.int32, device=dev)
@@ -219,3 +225,25 @@ def test_densify_capacity_and_bad_density(R, dev):
     rc = R._lib.vgr_render_forward(R._h, C.byref(bad), wl.scene.n, *[ptr(x) for x in t], 1,
                                    cams, outs)
     assert rc == L.VGR_ERR_INVALID_ARG
+
+
+def test_densify_stats_xray(R, dev):
+    """X-ray mode over three cone-beam views (no colour term in dL/dmu)."""
+    wl = scenes.config4(n=2000, n_views=64, size=64, seed=4, with_grad=False)
+    sc = wl.scene
+    cams = [wl.cams[k] for k in (0, 21, 43)]
+    st = _settings(mode="xray", tile=(8, 8))
+    n = sc.n
+    gnorm = torch.zeros(n, dtype=torch.float32, device=dev)
+    vcount = torch.zeros(n, dtype=torch.int32, device=dev)
+    R.set_densify_stats(gnorm, vcount)
+    try:
+        _, ds, _, _ = _multi_view_check(R, dev, sc, cams, st, seed=66)
+        g1 = gnorm.cpu().numpy().astype(np.float64)
+        c1 = vcount.cpu().numpy()
+        err = np.abs(g1 - ds["norm_sum"]) / (_norm_tolerance(ds) + 1e-30)
+        print(f"norm ratio {err.max():.3g}")
+        assert err.max() <= 1.0
+        assert np.all(c1 >= ds["visible_lo"]) and np.all(c1 <= ds["visible_hi"])
+    finally:
+        R.set_densify_stats(None, None)
