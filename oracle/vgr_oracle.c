@@ -35,7 +35,8 @@
  *   - comparison model (alpha_model = 1): the 3DGS splatting opacity the
  *     paper replaces (Sec. 3, eq. 3dgs_alpha, eq. affine_approx), with the
  *     density input read as the peak opacity o in [0, 1] (clamped) and the
- *     same compositing rules; forward only.
+ *     same compositing rules; its backward is the analytic chain of
+ *     chain_splat.
  *   - near_segment = 1: the integral along each ray starts where the ray
  *     crosses the near plane z = znear instead of covering the whole line,
  *     x = kappa sqrt(2 pi) beta G(o + gamma d) Phi((gamma - t_n) / beta), Phi the
