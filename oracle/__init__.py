@@ -54,6 +54,8 @@ class _Cam(C.Structure):
 class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
                 ("density", C.c_int32), ("alpha_model", C.c_int32), ("near_segment", C.c_int32),
+                ("tile_resort", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("pad2", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
 
@@ -72,6 +74,7 @@ class Settings:
     density: str = "kappa"         # "kappa" | "theta" (eq. density_reparam)
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS, eq. 3dgs_alpha)
     near_segment: bool = False     # integrate each ray from the near plane on (Sec. 4.2)
+    resort_tile: tuple = None      # (w, h): per-tile order by gamma on the tile-centre ray
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa",
@@ -132,6 +135,9 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     s.density = 1 if st.density == "theta" else 0
     s.alpha_model = 1 if st.alpha_model == "splat" else 0
     s.near_segment = 1 if st.near_segment else 0
+    if st.resort_tile:
+        s.tile_resort = 1
+        s.tile_w, s.tile_h = int(st.resort_tile[0]), int(st.resort_tile[1])
     s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
     s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
     s.bg[:] = [float(v) for v in st.bg]

@@ -42,6 +42,13 @@
  *     x = kappa sqrt(2 pi) beta G(o + gamma d) Phi((gamma - t_n) / beta), Phi the
  *     standard normal distribution function (Sec. 4.2, the finite-limit erf
  *     form with the argument (t - gamma) / (sqrt 2 beta)).
+ *   - tile_resort = 1 (colour mode): instead of the mean depth, each pixel
+ *     composites in ascending order of gamma on the ray through the centre of
+ *     its tile_w x tile_h screen tile (the position of each Gaussian's maximum
+ *     along that ray; ties by the depth key, then the index): the per-tile
+ *     level of the re-sorting that the paper points to against popping
+ *     (Sec. 8).  A pixel whose order rests on two keys closer than 1e-5
+ *     (relative) reports it in its decision margin (scaled by 100).
  *   - the density input is kappa itself, or theta with the reparameterisation
  *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
  *     density_reparam); theta outside the paper's range [0, 1] is clamped to
@@ -81,6 +88,9 @@ typedef struct {
     int32_t density;    /* 0: dens holds kappa; 1: dens holds theta (kappa_of) */
     int32_t alpha_model;/* 0: the paper's ray integral; 1: 3DGS splatting (splat_setup) */
     int32_t near_segment;/* 1: integrate each ray from the near plane on (finite segment) */
+    int32_t tile_resort; /* 1: per-tile order by the depth of each Gaussian's maximum */
+    int32_t tile_w, tile_h;
+    int32_t pad2;
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
 } orc_settings;
@@ -344,6 +354,22 @@ static void pixel_ray(const orc_camera *cam, int px, int py, double d[3])
     for (int i = 0; i < 3; ++i) d[i] /= len;
 }
 
+/* world-space unit direction of the ray through image point (X, Y) (pixel
+   units, pixel p spans [p, p + 1]) */
+static void point_ray(const orc_camera *cam, double X, double Y, double d[3])
+{
+    double u[3] = { (X - cam->cx) / cam->fx, (Y - cam->cy) / cam->fy, 1.0 };
+    double Ri[9];
+    inverse3(cam->R, Ri);
+    double len = 0;
+    for (int i = 0; i < 3; ++i) {
+        d[i] = Ri[i * 3] * u[0] + Ri[i * 3 + 1] * u[1] + Ri[i * 3 + 2] * u[2];
+        len += d[i] * d[i];
+    }
+    len = sqrt(len);
+    for (int i = 0; i < 3; ++i) d[i] /= len;
+}
+
 static float depth_key(const orc_camera *cam, const float *mu)
 {
     const float *R = cam->R;
@@ -498,6 +524,65 @@ static double rel_margin(double v, double thr)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Per-tile order (tile_resort).                                             */
+
+typedef struct {
+    double g;      /* gamma on the tile-centre ray */
+    float key;     /* depth key of the mean */
+    int64_t idx;
+} resort_item;
+
+static int cmp_resort(const void *pa, const void *pb)
+{
+    const resort_item *a = (const resort_item *)pa, *b = (const resort_item *)pb;
+    if (a->g < b->g) return -1;
+    if (a->g > b->g) return 1;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+/* Order of the visible Gaussians for pixel (px, py) under tile_resort, into
+   order[nvis]; returns the smallest relative gap between consecutive gammas
+   of Gaussians whose integral at the pixel (ray d) reaches the skip
+   threshold tau (INFINITY if fewer than two). */
+static double resort_order(const view_state *vs, const float *means, const orc_camera *cam,
+                           const orc_settings *st, int px, int py, const double d[3], double tau,
+                           int64_t *order)
+{
+    const int tx = px / st->tile_w, ty = py / st->tile_h;
+    double dc[3];
+    point_ray(cam, tx * st->tile_w + 0.5 * st->tile_w, ty * st->tile_h + 0.5 * st->tile_h, dc);
+    resort_item *it = (resort_item *)malloc(sizeof(resort_item) * (size_t)(vs->nvis > 0 ? vs->nvis : 1));
+    for (int64_t r = 0; r < vs->nvis; ++r) {
+        const int64_t i = vs->order[r];
+        const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+        ray_terms rt;
+        ray_integral(mu, vs->P + 9 * i, 1.0, vs->o, dc, &rt);
+        it[r].g = rt.gamma;
+        it[r].key = vs->key[i];
+        it[r].idx = i;
+    }
+    qsort(it, (size_t)vs->nvis, sizeof(resort_item), cmp_resort);
+    double gap = INFINITY, prev = NAN;
+    for (int64_t r = 0; r < vs->nvis; ++r) {
+        const int64_t i = it[r].idx;
+        order[r] = i;
+        const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+        ray_terms rt;
+        ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+        if (rt.x < tau) continue;
+        if (!isnan(prev)) {
+            const double m = fabs(it[r].g - prev) / fmax(fabs(it[r].g), 1e-300);
+            if (m < gap) gap = m;
+        }
+        prev = it[r].g;
+    }
+    free(it);
+    return gap;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Forward.                                                                  */
 
 typedef struct {
@@ -624,6 +709,8 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
     if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
+    if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
+        return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -633,10 +720,21 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
         double d[3];
         const double pc[2] = { pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5 };
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
-        shade_pixel(&vs, means, st, d, pc, out + C * p, T_out ? T_out + p : NULL,
+        view_state vp = vs;
+        double ogap = INFINITY;
+        if (st->tile_resort) {
+            vp.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(vs.nvis > 0 ? vs.nvis : 1));
+            ogap = resort_order(&vs, means, cam, st, pix[2 * p], pix[2 * p + 1], d,
+                                -log1p(-st->alpha_min), vp.order);
+        }
+        shade_pixel(&vp, means, st, d, pc, out + C * p, T_out ? T_out + p : NULL,
                     last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
                     margin_out ? margin_out + p : NULL, untrunc_out ? untrunc_out + p : NULL,
                     NULL);
+        if (st->tile_resort) {
+            if (margin_out && 100.0 * ogap < margin_out[p]) margin_out[p] = 100.0 * ogap;
+            free(vp.order);
+        }
     }
     view_free(&vs);
     return 0;
@@ -988,6 +1086,8 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
     if (n < 0 || npix < 0 || !cam || !st) return -1;
     if (st->mode == 0 && n > 0 && !sh) return -1;
     if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
+    if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
+        return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -1003,7 +1103,13 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         pixel_ray(cam, pix[2 * p], pix[2 * p + 1], d);
         blend_list bl = { NULL, 0, 0 };
         const double pc[2] = { pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5 };
-        shade_pixel(&vs, means, st, d, pc, out, NULL, NULL, NULL, NULL, NULL, &bl);
+        view_state vp = vs;
+        if (st->tile_resort) {
+            vp.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(vs.nvis > 0 ? vs.nvis : 1));
+            resort_order(&vs, means, cam, st, pix[2 * p], pix[2 * p + 1], d,
+                         -log1p(-st->alpha_min), vp.order);
+        }
+        shade_pixel(&vp, means, st, d, pc, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
             for (int64_t r = 0; r < bl.cnt; ++r)
                 chain_integral(bl.rec[r].idx, g[0], fabs(g[0]), 0.0, means, quats, scales, dens,
@@ -1044,6 +1150,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
             }
         }
         free(bl.rec);
+        if (st->tile_resort) free(vp.order);
     }
     view_free(&vs);
     return 0;
