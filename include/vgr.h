@@ -106,6 +106,12 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               behind it.  Evaluated only for records whose bound reaches
  *               within 6 standard deviations of the plane (elsewhere Phi = 1 to
  *               FP32 precision).  VOLUMETRIC only [0]
+ *   tile_resort 0: every tile composites in the depth order of the means.
+ *               1: within each tile, in ascending depth of each Gaussian's
+ *               maximum along the ray through the tile's centre (the
+ *               per-tile level of the re-sorting the paper points to against
+ *               popping, Sec. 8; ties by mean depth, then index).  The image
+ *               then depends on the tile shape.  Colour mode, VOLUMETRIC [0]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -120,7 +126,7 @@ typedef struct {
     int32_t density;
     int32_t alpha_model;
     int32_t near_segment;
-    int32_t reserved;
+    int32_t tile_resort;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */

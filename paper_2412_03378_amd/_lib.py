@@ -40,7 +40,7 @@ class vgr_settings(C.Structure):
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32),
-                ("near_segment", C.c_int32), ("reserved", C.c_int32)]
+                ("near_segment", C.c_int32), ("tile_resort", C.c_int32)]
 
 
 class vgr_stats(C.Structure):

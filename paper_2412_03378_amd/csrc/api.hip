@@ -40,6 +40,7 @@ struct vgr_ctx {
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id, pmask;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts, wg_time;
+    DevBuf rs_key, rs_idx, rs_key2, rs_idx2;   // per-tile re-sorting (instance-sized)
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
@@ -308,7 +309,8 @@ void vgr_destroy(vgr_ctx *c)
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->pmask, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
-                      &c->words, &c->counters, &c->views, &c->blk_counts, &c->wg_time };
+                      &c->words, &c->counters, &c->views, &c->blk_counts, &c->wg_time,
+                      &c->rs_key, &c->rs_idx, &c->rs_key2, &c->rs_idx2 };
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (c->h_views) (void)hipHostFree(c->h_views);
@@ -431,6 +433,10 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
         return fail(c, VGR_ERR_INVALID_ARG, "bad near_segment");
     if (st->near_segment && st->alpha_model == VGR_ALPHA_SPLAT)
         return fail(c, VGR_ERR_INVALID_ARG, "the near-plane segment needs the volumetric model");
+    if (st->tile_resort != 0 && st->tile_resort != 1)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad tile_resort");
+    if (st->tile_resort && (st->mode != VGR_MODE_COLOR || st->alpha_model != VGR_ALPHA_VOLUMETRIC))
+        return fail(c, VGR_ERR_INVALID_ARG, "tile_resort needs colour mode and the volumetric model");
     if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
         !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
         return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
@@ -455,6 +461,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.amin = st->alpha_min;
     rp.amax = st->alpha_max;
     rp.near_segment = st->near_segment;
+    rp.tile_resort = st->tile_resort;
     rp.n_views = n_views;
     rp.n = n;
     rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;
@@ -559,6 +566,10 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
                 (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
                 (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(K > p.sort_n ? K : p.sort_n))))
                 return rc;
+            if (rp.tile_resort &&
+                ((rc = ensure(c, c->rs_key, 4 * K)) || (rc = ensure(c, c->rs_idx, 4 * K)) ||
+                 (rc = ensure(c, c->rs_key2, 4 * K)) || (rc = ensure(c, c->rs_idx2, 4 * K))))
+                return rc;
             c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
             b = make_buffers(c);
             b.views = views_dev;
@@ -569,6 +580,16 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         HIP_TRY(c, launch_emit(rp, b, m, K, s));
         mark_end(c, ST_SCAN_EMIT);
         mark(c, ST_SORT_TILES);
+        if (rp.tile_resort) {
+            // order the instances by the depth of each maximum on its tile-centre
+            // ray; the stable tile sort below keeps that order within each tile
+            uint32_t *k1 = ptr<uint32_t>(c->rs_key), *i1 = ptr<uint32_t>(c->rs_idx);
+            uint32_t *k2 = ptr<uint32_t>(c->rs_key2), *i2 = ptr<uint32_t>(c->rs_idx2);
+            HIP_TRY(c, launch_resort_keys(rp, b, k1, i1, K, s));
+            HIP_TRY(c, launch_radix_sort(k1, i1, k2, i2, b.d_total, K, 32,
+                                         ptr<uint32_t>(c->sort_tmp), s));
+            HIP_TRY(c, launch_resort_permute(b, i1, k2, i2, K, s));
+        }
         HIP_TRY(c, launch_radix_sort(b.inst_key, b.inst_val, b.inst_key2, b.inst_val2, b.d_total, K,
                                      bits_for(p.tiles), ptr<uint32_t>(c->sort_tmp), s));
         mark_end(c, ST_SORT_TILES);
@@ -830,6 +851,10 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     if ((rc = prepare(c, st, n, means, quats, scales, dens, sh, n_views, cams, out, p))) return rc;
     const int64_t cap = (int64_t)ceil((double)c->K * capacity_factor) + 4096;
     const int64_t m = p.m;
+    if (p.rp.tile_resort &&
+        ((rc = ensure(c, c->rs_key, 4 * cap)) || (rc = ensure(c, c->rs_idx, 4 * cap)) ||
+         (rc = ensure(c, c->rs_key2, 4 * cap)) || (rc = ensure(c, c->rs_idx2, 4 * cap))))
+        return rc;
     if ((rc = ensure(c, c->inst_key, 4 * cap)) || (rc = ensure(c, c->inst_val, 4 * cap)) ||
         (rc = ensure(c, c->inst_key2, 4 * cap)) || (rc = ensure(c, c->inst_val2, 4 * cap)) ||
         (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(cap > p.sort_n ? cap : p.sort_n))) ||

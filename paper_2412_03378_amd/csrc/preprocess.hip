@@ -801,6 +801,61 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const uint32_t 
 // Heaviest-first launch order of the tiles, by a counting sort on 32 buckets
 // of the list length (2 buckets per octave, longest first).  The order within
 // a bucket is arbitrary: it only steers scheduling, never results.
+// Per-tile re-sorting key of instance j: the view depth s* = mz (v0 . w) / |w|^2
+// of the closest point to the mean on the ray through the centre of its tile
+// (w = L u for that ray, from the record), as order-preserving bits.
+__global__ void resort_key_kernel(RenderParams rp, Buffers b, uint32_t *__restrict__ key,
+                                  uint32_t *__restrict__ idx, int64_t bound)
+{
+    const int64_t K = b.d_total[0];
+    const int64_t m = rp.n * (int64_t)rp.n_views;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K && j < bound;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t gt = b.inst_key[j], item = b.inst_val[j];
+        uint32_t k = 0xFFFFFFFFu;
+        if (gt < (uint32_t)rp.total_tiles && (int64_t)item < m) {
+            int v = 0;
+            for (int q = 1; q < rp.n_views; ++q)
+                if (b.views[q].tile_off <= (int)gt) v = q;
+            const ViewInfo &vi = b.views[v];
+            const int lt = (int)gt - vi.tile_off;
+            const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+            const float4 *gp = b.geom + (size_t)item * kRecVec;
+            const float4 g0 = gp[0], g2 = gp[2], g3 = gp[3], g4 = gp[4], g5 = gp[5];
+            const float dx = ((float)(tx * rp.tile_w) + 0.5f * rp.tile_w - g0.x) - g0.z;
+            const float dy = ((float)(ty * rp.tile_h) + 0.5f * rp.tile_h - g0.y) - g0.w;
+            // A = [[g2.y, g3.x], [g2.z, g3.y], [g2.w, g3.z]], v0 = (g3.w, g4.x, g4.y)
+            const float w0 = __fmaf_rn(g3.x, dy, __fmaf_rn(g2.y, dx, g3.w));
+            const float w1 = __fmaf_rn(g3.y, dy, __fmaf_rn(g2.z, dx, g4.x));
+            const float w2 = __fmaf_rn(g3.z, dy, __fmaf_rn(g2.w, dx, g4.y));
+            const float vw = __fmaf_rn(g3.w, w0, __fmaf_rn(g4.x, w1, g4.y * w2));
+            const float ww = __fmaf_rn(w0, w0, __fmaf_rn(w1, w1, w2 * w2));
+            const float depth = g5.w * vw / ww;
+            const uint32_t u = __float_as_uint(depth);
+            k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+            if (k == 0xFFFFFFFFu) k = 0xFFFFFFFEu;   // keep the invalid slot last
+        }
+        key[j] = k;
+        idx[j] = (uint32_t)j;
+    }
+}
+
+__global__ void resort_gather_kernel(const uint32_t *__restrict__ d_total,
+                                     const uint32_t *__restrict__ src_key,
+                                     const uint32_t *__restrict__ src_val,
+                                     const uint32_t *__restrict__ idx, uint32_t *__restrict__ dst_key,
+                                     uint32_t *__restrict__ dst_val, int64_t bound)
+{
+    const int64_t K = d_total[0];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K && j < bound;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = idx ? idx[j] : (uint32_t)j;
+        const bool ok = (int64_t)i < K && (int64_t)i < bound;
+        dst_key[j] = ok ? src_key[i] : 0xFFFFFFFFu;
+        dst_val[j] = ok ? src_val[i] : 0u;
+    }
+}
+
 __device__ inline int tile_bucket(uint32_t len)
 {
     if (len == 0) return 31;
@@ -1273,6 +1328,32 @@ hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, h
     unsigned g = grid_for(bound, 256);
     if (g > 16384) g = 16384;
     ranges_kernel<<<g, 256, 0, s>>>(b.inst_key, b.d_total, b.ranges, bound, (uint32_t)total_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_resort_keys(const RenderParams &rp, const Buffers &b, uint32_t *key,
+                              uint32_t *idx, int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return hipSuccess;
+    unsigned g = grid_for(bound, 256);
+    if (g > 16384) g = 16384;
+    resort_key_kernel<<<g, 256, 0, s>>>(rp, b, key, idx, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_resort_permute(const Buffers &b, const uint32_t *idx, uint32_t *tmp_key,
+                                 uint32_t *tmp_val, int64_t bound, hipStream_t s)
+{
+    if (bound <= 0) return hipSuccess;
+    unsigned g = grid_for(bound, 256);
+    if (g > 16384) g = 16384;
+    resort_gather_kernel<<<g, 256, 0, s>>>(b.d_total, b.inst_key, b.inst_val, idx, tmp_key,
+                                           tmp_val, bound);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // and back (a plain copy of the first K entries)
+    resort_gather_kernel<<<g, 256, 0, s>>>(b.d_total, tmp_key, tmp_val, nullptr, b.inst_key,
+                                           b.inst_val, bound);
     return hipGetLastError();
 }
 

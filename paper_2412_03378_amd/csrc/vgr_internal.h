@@ -110,7 +110,7 @@ struct RenderParams {
     int32_t alpha_model; // VGR_ALPHA_VOLUMETRIC or VGR_ALPHA_SPLAT
     float amin, amax;    // alpha_min, alpha_max (splatting model)
     int32_t near_segment;// integrate from the near plane (records flagged by K' < 0)
-    int32_t pad1;
+    int32_t tile_resort; // per-tile order by the depth of the maximum on the tile-centre ray
 };
 
 // Device workspace views handed to kernels.
@@ -180,6 +180,15 @@ hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int6
                        hipStream_t s);
 hipError_t launch_ranges(const Buffers &b, int64_t capacity_bound, int32_t total_tiles,
                          hipStream_t s);
+// Per-tile re-sorting: key[j] = order-preserving bits of the view depth of
+// the maximum of instance j's Gaussian on its tile-centre ray, idx[j] = j
+// (j < the device instance count, at most bound).
+hipError_t launch_resort_keys(const RenderParams &rp, const Buffers &b, uint32_t *key,
+                              uint32_t *idx, int64_t bound, hipStream_t s);
+// Permute the instance lists: (inst_key, inst_val)[j] = old[idx[j]], through
+// the scratch arrays tmp_key / tmp_val.
+hipError_t launch_resort_permute(const Buffers &b, const uint32_t *idx, uint32_t *tmp_key,
+                                 uint32_t *tmp_val, int64_t bound, hipStream_t s);
 // Order tiles by decreasing list length (heaviest first) into b.tile_order.
 hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
                              hipStream_t s);

@@ -28,6 +28,7 @@ class Settings:
     density: str = "kappa"           # "kappa" | "theta": what `dens` holds
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (the 3DGS comparison model)
     near_segment: bool = False       # integrate each ray from the near plane on
+    tile_resort: bool = False        # per-tile order by the depth of each maximum
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -41,6 +42,7 @@ class Settings:
         s.density = L.VGR_DENSITY_THETA if self.density == "theta" else L.VGR_DENSITY_KAPPA
         s.alpha_model = L.VGR_ALPHA_SPLAT if self.alpha_model == "splat" else L.VGR_ALPHA_VOLUMETRIC
         s.near_segment = 1 if self.near_segment else 0
+        s.tile_resort = 1 if self.tile_resort else 0
         return s
 
     @staticmethod

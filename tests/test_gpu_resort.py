@@ -1,0 +1,103 @@
+"""GPU parity of the per-tile re-sorting (each tile composites in the order
+of the depth of every Gaussian's maximum on the tile-centre ray; the
+re-sorting the paper points to against popping, Sec. 8) against the FP64
+oracle through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import gpu_helpers as G
+import helpers as H
+from paper_2412_03378_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def R(dev):
+    from paper_2412_03378_amd import Renderer
+    return Renderer(0)
+
+
+def _settings(**kw):
+    from paper_2412_03378_amd import Settings
+    return Settings(tile_resort=True, **kw)
+
+
+def _oset(st):
+    return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
+                           T_min=st.T_min, bg=st.bg, act=st.act, resort_tile=tuple(st.tile))
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8)])
+def test_tile_resort_parity(R, dev, tile):
+    """The parity workload (128x128, 1000 Gaussians) with the per-tile order:
+    image and gradients; pixels whose order rests on keys closer than 1e-5
+    are in the flagged set."""
+    wl = scenes.config1()
+    sc, cam = wl.scene, wl.cams[0]
+    st = _settings(tile=tile, act="softplus", bg=(0.1, 0.2, 0.3))
+    ost = _oset(st)
+    ref = oracle.render(sc, cam, ost)
+    base = oracle.render(sc, cam, oracle.Settings(act="softplus", bg=(0.1, 0.2, 0.3)))
+    t = G.device_scene(sc, dev)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    e_ok, nflag, e_flag = G.compare_image(img, ref["image"], ref["margin"])
+    moved = float(np.abs(ref["image"] - base["image"]).max())
+    print(f"err {e_ok:.3g} flagged {nflag} ({e_flag:.3g}); largest change from the mean-depth order {moved:.3g}")
+    assert e_ok <= G.IMG_TOL and e_flag <= G.FLIP_TOL
+    assert moved > 1e-3            # the order matters on this scene
+    rng = np.random.default_rng(71)
+    dL = rng.standard_normal((3, cam.height, cam.width)) * (ref["margin"] > G.MARGIN)
+    grads = [torch.zeros_like(x) for x in t]
+    R.backward([torch.from_numpy(dL.astype(np.float32)).to(dev)], *grads)
+    torch.cuda.synchronize()
+    g = oracle.render_backward(sc, cam, ost, dL)
+    worst = {}
+    for k, gr in zip(("means", "quats", "scales", "dens", "sh"), grads):
+        worst[k] = G.grad_errors(gr.cpu().numpy(), g[k], g["abs_" + k], g["err_" + k])
+        print(k, f"ratio {worst[k]:.3g}", G.grad_worst(gr.cpu().numpy(), g[k], g["abs_" + k],
+                                                     g["err_" + k]))
+    assert max(worst.values()) <= 1.0, worst
+
+
+def test_tile_resort_flips_two_gaussians(R, dev):
+    """The long Gaussian whose maximum lies in front of a smaller one with a
+    nearer mean is composited first with the option, second without."""
+    cam = scenes.axis_camera(0.0, 16, 16, 30.0)    # one 16x16 tile centred on the axis
+    phi = -math.pi / 4
+    q = [math.cos(phi / 2), 0.0, math.sin(phi / 2), 0.0]
+    sc = H.scene([[0.0, 0.0, 4.7], [0.5, 0.0, 5.0]], [[0.08] * 3, [0.6, 0.05, 0.05]], [3.0, 4.0],
+                 quats=[[1, 0, 0, 0], q], rgb=[[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    t = G.device_scene(sc, dev)
+    from paper_2412_03378_amd import Settings
+    for st in (_settings(tile=(16, 16)), Settings(tile=(16, 16))):
+        img = R.forward(*t, [cam], st)[0].cpu().numpy()
+        ost = _oset(st) if st.tile_resort else oracle.Settings()
+        ref = oracle.render(sc, cam, ost)
+        assert np.abs(img - ref["image"]).max() <= G.IMG_TOL
+    c = 8
+    on = R.forward(*t, [cam], _settings(tile=(16, 16)))[0].cpu().numpy()[:, c, c]
+    off = R.forward(*t, [cam], Settings(tile=(16, 16)))[0].cpu().numpy()[:, c, c]
+    assert on[2] > off[2] and on[0] < off[0]     # blue (the long one) in front with the option
+
+
+def test_tile_resort_rejects_other_modes(R, dev):
+    from paper_2412_03378_amd import _lib as L
+    wl = scenes.config1(n=100, width=32, height=32)
+    t = G.device_scene(wl.scene, dev)
+    for kw in (dict(mode="xray"), dict(alpha_model="splat")):
+        with pytest.raises(L.VgrError) as ei:
+            R.forward(*t, wl.cams, _settings(tile=(8, 8), **kw))
+        assert ei.value.code == L.VGR_ERR_INVALID_ARG
