@@ -183,6 +183,12 @@ def bench_headline(args, torch, dev):
                                  Settings(sh_degree=3, tile=tile, near_segment=True),
                                  args.steps, torch, grads, dLs)}
         near_ab["fwd_bwd_ratio"] = round(near_ab["on"]["fwd_bwd_ms"] / near_ab["off"]["fwd_bwd_ms"], 3)
+        _log("A/B: per-tile re-sorting off vs on")
+        near_ab["tile_resort_on"] = _ab_leg(r, params, wl.cams,
+                                            Settings(sh_degree=3, tile=tile, tile_resort=True),
+                                            args.steps, torch, grads, dLs)
+        near_ab["tile_resort_fwd_bwd_ratio"] = round(
+            near_ab["tile_resort_on"]["fwd_bwd_ms"] / near_ab["off"]["fwd_bwd_ms"], 3)
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
                 flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab,
                 near_ab=near_ab)
@@ -216,7 +222,7 @@ def _ab_leg(r, params, cams, st, steps, torch, grads, dLs):
     r.forward(*params, cams, st)
     stats = r.stats()
     r.set_counting(False)
-    pick = ("preprocess_fwd", "raster_fwd", "raster_bwd", "preprocess_bwd")
+    pick = ("preprocess_fwd", "sort_tiles", "raster_fwd", "raster_bwd", "preprocess_bwd")
     return {"fwd_ms": round(fwd_ms, 4), "fwd_bwd_ms": round(step_ms, 4),
             "stages_ms": {k: round(stages[k], 4) for k in pick},
             "instances": stats["instances"], "pairs_tested": stats["pairs_tested"],
