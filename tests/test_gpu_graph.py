@@ -103,7 +103,8 @@ def test_autotune_picks_a_valid_tile(dev):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("opt", [{"alpha_model": "splat"}, {"near_segment": True, "density": "theta"}])
+@pytest.mark.parametrize("opt", [{"alpha_model": "splat"}, {"near_segment": True, "density": "theta"},
+                                 {"tile_resort": True}])
 def test_graph_replays_with_options(opt):
     """A captured step with the training and comparison options replays to
     the eager step's images and gradients (up to the order of the backward's
