@@ -111,7 +111,9 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               maximum along the ray through the tile's centre (the
  *               per-tile level of the re-sorting the paper points to against
  *               popping, Sec. 8; ties by mean depth, then index).  The image
- *               then depends on the tile shape.  Colour mode, VOLUMETRIC [0]
+ *               then depends on the tile shape (also on the one vgr_autotune
+ *               picks when tile_w = tile_h = 0).  Costs one more 32-bit sort
+ *               of the instances.  Colour mode, VOLUMETRIC [0]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
