@@ -159,10 +159,11 @@ def test_config2_near_segment_sampled(R, dev, cfg2):
     _sparse_backward(R, dev, t, wl.scene, [cam], st, [_pixels(cam, 30, 28)], 29, True)
 
 
-def test_config4_xray_sampled(R, dev):
+@pytest.mark.parametrize("tile", [TILE, (16, 16)])   # 16x16: the shape the benchmark's tuner picks
+def test_config4_xray_sampled(R, dev, tile):
     wl = scenes.config4(with_grad=False)
     t = G.device_scene(wl.scene, dev)
-    st = _settings(mode="xray", tile=TILE)
+    st = _settings(mode="xray", tile=tile)
     imgs = R.forward(*t, wl.cams, st)
     for v in (0, 21, 42, 63):
         _check_forward(imgs[v].cpu().numpy(), None, None, wl.scene, wl.cams[v], st,
