@@ -173,10 +173,11 @@ def test_config4_xray_sampled(R, dev, tile):
                                                       enumerate(cams)], 51, False)
 
 
-def test_config3_batched_sampled(R, dev):
+@pytest.mark.parametrize("tile", [TILE, (16, 16)])   # 16x16: the benchmark's tuned shape
+def test_config3_batched_sampled(R, dev, tile):
     wl = scenes.config3(with_grad=False)
     t = G.device_scene(wl.scene, dev)
-    st = _settings(sh_degree=3, tile=TILE)
+    st = _settings(sh_degree=3, tile=tile)
     imgs = [x.cpu().numpy() for x in R.forward(*t, wl.cams, st)]
     for v in (0, 7, 15):
         T, last = R.aux(v, wl.cams[v].height, wl.cams[v].width)
@@ -187,13 +188,17 @@ def test_config3_batched_sampled(R, dev):
         assert np.array_equal(one, imgs[v])
 
 
-def test_config5_two_views_sampled(R, dev):
+@pytest.mark.parametrize("tile,views", [(TILE, (0, 33)), ((16, 16), tuple(range(16)))])
+def test_config5_views_sampled(R, dev, tile, views):
+    """Two views at 8x8, and the benchmark's training call: 16 views in one
+    call at its tuned 16x16 tiles (two of them checked)."""
     wl = scenes.config5(with_grad=False)
     t = G.device_scene(wl.scene, dev)
-    st = _settings(sh_degree=3, tile=TILE)
-    cams = [wl.cams[0], wl.cams[33]]
+    st = _settings(sh_degree=3, tile=tile)
+    cams = [wl.cams[v] for v in views]
     imgs = [x.cpu().numpy() for x in R.forward(*t, cams, st)]
-    for v, cam in enumerate(cams):
+    for v in (0, len(cams) - 1):
+        cam = cams[v]
         T, last = R.aux(v, cam.height, cam.width)
         _check_forward(imgs[v], T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
                        _pixels(cam, 12, 70 + v))
