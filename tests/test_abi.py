@@ -71,3 +71,46 @@ def test_struct_layout_matches_header(tmp_path):
         assert got[name] == ctypes.sizeof(st), name
         for f in fs:
             assert got[f"{name}.{f}"] == getattr(st, f).offset, (name, f)
+
+
+def test_default_settings_are_the_documented_ones():
+    from paper_2412_03378_amd import _lib
+    lib = _lib.load()
+    s = _lib.vgr_settings()
+    lib.vgr_default_settings(ctypes.byref(s))
+    assert s.mode == _lib.VGR_MODE_COLOR and s.sh_degree == 0
+    assert abs(s.alpha_min - 1 / 255) < 1e-9 and abs(s.alpha_max - 0.99) < 1e-7
+    assert abs(s.T_min - 1e-4) < 1e-11 and abs(s.x_min_xray - 1e-6) < 1e-13
+    assert list(s.bg) == [0.0, 0.0, 0.0] and s.act == _lib.VGR_ACT_CLAMP0
+    assert (s.tile_w, s.tile_h) == (0, 0)
+    assert s.density == _lib.VGR_DENSITY_KAPPA and s.alpha_model == _lib.VGR_ALPHA_VOLUMETRIC
+    assert s.near_segment == 0 and s.tile_resort == 0
+
+
+def test_null_context_calls_fail_cleanly():
+    """Every entry point given a NULL context returns VGR_ERR_INVALID_ARG
+    (nothing is thrown, nothing touches a device)."""
+    from paper_2412_03378_amd import _lib
+    lib = _lib.load()
+    E = _lib.VGR_ERR_INVALID_ARG
+    assert lib.vgr_set_stream(None, None) == E
+    assert lib.vgr_set_counting(None, 1) == E
+    assert lib.vgr_set_timing(None, 1) == E
+    assert lib.vgr_set_densify_stats(None, None, None, 0) == E
+    assert lib.vgr_graph_launch(None) == E
+    assert lib.vgr_render_backward(None, None, None, None, None, None, None, 0) == E
+    assert lib.vgr_get_stats(None, None) == E
+    assert isinstance(lib.vgr_last_error(None), bytes)
+    lib.vgr_destroy(None)
+
+
+def test_create_without_a_device_returns_an_error():
+    import pytest
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_2412_03378_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.vgr_create(ctypes.byref(h), 0)
+    assert rc < 0 and not h.value
