@@ -585,7 +585,7 @@ def main():
         args.no_batched = args.no_xray = args.no_train = True
         args.no_cpu_baseline = args.no_splat = True
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(views would shard across GPUs with an all-reduce of parameter "
               "gradients; not built).", file=sys.stderr)
         sys.exit(2)
