@@ -232,7 +232,9 @@ int vgr_render_backward(vgr_ctx *ctx, const float *const *dL_dout, float *d_mean
  * Both are device arrays owned by the caller (n floats, n int32), either may
  * be NULL; both NULL turns the statistics off.  `capacity` is their length:
  * a later backward with n > capacity fails with VGR_ERR_INVALID_ARG.  The
- * caller clears them (e.g. at each densification step).  Adds one pass over
+ * caller clears them (e.g. at each densification step).  A captured graph
+ * keeps the arrays (and the on/off state) that were set when it was
+ * captured; re-capture after changing them.  Adds one pass over
  * the per-view tile counts (4 bytes per Gaussian and view) to the backward.
  * VGR_ERR_INVALID_ARG for a negative capacity. */
 int vgr_set_densify_stats(vgr_ctx *ctx, float *grad_norm_sum, int32_t *view_count,
