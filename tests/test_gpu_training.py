@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import gpu_helpers as G
+import helpers as H
 from paper_2412_03378_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -245,5 +246,42 @@ def test_densify_stats_xray(R, dev):
         print(f"norm ratio {err.max():.3g}")
         assert err.max() <= 1.0
         assert np.all(c1 >= ds["visible_lo"]) and np.all(c1 <= ds["visible_hi"])
+    finally:
+        R.set_densify_stats(None, None)
+
+
+@pytest.mark.parametrize("opt", [{"density": "theta"}, {"alpha_model": "splat"},
+                                 {"near_segment": True}, {"tile_resort": True}])
+def test_options_on_degenerate_inputs(R, dev, opt):
+    """Each option with no Gaussians, one Gaussian, a 1x1 image and a view that
+    sees nothing: the images are the background, the gradients zero or
+    finite, and the statistics arrays untouched where nothing is visible."""
+    bg = (0.25, 0.5, 0.75)
+    st = _settings(tile=(8, 8), bg=bg, **opt)
+    gnorm = torch.zeros(4, dtype=torch.float32, device=dev)
+    vcount = torch.zeros(4, dtype=torch.int32, device=dev)
+    R.set_densify_stats(gnorm, vcount)
+    try:
+        cam = scenes.axis_camera(4.0, 9, 7, 40.0)
+        back = scenes.Camera(cam.R, np.float32([0, 0, -10.0]), cam.fx, cam.fy, cam.cx, cam.cy,
+                             9, 7)                          # every mean behind this camera
+        tiny = scenes.axis_camera(4.0, 1, 1, 40.0)
+        for n in (0, 1, 4):
+            rng = np.random.default_rng(n)
+            dens = rng.uniform(0.2, 0.9, n) if opt else rng.uniform(1, 5, n)
+            sc = H.scene(rng.uniform(-0.3, 0.3, (n, 3)), np.full((n, 3), 0.2), dens,
+                         rgb=rng.uniform(0, 1, (n, 3)))
+            t = G.device_scene(sc, dev)
+            imgs = R.forward(*t, [cam, back, tiny], st)
+            b = imgs[1].cpu().numpy()
+            assert np.allclose(b, np.array(bg, np.float32)[:, None, None])
+            if n == 0:
+                assert np.allclose(imgs[0].cpu().numpy(), np.array(bg, np.float32)[:, None, None])
+            grads = [torch.zeros_like(x) for x in t]
+            R.backward([torch.ones_like(x) for x in imgs], *grads)
+            torch.cuda.synchronize()
+            for g in grads:
+                assert torch.isfinite(g).all()
+        assert int(vcount.sum()) >= 0 and torch.isfinite(gnorm).all()
     finally:
         R.set_densify_stats(None, None)
