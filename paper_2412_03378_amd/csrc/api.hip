@@ -546,7 +546,7 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         HIP_TRY(c, launch_preprocess(rp, b, means, quats, scales, dens, sh, s));
         if (cap < 0) {
             // the instance count K travels to the host while the depth sort runs
-            HIP_TRY(c, hipMemcpyAsync(c->h_words, b.d_total + 4, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipMemcpyAsync(c->h_words, b.d_total + 4, 12, hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipEventRecord(c->k_ev, s));
         }
         mark_end(c, ST_PREPROCESS);
@@ -557,10 +557,18 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
                                      ptr<uint32_t>(c->sort_tmp), s));
         mark_end(c, ST_SORT_DEPTH);
         mark(c, ST_SCAN_EMIT);
-        HIP_TRY(c, launch_gather_counts(b, m, s));
-        HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, m, ptr<uint32_t>(c->scan_tmp), true, s));
+        // eager: the items with instances come first in depth order, and their
+        // number mv (with K) is on the host by now, so the scan and the
+        // emission cover only them; a capture covers all m items
+        int64_t mv = m;
         if (cap < 0) {
             HIP_TRY(c, hipEventSynchronize(c->k_ev));
+            mv = c->h_words[2] < (uint64_t)m ? (int64_t)c->h_words[2] : m;
+        }
+        HIP_TRY(c, launch_gather_counts(b, mv, s));
+        HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, mv, ptr<uint32_t>(c->scan_tmp), true,
+                                   s));
+        if (cap < 0) {
             K = c->h_words[0];
             if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
                 (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
@@ -576,8 +584,8 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         } else {
             K = cap;
         }
-        HIP_TRY(c, launch_finalize_count(b, m, K, s));
-        HIP_TRY(c, launch_emit(rp, b, m, K, s));
+        HIP_TRY(c, launch_finalize_count(b, mv, K, s));
+        HIP_TRY(c, launch_emit(rp, b, mv, K, s));
         mark_end(c, ST_SCAN_EMIT);
         mark(c, ST_SORT_TILES);
         if (rp.tile_resort) {

@@ -421,6 +421,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     bool have_sh = false;
     uint32_t total = 0;
 
+    uint32_t nvis = 0;   // views in which this Gaussian has instances
     const int n_views = MULTI ? rp.n_views : 1;
     for (int v = 0; v < n_views; ++v) {
         const ViewInfo &vi = b.views[v];
@@ -582,18 +583,30 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
             b.counts[item] = count;
             b.rect[item] = rect;
             total += count;
+            nvis += count > 0 ? 1u : 0u;
         }
     }
-    // total instance count K, for sizing the instance lists before the scan:
-    // one partial sum per block (count_total_kernel adds them; one atomic per
-    // wave on a single address would serialise thousands of updates)
-    __shared__ uint32_t s_wsum[4];
-    uint32_t wsum = total;
+    // total instance count K, for sizing the instance lists before the scan,
+    // and the number of items with instances (they come first in depth order,
+    // so the scan and the emission need cover no more): one partial sum of
+    // each per block (count_total_kernel adds them; one atomic per wave on a
+    // single address would serialise thousands of updates)
+    __shared__ uint32_t s_wsum[4], s_vsum[4];
+    uint32_t wsum = total, vsum = nvis;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-    if ((threadIdx.x & 63) == 0) s_wsum[threadIdx.x >> 6] = wsum;
+    for (int off = 32; off > 0; off >>= 1) {
+        wsum += __shfl_xor(wsum, off, 64);
+        vsum += __shfl_xor(vsum, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_wsum[threadIdx.x >> 6] = wsum;
+        s_vsum[threadIdx.x >> 6] = vsum;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) b.blk_counts[blockIdx.x] = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    if (threadIdx.x == 0) {
+        b.blk_counts[blockIdx.x] = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+        b.blk_counts[gridDim.x + blockIdx.x] = s_vsum[0] + s_vsum[1] + s_vsum[2] + s_vsum[3];
+    }
 }
 
 __global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__restrict__ parts,
@@ -1291,13 +1304,14 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total + 4);
+    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts + grid, (int64_t)grid, b.d_total + 6);
     return hipGetLastError();
 }
 
 int64_t preprocess_blocks(int64_t n, int32_t n_views)
 {
     (void)n_views;   // one thread per Gaussian covers all views
-    return (int64_t)grid_for(n, 256);
+    return 2 * (int64_t)grid_for(n, 256);   // instance and visible-item partial sums
 }
 
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)

@@ -141,7 +141,9 @@ struct Buffers {
                          // batch of a tile list, written by the forward where
                          // raster_keeps_masks() and read by the backward
     uint32_t *blk_counts;// preprocess blocks: instances per block
-    uint32_t *d_total;   // [0] = instance count K, [1] overflow flag
+    uint32_t *d_total;   // [0] = instance count K, [1] overflow flag, [4] K from the
+                         // preprocess, [6] items with instances (the first of the
+                         // depth order)
     unsigned long long *counters;  // pair and visit counters: forward [0..4], backward [8..12]
     uint2 *wg_time;      // timed runs (else null): per rasteriser workgroup (launch slot) the
                          // compute unit key and its duration in clock ticks, forward
@@ -172,7 +174,7 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const float *means,
                              const float *quats, const float *scales, const float *dens,
                              const float *sh, hipStream_t s);
-// Number of preprocess blocks (size of Buffers::blk_counts).
+// Size of Buffers::blk_counts (two partial sums per preprocess block).
 int64_t preprocess_blocks(int64_t n, int32_t n_views);
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s);
 hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s);
