@@ -622,12 +622,15 @@ __global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__rest
     if (threadIdx.x == 0) *out = s_part[0] + s_part[1] + s_part[2] + s_part[3];
 }
 
+// Tile counts in depth order.  Items past the nvis[0] that have instances
+// (they sort last) have none, so their counts are not gathered.
 __global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
                                      const uint32_t *__restrict__ counts,
+                                     const uint32_t *__restrict__ nvis,
                                      uint32_t *__restrict__ out, int64_t m)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m) out[j] = counts[sorted_items[j]];
+    if (j < m) out[j] = j < (int64_t)nvis[0] ? counts[sorted_items[j]] : 0u;
 }
 
 // Instance count K = offsets[m], clamped to the capacity (overflow flag).
@@ -694,6 +697,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buf
     __shared__ uint32_t s_wsum[kEmitThreads / 64];
     const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
+    // items past those with instances (they sort last) emit nothing (uniform)
+    if (j0 >= (int64_t)b.d_total[6]) return;
     const int64_t jend = min(j0 + 64, m);
     const uint32_t base = b.offsets[j0];
     if (tid < 64) {   // wave 0: the block's Gaussians and their candidate row counts
@@ -1316,7 +1321,8 @@ int64_t preprocess_blocks(int64_t n, int32_t n_views)
 
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)
 {
-    gather_counts_kernel<<<grid_for(m, 256), 256, 0, s>>>(b.item_ids, b.counts, b.cnt_sorted, m);
+    gather_counts_kernel<<<grid_for(m, 256), 256, 0, s>>>(b.item_ids, b.counts, b.d_total + 6,
+                                                          b.cnt_sorted, m);
     return hipGetLastError();
 }
 
