@@ -110,7 +110,7 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               1: within each tile, in ascending depth of each Gaussian's
  *               maximum along the ray through the tile's centre (the
  *               per-tile level of the re-sorting the paper points to against
- *               popping, Sec. 8; ties by mean depth, then index).  The image
+ *               popping, Sec. 7, Limitations; ties by mean depth, then index).  The image
  *               then depends on the tile shape (also on the one vgr_autotune
  *               picks when tile_w = tile_h = 0).  Costs one more 32-bit sort
  *               of the instances.  Colour mode, VOLUMETRIC [0]
@@ -158,6 +158,11 @@ typedef struct {
     double load_balance_bwd; /*   1: per compute unit, the summed durations  */
                              /*   of its raster workgroups, max over mean    */
                              /*   (1 = balanced; 0 if not timed)             */
+    int32_t emit_mismatch;   /* (Gaussian, view) items whose emitted tiles did */
+                             /*   not number exactly the tile count the       */
+                             /*   preprocess gave them (0 expected; a nonzero */
+                             /*   value is a library defect)                  */
+    int32_t _pad;
 } vgr_stats;
 
 typedef struct vgr_ctx vgr_ctx;
@@ -319,6 +324,7 @@ int vgr_autotune(vgr_ctx *ctx, const vgr_settings *settings, int64_t n, const fl
  * rasteriser uses to order (tile, depth); exposed for testing.  Equal keys
  * keep their input order.  VGR_ERR_INVALID_ARG, VGR_ERR_OOM, VGR_ERR_HIP. */
 int vgr_sort_pairs(vgr_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits);
+
 
 #ifdef __cplusplus
 }

@@ -57,7 +57,8 @@ class _Settings(C.Structure):
                 ("tile_resort", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("pad2", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
-                ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3)]
+                ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3),
+                ("near_threshold", C.c_double)]
 
 
 @dataclass
@@ -200,9 +201,18 @@ def render(scene, cam, settings: Settings = None, pixels=None):
     """Render one view.  ``pixels``: (P, 2) int array of (x, y), or None for
     the whole image.  Returns dict with ``image`` ((C, P) or (C, H, W)),
     ``T`` (final transmittance), ``last`` (index of the last blended
-    Gaussian, -1 if none), ``nblend``, ``margin`` (smallest relative
-    distance of any deciding test to its threshold) and ``untrunc`` (X-ray
-    sum without the x_min cut)."""
+    Gaussian, -1 if none), ``nblend``, the decision margins and ``untrunc``
+    (X-ray sum without the x_min cut).
+
+    Decision margins (vgr_oracle.c, dec_margin): ``margin_x`` is the smallest,
+    over the tests of x or alpha against a threshold (skip, clamp, X-ray cut),
+    of the relative distance to the threshold divided by the amplification of
+    that value's FP32 rounding error (1 + D^2/2 for a line integral);
+    ``margin_T`` the same for the termination tests T (1 - alpha) < T_min
+    (amplification: the summed amplifications of the factors of T);
+    ``margin_order`` (per-tile re-sorting only, else inf) the smallest
+    relative gap between the order keys of two Gaussians that reach the
+    pixel."""
     lib = _load()
     st = settings or Settings()
     full = pixels is None
@@ -214,7 +224,7 @@ def render(scene, cam, settings: Settings = None, pixels=None):
     T = np.zeros(P, np.float64)
     last = np.zeros(P, np.int64)
     nblend = np.zeros(P, np.int32)
-    margin = np.zeros(P, np.float64)
+    margin = np.zeros((P, 3), np.float64)
     untrunc = np.zeros(P, np.float64)
     cam_s, set_s = _cam(cam), _settings(st, scene.sh_degree)
     rc = lib.orc_render(int(means.shape[0]), _ptr(means, C.c_float), _ptr(quats, C.c_float),
@@ -225,25 +235,34 @@ def render(scene, cam, settings: Settings = None, pixels=None):
                         _ptr(untrunc, C.c_double))
     if rc:
         raise RuntimeError(f"orc_render failed ({rc})")
-    res = dict(image=out.T.copy(), T=T, last=last, nblend=nblend, margin=margin,
-               untrunc=untrunc, pixels=pix)
+    res = dict(image=out.T.copy(), T=T, last=last, nblend=nblend,
+               margin_x=margin[:, 0].copy(), margin_T=margin[:, 1].copy(),
+               margin_order=margin[:, 2].copy(), untrunc=untrunc, pixels=pix)
     if full:
         H, W = int(cam.height), int(cam.width)
         res["image"] = res["image"].reshape(nch, H, W)
-        for k in ("T", "last", "nblend", "margin", "untrunc"):
+        for k in ("T", "last", "nblend", "margin_x", "margin_T", "margin_order", "untrunc"):
             res[k] = res[k].reshape(H, W)
     return res
 
 
-def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=True):
+def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=True,
+                    near_threshold=0.0):
     """Gradients of sum(dL * image) w.r.t. means, quats, scales, dens, sh for
     one view.  ``dL`` is (C, P) for a pixel list or (C, H, W) for the whole
     image.  Returns dict of FP64 gradients and, if ``with_abs``, the sums of
     absolute per-pixel contributions (``abs_*``) and the FP32 error scales
     (``err_*``: the same sums without cancellation of the upstream factor,
-    each pair weighted by its rounding amplification) used for tolerances."""
+    each pair weighted by its rounding amplification) used for tolerances.
+
+    ``near_threshold`` > 0 (X-ray mode only): chain only the pairs whose cut
+    decision has a margin (as ``margin_x`` of render) below it, on either side
+    of the cut; ``abs_*`` then bounds what flipping those decisions can change
+    in each gradient element."""
     lib = _load()
     st = settings or Settings()
+    if near_threshold > 0 and st.mode != "xray":
+        raise ValueError("near_threshold applies to X-ray mode only")
     full = pixels is None
     pix = all_pixels(cam) if full else np.ascontiguousarray(np.asarray(pixels, np.int32))
     P = pix.shape[0]
@@ -257,6 +276,7 @@ def render_backward(scene, cam, settings: Settings, dL, pixels=None, with_abs=Tr
     absg = {k: (np.zeros(s, np.float64) if with_abs else None) for k, s in shapes.items()}
     errg = {k: (np.zeros(s, np.float64) if with_abs else None) for k, s in shapes.items()}
     cam_s, set_s = _cam(cam), _settings(st, scene.sh_degree)
+    set_s.near_threshold = float(near_threshold)
     keys = ("means", "quats", "scales", "dens", "sh")
     rc = lib.orc_render_backward(
         int(n), _ptr(means, C.c_float), _ptr(quats, C.c_float), _ptr(scales, C.c_float),

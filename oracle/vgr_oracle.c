@@ -47,17 +47,19 @@
  *     its tile_w x tile_h screen tile (the position of each Gaussian's maximum
  *     along that ray; ties by the depth key, then the index): the per-tile
  *     level of the re-sorting that the paper points to against popping
- *     (Sec. 8).  A pixel whose order rests on two keys closer than 1e-5
- *     (relative) reports it in its decision margin (scaled by 100).
+ *     (Sec. 7, Limitations).  Each pixel reports the smallest relative gap
+ *     between the keys of two Gaussians that reach it as its order margin.
  *   - the density input is kappa itself, or theta with the reparameterisation
  *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
  *     density_reparam); theta outside the paper's range [0, 1] is clamped to
  *     it, with zero gradient outside.
  *
  * Decision margins: for every threshold test that decides the output (skip,
- * clamp, terminate) the oracle reports the smallest relative distance to the
- * threshold, so callers can set aside pixels where two results are both
- * correct up to rounding.
+ * clamp, X-ray cut; terminate) the oracle reports the smallest relative
+ * distance to the threshold in units of that value's FP32 error amplification
+ * (see dec_margin), and under tile_resort the smallest relative gap between
+ * the order keys of two Gaussians that reach the pixel, so callers can set
+ * aside pixels where two results are both correct up to rounding.
  *
  * The backward pass is the analytic chain rule of the same formulas, with the
  * transmittance in front of each Gaussian taken from forward prefix products.
@@ -93,6 +95,8 @@ typedef struct {
     int32_t pad2;
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
+    double near_threshold; /* > 0, X-ray backward only: chain just the pairs whose
+                              x-decision margin is below this value (see orc_render_backward) */
 } orc_settings;
 
 /* ------------------------------------------------------------------------ */
@@ -137,6 +141,7 @@ typedef struct {
     double gamma, beta, Gmax, x;
     double v[3];     /* mu - (o + gamma d) */
     double a;        /* d^T P d */
+    double D2;       /* v^T P v, the minimum Mahalanobis distance squared of the ray */
 } ray_terms;
 
 static void ray_integral(const double mu[3], const double P[9], double kappa,
@@ -152,7 +157,9 @@ static void ray_integral(const double mu[3], const double P[9], double kappa,
         xp[k] = o[k] + gamma * d[k];
         diff[k] = xp[k] - mu[k];
     }
-    double Gmax = exp(-0.5 * quad_form(P, diff, diff));
+    const double D2 = quad_form(P, diff, diff);
+    double Gmax = exp(-0.5 * D2);
+    rt->D2 = D2;
     rt->gamma = gamma;
     rt->beta = beta;
     rt->Gmax = Gmax;
@@ -282,6 +289,7 @@ typedef struct {
     double *raw;         /* n x 3 colour before activation */
     double *kappa;       /* n densities kappa */
     double *splat;       /* alpha_model 1: n x 6 (mu'_x, mu'_y, C00, C01, C11, o) */
+    double *aniso;       /* n: s_max / s_min (error amplification, see dec_margin) */
     double o[3];
     double zrow[3];      /* view-space depth axis in world coordinates (third row of R) */
     double znear;
@@ -472,7 +480,9 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
     vs->rgb = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     vs->raw = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     vs->kappa = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw || !vs->kappa) return -3;
+    vs->aniso = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!vs->order || !vs->key || !vs->P || !vs->rgb || !vs->raw || !vs->kappa || !vs->aniso)
+        return -3;
     if (st->alpha_model == 1) {
         vs->splat = (double *)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
         if (!vs->splat) return -3;
@@ -488,6 +498,12 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
         quat_rotation(quats + 4 * i, R, NULL, NULL);
         precision_matrix(R, scales + 3 * i, vs->P + 9 * i);
         vs->kappa[i] = kappa_of(st, dens[i], scales + 3 * i);
+        {
+            const float *sc = scales + 3 * i;
+            const double smax = fmax(sc[0], fmax(sc[1], sc[2]));
+            const double smin = fmin(sc[0], fmin(sc[1], sc[2]));
+            vs->aniso[i] = smax / smin;
+        }
         if (vs->splat) splat_setup(cam, means + 3 * i, R, scales + 3 * i, dens[i], vs->splat + 6 * i);
         vs->key[i] = depth_key(cam, means + 3 * i);
         if (st->mode == 0) {
@@ -515,12 +531,48 @@ static int view_setup(view_state *vs, int64_t n, const float *means, const float
 static void view_free(view_state *vs)
 {
     free(vs->order); free(vs->key); free(vs->P); free(vs->rgb); free(vs->raw); free(vs->kappa);
-    free(vs->splat);
+    free(vs->splat); free(vs->aniso);
 }
 
-static double rel_margin(double v, double thr)
+/* Decision margins.  A test of a computed value v against a threshold can go
+   the other way in an FP32 implementation only if the relative rounding error
+   of v reaches |v - thr| / |v|.  That error is a few units of roundoff times
+   an amplification factor `amp' that depends on the decision: for a line
+   integral x = kappa sqrt(2 pi) beta exp(-D^2/2), a relative error e in D^2
+   becomes D^2 e/2 in x, and a rotation error of angle e (the rounding of a
+   rotation matrix) changes D^2 by up to about D^2 e s_max/s_min for a Gaussian
+   with scales s, so amp = 1 + (D^2/2) s_max/s_min (plus, with the near-plane
+   factor Phi(eta), h(eta) (|gamma| + t_n)/beta, h = phi/Phi, for an error in
+   eta proportional to the lengths it is formed from); for the splatting
+   opacity alpha = o exp(-q/2), with q from the inverse of a 2x2 covariance
+   whose rounding is amplified by its condition number c, amp = 1 + c q/2;
+   for the transmittance T (1 - alpha_i) after a run of blends, the
+   amplifications of its factors 1 - alpha_j (x_j times the amplification of
+   x_j, or alpha_j/(1 - alpha_j) times that of a splat's alpha_j, 0 for a
+   clamped alpha), each plus one rounding for the product, combined as a
+   root sum of squares: the roundings of different factors are independent,
+   so their sum grows like a random walk (the probabilistic rounding-error
+   analysis of Higham and Mary, SIAM J. Sci. Comput. 2019) rather than like
+   the worst-case sum.  The margin
+   reported is |v - thr| / (|v| amp): the relative distance in units of the
+   amplified error, so one bound in units of roundoff decides which pixels
+   have two correct results. */
+static double dec_margin(double v, double thr, double amp)
 {
-    return fabs(v - thr) / fabs(thr);
+    if (v == 0.0) return v == thr ? 0.0 : INFINITY;
+    return fabs(v - thr) / (fabs(v) * amp);
+}
+
+/* amplification of the line integral's relative error (see dec_margin) */
+static double x_amp(const ray_terms *rt, double aniso, int near, double eta, double tn)
+{
+    double amp = 1.0 + 0.5 * rt->D2 * aniso;
+    if (near) {
+        const double Phi = norm_cdf(eta);
+        const double h = Phi > 0 ? norm_pdf(eta) / Phi : fabs(eta);
+        amp += h * (fabs(rt->gamma) + tn) / rt->beta;
+    }
+    return amp;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -605,13 +657,17 @@ static void list_push(blend_list *bl, blend_rec r)
     bl->rec[bl->cnt++] = r;
 }
 
-/* Composite one pixel; fills out[3] (colour) or out[0] (X-ray). */
+/* Composite one pixel; fills out[3] (colour) or out[0] (X-ray).  margin_out
+   (if given) receives two decision margins (see dec_margin): [0] the smallest
+   over the tests on x or alpha (skip, clamp, X-ray cut), [1] the smallest over
+   the termination tests T (1 - alpha) < T_min. */
 static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st,
                         const double d[3], const double pc[2], double *out,
                         double *T_out, int64_t *last_out, int32_t *nblend_out,
                         double *margin_out, double *untrunc_out, blend_list *bl)
 {
-    double margin = INFINITY;
+    double mx = INFINITY, mT = INFINITY;
+    const double tn = st->near_segment ? near_t(vs->zrow, vs->znear, d) : 0.0;
     if (st->mode == 1) {
         /* X-ray: sum of line integrals, every visible Gaussian, any order */
         double I = 0, full = 0;
@@ -621,11 +677,12 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_terms rt;
             ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
-            if (st->near_segment)
-                rt.x *= norm_cdf((rt.gamma - near_t(vs->zrow, vs->znear, d)) / rt.beta);
+            const double eta = (rt.gamma - tn) / rt.beta;
+            if (st->near_segment) rt.x *= norm_cdf(eta);
             full += rt.x;
-            double m = rel_margin(rt.x, st->x_min_xray);
-            if (m < margin) margin = m;
+            double m = dec_margin(rt.x, st->x_min_xray,
+                                  x_amp(&rt, vs->aniso[i], st->near_segment, eta, tn));
+            if (m < mx) mx = m;
             if (rt.x >= st->x_min_xray) {
                 I += rt.x;
                 ++cnt;
@@ -639,48 +696,59 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
         if (T_out) *T_out = exp(-I);
         if (last_out) *last_out = -1;
         if (nblend_out) *nblend_out = cnt;
-        if (margin_out) *margin_out = margin;
+        if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; }
         if (untrunc_out) *untrunc_out = full;
         return;
     }
     double tau = -log1p(-st->alpha_min);
     double xmax = -log1p(-st->alpha_max);
     double T = 1.0, C[3] = { 0, 0, 0 };
+    double ampT2 = 0.0;  /* sum of squared amplifications of T's factors so far */
     int64_t last = -1;
     int32_t cnt = 0;
     for (int64_t r = 0; r < vs->nvis; ++r) {
         int64_t i = vs->order[r];
-        double alpha, m;
+        double alpha, m, amp_om;
         ray_terms rt;
         if (vs->splat) {
             /* alpha = o exp(-1/2 dp^T C dp), dp = pixel centre - mu' */
             const double *sp = vs->splat + 6 * i;
             const double dx = pc[0] - sp[0], dy = pc[1] - sp[1];
-            alpha = sp[5] * exp(-0.5 * (sp[2] * dx * dx + 2.0 * sp[3] * dx * dy + sp[4] * dy * dy));
+            const double q = sp[2] * dx * dx + 2.0 * sp[3] * dx * dy + sp[4] * dy * dy;
+            alpha = sp[5] * exp(-0.5 * q);
             rt.x = -log1p(-alpha);
-            m = rel_margin(alpha, st->alpha_min);
-            if (m < margin) margin = m;
+            /* condition number of the 2x2 conic */
+            const double tr = 0.5 * (sp[2] + sp[4]);
+            const double dd = sqrt(0.25 * (sp[2] - sp[4]) * (sp[2] - sp[4]) + sp[3] * sp[3]);
+            const double cond = (tr + dd) / fmax(tr - dd, 1e-300 * (tr + dd));
+            const double amp = 1.0 + 0.5 * q * cond;
+            m = dec_margin(alpha, st->alpha_min, amp);
+            if (m < mx) mx = m;
             if (alpha < st->alpha_min) continue;
-            m = rel_margin(alpha, st->alpha_max);
-            if (m < margin) margin = m;
+            m = dec_margin(alpha, st->alpha_max, amp);
+            if (m < mx) mx = m;
+            amp_om = alpha < st->alpha_max ? alpha / (1.0 - alpha) * amp : 0.0;
         } else {
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
-            if (st->near_segment)
-                rt.x *= norm_cdf((rt.gamma - near_t(vs->zrow, vs->znear, d)) / rt.beta);
-            m = rel_margin(rt.x, tau);
-            if (m < margin) margin = m;
+            const double eta = (rt.gamma - tn) / rt.beta;
+            if (st->near_segment) rt.x *= norm_cdf(eta);
+            const double amp = x_amp(&rt, vs->aniso[i], st->near_segment, eta, tn);
+            m = dec_margin(rt.x, tau, amp);
+            if (m < mx) mx = m;
             if (rt.x < tau) continue;                  /* alpha < alpha_min */
             alpha = -expm1(-rt.x);
-            m = rel_margin(rt.x, xmax);
-            if (m < margin) margin = m;
+            m = dec_margin(rt.x, xmax, amp);
+            if (m < mx) mx = m;
+            amp_om = rt.x < xmax ? rt.x * amp : 0.0;
         }
         int clamped = 0;
         if (alpha > st->alpha_max) { alpha = st->alpha_max; clamped = 1; }
         double Tn = T * (1.0 - alpha);
         if (st->T_min > 0) {
-            m = rel_margin(Tn, st->T_min);
-            if (m < margin) margin = m;
+            m = dec_margin(Tn, st->T_min,
+                           1.0 + sqrt(ampT2 + (amp_om + 1.0) * (amp_om + 1.0)));
+            if (m < mT) mT = m;
         }
         if (Tn < st->T_min) break;                     /* stop before blending i */
         for (int ch = 0; ch < 3; ++ch) C[ch] += vs->rgb[3 * i + ch] * alpha * T;
@@ -689,6 +757,7 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             list_push(bl, br);
         }
         T = Tn;
+        ampT2 += (amp_om + 1.0) * (amp_om + 1.0);
         last = i;
         ++cnt;
     }
@@ -696,7 +765,7 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
     if (T_out) *T_out = T;
     if (last_out) *last_out = last;
     if (nblend_out) *nblend_out = cnt;
-    if (margin_out) *margin_out = margin;
+    if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; }
     if (untrunc_out) *untrunc_out = 0;
 }
 
@@ -729,12 +798,10 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
         }
         shade_pixel(&vp, means, st, d, pc, out + C * p, T_out ? T_out + p : NULL,
                     last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
-                    margin_out ? margin_out + p : NULL, untrunc_out ? untrunc_out + p : NULL,
-                    NULL);
-        if (st->tile_resort) {
-            if (margin_out && 100.0 * ogap < margin_out[p]) margin_out[p] = 100.0 * ogap;
-            free(vp.order);
-        }
+                    margin_out ? margin_out + 3 * p : NULL,
+                    untrunc_out ? untrunc_out + p : NULL, NULL);
+        if (margin_out) margin_out[3 * p + 2] = ogap;
+        if (st->tile_resort) free(vp.order);
     }
     view_free(&vs);
     return 0;
@@ -820,7 +887,7 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
         Pv[r] = P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2];
         D2 += rt.v[r] * Pv[r];
     }
-    const double ge = gabs * (1.0 + 0.5 * D2 + w_extra);
+    const double ge = gabs * (1.0 + 0.5 * D2 * vs->aniso[i] + w_extra);
     const double dx_dk = sqrt(2 * ORC_PI) * rt.beta * rt.Gmax * Phi;
     double dk_din, dk_ds[3];
     kappa_grad(st, dens[i], scales + 3 * i, &dk_din, dk_ds);
@@ -891,7 +958,14 @@ static void chain_colour(int64_t i, const double gc[3], double w, const view_sta
         double graw = gc[ch] * act_grad(st->act, vs->raw[3 * i + ch]);
         for (int k = 0; k < nb; ++k) {
             size_t e = ((size_t)i * nb + k) * 3 + ch;
-            add3(go->g_sh, go->a_sh, go->e_sh, (int64_t)e, Y[k], graw, w * graw);
+            /* FP32 evaluation of Y_k at a direction known to a few units of
+               roundoff errs by about u (|Y_k| + |grad Y_k|), not u |Y_k|: near
+               a nodal line of Y_k its relative error is unbounded */
+            const double yk_mag = fabs(Y[k]) + sqrt(dY[3 * k] * dY[3 * k] + dY[3 * k + 1] * dY[3 * k + 1] +
+                                                    dY[3 * k + 2] * dY[3 * k + 2]);
+            atomic_add(go->g_sh + e, graw * Y[k]);
+            if (go->a_sh) atomic_add(go->a_sh + e, fabs(graw * Y[k]));
+            if (go->e_sh) atomic_add(go->e_sh + e, fabs(w * graw) * yk_mag);
             for (int j = 0; j < 3; ++j) {
                 gv[j] += graw * sh[e] * dY[3 * k + j];
                 gva[j] += fabs(graw * sh[e] * dY[3 * k + j]);
@@ -1070,7 +1144,9 @@ static double pair_D2(int64_t i, const float *means, const float *quats, const f
 }
 
 /* Error scales (e_*): the contribution of each blended pair is weighted by
-   1 + D^2/2 (the exponential's amplification of a relative error in D^2) plus,
+   1 + (D^2/2) s_max/s_min (the exponential's amplification of a relative
+   error in D^2, which a rounded rotation makes up to s_max/s_min times the
+   rotation's error; see dec_margin) plus,
    in colour mode, the number of compositing steps between the pair and the end
    of the pixel's list (a reverse replay of T and the colour behind carries one
    rounding per step); the upstream factor dL/dalpha is taken as
@@ -1088,6 +1164,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
     if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
     if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
         return -1;
+    if (st->near_threshold > 0 && st->mode != 1) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -1108,6 +1185,28 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
             vp.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(vs.nvis > 0 ? vs.nvis : 1));
             resort_order(&vs, means, cam, st, pix[2 * p], pix[2 * p + 1], d,
                          -log1p(-st->alpha_min), vp.order);
+        }
+        if (st->mode == 1 && st->near_threshold > 0) {
+            /* only the pairs whose X-ray cut decision lies within the given
+               margin, on either side of the cut: their summed |contributions|
+               (the abs_* output) bound what flipping those decisions can
+               change in each gradient element */
+            const double tn = st->near_segment ? near_t(vs.zrow, vs.znear, d) : 0.0;
+            for (int64_t r = 0; r < vs.nvis; ++r) {
+                const int64_t i = vs.order[r];
+                const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
+                ray_terms rt;
+                ray_integral(mu, vs.P + 9 * i, vs.kappa[i], vs.o, d, &rt);
+                const double eta = (rt.gamma - tn) / rt.beta;
+                if (st->near_segment) rt.x *= norm_cdf(eta);
+                const double m = dec_margin(rt.x, st->x_min_xray,
+                                            x_amp(&rt, vs.aniso[i], st->near_segment, eta, tn));
+                if (m < st->near_threshold)
+                    chain_integral(i, g[0], fabs(g[0]), 0.0, means, quats, scales, dens, st, &vs,
+                                   d, &go);
+            }
+            if (st->tile_resort) free(vp.order);
+            continue;
         }
         shade_pixel(&vp, means, st, d, pc, out, NULL, NULL, NULL, NULL, NULL, &bl);
         if (st->mode == 1) {
@@ -1142,7 +1241,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                         chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales,
                                        dens, st, &vs, d, &go);
                     if (go.e_means || go.e_sh)
-                        w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d);
+                        w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d) * vs.aniso[i];
                 }
                 chain_colour(i, gc, w, &vs, means, sh, st, &go);
                 for (int ch = 0; ch < 3; ++ch)

@@ -52,7 +52,8 @@ class vgr_stats(C.Structure):
                 ("bwd_visits", C.c_int64), ("bwd_visits_full", C.c_int64),
                 ("overflow", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("n_views", C.c_int32),
-                ("load_balance_fwd", C.c_double), ("load_balance_bwd", C.c_double)]
+                ("load_balance_fwd", C.c_double), ("load_balance_bwd", C.c_double),
+                ("emit_mismatch", C.c_int32), ("_pad", C.c_int32)]
 
 
 class VgrError(RuntimeError):

@@ -757,12 +757,13 @@ int vgr_get_stats(vgr_ctx *c, vgr_stats *out)
     memset(out, 0, sizeof *out);
     if (!c->have_fwd) return fail(c, VGR_ERR_NO_FORWARD, "no forward");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    uint32_t words[2];
+    uint32_t words[8];
     HIP_TRY(c, hipMemcpy(words, c->words.p, sizeof words, hipMemcpyDeviceToHost));
     unsigned long long cnt[16] = {};
     if (c->counting) HIP_TRY(c, hipMemcpy(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost));
     out->instances = words[0];
     out->overflow = (int32_t)words[1];
+    out->emit_mismatch = c->rp.n > 0 && c->rp.n_views > 0 ? (int32_t)words[7] : 0;
     out->capacity = c->inst_capacity;
     out->pairs_tested = (int64_t)cnt[0];
     out->pairs_full = (int64_t)cnt[1];

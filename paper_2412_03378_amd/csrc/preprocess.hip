@@ -642,6 +642,7 @@ __global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int6
         d_total[0] = (int64_t)K > capacity ? (uint32_t)capacity : K;
         d_total[1] = (int64_t)K > capacity ? 1u : 0u;
         if ((int64_t)K > capacity) d_total[5] = 1u;   // sticky until the host clears it
+        d_total[7] = 0u;   // items whose emission will not match their count (emit_kernel)
     }
 }
 
@@ -695,6 +696,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buf
     __shared__ uint32_t s_rtile[kEmitRows];        // tile row << 16 | first tile column
     __shared__ uint8_t s_rg[kEmitRows];            // owning Gaussian (0..63)
     __shared__ uint32_t s_wsum[kEmitThreads / 64];
+    __shared__ uint32_t s_gemit[64];               // instances found per Gaussian
     const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
     // items past those with instances (they sort last) emit nothing (uniform)
@@ -719,6 +721,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buf
             rows = (uint32_t)rect.w - (uint32_t)rect.y + 1u;
         }
         s_item[tid] = item;
+        s_gemit[tid] = 0u;
         s_rect[tid] = rect;
         s_cull[tid] = cr;
         s_toff[tid] = toff;
@@ -758,6 +761,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buf
                 int t0 = 0, t1 = -1;
                 if (cull_row(s_cull[lo], row, rp.tile_w, rp.tile_h, rect.x, rect.z, t0, t1))
                     cnt[i] = (uint32_t)(t1 - t0 + 1);
+                if (cnt[i]) atomicAdd(&s_gemit[lo], cnt[i]);
                 s_rtile[rl] = ((uint32_t)row << 16) | (uint32_t)(t0 & 0xFFFF);
                 s_rg[rl] = (uint8_t)lo;
             }
@@ -797,6 +801,14 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buf
         }
         done += chunk;
         __syncthreads();   // the next chunk rewrites the row tables
+    }
+    // every Gaussian must have produced exactly the tile count the preprocess
+    // gave it (which sized the lists): count the items that did not
+    if (tid < 64) {
+        const int64_t j = j0 + tid;
+        const uint32_t want = j < m ? b.offsets[j + 1] - b.offsets[j] : 0u;
+        const uint64_t bad = __builtin_amdgcn_ballot_w64(s_gemit[tid] != want);
+        if (tid == 0 && bad != 0) atomicAdd(&b.d_total[7], (uint32_t)__builtin_popcountll(bad));
     }
 }
 

@@ -5,6 +5,8 @@ library; this module only marshals pointers, shapes and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import threading
+import weakref
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -91,6 +93,10 @@ class Renderer:
         self.n_views = 0
         self.shapes = []
         self.mode = "color"
+        # forwards run so far: an autograd node remembers the number of its
+        # own forward and refuses to differentiate another one
+        self.generation = 0
+        self._owner = None   # weak reference to the autograd node holding this context
 
     def close(self):
         if getattr(self, "_h", None):
@@ -127,6 +133,7 @@ class Renderer:
             self._h, C.byref(st), n, _dev_ptr(means), _dev_ptr(quats), _dev_ptr(scales),
             _dev_ptr(dens), _dev_ptr(sh) if settings.mode != "xray" else None, ncam, cam_arr,
             out_ptrs)
+        self.generation += 1
         L.check(rc, self._h)
         self.n_views = ncam
         self.shapes = [tuple(o.shape) for o in outs]
@@ -250,11 +257,19 @@ class Renderer:
         L.check(rc, self._h)
 
 
+class _NodeToken:
+    """Held by one autograd node; the context it uses stays reserved while
+    the token is alive (until the backward ran or the graph was freed)."""
+
+
 class _VolRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer, settings, cams, means, quats, scales, dens, sh):
         outs = renderer.forward(means, quats, scales, dens, sh, cams, settings)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
+        ctx.token = _NodeToken()
+        renderer._owner = weakref.ref(ctx.token)
         ctx.settings = settings
         ctx.save_for_backward(means, quats, scales, dens, sh if sh is not None else torch.empty(0))
         ctx.has_sh = sh is not None and settings.mode != "xray"
@@ -262,6 +277,12 @@ class _VolRender(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, *gouts):
+        r = ctx.renderer
+        if r.generation != ctx.generation:
+            raise RuntimeError(
+                "this render's context has run another forward since (the library keeps the "
+                "state of the last forward only); give each render that is differentiated "
+                "later its own Renderer, or let render() pick one")
         means, quats, scales, dens, sh = ctx.saved_tensors
         gm = torch.empty_like(means)
         gq = torch.empty_like(quats)
@@ -269,18 +290,44 @@ class _VolRender(torch.autograd.Function):
         gd = torch.empty_like(dens)
         gsh = torch.empty_like(sh) if ctx.has_sh else None
         gl = [g if g is not None else torch.zeros(s, device=means.device)
-              for g, s in zip(gouts, ctx.renderer.shapes)]
-        ctx.renderer.backward(gl, gm, gq, gs, gd, gsh, accumulate=False)
+              for g, s in zip(gouts, r.shapes)]
+        r.backward(gl, gm, gq, gs, gd, gsh, accumulate=False)
+        r._owner = None
         return None, None, None, gm, gq, gs, gd, gsh
+
+
+_POOL = {}
+_POOL_LOCK = threading.Lock()
+
+
+def _pooled_renderer(device: int) -> Renderer:
+    """A context of this device that no live autograd node holds: contexts
+    (and their workspaces) are reused from call to call instead of being
+    created per render."""
+    with _POOL_LOCK:
+        pool = _POOL.setdefault(device, [])
+        for r in pool:
+            if r._owner is None or r._owner() is None:
+                r._owner = None
+                return r
+        r = Renderer(device)
+        pool.append(r)
+        return r
 
 
 def render(means, quats, scales, dens, sh, cams, settings: Settings = None,
            renderer: Renderer = None):
     """Differentiable render of ``cams``; returns a tuple of per-view images.
-    A renderer keeps the state of one forward for its backward: pass one per
-    in-flight graph node (a fresh one is made when none is given)."""
+
+    A context keeps the state of one forward for its backward.  Without a
+    ``renderer``, one is taken from a per-device pool of contexts that no
+    pending autograd node holds (a node releases its context when its
+    backward has run or its graph is freed), so repeated training steps reuse
+    the same workspace.  A given ``renderer`` is used as is; a backward whose
+    context has run another forward since raises instead of returning the
+    other forward's gradients."""
     settings = settings or Settings()
-    renderer = renderer or Renderer(means.device.index or 0)
+    renderer = renderer or _pooled_renderer(means.device.index or 0)
     return _VolRender.apply(renderer, settings, list(cams), means.contiguous(),
                             quats.contiguous(), scales.contiguous(), dens.contiguous(),
                             None if sh is None else sh.contiguous())

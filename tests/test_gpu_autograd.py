@@ -48,3 +48,34 @@ def test_autograd_matches_explicit_backward(mode, opt):
             continue
         assert np.allclose(a.grad.cpu().numpy(), b.cpu().numpy(), rtol=1e-4,
                            atol=1e-6 * float(b.abs().max()) + 1e-12)
+
+
+def test_render_reuses_pooled_contexts_and_refuses_foreign_backward():
+    """render() without a renderer takes a pooled context: two pending nodes
+    hold two contexts, and after their backwards the next render reuses one
+    of them.  A node whose explicit renderer has run another forward since
+    refuses to differentiate (the library keeps only the last forward)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2412_03378_amd import Renderer, Settings, render
+    from paper_2412_03378_amd import renderer as RM
+    dev = torch.device("cuda", 0)
+    wl = scenes.config1(n=200, width=24, height=16)
+    st = Settings(tile=(8, 8))
+    t = [x.clone().requires_grad_(True) for x in G.device_scene(wl.scene, dev)]
+    a = render(*t, wl.cams, st)
+    b = render(*t, wl.cams, st)
+    ra, rb = a[0].grad_fn.renderer, b[0].grad_fn.renderer
+    assert ra is not rb
+    (a[0].sum() + b[0].sum()).backward()
+    c = render(*t, wl.cams, st)
+    assert c[0].grad_fn.renderer in (ra, rb)
+    assert len(RM._POOL[0]) >= 2
+    c[0].sum().backward()
+    # one explicit context, two forwards, backward of the first: refused
+    r = Renderer(0)
+    first = render(*t, wl.cams, st, renderer=r)
+    render(*t, wl.cams, st, renderer=r)
+    with pytest.raises(RuntimeError, match="another forward"):
+        first[0].sum().backward()
+    r.close()

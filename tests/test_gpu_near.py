@@ -69,26 +69,18 @@ def _check(R, dev, sc, cams, st, seed):
     for v, cam in enumerate(cams):
         ref = oracle.render(sc, cam, ost)
         img = imgs[v].cpu().numpy()
-        e_ok, nflag, e_flag = G.compare_image(img[None] if xray else img, ref["image"],
-                                              ref["margin"], xray=xray)
-        print(f"view {v}: err {e_ok:.3g} flagged {nflag} ({e_flag:.3g})")
-        assert e_ok <= (G.XRAY_REL if xray else G.IMG_TOL) and e_flag <= G.FLIP_TOL
-        nch = 1 if xray else 3
-        dLs.append(rng.standard_normal((nch, cam.height, cam.width)) * (ref["margin"] > G.MARGIN))
-    keys = ("means", "quats", "scales", "dens") + (() if xray else ("sh",))
+        G.check_image(img[None] if xray else img, ref, xray=xray, label=f"view {v}: ")
+        dLs.append(G.upstream(rng, ref, 1 if xray else 3, xray))
+    keys = G.GRAD_KEYS[:4] if xray else G.GRAD_KEYS
     grads = [torch.zeros_like(x) for x in t[:len(keys)]]
     R.backward([torch.from_numpy((d[0] if xray else d).astype(np.float32)).to(dev) for d in dLs],
                *grads, *([None] if xray else []))
     torch.cuda.synchronize()
     per = [oracle.render_backward(sc, cam, ost, d) for cam, d in zip(cams, dLs)]
-    worst = {}
-    for k, g in zip(keys, grads):
-        ref = sum(p[k] for p in per)
-        absr = sum(p["abs_" + k] for p in per)
-        errr = sum(p["err_" + k] for p in per)
-        worst[k] = G.grad_errors(g.cpu().numpy(), ref, absr, errr)
-        print(k, f"ratio {worst[k]:.3g}", G.grad_worst(g.cpu().numpy(), ref, absr, errr))
-    assert max(worst.values()) <= 1.0, worst
+    flips = ([oracle.render_backward(sc, cam, ost, d, near_threshold=G.MARGIN_X)
+              for cam, d in zip(cams, dLs)] if xray else None)
+    G.check_grads({k: g.cpu().numpy() for k, g in zip(keys, grads)},
+                  G.sum_backward(per, keys, flips))
     return imgs
 
 

@@ -46,10 +46,7 @@ def _check_views(R, dev, sc, cams, st):
     for v, cam in enumerate(cams):
         ref = oracle.render(sc, cam, _oset(st))
         img = imgs[v].cpu().numpy()
-        e_ok, nflag, e_flag = G.compare_image(img, ref["image"], ref["margin"])
-        print(f"view {v} {cam.width}x{cam.height}: err {e_ok:.3g} flagged {nflag} ({e_flag:.3g}) "
-              f"mean {img.mean():.4f}")
-        assert e_ok <= G.IMG_TOL and e_flag <= G.FLIP_TOL
+        G.check_image(img, ref, label=f"view {v} {cam.width}x{cam.height} mean {img.mean():.4f}: ")
         assert np.abs(img - ref["image"]).max() > 0 or img.max() > 0
         out.append(img)
     return out
@@ -109,20 +106,13 @@ def _grad_check(R, dev, sc, cams, st, seed):
     dLs, refs = [], []
     for cam in cams:
         ref = oracle.render(sc, cam, ost)
-        dLs.append(rng.standard_normal((3, cam.height, cam.width)) * (ref["margin"] > G.MARGIN))
+        dLs.append(G.upstream(rng, ref, 3))
     grads = [torch.zeros_like(x) for x in t]
     R.backward([torch.from_numpy(d.astype(np.float32)).to(dev) for d in dLs], *grads)
     torch.cuda.synchronize()
-    keys = ("means", "quats", "scales", "dens", "sh")
     per = [oracle.render_backward(sc, cam, ost, d) for cam, d in zip(cams, dLs)]
-    worst = {}
-    for k, g in zip(keys, grads):
-        ref = sum(p[k] for p in per)
-        absr = sum(p["abs_" + k] for p in per)
-        errr = sum(p["err_" + k] for p in per)
-        worst[k] = G.grad_errors(g.cpu().numpy(), ref, absr, errr)
-        print(k, f"ratio {worst[k]:.3g}", G.grad_worst(g.cpu().numpy(), ref, absr, errr))
-    assert max(worst.values()) <= 1.0, worst
+    G.check_grads({k: g.cpu().numpy() for k, g in zip(G.GRAD_KEYS, grads)},
+                  G.sum_backward(per, G.GRAD_KEYS))
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16)])

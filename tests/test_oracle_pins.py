@@ -467,7 +467,8 @@ def test_fd_gradients_with_thresholds():
     st = oracle.Settings(act="clamp")
     r = oracle.render(sc, cam, st)
     # keep only pixels whose decisions are far from every threshold
-    dL = rng.standard_normal((3, cam.height, cam.width)) * (r["margin"] > 1e-2)
+    ok = (r["margin_x"] > 1e-2) & (r["margin_T"] > 1e-2)
+    dL = rng.standard_normal((3, cam.height, cam.width)) * ok
     an = oracle.render_backward(sc, cam, st, dL)
     base = lambda s2: float(np.sum(oracle.render(s2, cam, st)["image"] * dL))
     for f, idx in [("means", (1, 0)), ("scales", (1, 2)), ("dens", (2,)), ("quats", (1, 3)),
@@ -494,6 +495,159 @@ def test_fd_gradients_with_thresholds():
     an = oracle.render_backward(sc, cam, st, dc)
     assert an["dens"][0] == 0.0
     assert an["sh"][0, 0, 0] == pytest.approx(0.99 * scenes.Y00, rel=1e-12)
+
+
+# ------------------------------- decision margins (Sec. 4.1 thresholds) ---
+# The oracle reports, per pixel, the relative distance of each deciding test
+# to its threshold divided by the amplification of the tested value's FP32
+# rounding (1 + (D^2/2) s_max/s_min for a line integral; for the termination
+# test 1 + the root sum of squares over the blends so far, the candidate
+# included, of x_j (1 + (D_j^2/2) s_max/s_min) + 1).  Each value below is
+# that formula evaluated on a closed-form line integral (isotropic or
+# axis-aligned Gaussian, known ray).
+
+def _iso_kappa(x_target, s):
+    """FP32 density that gives an on-axis integral close to x_target, and
+    the integral those FP32 inputs give exactly."""
+    k = f32(x_target / (H.SQRT2PI * s))
+    return k, H.isotropic_x(k, s, 0.0)
+
+
+@pytest.mark.parametrize("factor", [1.0005, 0.9995, 1.03])
+def test_margin_skip_on_axis(factor):
+    cam = H.odd_camera()
+    st = oracle.Settings()
+    tau = -math.log1p(-st.alpha_min)
+    s = f32(0.05)
+    k, x = _iso_kappa(factor * tau, s)
+    r = oracle.render(H.scene([[0, 0, 4.0]], [s] * 3, k), cam, st, pixels=[_centre(cam)])
+    assert r["margin_x"][0] == pytest.approx(abs(x - tau) / x, rel=1e-9)
+    assert r["nblend"][0] == (1 if x >= tau else 0)
+    # the termination test of the one candidate (made only if it is not
+    # skipped), at T = 1 with amplification 1 + (x + 1) + 1
+    Tn = math.exp(-x)
+    mT = abs(Tn - st.T_min) / (Tn * (2 + x)) if x >= tau else math.inf
+    assert r["margin_T"][0] == pytest.approx(mT, rel=1e-9)
+    assert r["margin_order"][0] == math.inf
+
+
+@pytest.mark.parametrize("aniso", [1.0, 3.0])
+def test_margin_skip_off_axis_amplified(aniso):
+    """Mean at perpendicular distance r = 1.5 s from the central ray of an
+    axis-aligned Gaussian with scales (s, s, aniso s): beta = aniso s,
+    D^2 = (r/s)^2, amplification 1 + (D^2/2) aniso."""
+    cam = H.odd_camera()
+    st = oracle.Settings()
+    tau = -math.log1p(-st.alpha_min)
+    s = f32(0.05)
+    sz = f32(aniso * s)
+    r_off = f32(1.5 * s)
+    D2 = (r_off / s) ** 2
+    k = f32(1.002 * tau / (H.SQRT2PI * sz * math.exp(-0.5 * D2)))
+    x = k * H.SQRT2PI * sz * math.exp(-0.5 * D2)
+    r = oracle.render(H.scene([[r_off, 0, 4.0]], [s, s, sz], k), cam, st, pixels=[_centre(cam)])
+    amp = 1.0 + 0.5 * D2 * (sz / s)
+    assert r["margin_x"][0] == pytest.approx(abs(x - tau) / (x * amp), rel=1e-7)
+
+
+def test_margin_clamp():
+    """x just above x_max = -ln(1 - alpha_max): the clamp decision sets the
+    margin (the skip test is far away)."""
+    cam = H.odd_camera()
+    st = oracle.Settings()
+    xmax = -math.log1p(-st.alpha_max)
+    s = f32(0.05)
+    k, x = _iso_kappa(xmax * (1 + 2e-4), s)
+    r = oracle.render(H.scene([[0, 0, 4.0]], [s] * 3, k), cam, st, pixels=[_centre(cam)])
+    assert r["margin_x"][0] == pytest.approx(abs(x - xmax) / x, rel=1e-9)
+    assert r["margin_x"][0] < 1e-3
+
+
+def test_margin_termination_one_and_two_blends():
+    """T (1 - alpha) next to T_min: one Gaussian (amplification 2 + x), and a
+    second one behind a first of x1 = 1 that stops the pixel (amplification
+    1 + sqrt((x1 + 1)^2 + (x2 + 1)^2) at the second test); alpha_max is moved
+    out of the way."""
+    cam = H.odd_camera()
+    st = oracle.Settings(alpha_max=1 - 1e-12)
+    s = f32(0.05)
+    k, x = _iso_kappa(-math.log(st.T_min * (1 + 3e-4)), s)
+    r = oracle.render(H.scene([[0, 0, 4.0]], [s] * 3, k), cam, st, pixels=[_centre(cam)])
+    Tn = math.exp(-x)
+    assert r["nblend"][0] == 1
+    assert r["margin_T"][0] == pytest.approx(abs(Tn - st.T_min) / (Tn * (2 + x)), rel=1e-9)
+    k1, x1 = _iso_kappa(1.0, s)
+    k2, x2 = _iso_kappa(-math.log(st.T_min * (1 - 2e-4)) - x1, s)
+    sc = H.scene([[0, 0, 4.0], [0, 0, 5.0]], [s] * 3, [k1, k2])
+    r = oracle.render(sc, cam, st, pixels=[_centre(cam)])
+    assert r["nblend"][0] == 1 and r["last"][0] == 0
+    T2 = math.exp(-x1 - x2)
+    amp = 1 + math.hypot(x1 + 1, x2 + 1)
+    assert r["margin_T"][0] == pytest.approx(abs(T2 - st.T_min) / (T2 * amp), rel=1e-9)
+
+
+def test_margin_xray_cut():
+    """X-ray: x = x_min (1 + 7e-4) next to a Gaussian far above the cut; the
+    smaller margin wins, and a Gaussian below the cut by the same relative
+    distance gives the same margin (both sides count)."""
+    cam = H.odd_camera()
+    st = oracle.Settings(mode="xray")
+    s = f32(0.02)
+    k, x = _iso_kappa(st.x_min_xray * (1 + 7e-4), s)
+    sc = H.scene([[0, 0, 4.0], [0, 0, 6.0]], [s] * 3, [k, 3.0])
+    r = oracle.render(sc, cam, st, pixels=[_centre(cam)])
+    assert r["margin_x"][0] == pytest.approx(abs(x - st.x_min_xray) / x, rel=1e-9)
+    assert r["image"][0, 0] == pytest.approx(x + H.isotropic_x(3.0, s, 0.0), rel=1e-12)
+    k, x = _iso_kappa(st.x_min_xray * (1 - 7e-4), s)
+    r = oracle.render(H.scene([[0, 0, 4.0]], [s] * 3, k), cam, st, pixels=[_centre(cam)])
+    assert r["margin_x"][0] == pytest.approx(abs(x - st.x_min_xray) / x, rel=1e-9)
+    assert r["image"][0, 0] == 0.0
+
+
+def test_margin_order_gap():
+    """Per-tile order with 1x1 tiles: two Gaussians centred on the optical
+    axis at depths z1 < z2 whose relative gap is 3e-6 (gamma on the axis ray
+    is the depth), and a third between them that does not reach the skip
+    threshold (it does not count)."""
+    cam = H.odd_camera()
+    s = f32(0.05)
+    z1 = f32(4.0)
+    z2 = f32(4.0 * (1 + 3e-6))
+    zm = f32(4.0 * (1 + 1.5e-6))
+    st = oracle.Settings(resort_tile=(1, 1))
+    sc = H.scene([[0, 0, z1], [0, 0, zm], [0, 0, z2]], [s] * 3, [2.0, 1e-3, 2.0])
+    r = oracle.render(sc, cam, st, pixels=[_centre(cam)])
+    assert r["nblend"][0] == 2
+    assert r["margin_order"][0] == pytest.approx((z2 - z1) / z2, rel=1e-9)
+
+
+def test_margin_empty_pixel():
+    """No Gaussian on the ray: no decision, every margin infinite."""
+    cam = H.odd_camera()
+    for mode in ("color", "xray"):
+        r = oracle.render(H.scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0)), cam,
+                          oracle.Settings(mode=mode), pixels=[_centre(cam)])
+        assert r["margin_x"][0] == math.inf and r["margin_T"][0] == math.inf
+
+
+def test_near_threshold_backward_is_the_flip_bound():
+    """X-ray backward restricted to pairs within a margin of the cut: only the
+    Gaussian next to the cut is chained; its |d x / d kappa| on the axis is
+    sqrt(2 pi) s (isotropic closed form), the other Gaussian contributes 0."""
+    cam = H.odd_camera()
+    st = oracle.Settings(mode="xray")
+    s = f32(0.02)
+    k, x = _iso_kappa(st.x_min_xray * (1 + 1e-7), s)
+    sc = H.scene([[0, 0, 4.0], [0, 0, 6.0]], [s] * 3, [k, 3.0])
+    g = np.array([[-2.5]])
+    r = oracle.render_backward(sc, cam, st, g, pixels=[_centre(cam)], near_threshold=1e-5)
+    assert r["abs_dens"][0] == pytest.approx(2.5 * H.SQRT2PI * s, rel=1e-12)
+    assert r["abs_dens"][1] == 0.0 and np.all(r["abs_means"][1] == 0.0)
+    full = oracle.render_backward(sc, cam, st, g, pixels=[_centre(cam)])
+    assert full["dens"][1] == pytest.approx(-2.5 * H.SQRT2PI * s, rel=1e-12)
+    with pytest.raises(ValueError):
+        oracle.render_backward(sc, cam, oracle.Settings(), np.ones((3, 1)),
+                               pixels=[_centre(cam)], near_threshold=1e-5)
 
 
 # ------------------------------------------------ FP32 error scales (tests) ---
@@ -526,6 +680,38 @@ def test_error_scale_weights():
     g = oracle.render_backward(wl.scene, wl.cams[0], oracle.Settings(), dL)
     for k in ("means", "quats", "scales", "dens", "sh"):
         assert np.all(g["err_" + k] >= g["abs_" + k] * (1 - 1e-12)), k
+
+
+def test_error_scale_anisotropy_and_sh_nodes():
+    """err_* of an axis-aligned Gaussian with scales (s, s, 3 s) seen along z
+    weighs by 1 + (D^2/2) 3 (the rounding of its rotation is amplified by
+    s_max/s_min); the SH error scale of a degree-1 coefficient is
+    |Y_k| + |grad Y_k| per unit of |contribution| / |Y_k| (Y_1 = -c1 y, whose
+    gradient has norm c1 = sqrt(3/4 pi)), since FP32 evaluation near a node of
+    Y_k loses its relative accuracy."""
+    s = f32(0.1)
+    sz = f32(0.3)
+    one = H.scene([[0.03, -0.02, 0.0]], [s, s, sz], 2.0, rgb=[[0.8, 0.3, 0.6]], deg=1)
+    cam = H.odd_camera(9, 30.0, 4.0)
+    px = (5, 3)
+    o, d = H.pixel_ray_world(cam, *px)
+    g = oracle.render_backward(one, cam, oracle.Settings(mode="xray"), np.array([[1.5]]),
+                               pixels=[px])
+    # the ray is nearly along z: D^2 from the exact closest approach
+    P = np.diag([1 / s ** 2, 1 / s ** 2, 1 / sz ** 2])
+    v = one.means[0].astype(np.float64) - o
+    a = d @ P @ d
+    D2 = v @ P @ v - (v @ P @ d) ** 2 / a
+    w = 1.0 + 0.5 * D2 * (sz / s)
+    assert g["err_dens"][0] == pytest.approx(w * g["abs_dens"][0], rel=1e-7)
+    st = oracle.Settings(act="clamp", alpha_min=1e-30)
+    g = oracle.render_backward(one, cam, st, np.array([[1.0], [0.0], [0.0]]), pixels=[px])
+    vhat = (one.means[0].astype(np.float64) - o) / np.linalg.norm(one.means[0] - o)
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    Y1 = -c1 * vhat[1]
+    w = 1.0 + 0.5 * D2 * (sz / s)
+    assert g["err_sh"][0, 1, 0] == pytest.approx(w * g["abs_sh"][0, 1, 0] * (abs(Y1) + c1) / abs(Y1),
+                                                 rel=1e-7)
 
 
 # ------------------------------------ Sec. 5 density reparameterisation ---
@@ -825,7 +1011,7 @@ def test_fd_gradients_near_segment(mode):
     assert _fd_check(sc, cam, st, rng, n_checks=80, rel_h=3e-6, xray=mode == "xray") < 1e-6
 
 
-# --------------------- Sec. 8: per-tile re-sorting by the depth of the maximum ---
+# --------------------- Sec. 7: per-tile re-sorting by the depth of the maximum ---
 
 def test_tile_resort_orders_by_the_maximum_along_the_ray():
     """A small Gaussian at depth 4.7 and a long one whose mean lies behind it
