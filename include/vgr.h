@@ -325,6 +325,20 @@ int vgr_autotune(vgr_ctx *ctx, const vgr_settings *settings, int64_t n, const fl
  * keep their input order.  VGR_ERR_INVALID_ARG, VGR_ERR_OOM, VGR_ERR_HIP. */
 int vgr_sort_pairs(vgr_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits);
 
+/* Largest n of vgr_sort_pairs_static. */
+#define VGR_STATIC_SORT_MAX (1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sort of
+ * vgr_sort_pairs with the same arguments, results and stream, that allocates
+ * nothing.  Its scratch (ping-pong halves and radix tables, 9 MiB) is a
+ * static device array of the library, one copy per device, set up by
+ * vgr_create; n is limited to VGR_STATIC_SORT_MAX (VGR_ERR_INVALID_ARG above
+ * it, before anything is enqueued).  Every call on a device shares that
+ * device's copy, so calls that can overlap on one GPU (several contexts or
+ * streams) race and must be serialised by the caller.  Does not touch the
+ * context's saved forward.  VGR_ERR_INVALID_ARG, VGR_ERR_HIP. */
+int vgr_sort_pairs_static(vgr_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits);
 
 #ifdef __cplusplus
 }

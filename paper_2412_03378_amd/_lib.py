@@ -18,6 +18,7 @@ VGR_ERR_OOM = -3
 VGR_ERR_CAPACITY = -4
 VGR_ERR_NOT_CAPTURED = -5
 VGR_ERR_NO_FORWARD = -6
+VGR_STATIC_SORT_MAX = 1 << 20   # include/vgr.h
 
 VGR_MODE_COLOR = 0
 VGR_MODE_XRAY = 1
@@ -83,6 +84,8 @@ _SIGNATURES = {
     "vgr_get_timing": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                  C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "vgr_sort_pairs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "vgr_sort_pairs_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_int32]),
     "vgr_graph_capture": (C.c_int, [C.c_void_p, C.POINTER(vgr_settings), C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.POINTER(vgr_camera), C.POINTER(C.c_void_p),

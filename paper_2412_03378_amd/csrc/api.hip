@@ -30,8 +30,20 @@ const char *kStageNames[ST_COUNT] = {
 
 }  // namespace
 
+// Scratch of vgr_sort_pairs_static, one array per device (file scope, so
+// every GPU the library runs on holds its own copy until the process ends):
+// the ping-pong halves of keys and values and the radix tables, followed by
+// the element-count word the sort kernels read.  Host code never uses the
+// array's name as an address: vgr_create looks up each device's copy with
+// hipGetSymbolAddress and keeps that pointer in the context.
+constexpr int64_t kStaticSortMax = VGR_STATIC_SORT_MAX;
+constexpr int64_t kStaticRadixWords = 256 * (kStaticSortMax / 1024) + 256;
+constexpr int64_t kStaticScratchWords = 4 * kStaticSortMax + kStaticRadixWords + 64;
+static __device__ __align__(256) uint32_t scratch[kStaticScratchWords];
+
 struct vgr_ctx {
     int device = 0;
+    uint32_t *static_scratch = nullptr;   // this device's copy of `scratch`
     hipStream_t stream = nullptr;
     std::string err;
 
@@ -291,6 +303,13 @@ int vgr_create(vgr_ctx **out, int device)
         vgr_destroy(c);
         return rc;
     }
+    // this device's copy of the static scratch (the device is current here)
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+        vgr_destroy(c);
+        return VGR_ERR_HIP;
+    }
+    c->static_scratch = static_cast<uint32_t *>(sp);
     *out = c;
     return VGR_OK;
 }
@@ -831,6 +850,32 @@ int vgr_sort_pairs(vgr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int32_
     HIP_TRY(c, launch_fill_u32(dn, (uint32_t)n, 1, s));
     HIP_TRY(c, launch_radix_sort(keys, vals, ptr<uint32_t>(c->inst_key2), ptr<uint32_t>(c->inst_val2),
                                  dn, n, bits, ptr<uint32_t>(c->sort_tmp), s));
+    return VGR_OK;
+}
+
+int vgr_sort_pairs_static(vgr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int32_t bits)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (n < 0 || bits < 1 || bits > 32) return fail(c, VGR_ERR_INVALID_ARG, "bad n or bits");
+    if (n > kStaticSortMax)
+        return fail(c, VGR_ERR_INVALID_ARG, "n = %lld exceeds the static scratch (%lld pairs)",
+                    (long long)n, (long long)kStaticSortMax);
+    if (n == 0) return VGR_OK;
+    if (!keys || !vals) return fail(c, VGR_ERR_INVALID_ARG, "keys/vals NULL");
+    if (!c->static_scratch) return fail(c, VGR_ERR_HIP, "no static scratch on this device");
+    if (radix_tmp_words(n) > kStaticRadixWords)
+        return fail(c, VGR_ERR_INVALID_ARG, "radix tables exceed the static scratch");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // layout: keys2 | vals2 | radix tables | count word (all overwritten by
+    // every call before they are read: nothing needs clearing)
+    uint32_t *k2 = c->static_scratch;
+    uint32_t *v2 = k2 + kStaticSortMax;
+    uint32_t *tmp = v2 + kStaticSortMax;
+    uint32_t *dn = tmp + kStaticRadixWords;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, launch_fill_u32(dn, (uint32_t)n, 1, s));
+    HIP_TRY(c, launch_radix_sort(keys, vals, k2, v2, dn, n, bits, tmp, s));
     return VGR_OK;
 }
 

@@ -256,6 +256,15 @@ class Renderer:
                                       int(bits))
         L.check(rc, self._h)
 
+    def sort_pairs_static(self, keys: torch.Tensor, vals: torch.Tensor, bits: int):
+        """The same sort without any device allocation (library-static scratch,
+        at most VGR_STATIC_SORT_MAX pairs; calls overlapping on one GPU race)."""
+        self._sync_stream()
+        assert keys.dtype in (torch.int32, torch.uint32) and vals.dtype in (torch.int32, torch.uint32)
+        rc = self._lib.vgr_sort_pairs_static(self._h, _dev_ptr(keys), _dev_ptr(vals),
+                                             int(keys.numel()), int(bits))
+        L.check(rc, self._h)
+
 
 class _NodeToken:
     """Held by one autograd node; the context it uses stays reserved while
