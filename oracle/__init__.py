@@ -10,7 +10,7 @@ duck-typed scene / camera objects (attributes ``means, quats, scales, dens,
 sh, sh_degree`` and ``R, t, fx, fy, cx, cy, width, height, znear``).
 
 Passages followed (arXiv 2412.03378): the density mixture and Gaussian
-(Sec. 3.2), the 3DGS splatting opacity the paper compares against (Sec. 3,
+(Sec. 3.2), the compact Epanechnikov primitive named as future work (Sec. 8), the 3DGS splatting opacity the paper compares against (Sec. 3,
 eq. 3dgs_alpha, eq. affine_approx), the alpha-blend without splatting (Sec. 4.1), the 1D Gaussian on
 a ray and its boxed full-line integral (Sec. 4.2, Supp. B), the density
 reparameterisation (Sec. 5, eq. density_reparam), tomography as a sum of line
@@ -55,7 +55,7 @@ class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
                 ("density", C.c_int32), ("alpha_model", C.c_int32), ("near_segment", C.c_int32),
                 ("tile_resort", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("pad2", C.c_int32),
+                ("kernel", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3),
                 ("near_threshold", C.c_double)]
@@ -76,13 +76,14 @@ class Settings:
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (3DGS, eq. 3dgs_alpha)
     near_segment: bool = False     # integrate each ray from the near plane on (Sec. 4.2)
     resort_tile: tuple = None      # (w, h): per-tile order by gamma on the tile-centre ray
+    kernel: str = "gaussian"       # "gaussian" | "epanechnikov" (compact, Sec. 8)
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa",
-                      near_segment=False):
+                      near_segment=False, kernel="gaussian"):
         return Settings(mode=mode, alpha_min=1e-300, alpha_max=1.0 - 1e-12, T_min=0.0,
                         x_min_xray=1e-300, bg=bg, act=act, density=density,
-                        near_segment=near_segment)
+                        near_segment=near_segment, kernel=kernel)
 
 
 def _load():
@@ -96,7 +97,7 @@ def _load():
     dp = C.POINTER(C.c_double)
     ip = C.POINTER(C.c_int32)
     lp = C.POINTER(C.c_int64)
-    lib.orc_ray_integral.argtypes = [fp, fp, fp, C.c_float, dp, dp, dp]
+    lib.orc_ray_integral.argtypes = [fp, fp, fp, C.c_float, dp, dp, C.c_int, dp]
     lib.orc_sh_basis.argtypes = [C.c_int, dp, dp, dp]
     lib.orc_render.argtypes = [C.c_int64, fp, fp, fp, fp, fp, C.POINTER(_Cam),
                                C.POINTER(_Settings), C.c_int64, ip, dp, dp, lp, ip, dp, dp]
@@ -136,6 +137,7 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     s.density = 1 if st.density == "theta" else 0
     s.alpha_model = 1 if st.alpha_model == "splat" else 0
     s.near_segment = 1 if st.near_segment else 0
+    s.kernel = 1 if st.kernel == "epanechnikov" else 0
     if st.resort_tile:
         s.tile_resort = 1
         s.tile_w, s.tile_h = int(st.resort_tile[0]), int(st.resort_tile[1])
@@ -167,9 +169,10 @@ def max_threads() -> int:
     return int(_load().orc_max_threads())
 
 
-def ray_integral(mean, quat, scale, dens, o, d):
-    """Full-line integral of one Gaussian along o + t d (d is normalised
-    here).  Returns dict(gamma, beta, Gmax, x, alpha)."""
+def ray_integral(mean, quat, scale, dens, o, d, kernel="gaussian"):
+    """Full-line integral of one Gaussian (or Epanechnikov primitive) along
+    o + t d (d is normalised here).  Returns dict(gamma, beta, Gmax, x, alpha);
+    Gmax = exp(-D^2/2) for either kernel."""
     lib = _load()
     d = np.asarray(d, np.float64)
     d = d / np.linalg.norm(d)
@@ -177,7 +180,8 @@ def ray_integral(mean, quat, scale, dens, o, d):
     lib.orc_ray_integral(_ptr(_f32(mean), C.c_float), _ptr(_f32(quat), C.c_float),
                          _ptr(_f32(scale), C.c_float), float(dens),
                          _ptr(np.ascontiguousarray(o, np.float64), C.c_double),
-                         _ptr(np.ascontiguousarray(d), C.c_double), _ptr(out, C.c_double))
+                         _ptr(np.ascontiguousarray(d), C.c_double),
+                         1 if kernel == "epanechnikov" else 0, _ptr(out, C.c_double))
     g, b, G, x = out
     return dict(gamma=g, beta=b, Gmax=G, x=x, alpha=-math.expm1(-x))
 

@@ -92,7 +92,7 @@ typedef struct {
     int32_t near_segment;/* 1: integrate each ray from the near plane on (finite segment) */
     int32_t tile_resort; /* 1: per-tile order by the depth of each Gaussian's maximum */
     int32_t tile_w, tile_h;
-    int32_t pad2;
+    int32_t kernel;     /* 0: Gaussian; 1: Epanechnikov (compact, see ray_integral) */
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
     double near_threshold; /* > 0, X-ray backward only: chain just the pairs whose
@@ -144,8 +144,15 @@ typedef struct {
     double D2;       /* v^T P v, the minimum Mahalanobis distance squared of the ray */
 } ray_terms;
 
+/* Line integral of kappa K(r^2), r^2 = (x-mu)^T P (x-mu), along o + t d.  On
+   the ray r^2 = (t - gamma)^2 / beta^2 + D^2 (Sec. 4.2, eq. betagamma), so
+     Gaussian      K = exp(-r^2/2):       x = kappa sqrt(2 pi) beta exp(-D^2/2)
+     Epanechnikov  K = max(0, 1 - r^2):   x = kappa beta int_{|s| < h} (h^2 - s^2) ds
+                                            = (4/3) kappa beta h^3, h^2 = 1 - D^2 > 0
+   (0 where the ray misses the support, D^2 >= 1; the compact kernel of Sec. 8,
+   future work).  kernel selects the profile; gamma, beta, D^2 are shared. */
 static void ray_integral(const double mu[3], const double P[9], double kappa,
-                         const double o[3], const double d[3], ray_terms *rt)
+                         const double o[3], const double d[3], ray_terms *rt, int kernel)
 {
     double dm[3] = { mu[0] - o[0], mu[1] - o[1], mu[2] - o[2] };
     double a = quad_form(P, d, d);
@@ -165,7 +172,19 @@ static void ray_integral(const double mu[3], const double P[9], double kappa,
     rt->Gmax = Gmax;
     rt->a = a;
     for (int k = 0; k < 3; ++k) rt->v[k] = -diff[k];
-    rt->x = kappa * sqrt(2.0 * ORC_PI) * beta * Gmax;
+    if (kernel == 1) {
+        const double h2 = 1.0 - D2;
+        rt->x = h2 > 0.0 ? kappa * (4.0 / 3.0) * beta * h2 * sqrt(h2) : 0.0;
+    } else {
+        rt->x = kappa * sqrt(2.0 * ORC_PI) * beta * Gmax;
+    }
+}
+
+/* d ln x / d D^2 of the kernel's line integral: -1/2 (Gaussian), -(3/2)/(1 - D^2)
+   (Epanechnikov, inside the support). */
+static double dlnx_dD2(int kernel, double D2)
+{
+    return kernel == 1 ? -1.5 / (1.0 - D2) : -0.5;
 }
 
 /* Standard normal distribution function and density. */
@@ -181,13 +200,13 @@ static double near_t(const double zrow[3], double znear, const double d[3])
 
 /* Exported for closed-form pins: out = {gamma, beta, Gmax, x}. */
 int orc_ray_integral(const float mean[3], const float quat[4], const float scale[3],
-                     float dens, const double o[3], const double d[3], double out[4])
+                     float dens, const double o[3], const double d[3], int kernel, double out[4])
 {
     double R[9], P[9], mu[3] = { mean[0], mean[1], mean[2] };
     quat_rotation(quat, R, NULL, NULL);
     precision_matrix(R, scale, P);
     ray_terms rt;
-    ray_integral(mu, P, (double)dens, o, d, &rt);
+    ray_integral(mu, P, (double)dens, o, d, &rt, kernel);
     out[0] = rt.gamma; out[1] = rt.beta; out[2] = rt.Gmax; out[3] = rt.x;
     return 0;
 }
@@ -564,9 +583,11 @@ static double dec_margin(double v, double thr, double amp)
 }
 
 /* amplification of the line integral's relative error (see dec_margin) */
-static double x_amp(const ray_terms *rt, double aniso, int near, double eta, double tn)
+static double x_amp(const ray_terms *rt, int kernel, double aniso, int near, double eta,
+                    double tn)
 {
-    double amp = 1.0 + 0.5 * rt->D2 * aniso;
+    /* |d ln x / d ln D^2|: D^2/2 (Gaussian), (3/2) D^2/(1 - D^2) (Epanechnikov) */
+    double amp = 1.0 + fabs(dlnx_dD2(kernel, rt->D2)) * rt->D2 * aniso;
     if (near) {
         const double Phi = norm_cdf(eta);
         const double h = Phi > 0 ? norm_pdf(eta) / Phi : fabs(eta);
@@ -610,7 +631,7 @@ static double resort_order(const view_state *vs, const float *means, const orc_c
         const int64_t i = vs->order[r];
         const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
         ray_terms rt;
-        ray_integral(mu, vs->P + 9 * i, 1.0, vs->o, dc, &rt);
+        ray_integral(mu, vs->P + 9 * i, 1.0, vs->o, dc, &rt, 0);
         it[r].g = rt.gamma;
         it[r].key = vs->key[i];
         it[r].idx = i;
@@ -622,7 +643,7 @@ static double resort_order(const view_state *vs, const float *means, const orc_c
         order[r] = i;
         const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
         ray_terms rt;
-        ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+        ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt, st->kernel);
         if (rt.x < tau) continue;
         if (!isnan(prev)) {
             const double m = fabs(it[r].g - prev) / fmax(fabs(it[r].g), 1e-300);
@@ -676,12 +697,12 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             int64_t i = vs->order[r];
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
             ray_terms rt;
-            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt, st->kernel);
             const double eta = (rt.gamma - tn) / rt.beta;
             if (st->near_segment) rt.x *= norm_cdf(eta);
             full += rt.x;
             double m = dec_margin(rt.x, st->x_min_xray,
-                                  x_amp(&rt, vs->aniso[i], st->near_segment, eta, tn));
+                                  x_amp(&rt, st->kernel, vs->aniso[i], st->near_segment, eta, tn));
             if (m < mx) mx = m;
             if (rt.x >= st->x_min_xray) {
                 I += rt.x;
@@ -730,10 +751,10 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             amp_om = alpha < st->alpha_max ? alpha / (1.0 - alpha) * amp : 0.0;
         } else {
             double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
-            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt);
+            ray_integral(mu, vs->P + 9 * i, vs->kappa[i], vs->o, d, &rt, st->kernel);
             const double eta = (rt.gamma - tn) / rt.beta;
             if (st->near_segment) rt.x *= norm_cdf(eta);
-            const double amp = x_amp(&rt, vs->aniso[i], st->near_segment, eta, tn);
+            const double amp = x_amp(&rt, st->kernel, vs->aniso[i], st->near_segment, eta, tn);
             m = dec_margin(rt.x, tau, amp);
             if (m < mx) mx = m;
             if (rt.x < tau) continue;                  /* alpha < alpha_min */
@@ -780,6 +801,7 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
     if (st->alpha_model != 0 && (st->mode != 0 || st->density != 0 || st->near_segment)) return -1;
     if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
         return -1;
+    if (st->kernel != 0 && (st->kernel != 1 || st->alpha_model != 0 || st->near_segment)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -865,7 +887,7 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
     double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     double kappa = kappa_of(st, dens[i], scales + 3 * i);
     ray_terms rt;
-    ray_integral(mu, P, kappa, o, d, &rt);
+    ray_integral(mu, P, kappa, o, d, &rt, st->kernel);
     /* x = kappa sqrt(2pi) a^-1/2 exp(-D^2/2),  D^2 = v^T P v, v = mu - o - gamma d
        dx/dkappa = sqrt(2pi) beta Gmax
        dx/dP     = x (-1/2 d d^T / a - 1/2 v v^T)
@@ -887,8 +909,12 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
         Pv[r] = P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2];
         D2 += rt.v[r] * Pv[r];
     }
-    const double ge = gabs * (1.0 + 0.5 * D2 * vs->aniso[i] + w_extra);
-    const double dx_dk = sqrt(2 * ORC_PI) * rt.beta * rt.Gmax * Phi;
+    /* c = d ln x / d D^2 (-1/2 for the Gaussian): dx/dP gets c x v v^T and
+       dx/dmu = 2 c x P v (envelope: gamma is the minimiser, D^2 = v^T P v) */
+    const double cD = dlnx_dD2(st->kernel, D2);
+    const double ge = gabs * (1.0 + fabs(cD) * D2 * vs->aniso[i] + w_extra);
+    const double dx_dk = (st->kernel == 1 ? (4.0 / 3.0) * rt.beta * pow(1.0 - D2, 1.5)
+                                          : sqrt(2 * ORC_PI) * rt.beta * rt.Gmax) * Phi;
     double dk_din, dk_ds[3];
     kappa_grad(st, dens[i], scales + 3 * i, &dk_din, dk_ds);
     add3(go->g_dens, go->a_dens, go->e_dens, i, dx_dk * dk_din, gx, ge);
@@ -898,7 +924,7 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
     double G[9];   /* dx/dP per unit gx */
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
-            G[r * 3 + c] = Phi * x * (-0.5 * d[r] * d[c] / rt.a - 0.5 * rt.v[r] * rt.v[c]);
+            G[r * 3 + c] = Phi * x * (-0.5 * d[r] * d[c] / rt.a + cD * rt.v[r] * rt.v[c]);
     double Pd[3] = { 0, 0, 0 };
     if (st->near_segment) {
         const double dm[3] = { mu[0] - o[0], mu[1] - o[1], mu[2] - o[2] };
@@ -916,8 +942,8 @@ static void chain_integral(int64_t i, double gx, double gabs, double w_extra, co
         for (int r = 0; r < 3; ++r) Pd[r] *= ra;
     }
     for (int r = 0; r < 3; ++r)
-        add3(go->g_means, go->a_means, go->e_means, 3 * i + r, -Phi * x * Pv[r] + xphi * Pd[r],
-             gx, ge);
+        add3(go->g_means, go->a_means, go->e_means, 3 * i + r,
+             2.0 * cD * Phi * x * Pv[r] + xphi * Pd[r], gx, ge);
     /* P = sum_k s_k^-2 r_k r_k^T, r_k = column k of R */
     double dR[9];
     for (int k = 0; k < 3; ++k) {
@@ -1136,7 +1162,7 @@ static double pair_D2(int64_t i, const float *means, const float *quats, const f
     precision_matrix(R, scales + 3 * i, P);
     double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
     ray_terms rt;
-    ray_integral(mu, P, 1.0, o, d, &rt);   /* D^2 does not depend on kappa */
+    ray_integral(mu, P, 1.0, o, d, &rt, 0);   /* D^2 does not depend on kappa */
     double D2 = 0;
     for (int r = 0; r < 3; ++r)
         D2 += rt.v[r] * (P[r * 3] * rt.v[0] + P[r * 3 + 1] * rt.v[1] + P[r * 3 + 2] * rt.v[2]);
@@ -1165,6 +1191,7 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
     if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
         return -1;
     if (st->near_threshold > 0 && st->mode != 1) return -1;
+    if (st->kernel != 0 && (st->kernel != 1 || st->alpha_model != 0 || st->near_segment)) return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -1196,11 +1223,11 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                 const int64_t i = vs.order[r];
                 const double mu[3] = { means[3 * i], means[3 * i + 1], means[3 * i + 2] };
                 ray_terms rt;
-                ray_integral(mu, vs.P + 9 * i, vs.kappa[i], vs.o, d, &rt);
+                ray_integral(mu, vs.P + 9 * i, vs.kappa[i], vs.o, d, &rt, st->kernel);
                 const double eta = (rt.gamma - tn) / rt.beta;
                 if (st->near_segment) rt.x *= norm_cdf(eta);
                 const double m = dec_margin(rt.x, st->x_min_xray,
-                                            x_amp(&rt, vs.aniso[i], st->near_segment, eta, tn));
+                                            x_amp(&rt, st->kernel, vs.aniso[i], st->near_segment, eta, tn));
                 if (m < st->near_threshold)
                     chain_integral(i, g[0], fabs(g[0]), 0.0, means, quats, scales, dens, st, &vs,
                                    d, &go);
@@ -1240,8 +1267,10 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
                     if (!br->clamped)
                         chain_integral(i, galpha * ex, gabs * ex, steps, means, quats, scales,
                                        dens, st, &vs, d, &go);
-                    if (go.e_means || go.e_sh)
-                        w += 0.5 * pair_D2(i, means, quats, scales, vs.o, d) * vs.aniso[i];
+                    if (go.e_means || go.e_sh) {
+                        const double D2 = pair_D2(i, means, quats, scales, vs.o, d);
+                        w += fabs(dlnx_dD2(st->kernel, D2)) * D2 * vs.aniso[i];
+                    }
                 }
                 chain_colour(i, gc, w, &vs, means, sh, st, &go);
                 for (int ch = 0; ch < 3; ++ch)

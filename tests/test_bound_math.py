@@ -40,8 +40,12 @@ def _bbox(cam, m, Rc, s, D2):
     return out  # x0, x1, y0, y1 in pixel coordinates (pixel centres at p + 0.5)
 
 
-@pytest.mark.parametrize("seed", range(4))
-def test_dual_conic_box_contains_every_visible_pixel(seed):
+@pytest.mark.parametrize("seed,kernel", [(k, "gaussian") for k in range(4)] +
+                         [(k, "epanechnikov") for k in range(4)])
+def test_dual_conic_box_contains_every_visible_pixel(seed, kernel):
+    """Gaussian: x <= kappa sqrt(2 pi) s_max exp(-D^2/2); Epanechnikov (Sec. 8,
+    compact primitives): x <= (4/3) kappa s_max (1 - D^2)^(3/2), so x >= tau
+    needs D^2 <= 1 - (tau / ((4/3) kappa s_max))^(2/3)."""
     rng = np.random.default_rng(seed)
     cam = scenes.look_at(rng.normal(0, 1, 3) * 0 + [0.3, -0.2, -3.0], (0, 0, 0), 64, 48, 45.0)
     tau = -math.log1p(-1.0 / 255.0)
@@ -51,13 +55,14 @@ def test_dual_conic_box_contains_every_visible_pixel(seed):
         s = np.float32(np.exp(rng.uniform(np.log(0.01), np.log(0.12), 3)))
         kappa = float(np.float32(np.exp(rng.uniform(np.log(0.5), np.log(40)))))
         m, Rc, s64 = _view(cam, mu, q, s)
-        Kk = kappa * math.sqrt(2 * math.pi) * s64.max()
+        epan = kernel == "epanechnikov"
+        Kk = kappa * (4.0 / 3.0 if epan else math.sqrt(2 * math.pi)) * s64.max()
         if Kk <= tau:
             continue
-        D2 = 2 * math.log(Kk / tau)
+        D2 = 1 - (tau / Kk) ** (2 / 3) if epan else 2 * math.log(Kk / tau)
         box = _bbox(cam, m, Rc, s64, D2)
         sc = H.scene([mu], [s], kappa, quats=[q])
-        x = -np.log(oracle.render(sc, cam, oracle.Settings.no_thresholds())["T"])
+        x = -np.log(oracle.render(sc, cam, oracle.Settings.no_thresholds(kernel=kernel))["T"])
         ys, xs = np.nonzero(x >= tau)
         if box is None or not len(xs):
             continue

@@ -65,6 +65,14 @@ def test_oracle_matches_closed_form(name, kw, value, cite):
                              alpha_model="splat")
         cam = _axis_cam(kw["z"], kw["f"])
         got = oracle.render(sc, cam, st, pixels=[(c + int(kw["r"]), c)])["image"][0, 0]
+    elif name == "epan_x":
+        s = kw["s"]
+        sc = H.scene([[kw["r_over_s"] * s, 0.0, 0.0]], [s] * 3, kw["kappa"])
+        st = oracle.Settings.no_thresholds(mode="xray", kernel="epanechnikov")
+        got = oracle.render(sc, _axis_cam(4.0, 100.0), st, pixels=[(c, c)])["image"][0, 0]
+        if value == 0.0:   # outside the support (up to the rounding of D^2 = 1)
+            assert abs(got) < 1e-20, cite
+            return
     else:
         pytest.fail(f"unknown row {name}")
     assert got == pytest.approx(value, rel=1e-6), cite

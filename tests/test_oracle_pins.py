@@ -497,6 +497,152 @@ def test_fd_gradients_with_thresholds():
     assert an["sh"][0, 0, 0] == pytest.approx(0.99 * scenes.Y00, rel=1e-12)
 
 
+# -------------------------- Sec. 8 compact primitives: the Epanechnikov kernel ---
+# kappa max(0, 1 - r^2), r^2 = (x - mu)^T Sigma^-1 (x - mu): on a ray,
+# r^2 = (t - gamma)^2 / beta^2 + D^2 (eq. betagamma), so the line integral is
+# (4/3) kappa beta (1 - D^2)^(3/2) inside the support and 0 outside.
+
+def _epan_density(mu, q, s, kappa):
+    R = H.rotation_matrix(q)
+    P = R @ np.diag(1.0 / np.asarray(s, np.float64) ** 2) @ R.T
+    mu = np.asarray(mu, np.float64)
+
+    def f(x):
+        v = x - mu
+        return kappa * max(0.0, 1.0 - v @ P @ v)
+    return f, P
+
+
+@pytest.mark.parametrize("r_over_s", [0.0, 0.3, 0.7, 0.95, 1.2])
+def test_epanechnikov_isotropic_chord(r_over_s):
+    """Sigma = s^2 I: the chord integral of the paraboloid profile,
+    (4/3) kappa s (1 - r^2/s^2)^(3/2), zero once the ray misses the ball."""
+    s = f32(0.1)
+    r = f32(r_over_s * s)
+    res = oracle.ray_integral([r, 0.0, 5.0], [1, 0, 0, 0], [s] * 3, 2.0, [0, 0, 0], [0, 0, 1],
+                              kernel="epanechnikov")
+    h2 = 1.0 - (r / s) ** 2
+    expect = (4.0 / 3.0) * 2.0 * s * h2 ** 1.5 if h2 > 0 else 0.0
+    assert res["x"] == pytest.approx(expect, rel=1e-12, abs=1e-300)
+    assert res["beta"] == pytest.approx(s, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_epanechnikov_quadrature_random_anisotropic(seed):
+    """Adaptive quadrature of kappa max(0, 1 - r^2) along a random ray through
+    a random anisotropic primitive, split at the chord's ends."""
+    rng = np.random.default_rng(50 + seed)
+    mu = np.float32(rng.uniform(-0.3, 0.3, 3))
+    q = np.float32(rng.standard_normal(4))
+    s = np.float32(np.exp(rng.uniform(np.log(0.05), np.log(0.4), 3)))
+    kappa = 3.0
+    o = np.array([0.1, -0.2, -4.0])
+    # aim at a point inside the support
+    target = mu.astype(np.float64) + 0.4 * s.min() * rng.standard_normal(3) / 3
+    d = target - o
+    d /= np.linalg.norm(d)
+    f, P = _epan_density(mu, q, s, kappa)
+    a = d @ P @ d
+    g = (mu - o) @ P @ d / a
+    D2 = (o + g * d - mu) @ P @ (o + g * d - mu)
+    assert D2 < 1
+    half = math.sqrt((1 - D2) / a)
+    val, _ = integrate.quad(lambda t: f(o + t * d), g - half, g + half, epsabs=0, epsrel=1e-13,
+                            limit=200)
+    res = oracle.ray_integral(mu, q, s, kappa, o, d, kernel="epanechnikov")
+    assert res["x"] == pytest.approx(val, rel=1e-10)
+    # outside the chord the profile is exactly zero
+    assert f(o + (g + 1.001 * half) * d) == 0.0 and f(o + (g - 1.001 * half) * d) == 0.0
+
+
+def test_epanechnikov_compact_support_is_exact():
+    """Every pixel whose ray misses every primitive's support ellipsoid
+    (D^2 >= 1 for all, computed here from the geometry) shows exactly the
+    background, with T exactly 1; the others are covered."""
+    rng = np.random.default_rng(57)
+    n = 12
+    cam = scenes.look_at([0.3, -0.2, -3.0], (0, 0, 0), 21, 17, 40.0)
+    sc = H.scene(rng.uniform(-0.5, 0.5, (n, 3)), np.exp(rng.uniform(np.log(0.05), np.log(0.25), (n, 3))),
+                 rng.uniform(0.5, 5, n), quats=rng.standard_normal((n, 4)),
+                 rgb=rng.uniform(0, 1, (n, 3)))
+    bg = (0.25, 0.5, 0.75)
+    st = oracle.Settings.no_thresholds(act="clamp", bg=bg, kernel="epanechnikov")
+    r = oracle.render(sc, cam, st)
+    for py in range(cam.height):
+        for px in range(cam.width):
+            o, d = H.pixel_ray_world(cam, px, py)
+            miss = True
+            for i in range(n):
+                _, P = _epan_density(sc.means[i], sc.quats[i], sc.scales[i], 1.0)
+                v = o - sc.means[i].astype(np.float64)
+                a = d @ P @ d
+                D2 = v @ P @ v - (v @ P @ d) ** 2 / a
+                miss &= D2 >= 1.0
+            if miss:
+                assert np.array_equal(r["image"][:, py, px], np.array(bg))
+                assert r["T"][py, px] == 1.0
+            else:
+                assert r["T"][py, px] < 1.0
+
+
+def test_epanechnikov_linear_in_kappa_and_translation_invariant():
+    """x is linear in kappa and does not change when the primitive moves
+    along the ray (full chord)."""
+    o = np.zeros(3)
+    d = np.array([0.1, 0.05, 1.0])
+    d /= np.linalg.norm(d)
+    q = [0.9, 0.1, -0.3, 0.2]
+    s = [f32(0.1), f32(0.2), f32(0.15)]
+    base = np.array([0.32, 0.2, 3.0])
+    a = oracle.ray_integral(base, q, s, 1.0, o, d, kernel="epanechnikov")["x"]
+    b = oracle.ray_integral(base, q, s, 4.0, o, d, kernel="epanechnikov")["x"]
+    assert a > 0 and b == pytest.approx(4.0 * a, rel=1e-12)
+    moved = np.float32(base + 0.5 * d)
+    c = oracle.ray_integral(moved, q, s, 1.0, o, d, kernel="epanechnikov")["x"]
+    ref = oracle.ray_integral(np.float32(base), q, s, 1.0, o, d, kernel="epanechnikov")["x"]
+    assert c == pytest.approx(ref, rel=1e-5)   # the FP32 means differ by rounding
+
+
+@pytest.mark.parametrize("mode", ["color", "xray"])
+def test_fd_gradients_epanechnikov(mode):
+    """Analytic backward of the compact kernel (d ln x / d D^2 = -(3/2)/(1 - D^2)
+    in place of -1/2) against central finite differences of the forward."""
+    rng = np.random.default_rng(58 if mode == "color" else 59)
+    n = 6
+    cam = scenes.look_at([0.5, -0.3, -3.0], (0, 0, 0), 13, 11, 35.0)
+    sc = H.scene(rng.uniform(-0.3, 0.3, (n, 3)), np.exp(rng.uniform(np.log(0.15), np.log(0.45), (n, 3))),
+                 rng.uniform(1, 8, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    st = oracle.Settings.no_thresholds(mode=mode, act="softplus", bg=(0.2, 0.3, 0.1),
+                                       kernel="epanechnikov")
+    # (1 - D^2)^(3/2) has an unbounded third derivative at the support's edge,
+    # so the central difference's O(h^2) error is large for pixels near it:
+    # a smaller step than the Gaussian's (the error falls as h^2)
+    assert _fd_check(sc, cam, st, rng, n_checks=80, rel_h=1e-6, xray=mode == "xray") < 1e-6
+
+
+def test_epanechnikov_margin_and_rejected_combinations():
+    """The x-decision amplification of the compact kernel is
+    1 + (3/2) D^2/(1 - D^2) (its |d ln x / d ln D^2|); the kernel is not
+    combined with the splatting model or the near-plane segment."""
+    cam = H.odd_camera()
+    st = oracle.Settings(kernel="epanechnikov")
+    tau = -math.log1p(-st.alpha_min)
+    s = f32(0.05)
+    r_off = f32(0.5 * s)
+    D2 = (r_off / s) ** 2
+    k = f32(1.003 * tau / ((4.0 / 3.0) * s * (1 - D2) ** 1.5))
+    x = k * (4.0 / 3.0) * s * (1 - D2) ** 1.5
+    r = oracle.render(H.scene([[r_off, 0, 4.0]], [s] * 3, k), cam, st, pixels=[_centre(cam)])
+    amp = 1.0 + 1.5 * D2 / (1.0 - D2)
+    assert r["margin_x"][0] == pytest.approx(abs(x - tau) / (x * amp), rel=1e-7)
+    one = H.scene([[0, 0, 4.0]], [s] * 3, 0.5)
+    for bad in (oracle.Settings(kernel="epanechnikov", alpha_model="splat"),
+                oracle.Settings(kernel="epanechnikov", near_segment=True)):
+        with pytest.raises(RuntimeError):
+            oracle.render(one, cam, bad, pixels=[_centre(cam)])
+
+
 # ------------------------------- decision margins (Sec. 4.1 thresholds) ---
 # The oracle reports, per pixel, the relative distance of each deciding test
 # to its threshold divided by the amplification of the tested value's FP32
