@@ -63,6 +63,7 @@ enum { VGR_MODE_COLOR = 0, VGR_MODE_XRAY = 1 };
 enum { VGR_ACT_CLAMP0 = 0, VGR_ACT_SOFTPLUS10 = 1 };
 enum { VGR_DENSITY_KAPPA = 0, VGR_DENSITY_THETA = 1 };
 enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
+enum { VGR_KERNEL_GAUSSIAN = 0, VGR_KERNEL_EPANECHNIKOV = 1 };
 
 /* Rendering rules.  Defaults in brackets (vgr_default_settings).
  *   mode        colour compositing or X-ray line integrals [COLOR]
@@ -114,6 +115,17 @@ enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
  *               then depends on the tile shape (also on the one vgr_autotune
  *               picks when tile_w = tile_h = 0).  Costs one more 32-bit sort
  *               of the instances.  Colour mode, VOLUMETRIC [0]
+ *   kernel      the primitive's density profile along Sigma (VOLUMETRIC
+ *               only).  GAUSSIAN: kappa exp(-r^2/2), r^2 = (x-mu)^T Sigma^-1
+ *               (x-mu), the paper's primitive.  EPANECHNIKOV: the compact
+ *               kernel the paper names as future work (Sec. 8, compact
+ *               primitives), kappa max(0, 1 - r^2), whose support is the
+ *               ellipsoid with semi-axes s; its line integral is
+ *               x = (4/3) kappa beta (1 - D^2)^(3/2) for D^2 < 1 and 0 beyond
+ *               (the same beta and D^2 as the Gaussian's), and the tiles come
+ *               from the same dual-conic box with D2max = 1 - (3 tau /
+ *               (4 kappa beta_max))^(2/3).  Not with the near-plane segment
+ *               [GAUSSIAN]
  * Gaussians are composited in ascending order of the FP32 view-space depth
  * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
  * keep the input index order.  The result does not depend on the tile size:
@@ -129,6 +141,7 @@ typedef struct {
     int32_t alpha_model;
     int32_t near_segment;
     int32_t tile_resort;
+    int32_t kernel;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */

@@ -28,6 +28,8 @@ VGR_DENSITY_KAPPA = 0
 VGR_DENSITY_THETA = 1
 VGR_ALPHA_VOLUMETRIC = 0
 VGR_ALPHA_SPLAT = 1
+VGR_KERNEL_GAUSSIAN = 0
+VGR_KERNEL_EPANECHNIKOV = 1
 
 
 class vgr_camera(C.Structure):
@@ -41,7 +43,7 @@ class vgr_settings(C.Structure):
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32),
-                ("near_segment", C.c_int32), ("tile_resort", C.c_int32)]
+                ("near_segment", C.c_int32), ("tile_resort", C.c_int32), ("kernel", C.c_int32)]
 
 
 class vgr_stats(C.Structure):

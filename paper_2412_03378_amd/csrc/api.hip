@@ -456,6 +456,12 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
         return fail(c, VGR_ERR_INVALID_ARG, "bad tile_resort");
     if (st->tile_resort && (st->mode != VGR_MODE_COLOR || st->alpha_model != VGR_ALPHA_VOLUMETRIC))
         return fail(c, VGR_ERR_INVALID_ARG, "tile_resort needs colour mode and the volumetric model");
+    if (st->kernel != VGR_KERNEL_GAUSSIAN && st->kernel != VGR_KERNEL_EPANECHNIKOV)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad kernel");
+    if (st->kernel == VGR_KERNEL_EPANECHNIKOV &&
+        (st->alpha_model != VGR_ALPHA_VOLUMETRIC || st->near_segment))
+        return fail(c, VGR_ERR_INVALID_ARG,
+                    "the Epanechnikov kernel needs the volumetric model without the near-plane segment");
     if (!(st->alpha_min > 0.f && st->alpha_min < 1.f) || !(st->alpha_max > st->alpha_min) ||
         !(st->alpha_max < 1.f) || !(st->T_min >= 0.f) || !(st->x_min_xray > 0.f))
         return fail(c, VGR_ERR_INVALID_ARG, "bad thresholds");
@@ -481,6 +487,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.amax = st->alpha_max;
     rp.near_segment = st->near_segment;
     rp.tile_resort = st->tile_resort;
+    rp.kernel = st->kernel;
     rp.n_views = n_views;
     rp.n = n;
     rp.tau = st->mode == VGR_MODE_COLOR ? (float)(-log1p(-(double)st->alpha_min)) : st->x_min_xray;

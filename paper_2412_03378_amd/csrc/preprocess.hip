@@ -18,6 +18,8 @@
 // tangent lines x = const give the exact screen bounding box used for binning
 // (a conservative replacement of the 3-sigma screen-space heuristic that the
 // paper notes should be adjusted for this rendering model, Sec. 8, future work).
+// The Epanechnikov kernel (x = (4/3) kappa beta (1 - D^2)^(3/2)) uses the same
+// box with D2max = 1 - (3 tau / (4 kappa s_max))^(2/3).
 // A second pass replaces s_max by an upper bound of beta over the rays of that
 // box (see beta_bound), which shrinks the box of anisotropic Gaussians seen
 // along a short axis; the bound pre-test and the tile culling use the same
@@ -396,6 +398,14 @@ __device__ inline float density_of(int density, float in, const float *s)
     return theta_log(in) * ((1.0f / s[0] + 1.0f / s[1] + 1.0f / s[2]) * (1.0f / 3.0f));
 }
 
+// Largest D^2 at which a ray whose integral has peak r tau (r = K beta / tau,
+// beta the ray's standard deviation) can still reach the skip threshold tau:
+// x = r tau exp(-D^2/2) (Gaussian), x = r tau (1 - D^2)^(3/2) (Epanechnikov).
+__device__ inline float d2max_of(bool epan, float r)
+{
+    return epan ? 1.0f - powf(r, -2.0f / 3.0f) : 2.0f * logf(r);
+}
+
 template <int DEG, bool MULTI, bool SPLAT>
 __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffers b,
                                                          const float *__restrict__ means,
@@ -429,7 +439,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
         uint32_t key = 0xFFFFFFFFu, count = 0;
         ushort4 rect = make_ushort4(0, 0, 0, 0);
         const float z = __fmaf_rn(vi.R[6], mu[0], __fmaf_rn(vi.R[7], mu[1], __fmaf_rn(vi.R[8], mu[2], vi.t[2])));
-        const float K = kappa * kSqrt2Pi;
+        const bool epan = rp.kernel == VGR_KERNEL_EPANECHNIKOV;   // uniform
+        // peak line integral per unit beta: kappa sqrt(2 pi) (Gaussian) or
+        // (4/3) kappa (Epanechnikov, at D = 0)
+        const float K = kappa * (epan ? 4.0f / 3.0f : kSqrt2Pi);
         const float smax = fmaxf(s[0], fmaxf(s[1], s[2]));
         const float op = fminf(fmaxf(kappa, 0.0f), 1.0f);   // splat: peak opacity
         if (SPLAT ? (valid && z > vi.znear && op >= rp.amin)
@@ -458,9 +471,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                     x0 = y0 = 0; x1 = y1 = -1;   // degenerate splat: no area
                 }
             } else {
-            // alpha >= alpha_min needs D^2 <= 2 ln(K beta / tau) with beta the
+            // alpha >= alpha_min needs D^2 <= D2max(K beta / tau) with beta the
             // ray's standard deviation; beta <= smax gives a first box ...
-            D2max = 2.0f * logf(K * smax / rp.tau);
+            D2max = d2max_of(epan, K * smax / rp.tau);
             const float s2[3] = { s[0] * s[0], s[1] * s[1], s[2] * s[2] };
             screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
             // ... and beta over the rays of that box bounds it tighter (tight for
@@ -469,7 +482,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                 const float beta = beta_bound(g, s, smax, vi, x0, x1, y0, y1);
                 if (beta < smax) {
                     if (K * beta > rp.tau) {
-                        D2max = 2.0f * logf(K * beta / rp.tau);
+                        D2max = d2max_of(epan, K * beta / rp.tau);
                         screen_box(g, s2, D2max, vi, x0, x1, y0, y1);
                     } else {
                         x1 = x0 - 1;   // alpha < alpha_min on every ray of the box
@@ -551,7 +564,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
                     const bool near = rp.near_segment &&
                                       (mz - vi.znear) / smax - sqrtf(D2max) <= 6.0f;
                     gp[4] = make_float4(v0[1], v0[2], near ? -(K * kLog2e) : K * kLog2e,
-                                        (0.5f * kLog2e) * mz * mz);
+                                        epan ? mz * mz : (0.5f * kLog2e) * mz * mz);
                 }
                 gp[6] = make_float4(cr.cx, cr.cy, cr.a, cr.P);
                 gp[7] = make_float4(cr.R, cr.ymax, cr.yl, cr.on);

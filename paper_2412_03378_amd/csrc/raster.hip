@@ -65,6 +65,20 @@ __device__ __forceinline__ float near_eta(float v0x, float v0y, float v0z, float
 }
 __device__ __forceinline__ float norm_cdf(float e) { return 0.5f * erfcf(-0.70710678f * e); }
 
+// Profile factor of the line integral at D^2 = se num rq2 (with se from the
+// record): exp2(-(log2 e / 2) D^2) for the Gaussian, (1 - D^2)^(3/2) (0 past
+// the support) for the Epanechnikov kernel.
+template <bool EPAN>
+__device__ __forceinline__ float profile(float se, float num, float rq2)
+{
+    if constexpr (EPAN) {
+        const float h2 = fmaxf(1.0f - se * num * rq2, 0.0f);
+        return h2 * __builtin_sqrtf(h2);
+    } else {
+        return fast_exp2(-(se * num * rq2));
+    }
+}
+
 // Timed runs (b.wg_time set) record for each workgroup the constant-rate
 // realtime counter difference between start and end, and a key of the compute unit it ran on (XCC id, then the
 // shader engine, array and CU fields of HW_ID), so that the host can sum the
@@ -228,9 +242,10 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear && MODE != kModeXrayEpan;
     constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
     constexpr bool NEAR = MODE == kModeColorNear || MODE == kModeXrayNear;
+    constexpr bool EPAN = MODE == kModeColorEpan || MODE == kModeXrayEpan;
     __shared__ Stage st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                         PairGeom g;
                         pair_geom(pr, fr, dx, dy, g);
                         const float rq = fast_rsq(g.qw);
-                        const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                        const float ex = profile<EPAN>(fr.se, g.num, rq * rq);
                         y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
                         if constexpr (NEAR) {
                             if (fr.K < 0.0f)
@@ -405,7 +420,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                     PairGeom g;
                     pair_geom(pr, fr, ct.dx, dy, g);
                     const float rq = fast_rsq(g.qw);
-                    const float ex = fast_exp2(-(fr.se * g.num * (rq * rq)));
+                    const float ex = profile<EPAN>(fr.se, g.num, rq * rq);
                     float y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
                     if constexpr (NEAR) {
                         if (fr.K < 0.0f)
@@ -557,9 +572,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 {
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
-    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear;
+    constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear && MODE != kModeXrayEpan;
     constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
     constexpr bool NEAR = MODE == kModeColorNear || MODE == kModeXrayNear;
+    constexpr bool EPAN = MODE == kModeColorEpan || MODE == kModeXrayEpan;
     constexpr int NCH = COLOR ? 3 : 1;
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
@@ -678,7 +694,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             pair_geom(pr, fr, dx, dy, pg);
             const float rq = fast_rsq(pg.qw);
             const float rq2 = rq * rq;
-            const float ex = fast_exp2(-(fr.se * pg.num * rq2));
+            const float ex = profile<EPAN>(fr.se, pg.num, rq2);
             float y = (NEAR ? fabsf(fr.K) : fr.K) * un[k] * rq * ex;
             // near-plane segment: y *= Phi(eta); hn = h (eta + 2 zn |w|) and
             // h = phi(eta) / Phi(eta) enter the moments below
@@ -736,7 +752,12 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const float z1 = cz * (pg.w2 * pg.n0 - pg.w0 * pg.n2);
             const float z2 = cz * (pg.w0 * pg.n1 - pg.w1 * pg.n0);
             const float p0 = pg.w0 * rq, p1 = pg.w1 * rq, p2 = pg.w2 * rq;
-            const float tz0 = t * z0, tz1 = t * z1, tz2 = t * z2;
+            // weight of the z terms: t, or t 3 / (1 - D^2) for the Epanechnikov
+            // kernel (1 - D^2 > 0 wherever t is not zero)
+            float tzw = t;
+            if constexpr (EPAN)
+                tzw = t != 0.0f ? t * (3.0f * fast_rcp(1.0f - fr.se * pg.num * rq2)) : 0.0f;
+            const float tz0 = tzw * z0, tz1 = tzw * z1, tz2 = tzw * z2;
             float tw = t;   // weight of w' w'^T
             if constexpr (NEAR) {
                 if (fr.K < 0.0f) {   // wave-uniform: the whole wave is on one record
@@ -861,6 +882,14 @@ hipError_t fwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipSt
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
         if (count) raster_fwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
         else raster_fwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.kernel == VGR_KERNEL_EPANECHNIKOV) {
+        if (rp.mode == VGR_MODE_COLOR) {
+            if (count) raster_fwd_kernel<TW, TH, kModeColorEpan, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeColorEpan, false><<<grid, block, 0, s>>>(rp, b);
+        } else {
+            if (count) raster_fwd_kernel<TW, TH, kModeXrayEpan, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeXrayEpan, false><<<grid, block, 0, s>>>(rp, b);
+        }
     } else if (rp.near_segment) {
         if (rp.mode == VGR_MODE_COLOR) {
             if (count) raster_fwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);
@@ -886,6 +915,14 @@ hipError_t bwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipSt
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
         if (count) raster_bwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
         else raster_bwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+    } else if (rp.kernel == VGR_KERNEL_EPANECHNIKOV) {
+        if (rp.mode == VGR_MODE_COLOR) {
+            if (count) raster_bwd_kernel<TW, TH, kModeColorEpan, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeColorEpan, false><<<grid, block, 0, s>>>(rp, b);
+        } else {
+            if (count) raster_bwd_kernel<TW, TH, kModeXrayEpan, true><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeXrayEpan, false><<<grid, block, 0, s>>>(rp, b);
+        }
     } else if (rp.near_segment) {
         if (rp.mode == VGR_MODE_COLOR) {
             if (count) raster_bwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);

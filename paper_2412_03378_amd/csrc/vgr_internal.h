@@ -22,8 +22,10 @@ constexpr float kCullLevel = 0.1f;   // tile culling level of the bound form (> 
 constexpr float kCullPad = 0.02f;    // pixels added on both ends of a culled row span
 constexpr int kGradFloats = 16;   // record gradient per (Gaussian, view)
 // rasteriser template modes beyond VGR_MODE_COLOR / VGR_MODE_XRAY: colour with
-// the splatting alpha; colour and X-ray with the near-plane segment
+// the splatting alpha; colour and X-ray with the near-plane segment; colour
+// and X-ray with the Epanechnikov kernel
 constexpr int kModeSplat = 2, kModeColorNear = 3, kModeXrayNear = 4;
+constexpr int kModeColorEpan = 5, kModeXrayEpan = 6;
 
 // Rasteriser record of one (Gaussian, view), 128 bytes (8 float4, one cache
 // line), in the Gaussian's view space with L = diag(1/s) Rc^T (Rc = R_view
@@ -39,7 +41,8 @@ constexpr int kModeSplat = 2, kModeColorNear = 3, kModeXrayNear = 4;
 //   g3 = (A01, A11, A21, v0x)   v0 = L m / mz: L applied to the ray through the mean
 //   g4 = (v0y, v0z, K', se)     K' = kappa sqrt(2 pi) log2 e,  se = (log2 e / 2) mz^2;
 //                               K' < 0 (|K'| the value) flags a record that needs
-//                               the near-plane segment factor
+//                               the near-plane segment factor.  Epanechnikov
+//                               kernel: K' = (4/3) kappa log2 e, se = mz^2
 //   g5 = (r, g, b, mz)          colour after the activation (0 in X-ray mode)
 //   g6 = (cx, cy, a, P)         tile-culling ellipse (see cull_row in the
 //   g7 = (R, ymax, yl, on)        preprocess source); on = 0: no culling
@@ -55,7 +58,8 @@ constexpr int kModeSplat = 2, kModeColorNear = 3, kModeXrayNear = 4;
 //   a = A d,  w = L u = v0 + a,  L m x L u = mz (v0 x a)
 //   D^2 = mz^2 |v0 x a|^2 / |w|^2   (minimum Mahalanobis distance of the ray;
 //                                    free of cancellation near the centre)
-//   beta = |u| / |w|,  log2(e) x = K' |u| exp2(-(log2 e / 2) D^2) / |w|.
+//   beta = |u| / |w|,  log2(e) x = K' |u| exp2(-(log2 e / 2) D^2) / |w|
+//   (Epanechnikov: log2(e) x = K' |u| (1 - D^2)^(3/2) / |w| for D^2 < 1, else 0).
 // Bound pre-test: f(d) = d^T Q d + 2 l^T d - 1 has the sign of D^2 - D2max
 // (it is |w|^2 (D^2 - D2max) / (D2max |v0|^2)), so f > 0.05 proves
 // alpha < alpha_min for that pixel at a cost of three FP32 operations.  The
@@ -70,7 +74,9 @@ constexpr int kModeSplat = 2, kModeColorNear = 3, kModeXrayNear = 4;
 //   d ln x / dSigma^-1 = -1/2 (u u^T / u^T Sigma^-1 u + v v^T)
 //                      = -1/2 L^-1 (w w^T / |w|^2 + z z^T) L^-T,
 // so the sums  M = sum t (w w^T/|w|^2 + z z^T)  (symmetric) and  Z = sum t z
-// carry the whole geometric gradient:
+// carry the whole geometric gradient (Epanechnikov kernel: ln x has
+// (3/2) ln(1 - D^2) in place of -D^2/2, so the z terms carry t 3/(1 - D^2)
+// in place of t):
 //   [0..5] M00 M01 M02 M11 M12 M22, [6..8] Z, [9] sum t (= K' dL/dK'), [10..12] dL/dc,
 //   [13..15] U = sum t h w/|w| (near-plane segment, else 0).
 // With the segment factor Phi(eta), eta = (gamma - t_n)/beta = mz (v0.w')
@@ -111,6 +117,7 @@ struct RenderParams {
     float amin, amax;    // alpha_min, alpha_max (splatting model)
     int32_t near_segment;// integrate from the near plane (records flagged by K' < 0)
     int32_t tile_resort; // per-tile order by the depth of the maximum on the tile-centre ray
+    int32_t kernel;      // VGR_KERNEL_GAUSSIAN or VGR_KERNEL_EPANECHNIKOV
 };
 
 // Device workspace views handed to kernels.

@@ -31,6 +31,7 @@ class Settings:
     alpha_model: str = "volumetric"  # "volumetric" | "splat" (the 3DGS comparison model)
     near_segment: bool = False       # integrate each ray from the near plane on
     tile_resort: bool = False        # per-tile order by the depth of each maximum
+    kernel: str = "gaussian"         # "gaussian" | "epanechnikov" (compact primitive)
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -45,15 +46,16 @@ class Settings:
         s.alpha_model = L.VGR_ALPHA_SPLAT if self.alpha_model == "splat" else L.VGR_ALPHA_VOLUMETRIC
         s.near_segment = 1 if self.near_segment else 0
         s.tile_resort = 1 if self.tile_resort else 0
+        s.kernel = L.VGR_KERNEL_EPANECHNIKOV if self.kernel == "epanechnikov" else L.VGR_KERNEL_GAUSSIAN
         return s
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), sh_degree=0,
-                      density="kappa", near_segment=False):
+                      density="kappa", near_segment=False, kernel="gaussian"):
         """Smallest thresholds FP32 allows (for finite-difference checks)."""
         return Settings(mode=mode, sh_degree=sh_degree, alpha_min=1e-30, alpha_max=1 - 2 ** -20,
                         T_min=0.0, x_min_xray=1e-30, bg=bg, act=act, density=density,
-                        near_segment=near_segment)
+                        near_segment=near_segment, kernel=kernel)
 
 
 def camera_struct(cam) -> L.vgr_camera:

@@ -14,7 +14,9 @@ torch = pytest.importorskip("torch")
 @pytest.mark.parametrize("mode,opt", [("color", {}), ("xray", {}), ("color", {"density": "theta"}),
                                       ("color", {"alpha_model": "splat"}),
                                       ("xray", {"near_segment": True}),
-                                      ("color", {"tile_resort": True})])
+                                      ("color", {"tile_resort": True}),
+                                      ("color", {"kernel": "epanechnikov"}),
+                                      ("xray", {"kernel": "epanechnikov"})])
 def test_autograd_matches_explicit_backward(mode, opt):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
