@@ -280,9 +280,10 @@ def bench_batched(args, torch, dev):
     r = Renderer(0)
     nv = len(wl.cams)
     _log("autotuning the tile shape")
-    tile, tune_ms = r.autotune(params, wl.cams, Settings(sh_degree=3), outs, dLs, grads, iters=2)
-    st = Settings(sh_degree=3, tile=tile)
-    res = {"tile": list(tile), "autotune_ms": [round(x, 3) for x in tune_ms]}
+    tile, batch, tune_ms = r.autotune(params, wl.cams, Settings(sh_degree=3), outs, dLs, grads,
+                                      iters=2)
+    st = Settings(sh_degree=3, tile=tile, batch=batch)
+    res = {"tile": list(tile), "batch": batch, "autotune_ms": [round(x, 3) for x in tune_ms]}
     _log("batched views, one captured graph")
     # load balance over the compute units (workgroup timing, one eager call)
     r.set_counting(False, wg_timing=True)
@@ -302,10 +303,11 @@ def bench_batched(args, torch, dev):
     _log("single-view calls")
     # single-view calls get their own tuned tile (tuned on the largest view)
     big = max(range(nv), key=lambda k: wl.cams[k].width * wl.cams[k].height)
-    tile1, _ = r.autotune(params, [wl.cams[big]], Settings(sh_degree=3), [outs[big]], [dLs[big]],
-                          grads, iters=2)
-    st1 = Settings(sh_degree=3, tile=tile1)
+    tile1, batch1, _ = r.autotune(params, [wl.cams[big]], Settings(sh_degree=3), [outs[big]],
+                                  [dLs[big]], grads, iters=2)
+    st1 = Settings(sh_degree=3, tile=tile1, batch=batch1)
     res["tile_single"] = list(tile1)
+    res["batch_single"] = batch1
 
     def run():
         for k, (c, d) in enumerate(zip(wl.cams, dLs)):
@@ -341,8 +343,9 @@ def bench_xray(args, torch, dev):
     outs = [torch.empty((c.height, c.width), device=dev) for c in wl.cams]
     r = Renderer(0)
     _log("autotuning the tile shape (X-ray)")
-    tile, tune_ms = r.autotune(params, wl.cams, Settings(mode="xray"), outs, dLs, grads, iters=1)
-    st = Settings(mode="xray", tile=tile)
+    tile, batch, tune_ms = r.autotune(params, wl.cams, Settings(mode="xray"), outs, dLs, grads,
+                                      iters=1)
+    st = Settings(mode="xray", tile=tile, batch=batch)
     for _ in range(max(1, args.warmup // 2)):
         _step(r, params, grads, wl.cams, st, dLs)
     torch.cuda.synchronize()
@@ -398,10 +401,10 @@ def bench_train(args, torch, dev, views_per_call=16):
     nv = len(wl.cams)
     _log("autotuning the tile shape (training calls)")
     outs = [torch.empty((3, c.height, c.width), device=dev) for c in wl.cams[:views_per_call]]
-    tile, _ = r.autotune(params, wl.cams[:views_per_call], Settings(sh_degree=3), outs,
-                         dLs[:views_per_call], grads, iters=1)
+    tile, batch, _ = r.autotune(params, wl.cams[:views_per_call], Settings(sh_degree=3), outs,
+                                dLs[:views_per_call], grads, iters=1)
     del outs
-    st = Settings(sh_degree=3, tile=tile)
+    st = Settings(sh_degree=3, tile=tile, batch=batch)
 
     def step(p, s):
         for v0 in range(0, nv, views_per_call):
@@ -446,7 +449,7 @@ def bench_train(args, torch, dev, views_per_call=16):
     gnorm = torch.zeros(wl.scene.n, dtype=torch.float32, device=dev)
     vcount = torch.zeros(wl.scene.n, dtype=torch.int32, device=dev)
     r.set_densify_stats(gnorm, vcount)
-    dt2, stages2 = timed(p_theta, Settings(sh_degree=3, tile=tile, density="theta"))
+    dt2, stages2 = timed(p_theta, Settings(sh_degree=3, tile=tile, batch=batch, density="theta"))
     r.set_densify_stats(None, None)
     pick = lambda d: {k: round(d.get(k, 0.0) * 4, 3) for k in ("preprocess_fwd", "preprocess_bwd")}
     out["stage_ms_per_step"] = {k: round(v * 4, 3) for k, v in stages.items()}

@@ -80,7 +80,13 @@ enum { VGR_KERNEL_GAUSSIAN = 0, VGR_KERNEL_EPANECHNIKOV = 1 };
  *               from the camera centre to the mean; max(.,0) or
  *               softplus(10 y)/10 (Supp. D) [CLAMP0]
  *   tile_w/h    screen tile in pixels, one of 8x8, 16x8, 16x16, 32x8;
- *               0 = the context's tuned choice (8x8 until vgr_autotune) [0, 0]
+ *               0 = tuned: vgr_autotune's choice for the call's workload class
+ *               (total pixels and Gaussians in powers of two, mode,
+ *               alpha_model, kernel, tile_resort, near_segment), else the
+ *               context's last tuned shape (8x8 until vgr_autotune) [0, 0]
+ *   batch       records staged in LDS per rasteriser batch (the block
+ *               shape), 32 or 64; 0 = tuned as tile_w/h (64 until
+ *               vgr_autotune).  Never changes the result [0]
  *   density     what the `dens` input holds: KAPPA, the density kappa >= 0
  *               itself, or THETA, the paper's density parameter theta, with
  *               kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3
@@ -142,6 +148,7 @@ typedef struct {
     int32_t near_segment;
     int32_t tile_resort;
     int32_t kernel;
+    int32_t batch;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */
@@ -308,6 +315,27 @@ int vgr_graph_capture(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
                       float *d_means, float *d_quats, float *d_scales, float *d_dens,
                       float *d_sh, float capacity_factor, int32_t zero_grads);
 
+/* Largest number of calls one captured graph holds. */
+#define VGR_MAX_GRAPH_CALLS 16
+
+/* Capture several forward + backward calls into one HIP graph: call k renders
+ * the views_per_call[k] (host array, each in [1, 64]) cameras that follow the
+ * previous calls' in cams / out / dL_dout (host arrays over all views), and
+ * its backward adds to the same gradient arrays (call 0 overwrites them when
+ * zero_grads is set).  This is the multi-view training step that does not
+ * fit one call (more than 64 views, or a working set split on purpose), as
+ * one replayable graph.  The calls share the context's workspace one after
+ * the other; the instance capacity is capacity_factor times the largest
+ * call's count.  Otherwise as vgr_graph_capture.  n_calls in
+ * [1, VGR_MAX_GRAPH_CALLS]. */
+int vgr_graph_capture_calls(vgr_ctx *ctx, const vgr_settings *settings, int64_t n,
+                            const float *means, const float *quats, const float *scales,
+                            const float *dens, const float *sh, int32_t n_calls,
+                            const int32_t *views_per_call, const vgr_camera *cams,
+                            float *const *out, const float *const *dL_dout, float *d_means,
+                            float *d_quats, float *d_scales, float *d_dens, float *d_sh,
+                            float capacity_factor, int32_t zero_grads);
+
 /* Enqueue one replay of the captured graph.  VGR_ERR_NOT_CAPTURED if there is
  * none or it was invalidated; otherwise returns without waiting. */
 int vgr_graph_launch(vgr_ctx *ctx);
@@ -319,18 +347,41 @@ int vgr_graph_launch(vgr_ctx *ctx);
  * instance count. */
 int vgr_graph_check(vgr_ctx *ctx, int64_t *instances);
 
+/* Number of launch shapes vgr_autotune times. */
+#define VGR_TUNE_CANDIDATES 8
+
 /* Time the step (forward, plus backward when dL_dout is not NULL) for each
- * tile shape 8x8, 16x8, 16x16, 32x8 with HIP events over `iters` calls after
- * one warm-up call, keep the fastest as the context's tile for settings with
- * tile_w = tile_h = 0, and report it in *best_tile_w, *best_tile_h and the
- * mean ms of each candidate in ms_per_candidate[4] (any may be NULL).  The
- * gradient arrays receive the sum of all the backward passes run. */
+ * launch shape: tile 8x8, 16x8, 16x16, 32x8 with 64-record batches, then the
+ * same tiles with 32-record batches (candidates 0..7), with HIP events over
+ * `iters` calls after one warm-up call.  The fastest becomes the context's
+ * shape for calls of the same workload class that leave tile_w = tile_h = 0
+ * or batch = 0 (the class: total pixels and Gaussians in powers of two, mode,
+ * alpha_model, kernel, tile_resort, near_segment), and its last tuned shape
+ * for other classes.  Reports it in *best_tile_w, *best_tile_h, *best_batch
+ * and the mean ms of each candidate in ms_per_candidate[VGR_TUNE_CANDIDATES]
+ * (any may be NULL).  The gradient arrays receive the sum of all the
+ * backward passes run.  The per-class choices persist through
+ * vgr_tune_export / vgr_tune_import. */
 int vgr_autotune(vgr_ctx *ctx, const vgr_settings *settings, int64_t n, const float *means,
                  const float *quats, const float *scales, const float *dens, const float *sh,
                  int32_t n_views, const vgr_camera *cams, float *const *out,
                  const float *const *dL_dout, float *d_means, float *d_quats,
                  float *d_scales, float *d_dens, float *d_sh, int32_t iters,
-                 int32_t *best_tile_w, int32_t *best_tile_h, float *ms_per_candidate);
+                 int32_t *best_tile_w, int32_t *best_tile_h, int32_t *best_batch,
+                 float *ms_per_candidate);
+
+/* The context's tuned shapes as text (host buffer of cap bytes, NUL
+ * terminated; *len receives the size needed, also when buf is NULL): one line
+ * per workload class, "pix_log2 n_log2 mode alpha_model kernel tile_resort
+ * near_segment tile_w tile_h batch ms".  VGR_ERR_INVALID_ARG if cap is too
+ * small. */
+int vgr_tune_export(vgr_ctx *ctx, char *buf, int64_t cap, int64_t *len);
+
+/* Merge tuned shapes written by vgr_tune_export (host text) into the
+ * context's cache; lines of a class already present replace it.  A malformed
+ * line (wrong field count, unsupported tile or batch) rejects the whole text
+ * with VGR_ERR_INVALID_ARG and changes nothing. */
+int vgr_tune_import(vgr_ctx *ctx, const char *text);
 
 /* Stable LSD radix sort of n (key, value) pairs on the low `bits` bits of
  * key, in place (keys, vals: device u32 arrays of n).  This is the sort the

@@ -19,6 +19,8 @@ VGR_ERR_CAPACITY = -4
 VGR_ERR_NOT_CAPTURED = -5
 VGR_ERR_NO_FORWARD = -6
 VGR_STATIC_SORT_MAX = 1 << 20   # include/vgr.h
+VGR_TUNE_CANDIDATES = 8
+VGR_MAX_GRAPH_CALLS = 16
 
 VGR_MODE_COLOR = 0
 VGR_MODE_XRAY = 1
@@ -43,7 +45,8 @@ class vgr_settings(C.Structure):
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("x_min_xray", C.c_float),
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32),
-                ("near_segment", C.c_int32), ("tile_resort", C.c_int32), ("kernel", C.c_int32)]
+                ("near_segment", C.c_int32), ("tile_resort", C.c_int32), ("kernel", C.c_int32),
+                ("batch", C.c_int32)]
 
 
 class vgr_stats(C.Structure):
@@ -93,6 +96,13 @@ _SIGNATURES = {
                                     C.POINTER(vgr_camera), C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_float, C.c_int32]),
+    "vgr_graph_capture_calls": (C.c_int, [C.c_void_p, C.POINTER(vgr_settings), C.c_int64,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                          C.POINTER(vgr_camera), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                          C.c_int32]),
     "vgr_graph_launch": (C.c_int, [C.c_void_p]),
     "vgr_graph_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "vgr_autotune": (C.c_int, [C.c_void_p, C.POINTER(vgr_settings), C.c_int64, C.c_void_p,
@@ -100,7 +110,9 @@ _SIGNATURES = {
                                C.POINTER(vgr_camera), C.POINTER(C.c_void_p),
                                C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
-                               C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "vgr_tune_export": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "vgr_tune_import": (C.c_int, [C.c_void_p, C.c_char_p]),
 }
 
 EXPORTED = tuple(_SIGNATURES)

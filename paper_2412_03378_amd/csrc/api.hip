@@ -28,6 +28,38 @@ const char *kStageNames[ST_COUNT] = {
     "zero_record_grads", "raster_bwd", "preprocess_bwd"
 };
 
+// Workload class of the autotuner's cache: total pixels and Gaussians in
+// powers of two, and the rules that change the rasterisers' work.
+struct TuneKey {
+    int32_t pix_log2, n_log2, mode, alpha_model, kernel, tile_resort, near_segment;
+    bool operator<(const TuneKey &o) const
+    {
+        const int32_t a[7] = { pix_log2, n_log2, mode, alpha_model, kernel, tile_resort, near_segment };
+        const int32_t b[7] = { o.pix_log2, o.n_log2, o.mode, o.alpha_model, o.kernel, o.tile_resort,
+                               o.near_segment };
+        for (int k = 0; k < 7; ++k)
+            if (a[k] != b[k]) return a[k] < b[k];
+        return false;
+    }
+};
+struct TuneVal {
+    int32_t tile_w, tile_h, batch;
+    float ms;
+};
+
+int32_t log2_bucket(int64_t v)
+{
+    return v <= 1 ? 0 : (int32_t)lround(log2((double)v));
+}
+
+TuneKey tune_key(const vgr_settings *st, int64_t n, int32_t n_views, const vgr_camera *cams)
+{
+    int64_t pix = 0;
+    for (int v = 0; v < n_views; ++v) pix += (int64_t)cams[v].width * cams[v].height;
+    return TuneKey{ log2_bucket(pix), log2_bucket(n), st->mode, st->alpha_model, st->kernel,
+                    st->tile_resort, st->near_segment };
+}
+
 }  // namespace
 
 // Scratch of vgr_sort_pairs_static, one array per device (file scope, so
@@ -37,6 +69,7 @@ const char *kStageNames[ST_COUNT] = {
 // array's name as an address: vgr_create looks up each device's copy with
 // hipGetSymbolAddress and keeps that pointer in the context.
 constexpr int64_t kStaticSortMax = VGR_STATIC_SORT_MAX;
+constexpr int kMaxGraphCalls = VGR_MAX_GRAPH_CALLS;
 constexpr int64_t kStaticRadixWords = 256 * (kStaticSortMax / 1024) + 256;
 constexpr int64_t kStaticScratchWords = 4 * kStaticSortMax + kStaticRadixWords + 64;
 static __device__ __align__(256) uint32_t scratch[kStaticScratchWords];
@@ -85,7 +118,11 @@ struct vgr_ctx {
     std::vector<EvSet> evsets;
     size_t ev_next = 0;
     EvSet *cur = nullptr;
-    int tuned_w = 8, tuned_h = 8;
+    // launch shape of calls that leave it to the library (tile_w = tile_h = 0,
+    // batch = 0): the tuner's choice for the call's workload class, else the
+    // last tuned shape (8x8 tiles, 64-record batches until vgr_autotune)
+    int tuned_w = 8, tuned_h = 8, tuned_b = 64;
+    std::map<TuneKey, TuneVal> tune_cache;
 
     // captured forward + backward (hipGraph)
     hipGraph_t graph = nullptr;
@@ -473,8 +510,18 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
             return rc;
         if (st->mode == VGR_MODE_COLOR && (rc = check_ptr(c, sh, "sh"))) return rc;
     }
-    int tw = st->tile_w, th = st->tile_h;
-    if (tw == 0 && th == 0) { tw = c->tuned_w; th = c->tuned_h; }
+    if (st->batch != 0 && st->batch != 32 && st->batch != 64)
+        return fail(c, VGR_ERR_INVALID_ARG, "batch must be 0, 32 or 64");
+    int tw = st->tile_w, th = st->tile_h, tb = st->batch;
+    if ((tw == 0 && th == 0) || tb == 0) {
+        const auto it = c->tune_cache.find(tune_key(st, n, n_views, cams));
+        const bool hit = it != c->tune_cache.end();
+        if (tw == 0 && th == 0) {
+            tw = hit ? it->second.tile_w : c->tuned_w;
+            th = hit ? it->second.tile_h : c->tuned_h;
+        }
+        if (tb == 0) tb = hit ? it->second.batch : c->tuned_b;
+    }
     if (!valid_tile(tw, th)) return fail(c, VGR_ERR_INVALID_ARG, "unsupported tile %dx%d", tw, th);
 
     RenderParams &rp = p.rp;
@@ -497,6 +544,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     for (int k = 0; k < 3; ++k) rp.bg[k] = st->bg[k];
     rp.tile_w = tw;
     rp.tile_h = th;
+    rp.batch = tb;
 
     p.vinfo.assign(n_views, ViewInfo{});
     int64_t tiles = 0, pix = 0;
@@ -637,7 +685,7 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     if (cap < 0 && raster_keeps_masks(rp.mode, rp.tile_w, rp.tile_h)) {
         // (a capture sizes this buffer for its capacity before it starts)
         if ((rc = ensure(c, c->pmask,
-                         8 * (size_t)pmask_words(K, rp.total_tiles, rp.tile_w, rp.tile_h))))
+                         8 * (size_t)pmask_words(K, rp.total_tiles, rp.tile_w, rp.tile_h, rp.batch))))
             return rc;
         b.pmask = ptr<uint64_t>(c->pmask);
     }
@@ -886,53 +934,79 @@ int vgr_sort_pairs_static(vgr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n,
     return VGR_OK;
 }
 
-int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
-                      const float *quats, const float *scales, const float *dens, const float *sh,
-                      int32_t n_views, const vgr_camera *cams, float *const *out,
-                      const float *const *dL, float *d_means, float *d_quats, float *d_scales,
-                      float *d_dens, float *d_sh, float capacity_factor, int32_t zero_grads)
+int vgr_graph_capture_calls(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                            const float *quats, const float *scales, const float *dens,
+                            const float *sh, int32_t n_calls, const int32_t *views_per_call,
+                            const vgr_camera *cams, float *const *out, const float *const *dL,
+                            float *d_means, float *d_quats, float *d_scales, float *d_dens,
+                            float *d_sh, float capacity_factor, int32_t zero_grads)
 {
     if (!c) return VGR_ERR_INVALID_ARG;
     c->err.clear();
     if (!dL) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout is NULL");
+    if (n_calls < 1 || n_calls > kMaxGraphCalls || !views_per_call)
+        return fail(c, VGR_ERR_INVALID_ARG, "n_calls must be in [1, %d]", kMaxGraphCalls);
+    std::vector<int32_t> off(n_calls + 1, 0);
+    for (int k = 0; k < n_calls; ++k) {
+        if (views_per_call[k] < 1 || views_per_call[k] > kMaxViews)
+            return fail(c, VGR_ERR_INVALID_ARG, "call %d: views must be in [1, %d]", k, kMaxViews);
+        off[k + 1] = off[k] + views_per_call[k];
+    }
     if (!(capacity_factor >= 1.0f)) capacity_factor = 1.25f;
-    int rc;
-    // one eager pass sizes every buffer and measures the instance count
+    int rc = VGR_OK;
+    // one eager pass per call sizes every buffer and measures the instance counts
     const bool counting = c->counting, timing = c->timing;
     c->counting = false;
     c->timing = false;
     c->cur = nullptr;
-    rc = vgr_render_forward(c, st, n, means, quats, scales, dens, sh, n_views, cams, out);
-    if (!rc) rc = vgr_render_backward(c, dL, d_means, d_quats, d_scales, d_dens, d_sh, zero_grads ? 0 : 1);
+    int64_t kmax = 0;
+    for (int k = 0; k < n_calls && !rc; ++k) {
+        rc = vgr_render_forward(c, st, n, means, quats, scales, dens, sh, views_per_call[k],
+                                cams + off[k], out + off[k]);
+        if (!rc)
+            rc = vgr_render_backward(c, dL + off[k], d_means, d_quats, d_scales, d_dens, d_sh,
+                                     (zero_grads && k == 0) ? 0 : 1);
+        if (!rc) kmax = c->K > kmax ? c->K : kmax;
+    }
     c->counting = counting;
     c->timing = timing;
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    Prepared p;
-    if ((rc = prepare(c, st, n, means, quats, scales, dens, sh, n_views, cams, out, p))) return rc;
-    const int64_t cap = (int64_t)ceil((double)c->K * capacity_factor) + 4096;
-    const int64_t m = p.m;
-    if (p.rp.tile_resort &&
+    std::vector<Prepared> ps(n_calls);
+    for (int k = 0; k < n_calls; ++k)
+        if ((rc = prepare(c, st, n, means, quats, scales, dens, sh, views_per_call[k],
+                          cams + off[k], out + off[k], ps[k])))
+            return rc;
+    const int64_t cap = (int64_t)ceil((double)kmax * capacity_factor) + 4096;
+    int64_t mmax = 0, sort_n = 0, pmw = 0;
+    for (const Prepared &p : ps) {
+        mmax = p.m > mmax ? p.m : mmax;
+        sort_n = p.sort_n > sort_n ? p.sort_n : sort_n;
+        if (raster_keeps_masks(p.rp.mode, p.rp.tile_w, p.rp.tile_h)) {
+            const int64_t w = pmask_words(cap, p.rp.total_tiles, p.rp.tile_w, p.rp.tile_h, p.rp.batch);
+            pmw = w > pmw ? w : pmw;
+        }
+    }
+    if (ps[0].rp.tile_resort &&
         ((rc = ensure(c, c->rs_key, 4 * cap)) || (rc = ensure(c, c->rs_idx, 4 * cap)) ||
          (rc = ensure(c, c->rs_key2, 4 * cap)) || (rc = ensure(c, c->rs_idx2, 4 * cap))))
         return rc;
     if ((rc = ensure(c, c->inst_key, 4 * cap)) || (rc = ensure(c, c->inst_val, 4 * cap)) ||
         (rc = ensure(c, c->inst_key2, 4 * cap)) || (rc = ensure(c, c->inst_val2, 4 * cap)) ||
-        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(cap > p.sort_n ? cap : p.sort_n))) ||
-        (rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1))) ||
-        (rc = ensure(c, c->views_graph, sizeof(ViewInfo) * kMaxViews)))
+        (rc = ensure(c, c->sort_tmp, 4 * radix_tmp_words(cap > sort_n ? cap : sort_n))) ||
+        (rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (mmax > 0 ? mmax : 1))) ||
+        (rc = ensure(c, c->views_graph, sizeof(ViewInfo) * (size_t)off[n_calls])))
         return rc;
-    if (raster_keeps_masks(p.rp.mode, p.rp.tile_w, p.rp.tile_h) &&
-        (rc = ensure(c, c->pmask,
-                     8 * (size_t)pmask_words(cap, p.rp.total_tiles, p.rp.tile_w, p.rp.tile_h))))
-        return rc;
+    if (pmw > 0 && (rc = ensure(c, c->pmask, 8 * (size_t)pmw))) return rc;
     c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
-    for (int v = 0; v < n_views; ++v) {
-        if (!dL[v]) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout[%d] is NULL", v);
-        p.vinfo[v].dL = dL[v];
+    for (int k = 0; k < n_calls; ++k) {
+        for (int v = 0; v < views_per_call[k]; ++v) {
+            if (!dL[off[k] + v]) return fail(c, VGR_ERR_INVALID_ARG, "dL_dout[%d] is NULL", off[k] + v);
+            ps[k].vinfo[v].dL = dL[off[k] + v];
+        }
+        HIP_TRY(c, hipMemcpy(ptr<ViewInfo>(c->views_graph) + off[k], ps[k].vinfo.data(),
+                             sizeof(ViewInfo) * views_per_call[k], hipMemcpyHostToDevice));
     }
-    HIP_TRY(c, hipMemcpy(c->views_graph.p, p.vinfo.data(), sizeof(ViewInfo) * n_views,
-                         hipMemcpyHostToDevice));
     HIP_TRY(c, launch_fill_u32(ptr<uint32_t>(c->words) + 5, 0u, 1, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
@@ -950,11 +1024,15 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     Buffers b;
     int64_t K;
     rc = VGR_OK;
-    const ViewInfo *vg = ptr<ViewInfo>(c->views_graph);
-    if (!rc) rc = enqueue_forward(c, p, means, quats, scales, dens, sh, vg, cap, s, b, K);
-    if (!rc)
-        rc = enqueue_backward(c, p.rp, b, vg, means, quats, scales, dens, sh, d_means, d_quats,
-                              d_scales, d_dens, d_sh, zero_grads == 0, s);
+    // the calls run one after the other on the one workspace: each backward
+    // consumes its own forward before the next forward overwrites it
+    for (int k = 0; k < n_calls && !rc; ++k) {
+        const ViewInfo *vg = ptr<ViewInfo>(c->views_graph) + off[k];
+        rc = enqueue_forward(c, ps[k], means, quats, scales, dens, sh, vg, cap, s, b, K);
+        if (!rc)
+            rc = enqueue_backward(c, ps[k].rp, b, vg, means, quats, scales, dens, sh, d_means,
+                                  d_quats, d_scales, d_dens, d_sh, !(zero_grads && k == 0), s);
+    }
     c->counting = counting2;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -971,14 +1049,28 @@ int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float
     c->graph = g;
     c->graph_cap = cap;
     c->graph_valid = true;
-    // the captured pass also serves as the saved forward of this context
-    c->rp = p.rp;
+    // the last captured call also serves as the saved forward of this context
+    c->rp = ps[n_calls - 1].rp;
     c->buf = b;
     c->K = cap;
-    c->vinfo = p.vinfo;
+    c->vinfo = ps[n_calls - 1].vinfo;
     c->means = means; c->quats = quats; c->scales = scales; c->dens = dens; c->sh = sh;
     c->have_fwd = false;
     return VGR_OK;
+}
+
+int vgr_graph_capture(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
+                      const float *quats, const float *scales, const float *dens, const float *sh,
+                      int32_t n_views, const vgr_camera *cams, float *const *out,
+                      const float *const *dL, float *d_means, float *d_quats, float *d_scales,
+                      float *d_dens, float *d_sh, float capacity_factor, int32_t zero_grads)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    if (n_views < 1 || n_views > kMaxViews)
+        return fail(c, VGR_ERR_INVALID_ARG, "n_views must be in [1, %d]", kMaxViews);
+    return vgr_graph_capture_calls(c, st, n, means, quats, scales, dens, sh, 1, &n_views, cams, out,
+                                   dL, d_means, d_quats, d_scales, d_dens, d_sh, capacity_factor,
+                                   zero_grads);
 }
 
 int vgr_graph_launch(vgr_ctx *c)
@@ -1015,10 +1107,14 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
                  int32_t n_views, const vgr_camera *cams, float *const *out,
                  const float *const *dL, float *d_means, float *d_quats, float *d_scales,
                  float *d_dens, float *d_sh, int32_t iters, int32_t *best_w, int32_t *best_h,
-                 float *ms_per_candidate)
+                 int32_t *best_batch, float *ms_per_candidate)
 {
     if (!c || !st) return VGR_ERR_INVALID_ARG;
-    static const int cand[4][2] = { { 8, 8 }, { 16, 8 }, { 16, 16 }, { 32, 8 } };
+    if (n_views < 1 || n_views > kMaxViews || !cams)
+        return fail(c, VGR_ERR_INVALID_ARG, "bad views");
+    static const int cand[VGR_TUNE_CANDIDATES][3] = {
+        { 8, 8, 64 }, { 16, 8, 64 }, { 16, 16, 64 }, { 32, 8, 64 },
+        { 8, 8, 32 }, { 16, 8, 32 }, { 16, 16, 32 }, { 32, 8, 32 } };
     if (iters < 1) iters = 3;
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
@@ -1027,10 +1123,11 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
     c->timing = false;
     float best = 1e30f;
     int bi = -1, rc = VGR_OK;
-    for (int k = 0; k < 4 && !rc; ++k) {
+    for (int k = 0; k < VGR_TUNE_CANDIDATES && !rc; ++k) {
         vgr_settings s2 = *st;
         s2.tile_w = cand[k][0];
         s2.tile_h = cand[k][1];
+        s2.batch = cand[k][2];
         float ms = 0.f;
         for (int it = 0; it <= iters && !rc; ++it) {   // the first pass warms up
             if (it == 1) (void)hipEventRecord(e0, c->stream);
@@ -1052,8 +1149,63 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
     if (rc) return rc;
     c->tuned_w = cand[bi][0];
     c->tuned_h = cand[bi][1];
+    c->tuned_b = cand[bi][2];
+    c->tune_cache[tune_key(st, n, n_views, cams)] = TuneVal{ c->tuned_w, c->tuned_h, c->tuned_b, best };
     if (best_w) *best_w = c->tuned_w;
     if (best_h) *best_h = c->tuned_h;
+    if (best_batch) *best_batch = c->tuned_b;
+    return VGR_OK;
+}
+
+int vgr_tune_export(vgr_ctx *c, char *buf, int64_t cap, int64_t *len)
+{
+    if (!c) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    std::string txt;
+    char line[160];
+    for (const auto &kv : c->tune_cache) {
+        const TuneKey &k = kv.first;
+        const TuneVal &v = kv.second;
+        snprintf(line, sizeof line, "%d %d %d %d %d %d %d %d %d %d %.6g\n", k.pix_log2, k.n_log2,
+                 k.mode, k.alpha_model, k.kernel, k.tile_resort, k.near_segment, v.tile_w, v.tile_h,
+                 v.batch, (double)v.ms);
+        txt += line;
+    }
+    if (len) *len = (int64_t)txt.size() + 1;
+    if (!buf) return VGR_OK;
+    if (cap < (int64_t)txt.size() + 1)
+        return fail(c, VGR_ERR_INVALID_ARG, "buffer too small (%lld bytes needed)",
+                    (long long)txt.size() + 1);
+    memcpy(buf, txt.c_str(), txt.size() + 1);
+    return VGR_OK;
+}
+
+int vgr_tune_import(vgr_ctx *c, const char *text)
+{
+    if (!c || !text) return VGR_ERR_INVALID_ARG;
+    c->err.clear();
+    std::map<TuneKey, TuneVal> add;
+    const char *p = text;
+    int lineno = 0;
+    while (*p) {
+        const char *e = strchr(p, '\n');
+        const size_t L = e ? (size_t)(e - p) : strlen(p);
+        ++lineno;
+        std::string ln(p, L);
+        p += L + (e ? 1 : 0);
+        if (ln.find_first_not_of(" \t\r") == std::string::npos) continue;
+        TuneKey k{};
+        TuneVal v{};
+        double ms = 0.0;
+        if (sscanf(ln.c_str(), "%d %d %d %d %d %d %d %d %d %d %lf", &k.pix_log2, &k.n_log2, &k.mode,
+                   &k.alpha_model, &k.kernel, &k.tile_resort, &k.near_segment, &v.tile_w, &v.tile_h,
+                   &v.batch, &ms) != 11 ||
+            !valid_tile(v.tile_w, v.tile_h) || (v.batch != 32 && v.batch != 64))
+            return fail(c, VGR_ERR_INVALID_ARG, "tuning line %d is malformed", lineno);
+        v.ms = (float)ms;
+        add[k] = v;
+    }
+    for (const auto &kv : add) c->tune_cache[kv.first] = kv.second;
     return VGR_OK;
 }
 

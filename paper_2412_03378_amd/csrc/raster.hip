@@ -3,7 +3,8 @@
 // One wave (64 lanes) owns one screen tile of TW x TH pixels; lane l holds the
 // TW*TH/64 pixels of column l % TW, rows l / TW + k * (64 / TW) ("slot" k).
 // Tiles are launched in the order of b.tile_order (heaviest lists first).
-// The tile's depth-sorted Gaussian list is walked in batches of 64 records
+// The tile's depth-sorted Gaussian list is walked in batches of B records
+// (B = 64 or 32, the block shape the autotuner picks with the tile shape)
 // staged in LDS (structure of arrays).  The colour forward (and the X-ray
 // forward with one pixel per lane) pre-tests the whole batch with broadcast
 // reads and then lets every lane evaluate its own passing records in order
@@ -95,10 +96,19 @@ __device__ __forceinline__ uint32_t cu_key()
 // which the branch tests directly.
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
+template <int B>
 struct Stage {
-    float4 g[kStageVec][64];
-    uint32_t item[64];
+    float4 g[kStageVec][B];
+    uint32_t item[B];
 };
+
+// Word of the kept pre-test mask of lane `lane` for the batch that starts at
+// list position bs of global tile gt (layout: raster_keeps_masks).
+template <int B>
+__device__ __forceinline__ size_t mask_word(uint32_t bs, int gt, int lane)
+{
+    return (size_t)bs * (64 / B) + 64 * (size_t)gt + lane;
+}
 
 // Fields of the bound pre-test (g0..g2) and of the full evaluation (g3..g5).
 struct PreRec {
@@ -108,7 +118,8 @@ struct FullRec {
     float A01, A11, A21, v0x, v0y, v0z, K, se, c0, c1, c2, mz;
 };
 
-__device__ __forceinline__ PreRec load_pre(const Stage &st, int q)
+template <class ST>
+__device__ __forceinline__ PreRec load_pre(const ST &st, int q)
 {
     const float4 a = st.g[0][q], b = st.g[1][q], c = st.g[2][q];
     PreRec r;
@@ -118,7 +129,8 @@ __device__ __forceinline__ PreRec load_pre(const Stage &st, int q)
     return r;
 }
 
-__device__ __forceinline__ FullRec load_full(const Stage &st, int q)
+template <class ST>
+__device__ __forceinline__ FullRec load_full(const ST &st, int q)
 {
     const float4 a = st.g[3][q], b = st.g[4][q], c = st.g[5][q];
     FullRec r;
@@ -133,7 +145,8 @@ struct RecRegs {
     float4 g[kStageVec];
 };
 
-__device__ __forceinline__ RecRegs load_regs(const Stage &st, int q)
+template <class ST>
+__device__ __forceinline__ RecRegs load_regs(const ST &st, int q)
 {
     RecRegs r;
 #pragma unroll
@@ -164,7 +177,8 @@ __device__ __forceinline__ FullRec full_of(const RecRegs &x)
     return r;
 }
 
-__device__ __forceinline__ void stage_record(Stage &st, const Buffers &b, int lane, uint32_t item)
+template <class ST>
+__device__ __forceinline__ void stage_record(ST &st, const Buffers &b, int lane, uint32_t item)
 {
     const float4 *gp = b.geom + (size_t)item * kRecVec;
 #pragma unroll
@@ -237,16 +251,17 @@ struct Counts {
     uint32_t test = 0, full = 0, blend = 0, visits = 0, visits_full = 0;
 };
 
-template <int TW, int TH, int MODE, bool COUNT>
+template <int TW, int TH, int MODE, bool COUNT, int B>
 __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers b)
 {
+    static_assert(B == 32 || B == 64, "records per batch");
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
     constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear && MODE != kModeXrayEpan;
     constexpr bool SPLAT = MODE == kModeSplat;   // colour with the 3DGS splatting alpha
     constexpr bool NEAR = MODE == kModeColorNear || MODE == kModeXrayNear;
     constexpr bool EPAN = MODE == kModeColorEpan || MODE == kModeXrayEpan;
-    __shared__ Stage st;
+    __shared__ Stage<B> st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
     const uint64_t t_start = timed ? wg_clock() : 0;
@@ -282,11 +297,11 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     const float amin = rp.amin, amax = rp.amax;
     const float zn = vi.znear;
 
-    for (uint32_t bs = range.x; bs < range.y; bs += 64) {
+    for (uint32_t bs = range.x; bs < range.y; bs += B) {
         const uint32_t j = bs + lane;
-        if (j < range.y) stage_record(st, b, lane, b.inst_val[j]);
+        if (lane < B && j < range.y) stage_record(st, b, lane, b.inst_val[j]);
         __syncthreads();
-        const int nb = (int)min(64u, range.y - bs);
+        const int nb = (int)min((uint32_t)B, range.y - bs);
         if constexpr (PPL == 1 || COLOR) {
             // Phase 1: bound pre-test of the whole batch (broadcast records);
             // bit q of mask[k] marks record q as passing for the lane's slot k.
@@ -294,7 +309,9 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
             // select of a wave-uniform constant.
             uint32_t mhalf[2][PPL];
     #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int k = 0; k < PPL; ++k) mhalf[1][k] = 0u;   // B = 32: one half
+    #pragma unroll
+            for (int h = 0; h < B / 32; ++h) {
     #pragma unroll
                 for (int k = 0; k < PPL; ++k) mhalf[h][k] = 0u;
                 const int qend = min(nb, 32 * h + 32);
@@ -322,7 +339,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
             // kept for the backward (layout: raster_keeps_masks)
     #pragma unroll
             for (int k = 0; k < PPL; ++k)
-                b.pmask[((size_t)bs + 64 * (size_t)gt + lane) * PPL + k] = mask[k];
+                b.pmask[mask_word<B>(bs, gt, lane) * PPL + k] = mask[k];
             // Phase 2: every lane evaluates and blends its own passing records in
             // list order, one per step (records read from LDS at per-lane
             // addresses), so a step does useful work on every lane that still has
@@ -567,9 +584,10 @@ __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
     return v[0];
 }
 
-template <int TW, int TH, int MODE, bool COUNT>
+template <int TW, int TH, int MODE, bool COUNT, int B>
 __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers b)
 {
+    static_assert(B == 32 || B == 64, "records per batch");
     constexpr int PPL = TileMap<TW, TH>::PPL;
     constexpr int RS = TileMap<TW, TH>::RS;
     constexpr bool COLOR = MODE != VGR_MODE_XRAY && MODE != kModeXrayNear && MODE != kModeXrayEpan;
@@ -579,7 +597,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     constexpr int NCH = COLOR ? 3 : 1;
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
-    __shared__ Stage st;
+    __shared__ Stage<B> st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
     const uint64_t t_start = timed ? wg_clock() : 0;
@@ -789,10 +807,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     if constexpr (KEEP) {
         // Batches aligned as in the forward, whose pre-test masks are reused:
         // the walk visits only records some pixel of the tile admits.
-        for (int bs = (int)range.x + ((maxlast - (int)range.x) & ~63); bs >= (int)range.x;
-             bs -= 64) {
+        for (int bs = (int)range.x + ((maxlast - (int)range.x) / B) * B; bs >= (int)range.x;
+             bs -= B) {
             const int j = bs + lane;
-            if (j <= maxlast) stage_record(st, b, lane, b.inst_val[j]);
+            if (lane < B && j <= maxlast) stage_record(st, b, lane, b.inst_val[j]);
             uint64_t mask[PPL];
             uint64_t any = 0;
 #pragma unroll
@@ -800,7 +818,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 // records of the batch up to the pixel's last blended one
                 const int d = last[k] - bs;
                 const uint64_t lim = d < 0 ? 0ull : (d >= 63 ? ~0ull : (2ull << d) - 1ull);
-                mask[k] = b.pmask[((size_t)bs + 64 * (size_t)gt + lane) * PPL + k] & lim;
+                mask[k] = b.pmask[mask_word<B>((uint32_t)bs, gt, lane) * PPL + k] & lim;
                 any |= mask[k];
             }
             // union over the wave: OR within each row of 16 lanes, then of the rows
@@ -834,10 +852,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             __syncthreads();
         }
     } else {
-        for (int be = maxlast + 1; be > (int)range.x; be -= 64) {
-            const int bs = max((int)range.x, be - 64);
+        for (int be = maxlast + 1; be > (int)range.x; be -= B) {
+            const int bs = max((int)range.x, be - B);
             const int j = bs + lane;
-            if (j < be) stage_record(st, b, lane, b.inst_val[j]);
+            if (lane < B && j < be) stage_record(st, b, lane, b.inst_val[j]);
             __syncthreads();
             for (int qi = be - 1 - bs; qi >= 0; --qi) {
                 const int jpos = bs + qi;
@@ -875,70 +893,92 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int B>
 hipError_t fwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     const dim3 grid(rp.total_tiles), block(64);
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
-        if (count) raster_fwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_fwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_fwd_kernel<TW, TH, kModeSplat, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_fwd_kernel<TW, TH, kModeSplat, false, B><<<grid, block, 0, s>>>(rp, b);
     } else if (rp.kernel == VGR_KERNEL_EPANECHNIKOV) {
         if (rp.mode == VGR_MODE_COLOR) {
-            if (count) raster_fwd_kernel<TW, TH, kModeColorEpan, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_fwd_kernel<TW, TH, kModeColorEpan, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_fwd_kernel<TW, TH, kModeColorEpan, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeColorEpan, false, B><<<grid, block, 0, s>>>(rp, b);
         } else {
-            if (count) raster_fwd_kernel<TW, TH, kModeXrayEpan, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_fwd_kernel<TW, TH, kModeXrayEpan, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_fwd_kernel<TW, TH, kModeXrayEpan, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeXrayEpan, false, B><<<grid, block, 0, s>>>(rp, b);
         }
     } else if (rp.near_segment) {
         if (rp.mode == VGR_MODE_COLOR) {
-            if (count) raster_fwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_fwd_kernel<TW, TH, kModeColorNear, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_fwd_kernel<TW, TH, kModeColorNear, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeColorNear, false, B><<<grid, block, 0, s>>>(rp, b);
         } else {
-            if (count) raster_fwd_kernel<TW, TH, kModeXrayNear, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_fwd_kernel<TW, TH, kModeXrayNear, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_fwd_kernel<TW, TH, kModeXrayNear, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_fwd_kernel<TW, TH, kModeXrayNear, false, B><<<grid, block, 0, s>>>(rp, b);
         }
     } else if (rp.mode == VGR_MODE_COLOR) {
-        if (count) raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_fwd_kernel<TW, TH, VGR_MODE_COLOR, false, B><<<grid, block, 0, s>>>(rp, b);
     } else {
-        if (count) raster_fwd_kernel<TW, TH, VGR_MODE_XRAY, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_fwd_kernel<TW, TH, VGR_MODE_XRAY, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_fwd_kernel<TW, TH, VGR_MODE_XRAY, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_fwd_kernel<TW, TH, VGR_MODE_XRAY, false, B><<<grid, block, 0, s>>>(rp, b);
     }
     return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int B>
 hipError_t bwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     const dim3 grid(rp.total_tiles), block(64);
     if (rp.alpha_model == VGR_ALPHA_SPLAT) {
-        if (count) raster_bwd_kernel<TW, TH, kModeSplat, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_bwd_kernel<TW, TH, kModeSplat, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_bwd_kernel<TW, TH, kModeSplat, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_bwd_kernel<TW, TH, kModeSplat, false, B><<<grid, block, 0, s>>>(rp, b);
     } else if (rp.kernel == VGR_KERNEL_EPANECHNIKOV) {
         if (rp.mode == VGR_MODE_COLOR) {
-            if (count) raster_bwd_kernel<TW, TH, kModeColorEpan, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_bwd_kernel<TW, TH, kModeColorEpan, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_bwd_kernel<TW, TH, kModeColorEpan, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeColorEpan, false, B><<<grid, block, 0, s>>>(rp, b);
         } else {
-            if (count) raster_bwd_kernel<TW, TH, kModeXrayEpan, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_bwd_kernel<TW, TH, kModeXrayEpan, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_bwd_kernel<TW, TH, kModeXrayEpan, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeXrayEpan, false, B><<<grid, block, 0, s>>>(rp, b);
         }
     } else if (rp.near_segment) {
         if (rp.mode == VGR_MODE_COLOR) {
-            if (count) raster_bwd_kernel<TW, TH, kModeColorNear, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_bwd_kernel<TW, TH, kModeColorNear, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_bwd_kernel<TW, TH, kModeColorNear, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeColorNear, false, B><<<grid, block, 0, s>>>(rp, b);
         } else {
-            if (count) raster_bwd_kernel<TW, TH, kModeXrayNear, true><<<grid, block, 0, s>>>(rp, b);
-            else raster_bwd_kernel<TW, TH, kModeXrayNear, false><<<grid, block, 0, s>>>(rp, b);
+            if (count) raster_bwd_kernel<TW, TH, kModeXrayNear, true, B><<<grid, block, 0, s>>>(rp, b);
+            else raster_bwd_kernel<TW, TH, kModeXrayNear, false, B><<<grid, block, 0, s>>>(rp, b);
         }
     } else if (rp.mode == VGR_MODE_COLOR) {
-        if (count) raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_bwd_kernel<TW, TH, VGR_MODE_COLOR, false, B><<<grid, block, 0, s>>>(rp, b);
     } else {
-        if (count) raster_bwd_kernel<TW, TH, VGR_MODE_XRAY, true><<<grid, block, 0, s>>>(rp, b);
-        else raster_bwd_kernel<TW, TH, VGR_MODE_XRAY, false><<<grid, block, 0, s>>>(rp, b);
+        if (count) raster_bwd_kernel<TW, TH, VGR_MODE_XRAY, true, B><<<grid, block, 0, s>>>(rp, b);
+        else raster_bwd_kernel<TW, TH, VGR_MODE_XRAY, false, B><<<grid, block, 0, s>>>(rp, b);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+namespace {
+
+template <int B>
+hipError_t fwd_batch(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
+{
+    if (rp.tile_w == 8 && rp.tile_h == 8) return fwd_shape<8, 8, B>(rp, b, count, s);
+    if (rp.tile_w == 16 && rp.tile_h == 8) return fwd_shape<16, 8, B>(rp, b, count, s);
+    if (rp.tile_w == 32 && rp.tile_h == 8) return fwd_shape<32, 8, B>(rp, b, count, s);
+    return fwd_shape<16, 16, B>(rp, b, count, s);
+}
+
+template <int B>
+hipError_t bwd_batch(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
+{
+    if (rp.tile_w == 8 && rp.tile_h == 8) return bwd_shape<8, 8, B>(rp, b, count, s);
+    if (rp.tile_w == 16 && rp.tile_h == 8) return bwd_shape<16, 8, B>(rp, b, count, s);
+    if (rp.tile_w == 32 && rp.tile_h == 8) return bwd_shape<32, 8, B>(rp, b, count, s);
+    return bwd_shape<16, 16, B>(rp, b, count, s);
 }
 
 }  // namespace
@@ -946,19 +986,13 @@ hipError_t bwd_shape(const RenderParams &rp, const Buffers &b, bool count, hipSt
 hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     if (rp.total_tiles <= 0) return hipSuccess;
-    if (rp.tile_w == 8 && rp.tile_h == 8) return fwd_shape<8, 8>(rp, b, count, s);
-    if (rp.tile_w == 16 && rp.tile_h == 8) return fwd_shape<16, 8>(rp, b, count, s);
-    if (rp.tile_w == 32 && rp.tile_h == 8) return fwd_shape<32, 8>(rp, b, count, s);
-    return fwd_shape<16, 16>(rp, b, count, s);
+    return rp.batch == 32 ? fwd_batch<32>(rp, b, count, s) : fwd_batch<64>(rp, b, count, s);
 }
 
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     if (rp.total_tiles <= 0) return hipSuccess;
-    if (rp.tile_w == 8 && rp.tile_h == 8) return bwd_shape<8, 8>(rp, b, count, s);
-    if (rp.tile_w == 16 && rp.tile_h == 8) return bwd_shape<16, 8>(rp, b, count, s);
-    if (rp.tile_w == 32 && rp.tile_h == 8) return bwd_shape<32, 8>(rp, b, count, s);
-    return bwd_shape<16, 16>(rp, b, count, s);
+    return rp.batch == 32 ? bwd_batch<32>(rp, b, count, s) : bwd_batch<64>(rp, b, count, s);
 }
 
 }  // namespace vgr

@@ -118,6 +118,7 @@ struct RenderParams {
     int32_t near_segment;// integrate from the near plane (records flagged by K' < 0)
     int32_t tile_resort; // per-tile order by the depth of the maximum on the tile-centre ray
     int32_t kernel;      // VGR_KERNEL_GAUSSIAN or VGR_KERNEL_EPANECHNIKOV
+    int32_t batch;       // records staged per rasteriser batch: 32 or 64
 };
 
 // Device workspace views handed to kernels.
@@ -144,7 +145,7 @@ struct Buffers {
     int32_t *last_pos;   // total pixels: list position of last blended (-1)
     int32_t *last_id;    // total pixels: Gaussian index of last blended (-1)
     float4 *rgrad;       // n_views * n * 4 float4 (record gradients)
-    uint64_t *pmask;     // pmask_words(): bound pre-test lane masks of each 64-record
+    uint64_t *pmask;     // pmask_words(): bound pre-test lane masks of each B-record
                          // batch of a tile list, written by the forward where
                          // raster_keeps_masks() and read by the backward
     uint32_t *blk_counts;// preprocess blocks: instances per block
@@ -158,20 +159,21 @@ struct Buffers {
     const ViewInfo *views;
 };
 
-// The forward keeps, for each 64-record batch of a tile's list, every lane's
+// The forward keeps, for each B-record batch of a tile's list, every lane's
 // bound pre-test mask per pixel slot (bit q: record q of the batch may reach
 // the pixel), where it computes them for the whole batch: colour mode, and
 // X-ray mode with one pixel per lane.  Batch k of tile t (records
-// start_t + 64 k ...) keeps its masks at words
-// ((start_t + 64 t + 64 k + lane) * ppl + slot): tile t's batches span fewer
-// than len_t + 64 instance slots, so the tiles' spans do not overlap.
+// start_t + B k ...) keeps its masks at words
+// (((start_t + B k) 64/B + 64 t + lane) * ppl + slot): tile t's batches span
+// fewer than len_t 64/B + 64 slots, so the tiles' spans do not overlap.
 inline bool raster_keeps_masks(int mode, int tile_w, int tile_h)
 {
     return mode == VGR_MODE_COLOR || tile_w * tile_h == 64;
 }
-inline int64_t pmask_words(int64_t instances, int32_t total_tiles, int tile_w, int tile_h)
+inline int64_t pmask_words(int64_t instances, int32_t total_tiles, int tile_w, int tile_h,
+                           int batch)
 {
-    return (instances + 64 * (int64_t)total_tiles) * (int64_t)(tile_w * tile_h / 64);
+    return (instances * (64 / batch) + 64 * (int64_t)total_tiles) * (int64_t)(tile_w * tile_h / 64);
 }
 
 // ---- launches (each returns hipSuccess or the first error) ----

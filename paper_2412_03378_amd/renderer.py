@@ -32,6 +32,7 @@ class Settings:
     near_segment: bool = False       # integrate each ray from the near plane on
     tile_resort: bool = False        # per-tile order by the depth of each maximum
     kernel: str = "gaussian"         # "gaussian" | "epanechnikov" (compact primitive)
+    batch: int = 0                   # records per rasteriser batch: 32, 64, 0 = tuned
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -47,6 +48,7 @@ class Settings:
         s.near_segment = 1 if self.near_segment else 0
         s.tile_resort = 1 if self.tile_resort else 0
         s.kernel = L.VGR_KERNEL_EPANECHNIKOV if self.kernel == "epanechnikov" else L.VGR_KERNEL_GAUSSIAN
+        s.batch = int(self.batch)
         return s
 
     @staticmethod
@@ -231,6 +233,20 @@ class Renderer:
         L.check(self._lib.vgr_graph_capture(self._h, *args, float(capacity_factor),
                                             int(bool(zero_grads))), self._h)
 
+    def graph_capture_calls(self, params, cams, views_per_call, settings, outs, dL, grads,
+                            capacity_factor=1.25, zero_grads=True):
+        """Capture several forward + backward calls (views_per_call[k] of the
+        cameras each, in order) into one HIP graph (vgr_graph_capture_calls);
+        the backwards add to the same gradients."""
+        self._sync_stream()
+        keep, args = self._step_args(params, cams, settings, outs, dL, grads)
+        vpc = (C.c_int32 * len(views_per_call))(*[int(v) for v in views_per_call])
+        self._graph_keep = (keep, params, outs, dL, grads, vpc)
+        # args: settings, n, 5 params, n_views, cams, outs, dL, 5 grads
+        L.check(self._lib.vgr_graph_capture_calls(
+            self._h, args[0], args[1], *args[2:7], len(views_per_call), vpc, *args[8:],
+            float(capacity_factor), int(bool(zero_grads))), self._h)
+
     def graph_launch(self):
         L.check(self._lib.vgr_graph_launch(self._h), self._h)
 
@@ -241,14 +257,27 @@ class Renderer:
         return int(k.value)
 
     def autotune(self, params, cams, settings, outs, dL=None, grads=None, iters=3):
-        """Pick the fastest tile shape for this workload; returns ((w, h), ms list)."""
+        """Pick the fastest launch shape (tile and records per batch) for this
+        workload; returns ((w, h), batch, ms per candidate)."""
         self._sync_stream()
         keep, args = self._step_args(params, cams, settings, outs, dL, grads)
-        bw, bh = C.c_int32(), C.c_int32()
-        ms = (C.c_float * 4)()
-        L.check(self._lib.vgr_autotune(self._h, *args, int(iters), C.byref(bw), C.byref(bh), ms),
-                self._h)
-        return (bw.value, bh.value), [float(x) for x in ms]
+        bw, bh, bb = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = (C.c_float * L.VGR_TUNE_CANDIDATES)()
+        L.check(self._lib.vgr_autotune(self._h, *args, int(iters), C.byref(bw), C.byref(bh),
+                                       C.byref(bb), ms), self._h)
+        return (bw.value, bh.value), bb.value, [float(x) for x in ms]
+
+    def tuning_text(self) -> str:
+        """The tuned shapes per workload class (vgr_tune_export)."""
+        n = C.c_int64()
+        L.check(self._lib.vgr_tune_export(self._h, None, 0, C.byref(n)), self._h)
+        buf = C.create_string_buffer(int(n.value))
+        L.check(self._lib.vgr_tune_export(self._h, buf, int(n.value), C.byref(n)), self._h)
+        return buf.value.decode()
+
+    def load_tuning(self, text: str):
+        """Merge shapes written by tuning_text (vgr_tune_import)."""
+        L.check(self._lib.vgr_tune_import(self._h, text.encode()), self._h)
 
     def sort_pairs(self, keys: torch.Tensor, vals: torch.Tensor, bits: int):
         """In-place stable radix sort of (u32 key, u32 value) device pairs."""
