@@ -125,7 +125,7 @@ def bench_headline(args, torch, dev):
     dLs = [torch.from_numpy(d).to(dev) for d in wl.dL]
     grads = [torch.zeros_like(p) for p in params]
     tile = tuple(args.tile)
-    st = Settings(sh_degree=3, tile=tile)
+    st = Settings(sh_degree=3, tile=tile, batch=args.batch)
     r = Renderer(0)
     cams = wl.cams
     _log("warm-up")
@@ -309,18 +309,28 @@ def bench_batched(args, torch, dev):
     res["tile_single"] = list(tile1)
     res["batch_single"] = batch1
 
-    def run():
+    def eager(calls):
+        for _ in range(max(1, args.warmup // 2)):
+            calls()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            calls()
+        torch.cuda.synchronize()
+        return nv / ((time.perf_counter() - t0) / args.batched_steps)
+
+    def run_single():
         for k, (c, d) in enumerate(zip(wl.cams, dLs)):
             r.forward(*params, [c], st1)
             r.backward([d], *grads, accumulate=k > 0)
-    for _ in range(max(1, args.warmup // 2)):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.batched_steps):
-        run()
-    torch.cuda.synchronize()
-    res["single"] = nv / ((time.perf_counter() - t0) / args.batched_steps)
+    # like for like: eager against eager (each single-view call waits on the
+    # host for its instance count, as the batched call does once), and one
+    # captured graph against one captured graph of the 16 single-view calls
+    res["single"] = eager(run_single)
+    res["batched_eager"] = eager(call_all)
+    r.graph_capture_calls(params, wl.cams, [1] * nv, st1, outs, dLs, grads, capacity_factor=1.1,
+                          zero_grads=True)
+    res["single_graph"] = nv / _graph_time(r, args.batched_steps, torch)
     del params, grads, dLs, outs
     if not args.no_cpu_baseline:
         import oracle
@@ -427,12 +437,24 @@ def bench_train(args, torch, dev, views_per_call=16):
         return dt, stages
 
     dt, stages = timed(params, st)
+    # the same step as one captured graph of its four 16-view calls
+    _log("training step as one captured graph")
+    outs = [torch.empty((3, c.height, c.width), device=dev) for c in wl.cams]
+    r.graph_capture_calls(params, wl.cams, [views_per_call] * (nv // views_per_call), st, outs,
+                          dLs, grads, capacity_factor=1.1, zero_grads=True)
+    dt_graph = _graph_time(r, args.train_steps, torch)
+    del outs
+
     def call_one():
         r.forward(*params, wl.cams[:views_per_call], st)
         r.backward(dLs[:views_per_call], *grads, accumulate=True)
     out = {"workload": "training step: 6M Gaussians (1024 clusters), SH3, 64 views 1920x1080, "
                        "fwd+bwd accumulated into FP32 parameter gradients, 16 views per call",
-           "tile": list(tile), "ms_per_step": round(dt * 1e3, 2), "views_per_s": round(nv / dt, 1),
+           "tile": list(tile), "batch": batch, "ms_per_step": round(dt * 1e3, 2),
+           "views_per_s": round(nv / dt, 1),
+           "graph": {"ms_per_step": round(dt_graph * 1e3, 2),
+                     "views_per_s": round(nv / dt_graph, 1),
+                     "note": "the four 16-view calls captured in one hipGraph and replayed"},
            "rasterisers_one_call": _raster_rates(r, call_one, tile[0] * tile[1] / 64.0, "color")}
     # the same step with the paper's training inputs: theta as the density
     # input (kappa computed in the preprocess) and the densification
@@ -493,14 +515,35 @@ def _oracle_view_ms(scene, cam, dL, n_pix, st, seed=0):
     return (setup + per_pix * cam.width * cam.height) * 1e3, t1 + t2
 
 
-def cpu_baseline(wl, n_pix):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, n_pix, n_pix_1core=16):
     """FP64 oracle, forward + backward on n_pix pixels of the headline frame
-    (all Gaussians per pixel), extrapolated to the whole frame."""
+    (all Gaussians per pixel), extrapolated to the whole frame, on all host
+    threads and on one."""
     import oracle
     cam = wl.cams[0]
     total_ms, t_all = _oracle_view_ms(wl.scene, cam, wl.dL[0], n_pix, oracle.Settings())
+    threads = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        one_ms, t_one = _oracle_view_ms(wl.scene, cam, wl.dL[0], n_pix_1core, oracle.Settings())
+    finally:
+        oracle.set_threads(threads)
     return {"value": total_ms, "unit": "ms per fwd+bwd (extrapolated)",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle", "cpu_model": _cpu_model(),
+            "one_core": {"value": one_ms, "cores": 1,
+                         "sample": f"{n_pix_1core // 2} and then {n_pix_1core} pixels "
+                                   f"({t_one:.1f} s), extrapolated the same way"},
             "sample": f"fwd+bwd of {n_pix // 2} and then {n_pix} random pixels of the "
                       f"1920x1080 frame over all {wl.scene.n} Gaussians in FP64 ({t_all:.1f} s); "
                       f"per-pixel cost from the difference, scaled to "
@@ -560,12 +603,112 @@ def write_traffic(fetch_csv, write_csv, out_path=TRAFFIC_FILE):
     print(json.dumps(res))
 
 
+# Algorithmic HBM bytes per dispatch of the headline step (1M Gaussians, SH3,
+# one 1920x1080 view, 8x8 tiles): n = m = 1M items, K instances, 32400 tiles.
+#   preprocess: parameters in (means 12, quats 16, scales 12, dens 4, SH 192 B)
+#     and record (128 B), depth key, item id, tile count (4 B each) and tile
+#     rectangle (8 B) out per Gaussian                      236 + 148 B per item
+#   radix scatter: key and value read and written once          16 B per key
+#   radix histogram: key read once                               4 B per key
+#   emission: key and value written per instance                  8 B per instance
+#   ranges: key read per instance                                 4 B per instance
+#   record-gradient zeroing: 16 floats per item                 64 B per item
+#   preprocess backward: parameters (236 B) and record gradient (64 B) in,
+#     parameter gradients (236 B) out                           536 B per item
+def algorithmic_bytes(kernel, n_items, n_inst):
+    depth = kernel.endswith("<4>")          # the 1M-key depth sort uses 1024-key tiles
+    keys = n_items if depth else n_inst
+    table = {"preprocess_kernel": 384 * n_items, "radix_scatter_kernel": 16 * keys,
+             "radix_hist_kernel": 4 * keys, "emit_kernel": 8 * n_inst, "ranges_kernel": 4 * n_inst,
+             "fill_f32_kernel": 64 * n_items, "preprocess_bwd_kernel": 536 * n_items}
+    for k, v in table.items():
+        if kernel.startswith(k):
+            return v
+    return None
+
+
+def _short_kernel(name):
+    import re
+    k = re.sub(r"^void ", "", name)
+    k = re.sub(r"vgr::\(anonymous namespace\)::", "", k)
+    return k.split("(")[0].strip()
+
+
+def profile_summary(root, n_items=1_000_000):
+    """Markdown table of every kernel of the `bench.py --profile` run from
+    rocprofv3 output under root/{trace,fetch,write,sq}: mean duration (kernel
+    trace), HBM bytes per dispatch (FETCH_SIZE and WRITE_SIZE scaled by the
+    calibration copy), achieved GB/s and share of 8 TB/s, algorithmic bytes
+    where stated, VALU instructions and the FP32 FLOP counter (unit from the
+    calibration multiply)."""
+    import csv
+    import statistics
+
+    def counters(sub):
+        per = {}
+        for row in csv.DictReader(open(os.path.join(root, sub, "run_counter_collection.csv"))):
+            per.setdefault((_short_kernel(row["Kernel_Name"]), row["Counter_Name"]), []).append(
+                float(row["Counter_Value"]))
+        return per
+
+    stats = {}
+    for row in csv.DictReader(open(os.path.join(root, "trace", "run_kernel_stats.csv"))):
+        stats[_short_kernel(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]))
+    fetch, write, sq = counters("fetch"), counters("write"), counters("sq")
+    copy = "__amd_rocclr_copyBuffer"
+    fscale = CALIB_COPY_BYTES / (max(fetch[(copy, "FETCH_SIZE")]) * 1024.0)
+    wscale = CALIB_COPY_BYTES / (max(write[(copy, "WRITE_SIZE")]) * 1024.0)
+    mul = [k for (k, c) in sq if c == "SQ_INSTS_VALU_FLOPS_FP32" and "MulFunctor" in k]
+    flop_unit = None
+    if mul:
+        v = max(sq[(mul[0], "SQ_INSTS_VALU_FLOPS_FP32")])
+        flop_unit = (CALIB_COPY_BYTES // 4) / v if v > 0 else None
+    n_inst = None
+    lines = []
+    rows = []
+    for k, (calls, avg_ns) in sorted(stats.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        if k.startswith("at::native") or k == copy:
+            continue
+        f = fetch.get((k, "FETCH_SIZE"))
+        w = write.get((k, "WRITE_SIZE"))
+        fb = statistics.median(f) * 1024.0 * fscale if f else None
+        wb = statistics.median(w) * 1024.0 * wscale if w else None
+        tot = (fb or 0.0) + (wb or 0.0) if (fb is not None or wb is not None) else None
+        valu = sq.get((k, "SQ_INSTS_VALU"))
+        flops = sq.get((k, "SQ_INSTS_VALU_FLOPS_FP32"))
+        rows.append(dict(kernel=k, calls=calls, us=avg_ns / 1e3, fetch=fb, write=wb, total=tot,
+                         valu=statistics.median(valu) if valu else None,
+                         flops=statistics.median(flops) if flops else None))
+    return rows, fscale, wscale, flop_unit
+
+
+def print_profile_summary(root, n_inst, n_items=1_000_000):
+    rows, fscale, wscale, flop_unit = profile_summary(root, n_items)
+    print(f"FETCH_SIZE x {fscale:.4f}, WRITE_SIZE x {wscale:.4f} (256 MiB calibration copy); "
+          f"SQ_INSTS_VALU_FLOPS_FP32 x {flop_unit if flop_unit is None else round(flop_unit, 3)} "
+          f"= FP32 FLOPs (calibration: one multiply per element of 2^26)\n")
+    print("| kernel | calls | mean us | HBM bytes / dispatch | GB/s | of 8 TB/s | algorithmic bytes "
+          "| algorithmic GB/s | VALU insts | FP32 FLOPs (counter) |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        gbs = r["total"] / (r["us"] * 1e3) if r["total"] is not None else None
+        ab = algorithmic_bytes(r["kernel"], n_items, n_inst)
+        abs_ = ab / (r["us"] * 1e3) if ab else None
+        fl = r["flops"] * flop_unit if (r["flops"] is not None and flop_unit) else None
+        fmt = lambda v, f: "-" if v is None else format(v, f)
+        print(f"| `{r['kernel']}` | {r['calls']} | {r['us']:.1f} | {fmt(r['total'], '.3g')} | "
+              f"{fmt(gbs, '.0f')} | {fmt(None if gbs is None else gbs / 8000.0, '.3f')} | "
+              f"{fmt(ab, '.3g')} | {fmt(abs_, '.0f')} | {fmt(r['valu'], '.3g')} | {fmt(fl, '.3g')} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", type=int, nargs=2, default=(8, 8))
+    ap.add_argument("--batch", type=int, default=64, choices=(32, 64),
+                    help="records per rasteriser batch of the headline step")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-xray", action="store_true")
@@ -577,10 +720,16 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter-based traffic summary from two rocprofv3 --pmc "
                          "counter_collection.csv files and exit")
+    ap.add_argument("--profile-summary", nargs=2, metavar=("PROF_DIR", "N_INSTANCES"),
+                    help="print the per-kernel table of a profiled run (rocprofv3 output in "
+                         "PROF_DIR/{trace,fetch,write,sq}) as markdown and exit")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one plain device copy of known size "
                          "(counter calibration), then warm-up and timed headline steps only")
     args = ap.parse_args()
+    if args.profile_summary:
+        print_profile_summary(args.profile_summary[0], int(args.profile_summary[1]))
+        return
     if args.traffic_from:
         write_traffic(*args.traffic_from)
         return
@@ -601,6 +750,9 @@ def main():
         src = torch.ones(CALIB_COPY_BYTES // 4, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
+        # one FP32 multiply per element of a known count: calibrates the unit
+        # of the FP32 FLOP counter
+        dst.mul_(1.0001)
         torch.cuda.synchronize()
         del src, dst
     h = bench_headline(args, torch, dev)
@@ -617,7 +769,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single view 1920x1080, 1M clustered Gaussians (64 clusters), "
                                "SH degree 3, fwd+bwd, upstream N(0,1)",
-                   "tile": list(args.tile), "instances": h["stats"]["instances"]},
+                   "tile": list(args.tile), "batch": args.batch,
+                   "instances": h["stats"]["instances"]},
         "graph_ms_per_step": round(h["graph_ms"], 4),
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "pairs": {k: h["stats"][k] for k in ("pairs_tested", "pairs_full", "pairs_blended",
@@ -639,11 +792,23 @@ def main():
         out["batched"] = {"workload": "16 views mixed resolution (640x480..1920x1080), 3M "
                                       "Gaussians, SH3, fwd+bwd; batched = one hipGraph "
                                       "replay of all views, single = one call per view",
-                          "tile": res["tile"], "autotune_ms": res["autotune_ms"],
-                          "tile_single": res["tile_single"],
+                          "tile": res["tile"], "batch": res["batch"],
+                          "autotune_ms": res["autotune_ms"],
+                          "tile_single": res["tile_single"], "batch_single": res["batch_single"],
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3),
+                          "like_for_like": {
+                              "graph": {"batched": round(res["batched"], 2),
+                                        "single": round(res["single_graph"], 2),
+                                        "speedup": round(res["batched"] / res["single_graph"], 3),
+                                        "note": "one graph of the 16-view call against one "
+                                                "graph of the 16 single-view calls"},
+                              "eager": {"batched": round(res["batched_eager"], 2),
+                                        "single": round(res["single"], 2),
+                                        "speedup": round(res["batched_eager"] / res["single"], 3),
+                                        "note": "one eager 16-view call against 16 eager "
+                                                "single-view calls"}},
                           "load_balance": res["load_balance"],
                           "rasterisers": res["rasterisers"]}
         if "oracle" in res:
