@@ -55,7 +55,7 @@ class _Settings(C.Structure):
     _fields_ = [("mode", C.c_int32), ("sh_degree", C.c_int32), ("act", C.c_int32),
                 ("density", C.c_int32), ("alpha_model", C.c_int32), ("near_segment", C.c_int32),
                 ("tile_resort", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("kernel", C.c_int32),
+                ("kernel", C.c_int32), ("pixel_window", C.c_int32), ("pad3", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("T_min", C.c_double), ("x_min_xray", C.c_double), ("bg", C.c_double * 3),
                 ("near_threshold", C.c_double)]
@@ -77,6 +77,7 @@ class Settings:
     near_segment: bool = False     # integrate each ray from the near plane on (Sec. 4.2)
     resort_tile: tuple = None      # (w, h): per-tile order by gamma on the tile-centre ray
     kernel: str = "gaussian"       # "gaussian" | "epanechnikov" (compact, Sec. 8)
+    pixel_window: int = 0          # > 0 (with resort_tile): per-pixel re-sorting window
 
     @staticmethod
     def no_thresholds(mode="color", act="softplus", bg=(0.0, 0.0, 0.0), density="kappa",
@@ -141,6 +142,7 @@ def _settings(st: Settings, sh_degree: int) -> _Settings:
     if st.resort_tile:
         s.tile_resort = 1
         s.tile_w, s.tile_h = int(st.resort_tile[0]), int(st.resort_tile[1])
+    s.pixel_window = int(st.pixel_window or 0)
     s.alpha_min, s.alpha_max = float(st.alpha_min), float(st.alpha_max)
     s.T_min, s.x_min_xray = float(st.T_min), float(st.x_min_xray)
     s.bg[:] = [float(v) for v in st.bg]
@@ -216,7 +218,14 @@ def render(scene, cam, settings: Settings = None, pixels=None):
     (amplification: the summed amplifications of the factors of T);
     ``margin_order`` (per-tile re-sorting only, else inf) the smallest
     relative gap between the order keys of two Gaussians that reach the
-    pixel."""
+    pixel (per-tile keys, and with a pixel window the per-pixel gammas too).
+
+    ``pixel_window`` W > 0 (with ``resort_tile``): the Gaussians that reach
+    alpha_min at a pixel, in the per-tile order, pass through a window of W
+    entries ordered by gamma on the pixel's own ray; the smallest leaves the
+    window to be composited whenever it is full, the rest at the end.  W = 1
+    is the per-tile order; W at least the number of such Gaussians is the
+    exact per-pixel order by gamma."""
     lib = _load()
     st = settings or Settings()
     full = pixels is None

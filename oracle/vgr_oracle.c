@@ -93,6 +93,8 @@ typedef struct {
     int32_t tile_resort; /* 1: per-tile order by the depth of each Gaussian's maximum */
     int32_t tile_w, tile_h;
     int32_t kernel;     /* 0: Gaussian; 1: Epanechnikov (compact, see ray_integral) */
+    int32_t pixel_window; /* > 0 (with tile_resort): per-pixel re-sorting window (shade_pixel) */
+    int32_t pad3;
     double alpha_min, alpha_max, T_min, x_min_xray;
     double bg[3];
     double near_threshold; /* > 0, X-ray backward only: chain just the pairs whose
@@ -678,10 +680,54 @@ static void list_push(blend_list *bl, blend_rec r)
     bl->rec[bl->cnt++] = r;
 }
 
+/* A Gaussian that reaches alpha_min at the pixel: index, list position,
+   line integral, (clamped) alpha, amplification of its 1 - alpha, gamma on
+   the pixel's ray. */
+typedef struct {
+    int64_t idx, pos;
+    double x, alpha, amp_om, gamma;
+    int clamped;
+} cand_rec;
+
+#define ORC_MAX_WINDOW 64
+
+static int cmp_double(const void *pa, const void *pb)
+{
+    const double a = *(const double *)pa, b = *(const double *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Front-to-back compositing of one candidate (Sec. 4.1, eq. our_alpha_blend):
+   stops (returns 1, not blended) when T (1 - alpha) < T_min. */
+static int composite(const cand_rec *c, const view_state *vs, const orc_settings *st, double *T,
+                     double C[3], double *ampT2, double *mT, int64_t *last, int32_t *cnt,
+                     blend_list *bl)
+{
+    const double Tn = *T * (1.0 - c->alpha);
+    if (st->T_min > 0) {
+        const double m = dec_margin(Tn, st->T_min,
+                                    1.0 + sqrt(*ampT2 + (c->amp_om + 1.0) * (c->amp_om + 1.0)));
+        if (m < *mT) *mT = m;
+    }
+    if (Tn < st->T_min) return 1;                      /* stop before blending */
+    for (int ch = 0; ch < 3; ++ch) C[ch] += vs->rgb[3 * c->idx + ch] * c->alpha * *T;
+    if (bl) {
+        blend_rec br = { c->idx, c->x, c->alpha, *T, c->clamped };
+        list_push(bl, br);
+    }
+    *T = Tn;
+    *ampT2 += (c->amp_om + 1.0) * (c->amp_om + 1.0);
+    *last = c->idx;
+    ++*cnt;
+    return 0;
+}
+
 /* Composite one pixel; fills out[3] (colour) or out[0] (X-ray).  margin_out
-   (if given) receives two decision margins (see dec_margin): [0] the smallest
+   (if given) receives the decision margins (see dec_margin): [0] the smallest
    over the tests on x or alpha (skip, clamp, X-ray cut), [1] the smallest over
-   the termination tests T (1 - alpha) < T_min. */
+   the termination tests T (1 - alpha) < T_min, [2] with the per-pixel window
+   the smallest relative gap between the per-pixel keys it compares (else
+   inf). */
 static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st,
                         const double d[3], const double pc[2], double *out,
                         double *T_out, int64_t *last_out, int32_t *nblend_out,
@@ -717,7 +763,7 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
         if (T_out) *T_out = exp(-I);
         if (last_out) *last_out = -1;
         if (nblend_out) *nblend_out = cnt;
-        if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; }
+        if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; margin_out[2] = INFINITY; }
         if (untrunc_out) *untrunc_out = full;
         return;
     }
@@ -727,7 +773,20 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
     double ampT2 = 0.0;  /* sum of squared amplifications of T's factors so far */
     int64_t last = -1;
     int32_t cnt = 0;
-    for (int64_t r = 0; r < vs->nvis; ++r) {
+    /* Per-pixel re-sorting (pixel_window = W > 0): the Gaussians that reach
+       alpha_min at this pixel, taken in the list order, pass through a window
+       of W entries ordered by gamma on this pixel's own ray (ties by list
+       position); when the window is full its smallest entry is composited,
+       and at the end of the list the rest in order.  W = 1 is the list order;
+       a W of at least the number of such Gaussians is the exact per-pixel
+       order by gamma. */
+    const int W = st->pixel_window;
+    cand_rec win[ORC_MAX_WINDOW];
+    int nw = 0, stopped = 0;
+    double gam[ORC_MAX_WINDOW * 8];
+    int ngam = 0;
+    double pgap = INFINITY;
+    for (int64_t r = 0; r < vs->nvis && !stopped; ++r) {
         int64_t i = vs->order[r];
         double alpha, m, amp_om;
         ray_terms rt;
@@ -738,6 +797,7 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             const double q = sp[2] * dx * dx + 2.0 * sp[3] * dx * dy + sp[4] * dy * dy;
             alpha = sp[5] * exp(-0.5 * q);
             rt.x = -log1p(-alpha);
+            rt.gamma = 0.0;
             /* condition number of the 2x2 conic */
             const double tr = 0.5 * (sp[2] + sp[4]);
             const double dd = sqrt(0.25 * (sp[2] - sp[4]) * (sp[2] - sp[4]) + sp[3] * sp[3]);
@@ -765,28 +825,39 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
         }
         int clamped = 0;
         if (alpha > st->alpha_max) { alpha = st->alpha_max; clamped = 1; }
-        double Tn = T * (1.0 - alpha);
-        if (st->T_min > 0) {
-            m = dec_margin(Tn, st->T_min,
-                           1.0 + sqrt(ampT2 + (amp_om + 1.0) * (amp_om + 1.0)));
-            if (m < mT) mT = m;
+        const cand_rec cr = { i, r, rt.x, alpha, amp_om, rt.gamma, clamped };
+        if (W <= 0) {
+            stopped = composite(&cr, vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
+            continue;
         }
-        if (Tn < st->T_min) break;                     /* stop before blending i */
-        for (int ch = 0; ch < 3; ++ch) C[ch] += vs->rgb[3 * i + ch] * alpha * T;
-        if (bl) {
-            blend_rec br = { i, rt.x, alpha, T, clamped };
-            list_push(bl, br);
+        if (ngam < (int)(sizeof gam / sizeof gam[0])) gam[ngam++] = rt.gamma;
+        /* insert into the window, ordered by (gamma, list position) */
+        int k = nw++;
+        while (k > 0 && win[k - 1].gamma > cr.gamma) { win[k] = win[k - 1]; --k; }
+        win[k] = cr;
+        if (nw == W) {
+            const cand_rec first = win[0];
+            for (int j = 1; j < nw; ++j) win[j - 1] = win[j];
+            --nw;
+            stopped = composite(&first, vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
         }
-        T = Tn;
-        ampT2 += (amp_om + 1.0) * (amp_om + 1.0);
-        last = i;
-        ++cnt;
+    }
+    for (int j = 0; j < nw && !stopped; ++j)
+        stopped = composite(&win[j], vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
+    if (W > 0 && ngam > 1) {
+        /* smallest relative gap between the per-pixel keys of two Gaussians
+           that reach alpha_min here (the window's comparisons) */
+        qsort(gam, (size_t)ngam, sizeof(double), cmp_double);
+        for (int j = 1; j < ngam; ++j) {
+            const double g = fabs(gam[j] - gam[j - 1]) / fmax(fabs(gam[j]), 1e-300);
+            if (g < pgap) pgap = g;
+        }
     }
     for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * st->bg[ch];
     if (T_out) *T_out = T;
     if (last_out) *last_out = last;
     if (nblend_out) *nblend_out = cnt;
-    if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; }
+    if (margin_out) { margin_out[0] = mx; margin_out[1] = mT; margin_out[2] = pgap; }
     if (untrunc_out) *untrunc_out = 0;
 }
 
@@ -802,6 +873,9 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
     if (st->tile_resort && (st->mode != 0 || st->alpha_model != 0 || st->tile_w < 1 || st->tile_h < 1))
         return -1;
     if (st->kernel != 0 && (st->kernel != 1 || st->alpha_model != 0 || st->near_segment)) return -1;
+    if (st->pixel_window < 0 || st->pixel_window > ORC_MAX_WINDOW ||
+        (st->pixel_window > 0 && !st->tile_resort))
+        return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }
@@ -822,7 +896,7 @@ int orc_render(int64_t n, const float *means, const float *quats, const float *s
                     last_out ? last_out + p : NULL, nblend_out ? nblend_out + p : NULL,
                     margin_out ? margin_out + 3 * p : NULL,
                     untrunc_out ? untrunc_out + p : NULL, NULL);
-        if (margin_out) margin_out[3 * p + 2] = ogap;
+        if (margin_out && ogap < margin_out[3 * p + 2]) margin_out[3 * p + 2] = ogap;
         if (st->tile_resort) free(vp.order);
     }
     view_free(&vs);
@@ -1192,6 +1266,9 @@ int orc_render_backward(int64_t n, const float *means, const float *quats, const
         return -1;
     if (st->near_threshold > 0 && st->mode != 1) return -1;
     if (st->kernel != 0 && (st->kernel != 1 || st->alpha_model != 0 || st->near_segment)) return -1;
+    if (st->pixel_window < 0 || st->pixel_window > ORC_MAX_WINDOW ||
+        (st->pixel_window > 0 && !st->tile_resort))
+        return -1;
     view_state vs;
     int rc = view_setup(&vs, n, means, quats, scales, dens, sh, cam, st);
     if (rc) { view_free(&vs); return rc; }

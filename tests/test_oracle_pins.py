@@ -1221,3 +1221,124 @@ def test_fd_gradients_tile_resort():
     st = oracle.Settings.no_thresholds(act="softplus", bg=(0.2, 0.3, 0.1))
     st.resort_tile = (4, 4)
     assert _fd_check(sc, cam, st, rng, n_checks=60) < 1e-6
+
+
+# ------- Sec. 7: per-pixel re-sorting through a bounded window (per-tile list) ---
+
+def _composite(order, alphas, cols):
+    """Front-to-back compositing (eq. our_alpha_blend) in the given order,
+    black background."""
+    T, C = 1.0, np.zeros(3)
+    for i in order:
+        C = C + cols[i] * alphas[i] * T
+        T *= 1.0 - alphas[i]
+    return C
+
+
+def test_pixel_window_hand_built_order():
+    """Three isotropic Gaussians A, B, C at depths 4.0, 4.2, 4.4 on the optical
+    axis side: on the tile-centre ray (the optical axis) they peak in the order
+    A, B, C; on the ray of the edge pixel, which leans towards +x while B and C
+    sit further towards -x, in the order C, B, A.  A window of one composites
+    the list order A, B, C; a window of two takes A and B, lets B go first,
+    takes C, lets C go, then A (B, C, A); a window of three is the per-pixel
+    order C, B, A."""
+    cam = H.odd_camera(9, 90.0, 0.0)
+    pix = [(8, 4)]
+    sc = H.scene([[0.0, 0.0, 4.0], [-0.5, 0.0, 4.2], [-1.0, 0.0, 4.4]], [f32(1.5)] * 3,
+                 [0.3, 0.25, 0.35], rgb=[[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    o, d = H.pixel_ray_world(cam, *pix[0])
+    oc, dc = H.pixel_ray_world(cam, 4, 4)
+    ri = lambda i, dd: oracle.ray_integral(sc.means[i], sc.quats[i], sc.scales[i], sc.dens[i], o, dd)
+    g_tile = [ri(i, dc)["gamma"] for i in range(3)]
+    g_pix = [ri(i, d)["gamma"] for i in range(3)]
+    assert g_tile[0] < g_tile[1] < g_tile[2]
+    assert g_pix[2] < g_pix[1] < g_pix[0]
+    alphas = [ri(i, d)["alpha"] for i in range(3)]
+    assert min(alphas) > 0.05
+    cols = np.maximum(0.5 + sc.sh[:, 0, :].astype(np.float64) * scenes.Y00, 0.0)  # act clamp
+    for W, order in ((1, [0, 1, 2]), (2, [1, 2, 0]), (3, [2, 1, 0]), (8, [2, 1, 0])):
+        st = oracle.Settings(act="clamp", alpha_min=1e-30, alpha_max=1 - 1e-12, T_min=0.0,
+                             resort_tile=(9, 9), pixel_window=W)
+        r = oracle.render(sc, cam, st, pixels=pix)
+        assert np.allclose(r["image"][:, 0], _composite(order, alphas, cols), rtol=1e-12,
+                           atol=1e-15), W
+        assert r["last"][0] == order[-1]
+
+
+def _window_scene(seed, n=14):
+    rng = np.random.default_rng(seed)
+    cam = scenes.look_at([0.4, -0.3, -3.0], (0, 0, 0), 17, 13, 45.0)
+    sc = H.scene(rng.uniform(-0.35, 0.35, (n, 3)),
+                 np.exp(rng.uniform(np.log(0.05), np.log(0.4), (n, 3))),
+                 rng.uniform(1, 8, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    return rng, cam, sc
+
+
+def test_pixel_window_of_one_is_the_tile_order():
+    """W = 1 passes the per-tile list through unchanged: the same image,
+    transmittance, last Gaussian and count as the per-tile order alone."""
+    _, cam, sc = _window_scene(31)
+    a = oracle.render(sc, cam, oracle.Settings(resort_tile=(4, 4)))
+    b = oracle.render(sc, cam, oracle.Settings(resort_tile=(4, 4), pixel_window=1))
+    for k in ("image", "T", "last", "nblend"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("T_min", [1e-4, 0.3])
+def test_pixel_window_wide_is_the_per_pixel_order(T_min):
+    """A window at least as long as the list sorts each pixel by gamma on its
+    own ray, which the per-tile order with 1x1 tiles does by a full sort of
+    every pixel's list (termination included)."""
+    _, cam, sc = _window_scene(32)
+    exact = oracle.render(sc, cam, oracle.Settings(resort_tile=(1, 1), T_min=T_min))
+    for tile in ((8, 8), (16, 16)):
+        w = oracle.render(sc, cam, oracle.Settings(resort_tile=tile, pixel_window=64, T_min=T_min))
+        assert np.allclose(w["image"], exact["image"], rtol=1e-12, atol=1e-14)
+        assert np.array_equal(w["last"], exact["last"])
+        assert np.array_equal(w["nblend"], exact["nblend"])
+
+
+def test_pixel_window_order_margin_covers_the_pixel_keys():
+    """The order margin of a windowed pixel is at most the smallest relative
+    gap between the per-pixel gammas of two Gaussians that reach alpha_min
+    there, found by brute force."""
+    _, cam, sc = _window_scene(33, n=10)
+    st = oracle.Settings(resort_tile=(4, 4), pixel_window=3)
+    r = oracle.render(sc, cam, st)
+    tau = -math.log1p(-st.alpha_min)
+    for py in range(0, cam.height, 2):
+        for px in range(0, cam.width, 2):
+            o, d = H.pixel_ray_world(cam, px, py)
+            rs = [oracle.ray_integral(sc.means[i], sc.quats[i], sc.scales[i], sc.dens[i], o, d)
+                  for i in range(len(sc.dens))]
+            g = sorted(t["gamma"] for t in rs if t["x"] >= tau)
+            gaps = [abs(g[j] - g[j - 1]) / abs(g[j]) for j in range(1, len(g))]
+            if gaps:
+                assert r["margin_order"][py, px] <= min(gaps) * (1 + 1e-9)
+
+
+def test_pixel_window_rejected_without_tile_order():
+    _, cam, sc = _window_scene(34, n=3)
+    with pytest.raises(RuntimeError):
+        oracle.render(sc, cam, oracle.Settings(pixel_window=2))
+    with pytest.raises(RuntimeError):
+        oracle.render(sc, cam, oracle.Settings(resort_tile=(4, 4), pixel_window=65))
+
+
+@pytest.mark.parametrize("W", [2, 3])
+def test_fd_gradients_pixel_window(W):
+    """Gradients with the windowed order (fixed away from ties) against central
+    finite differences."""
+    rng = np.random.default_rng(35 + W)
+    n = 6
+    cam = scenes.look_at([0.5, -0.3, -3.0], (0, 0, 0), 13, 11, 35.0)
+    means = np.c_[rng.uniform(-0.3, 0.3, (n, 2)), np.linspace(-0.6, 0.6, n)]
+    sc = H.scene(means, np.exp(rng.uniform(np.log(0.05), np.log(0.3), (n, 3))),
+                 rng.uniform(1, 10, n), quats=rng.standard_normal((n, 4)),
+                 sh=rng.normal(0, 0.3, (n, 4, 3)), deg=1)
+    st = oracle.Settings.no_thresholds(act="softplus", bg=(0.2, 0.3, 0.1))
+    st.resort_tile = (13, 11)
+    st.pixel_window = W
+    assert _fd_check(sc, cam, st, rng, n_checks=60) < 1e-6
