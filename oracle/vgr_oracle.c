@@ -49,6 +49,13 @@
  *     level of the re-sorting that the paper points to against popping
  *     (Sec. 7, Limitations).  Each pixel reports the smallest relative gap
  *     between the keys of two Gaussians that reach it as its order margin.
+ *   - pixel_window = W > 0 (with tile_resort): the per-pixel level of that
+ *     re-sorting.  The Gaussians that reach alpha_min at a pixel, in the
+ *     per-tile order, pass through a window of W entries kept in ascending
+ *     gamma on the pixel's own ray (ties by list position); when it is full
+ *     the smallest entry is composited, and at the end of the list the rest
+ *     in order; termination ends the pixel.  The order margin adds, over the
+ *     pops, the relative gap between the entry taken and the next smallest.
  *   - the density input is kappa itself, or theta with the reparameterisation
  *     kappa = -ln(1 - 0.99 theta) (1/s_x + 1/s_y + 1/s_z) / 3 (Sec. 5, eq.
  *     density_reparam); theta outside the paper's range [0, 1] is clamped to
@@ -691,12 +698,6 @@ typedef struct {
 
 #define ORC_MAX_WINDOW 64
 
-static int cmp_double(const void *pa, const void *pb)
-{
-    const double a = *(const double *)pa, b = *(const double *)pb;
-    return (a > b) - (a < b);
-}
-
 /* Front-to-back compositing of one candidate (Sec. 4.1, eq. our_alpha_blend):
    stops (returns 1, not blended) when T (1 - alpha) < T_min. */
 static int composite(const cand_rec *c, const view_state *vs, const orc_settings *st, double *T,
@@ -726,8 +727,8 @@ static int composite(const cand_rec *c, const view_state *vs, const orc_settings
    (if given) receives the decision margins (see dec_margin): [0] the smallest
    over the tests on x or alpha (skip, clamp, X-ray cut), [1] the smallest over
    the termination tests T (1 - alpha) < T_min, [2] with the per-pixel window
-   the smallest relative gap between the per-pixel keys it compares (else
-   inf). */
+   the smallest relative gap, over the window's pops, between the key of the
+   entry taken and the next smallest key in the window (else inf). */
 static void shade_pixel(const view_state *vs, const float *means, const orc_settings *st,
                         const double d[3], const double pc[2], double *out,
                         double *T_out, int64_t *last_out, int32_t *nblend_out,
@@ -783,8 +784,8 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
     const int W = st->pixel_window;
     cand_rec win[ORC_MAX_WINDOW];
     int nw = 0, stopped = 0;
-    double gam[ORC_MAX_WINDOW * 8];
-    int ngam = 0;
+    /* smallest relative gap between the entry each pop takes and the next
+       smallest one in the window: the only comparison that decides the pop */
     double pgap = INFINITY;
     for (int64_t r = 0; r < vs->nvis && !stopped; ++r) {
         int64_t i = vs->order[r];
@@ -830,28 +831,27 @@ static void shade_pixel(const view_state *vs, const float *means, const orc_sett
             stopped = composite(&cr, vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
             continue;
         }
-        if (ngam < (int)(sizeof gam / sizeof gam[0])) gam[ngam++] = rt.gamma;
         /* insert into the window, ordered by (gamma, list position) */
         int k = nw++;
         while (k > 0 && win[k - 1].gamma > cr.gamma) { win[k] = win[k - 1]; --k; }
         win[k] = cr;
         if (nw == W) {
+            if (nw > 1) {
+                const double g = fabs(win[1].gamma - win[0].gamma) / fmax(fabs(win[1].gamma), 1e-300);
+                if (g < pgap) pgap = g;
+            }
             const cand_rec first = win[0];
             for (int j = 1; j < nw; ++j) win[j - 1] = win[j];
             --nw;
             stopped = composite(&first, vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
         }
     }
-    for (int j = 0; j < nw && !stopped; ++j)
-        stopped = composite(&win[j], vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
-    if (W > 0 && ngam > 1) {
-        /* smallest relative gap between the per-pixel keys of two Gaussians
-           that reach alpha_min here (the window's comparisons) */
-        qsort(gam, (size_t)ngam, sizeof(double), cmp_double);
-        for (int j = 1; j < ngam; ++j) {
-            const double g = fabs(gam[j] - gam[j - 1]) / fmax(fabs(gam[j]), 1e-300);
+    for (int j = 0; j < nw && !stopped; ++j) {
+        if (j + 1 < nw) {
+            const double g = fabs(win[j + 1].gamma - win[j].gamma) / fmax(fabs(win[j + 1].gamma), 1e-300);
             if (g < pgap) pgap = g;
         }
+        stopped = composite(&win[j], vs, st, &T, C, &ampT2, &mT, &last, &cnt, bl);
     }
     for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * st->bg[ch];
     if (T_out) *T_out = T;

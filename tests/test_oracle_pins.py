@@ -1300,11 +1300,40 @@ def test_pixel_window_wide_is_the_per_pixel_order(T_min):
         assert np.array_equal(w["nblend"], exact["nblend"])
 
 
-def test_pixel_window_order_margin_covers_the_pixel_keys():
-    """The order margin of a windowed pixel is at most the smallest relative
-    gap between the per-pixel gammas of two Gaussians that reach alpha_min
-    there, found by brute force."""
+def test_pixel_window_order_margin_hand_built():
+    """The order margin of the three-Gaussian pixel above (list order A, B, C;
+    pixel order C, B, A), from the pops worked out by hand: the per-tile gaps
+    (B-A, C-B on the tile-centre ray) always count; a window of two takes B
+    over A, then C over A (gaps A-B, A-C), a window of three takes C over B,
+    then B over A (gaps B-C, A-B), and so does a longer one while draining; a
+    window of one compares nothing."""
+    cam = H.odd_camera(9, 90.0, 0.0)
+    pix = [(8, 4)]
+    sc = H.scene([[0.0, 0.0, 4.0], [-0.5, 0.0, 4.2], [-1.0, 0.0, 4.4]], [f32(1.5)] * 3,
+                 [0.3, 0.25, 0.35])
+    o, d = H.pixel_ray_world(cam, *pix[0])
+    oc, dc = H.pixel_ray_world(cam, 4, 4)
+    ri = lambda i, dd: oracle.ray_integral(sc.means[i], sc.quats[i], sc.scales[i], sc.dens[i], o, dd)
+    ta, tb, tc = (ri(i, dc)["gamma"] for i in range(3))
+    ga, gb, gc = (ri(i, d)["gamma"] for i in range(3))
+    rel = lambda lo, hi: (hi - lo) / hi
+    tile = min(rel(ta, tb), rel(tb, tc))
+    expect = {1: tile, 2: min(tile, rel(gb, ga), rel(gc, ga)),
+              3: min(tile, rel(gc, gb), rel(gb, ga)), 8: min(tile, rel(gc, gb), rel(gb, ga))}
+    for W, m in expect.items():
+        st = oracle.Settings(act="clamp", alpha_min=1e-30, alpha_max=1 - 1e-12, T_min=0.0,
+                             resort_tile=(9, 9), pixel_window=W)
+        got = oracle.render(sc, cam, st, pixels=pix)["margin_order"][0]
+        assert got == pytest.approx(m, rel=1e-9), W
+
+
+def test_pixel_window_order_margin_bounds():
+    """Each pop compares two of the pixel's Gaussians that reach alpha_min,
+    so the windowed order margin lies between the smallest relative gap over
+    all such pairs (brute force; with the per-tile margin) and the per-tile
+    margin alone (W = 1)."""
     _, cam, sc = _window_scene(33, n=10)
+    tile = oracle.render(sc, cam, oracle.Settings(resort_tile=(4, 4), pixel_window=1))
     st = oracle.Settings(resort_tile=(4, 4), pixel_window=3)
     r = oracle.render(sc, cam, st)
     tau = -math.log1p(-st.alpha_min)
@@ -1315,8 +1344,9 @@ def test_pixel_window_order_margin_covers_the_pixel_keys():
                   for i in range(len(sc.dens))]
             g = sorted(t["gamma"] for t in rs if t["x"] >= tau)
             gaps = [abs(g[j] - g[j - 1]) / abs(g[j]) for j in range(1, len(g))]
-            if gaps:
-                assert r["margin_order"][py, px] <= min(gaps) * (1 + 1e-9)
+            m, m1 = r["margin_order"][py, px], tile["margin_order"][py, px]
+            assert m <= m1
+            assert m >= min([m1] + gaps) * (1 - 1e-9)
 
 
 def test_pixel_window_rejected_without_tile_order():
