@@ -189,6 +189,13 @@ def bench_headline(args, torch, dev):
                                             args.steps, torch, grads, dLs)
         near_ab["tile_resort_fwd_bwd_ratio"] = round(
             near_ab["tile_resort_on"]["fwd_bwd_ms"] / near_ab["off"]["fwd_bwd_ms"], 3)
+        _log("A/B: per-tile re-sorting with a per-pixel window of 8 (8x8 tiles)")
+        near_ab["pixel_window_8"] = _ab_leg(r, params, wl.cams,
+                                            Settings(sh_degree=3, tile=(8, 8), tile_resort=True,
+                                                     pixel_window=8),
+                                            args.steps, torch, grads, dLs)
+        near_ab["pixel_window_8_fwd_bwd_ratio"] = round(
+            near_ab["pixel_window_8"]["fwd_bwd_ms"] / near_ab["off"]["fwd_bwd_ms"], 3)
     return dict(ms=ms, stages=stages, stats=stats, roofline=roofline, wl=wl, graph_ms=graph_ms,
                 flops={"raster_fwd": fl_fwd, "raster_bwd": fl_bwd}, splat_ab=splat_ab,
                 near_ab=near_ab)

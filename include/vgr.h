@@ -65,6 +65,9 @@ enum { VGR_DENSITY_KAPPA = 0, VGR_DENSITY_THETA = 1 };
 enum { VGR_ALPHA_VOLUMETRIC = 0, VGR_ALPHA_SPLAT = 1 };
 enum { VGR_KERNEL_GAUSSIAN = 0, VGR_KERNEL_EPANECHNIKOV = 1 };
 
+/* Largest per-pixel re-sorting window (vgr_settings.pixel_window). */
+#define VGR_MAX_PIXEL_WINDOW 32
+
 /* Rendering rules.  Defaults in brackets (vgr_default_settings).
  *   mode        colour compositing or X-ray line integrals [COLOR]
  *   sh_degree   0..3, real spherical harmonics with the Condon-Shortley
@@ -132,9 +135,25 @@ enum { VGR_KERNEL_GAUSSIAN = 0, VGR_KERNEL_EPANECHNIKOV = 1 };
  *               from the same dual-conic box with D2max = 1 - (3 tau /
  *               (4 kappa beta_max))^(2/3).  Not with the near-plane segment
  *               [GAUSSIAN]
- * Gaussians are composited in ascending order of the FP32 view-space depth
- * of their mean, z = fmaf(R20, mx, fmaf(R21, my, fmaf(R22, mz, t2))); ties
- * keep the input index order.  The result does not depend on the tile size:
+ *   pixel_window W > 0 (needs tile_resort): the per-pixel level of the
+ *               re-sorting (Sec. 7, Limitations).  At each pixel the Gaussians
+ *               that reach alpha_min, in the per-tile order, pass through a
+ *               window of W entries ordered by the depth of each maximum on
+ *               the pixel's own ray (ties by list position); when the window
+ *               is full its smallest entry is composited, at the end of the
+ *               list the rest in order; termination ends the pixel, leaving
+ *               what the window still holds.  W = 1 is the per-tile order; a
+ *               W at least the number of such Gaussians sorts each pixel
+ *               exactly.  At most VGR_MAX_PIXEL_WINDOW; 8x8 tiles and
+ *               64-record batches (tile_w/h and batch 0 or those values).
+ *               The forward keeps, per (tile pixel, list entry), the
+ *               compositing sequence and 8 bytes for the backward's replay:
+ *               28 bytes x 64 per instance of workspace.  Pair counters
+ *               (vgr_set_counting) stay zero [0]
+ * Without tile_resort, Gaussians are composited in ascending order of the
+ * FP32 view-space depth of their mean, z = fmaf(R20, mx, fmaf(R21, my,
+ * fmaf(R22, mz, t2))); ties keep the input index order.  The result then
+ * does not depend on the tile size:
  * tiles only bound, conservatively, where alpha >= alpha_min can occur. */
 typedef struct {
     int32_t mode;
@@ -149,6 +168,7 @@ typedef struct {
     int32_t tile_resort;
     int32_t kernel;
     int32_t batch;
+    int32_t pixel_window;
 } vgr_settings;
 
 /* Counters of the last forward (host struct). */

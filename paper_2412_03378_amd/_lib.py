@@ -32,6 +32,7 @@ VGR_ALPHA_VOLUMETRIC = 0
 VGR_ALPHA_SPLAT = 1
 VGR_KERNEL_GAUSSIAN = 0
 VGR_KERNEL_EPANECHNIKOV = 1
+VGR_MAX_PIXEL_WINDOW = 32
 
 
 class vgr_camera(C.Structure):
@@ -46,7 +47,7 @@ class vgr_settings(C.Structure):
                 ("bg", C.c_float * 3), ("act", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("density", C.c_int32), ("alpha_model", C.c_int32),
                 ("near_segment", C.c_int32), ("tile_resort", C.c_int32), ("kernel", C.c_int32),
-                ("batch", C.c_int32)]
+                ("batch", C.c_int32), ("pixel_window", C.c_int32)]
 
 
 class vgr_stats(C.Structure):

@@ -86,6 +86,7 @@ struct vgr_ctx {
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts, wg_time;
     DevBuf rs_key, rs_idx, rs_key2, rs_idx2;   // per-tile re-sorting (instance-sized)
+    DevBuf wseq, wseq_pos, wpair, wcount;      // per-pixel window (pair slots, pixels)
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
@@ -284,6 +285,10 @@ Buffers make_buffers(vgr_ctx *c)
     b.last_pos = ptr<int32_t>(c->last_pos);
     b.last_id = ptr<int32_t>(c->last_id);
     b.rgrad = ptr<float4>(c->rgrad);
+    b.wseq = ptr<float4>(c->wseq);
+    b.wseq_pos = ptr<int32_t>(c->wseq_pos);
+    b.wpair = ptr<float2>(c->wpair);
+    b.wcount = ptr<int32_t>(c->wcount);
     b.d_total = ptr<uint32_t>(c->words);
     b.blk_counts = ptr<uint32_t>(c->blk_counts);
     b.counters = ptr<unsigned long long>(c->counters);
@@ -366,7 +371,8 @@ void vgr_destroy(vgr_ctx *c)
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
                       &c->words, &c->counters, &c->views, &c->blk_counts, &c->wg_time,
-                      &c->rs_key, &c->rs_idx, &c->rs_key2, &c->rs_idx2 };
+                      &c->rs_key, &c->rs_idx, &c->rs_key2, &c->rs_idx2,
+                      &c->wseq, &c->wseq_pos, &c->wpair, &c->wcount };
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (c->h_views) (void)hipHostFree(c->h_views);
@@ -512,7 +518,18 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     }
     if (st->batch != 0 && st->batch != 32 && st->batch != 64)
         return fail(c, VGR_ERR_INVALID_ARG, "batch must be 0, 32 or 64");
+    if (st->pixel_window < 0 || st->pixel_window > VGR_MAX_PIXEL_WINDOW)
+        return fail(c, VGR_ERR_INVALID_ARG, "pixel_window must be in [0, %d]", VGR_MAX_PIXEL_WINDOW);
     int tw = st->tile_w, th = st->tile_h, tb = st->batch;
+    if (st->pixel_window > 0) {
+        // one pixel per lane and the 64-record batch layout of the pair slots
+        if (!st->tile_resort)
+            return fail(c, VGR_ERR_INVALID_ARG, "pixel_window needs tile_resort");
+        if (!((tw == 0 && th == 0) || (tw == 8 && th == 8)) || !(tb == 0 || tb == 64))
+            return fail(c, VGR_ERR_INVALID_ARG, "pixel_window needs 8x8 tiles and 64-record batches");
+        tw = th = 8;
+        tb = 64;
+    }
     if ((tw == 0 && th == 0) || tb == 0) {
         const auto it = c->tune_cache.find(tune_key(st, n, n_views, cams));
         const bool hit = it != c->tune_cache.end();
@@ -545,6 +562,7 @@ int prepare(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *means,
     rp.tile_w = tw;
     rp.tile_h = th;
     rp.batch = tb;
+    rp.pixel_window = st->pixel_window;
 
     p.vinfo.assign(n_views, ViewInfo{});
     int64_t tiles = 0, pix = 0;
@@ -688,6 +706,18 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
                          8 * (size_t)pmask_words(K, rp.total_tiles, rp.tile_w, rp.tile_h, rp.batch))))
             return rc;
         b.pmask = ptr<uint64_t>(c->pmask);
+    }
+    if (rp.pixel_window > 0) {
+        // (a capture sizes these buffers before it starts)
+        if (cap < 0 && ((rc = ensure(c, c->wcount, 4 * (size_t)(p.pix > 0 ? p.pix : 1))) ||
+                        (rc = ensure(c, c->wseq, 16 * 64 * (size_t)K)) ||
+                        (rc = ensure(c, c->wseq_pos, 4 * 64 * (size_t)K)) ||
+                        (rc = ensure(c, c->wpair, 8 * 64 * (size_t)K))))
+            return rc;
+        b.wseq = ptr<float4>(c->wseq);
+        b.wseq_pos = ptr<int32_t>(c->wseq_pos);
+        b.wpair = ptr<float2>(c->wpair);
+        b.wcount = ptr<int32_t>(c->wcount);
     }
     if (c->counting)
         HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(b.counters), 0u, 16, s));
@@ -998,6 +1028,14 @@ int vgr_graph_capture_calls(vgr_ctx *c, const vgr_settings *st, int64_t n, const
         (rc = ensure(c, c->views_graph, sizeof(ViewInfo) * (size_t)off[n_calls])))
         return rc;
     if (pmw > 0 && (rc = ensure(c, c->pmask, 8 * (size_t)pmw))) return rc;
+    int64_t pixmax = 1;
+    for (const Prepared &p : ps) pixmax = p.pix > pixmax ? p.pix : pixmax;
+    if (ps[0].rp.pixel_window > 0 &&
+        ((rc = ensure(c, c->wcount, 4 * (size_t)pixmax)) ||
+         (rc = ensure(c, c->wseq, 16 * 64 * (size_t)cap)) ||
+         (rc = ensure(c, c->wseq_pos, 4 * 64 * (size_t)cap)) ||
+         (rc = ensure(c, c->wpair, 8 * 64 * (size_t)cap))))
+        return rc;
     c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);
     for (int k = 0; k < n_calls; ++k) {
         for (int v = 0; v < views_per_call[k]; ++v) {
@@ -1112,6 +1150,8 @@ int vgr_autotune(vgr_ctx *c, const vgr_settings *st, int64_t n, const float *mea
     if (!c || !st) return VGR_ERR_INVALID_ARG;
     if (n_views < 1 || n_views > kMaxViews || !cams)
         return fail(c, VGR_ERR_INVALID_ARG, "bad views");
+    if (st->pixel_window > 0)
+        return fail(c, VGR_ERR_INVALID_ARG, "pixel_window fixes the launch shape: nothing to tune");
     static const int cand[VGR_TUNE_CANDIDATES][3] = {
         { 8, 8, 64 }, { 16, 8, 64 }, { 16, 16, 64 }, { 32, 8, 64 },
         { 8, 8, 32 }, { 16, 8, 32 }, { 16, 16, 32 }, { 32, 8, 32 } };

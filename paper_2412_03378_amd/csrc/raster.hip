@@ -584,7 +584,7 @@ __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
     return v[0];
 }
 
-template <int TW, int TH, int MODE, bool COUNT, int B>
+template <int TW, int TH, int MODE, bool COUNT, int B, bool WIN = false>
 __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers b)
 {
     static_assert(B == 32 || B == 64, "records per batch");
@@ -653,9 +653,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     const float zn = vi.znear;
     float *rg = reinterpret_cast<float *>(b.rgrad);
 
-    // One record of the batch against the lane's pixels: pass[k] marks the
-    // slots whose pixel the bound pre-test admits (dy is recomputed here).
-    auto record = [&](int qi, const PreRec &pr, float dx, const bool (&pass)[PPL]) {
+    // One record of the batch (list position jpos) against the lane's pixels:
+    // pass[k] marks the slots whose pixel the bound pre-test admits (dy is
+    // recomputed here).
+    auto record = [&](int qi, const PreRec &pr, float dx, const bool (&pass)[PPL], int jpos) {
         float acc[16];
         // -0 is the exact identity of addition, so the first term of each
         // sum needs no add
@@ -731,12 +732,24 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     hn = hh * __fmaf_rn(2.0f * zn, pg.qw * rq, eta);
                 }
             }
-            const bool bl = pass[k] && !(y < tau2);
+            bool bl = pass[k] && !(y < tau2);
             if (COUNT) n.blend += bl ? 1u : 0u;
             const uint64_t bm = __builtin_amdgcn_ballot_w64(!(y < tau2)) & pm;
             if (bm == 0) continue;                      // wave-uniform
             float dy_;
-            if constexpr (COLOR) {
+            if constexpr (WIN) {
+                // per-pixel window: the replay left this pair's dL/dy and
+                // alpha T_before over the forward's marker (0, -1); a pair the
+                // forward took in but never composited keeps the marker
+                float2 wv = make_float2(0.0f, -1.0f);
+                if (bl) wv = b.wpair[(size_t)jpos * 64 + lane];
+                bl = bl && wv.y >= 0.0f;
+                const float wgt = bl ? wv.y : 0.0f;
+                acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
+                acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
+                acc[12] = __fmaf_rn(g[k][2], wgt, acc[12]);
+                dy_ = bl ? wv.x : 0.0f;
+            } else if constexpr (COLOR) {
                 const bool clamped = y > ymax;
                 const float om = fast_exp2(-(clamped ? ymax : y));
                 const float inv = fast_rcp(om);
@@ -847,7 +860,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 bool pass[PPL];
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) pass[k] = (mask[k] >> qi) & 1u;
-                record(qi, pr, dx, pass);
+                record(qi, pr, dx, pass, bs + qi);
             }
             __syncthreads();
         }
@@ -876,7 +889,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     }
                 }
                 if (!wave_any(anyp)) continue;             // wave-uniform
-                record(qi, pr, ct.dx, pass);
+                record(qi, pr, ct.dx, pass, jpos);
             }
             __syncthreads();
         }
@@ -891,6 +904,312 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     if (timed && lane == 0)
         b.wg_time[rp.total_tiles + blockIdx.x] =
             make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel re-sorting window (rp.pixel_window = W > 0, on top of the
+// per-tile order; 8x8 tiles, one pixel per lane, 64-record batches).
+//
+// Forward: each lane walks its pixel's passing pairs in list order as the
+// colour forward does.  A pair that reaches alpha_min meets a window of W - 1
+// register slots: whichever of the pair and the slots has the smallest key
+// (the view depth of the Gaussian's maximum on the pixel's own ray,
+// mz (v0 . w) / |w|^2; ties by list position) is composited, and the pair
+// takes the freed slot.  Empty slots count as smaller than every key, so the
+// first W - 1 pairs only fill the window; at the end of the list it drains
+// in key order.  Each composited pair is appended to the pixel's compositing
+// sequence (wseq, wseq_pos), and each pair taken in gets the marker (0, -1)
+// at its list position in wpair.
+//
+// Backward: raster_bwd_window_replay_kernel walks each pixel's sequence from
+// its end with the colour backward's replay arithmetic and writes every
+// composited pair's dL/dy and alpha T_before over its marker; the rasteriser
+// backward (WIN) then visits the records as usual and reads those values
+// instead of replaying in list order.
+template <int WS>
+struct Window {
+    float k[WS], o[WS], c0[WS], c1[WS], c2[WS];   // key, 1 - alpha (negated if clamped), colour
+    int p[WS];                                    // list position (-1: empty)
+    float mink;                                   // smallest (key, position) ...
+    int mins;                                     // ... and its slot
+
+    __device__ __forceinline__ void rescan()
+    {
+        mink = k[0];
+        mins = 0;
+        int mp = p[0];
+#pragma unroll
+        for (int s = 1; s < WS; ++s) {
+            const bool lt = k[s] < mink || (k[s] == mink && p[s] < mp);
+            mink = lt ? k[s] : mink;
+            mins = lt ? s : mins;
+            mp = lt ? p[s] : mp;
+        }
+    }
+    // the smallest slot's entry
+    __device__ __forceinline__ void take(float &so, float &s0, float &s1, float &s2, int &sp) const
+    {
+        so = 1.0f; s0 = s1 = s2 = 0.0f; sp = -1;
+#pragma unroll
+        for (int s = 0; s < WS; ++s) {
+            const bool hit = s == mins;
+            so = hit ? o[s] : so;
+            s0 = hit ? c0[s] : s0;
+            s1 = hit ? c1[s] : s1;
+            s2 = hit ? c2[s] : s2;
+            sp = hit ? p[s] : sp;
+        }
+    }
+    __device__ __forceinline__ void put(bool on, float key, float om, float a0, float a1, float a2,
+                                        int pos)
+    {
+#pragma unroll
+        for (int s = 0; s < WS; ++s) {
+            const bool w = on && s == mins;
+            k[s] = w ? key : k[s];
+            o[s] = w ? om : o[s];
+            c0[s] = w ? a0 : c0[s];
+            c1[s] = w ? a1 : c1[s];
+            c2[s] = w ? a2 : c2[s];
+            p[s] = w ? pos : p[s];
+        }
+    }
+};
+
+template <int MODE, int WS>
+__global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, Buffers b)
+{
+    constexpr int B = 64;
+    constexpr bool NEAR = MODE == kModeColorNear;
+    constexpr bool EPAN = MODE == kModeColorEpan;
+    __shared__ Stage<B> st;
+
+    const bool timed = b.wg_time != nullptr;   // uniform
+    const uint64_t t_start = timed ? wg_clock() : 0;
+    const int gt = (int)b.tile_order[blockIdx.x];
+    const int v = find_view(b.views, rp.n_views, gt);
+    const ViewInfo &vi = b.views[v];
+    const int lt = gt - vi.tile_off;
+    const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+    const int lane = threadIdx.x;
+    const int px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
+    const int W = vi.width, H = vi.height;
+    const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+    const float ux = (pxc - vi.cx) / vi.fx;
+    const float uyn = (pyc - vi.cy) / vi.fy;
+    const float un = sqrtf(ux * ux + uyn * uyn + 1.0f);
+    bool act = px < W && py < H;
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    int nseq = 0, lastp = -1, visited = -1;
+    const uint2 range = b.ranges[gt];
+    const float tau2 = rp.tau2, ymax = rp.ymax, Tmin = rp.T_min;
+    const float zn = vi.znear;
+    const int nslot = rp.pixel_window - 1;
+    Window<WS> win;
+#pragma unroll
+    for (int s = 0; s < WS; ++s) {
+        win.k[s] = s < nslot ? -INFINITY : INFINITY;   // empty: taken first; unused: never
+        win.o[s] = 1.0f;
+        win.c0[s] = win.c1[s] = win.c2[s] = 0.0f;
+        win.p[s] = -1;
+    }
+    win.rescan();
+    const size_t seq0 = (size_t)range.x * 64 + lane;
+    // Composite one pair (oms: 1 - alpha, negated where alpha was clamped) if
+    // `on`, or stop the pixel where T (1 - alpha) < T_min (Sec. 4.1).
+    auto composite = [&](bool on, float oms, float c0, float c1, float c2, int pos) {
+        const float om = fabsf(oms);
+        const float Tn = T * om;
+        const bool stop = on && Tn < Tmin;
+        const bool dob = on && !stop;
+        const float wgt = dob ? (1.0f - om) * T : 0.0f;
+        C0 = __fmaf_rn(c0, wgt, C0);
+        C1 = __fmaf_rn(c1, wgt, C1);
+        C2 = __fmaf_rn(c2, wgt, C2);
+        if (dob) {
+            const size_t q = seq0 + (size_t)nseq * 64;
+            b.wseq[q] = make_float4(oms, c0, c1, c2);
+            b.wseq_pos[q] = pos;
+        }
+        T = dob ? Tn : T;
+        lastp = dob ? pos : lastp;
+        nseq += dob ? 1 : 0;
+        act = act && !stop;
+    };
+
+    for (uint32_t bs = range.x; bs < range.y; bs += B) {
+        const uint32_t j = bs + lane;
+        if (j < range.y) stage_record(st, b, lane, b.inst_val[j]);
+        __syncthreads();
+        const int nb = (int)min((uint32_t)B, range.y - bs);
+        // bound pre-test of the batch (broadcast records), kept for the backward
+        uint32_t mh[2] = { 0u, 0u };
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int qend = min(nb, 32 * h + 32);
+            for (int qi = 32 * h; qi < qend; ++qi) {
+                const PreRec pr = load_pre(st, qi);
+                const ColTerms ct = col_terms(pr, pxc);
+                float dy;
+                const bool pass = act && pre_test(pr, ct, pyc, dy);
+                mh[h] |= pass ? 1u << (qi & 31) : 0u;
+            }
+        }
+        uint64_t mk = ((uint64_t)mh[1] << 32) | mh[0];
+        b.pmask[mask_word<B>(bs, gt, lane)] = mk;
+        while (wave_any(mk != 0 && act)) {                 // wave-uniform loop
+            const bool has = mk != 0 && act;
+            const int qi = has ? (int)__builtin_ctzll(mk) : 0;
+            mk &= mk - 1;
+            const RecRegs rr = load_regs(st, qi);
+            const PreRec pr = pre_of(rr);
+            const FullRec fr = full_of(rr);
+            const float dx = (pxc - pr.hx) - pr.lx;
+            const float dy = (pyc - pr.hy) - pr.ly;
+            PairGeom g;
+            pair_geom(pr, fr, dx, dy, g);
+            const float rq = fast_rsq(g.qw);
+            const float ex = profile<EPAN>(fr.se, g.num, rq * rq);
+            float y = (NEAR ? fabsf(fr.K) : fr.K) * un * rq * ex;
+            if constexpr (NEAR) {
+                if (fr.K < 0.0f)
+                    y *= norm_cdf(near_eta(fr.v0x, fr.v0y, fr.v0z, fr.mz, g.w0, g.w1, g.w2, g.qw, rq,
+                                           zn));
+            }
+            const bool cand = has && !(y < tau2);
+            const float om = fast_exp2(-(y > ymax ? ymax : y));
+            const float oms = y > ymax ? -om : om;
+            const float vw = __fmaf_rn(fr.v0x, g.w0, __fmaf_rn(fr.v0y, g.w1, fr.v0z * g.w2));
+            const float key = fr.mz * vw * (rq * rq);
+            const int pos = (int)bs + qi;
+            visited = has ? pos : visited;
+            if (cand) b.wpair[(size_t)pos * 64 + lane] = make_float2(0.0f, -1.0f);
+            // the pair goes first if it precedes every entry; otherwise the
+            // smallest entry leaves (none while its slot is empty) and the
+            // pair takes the slot
+            const bool direct = cand && key < win.mink;
+            const bool swap = cand && !direct;
+            float so, s0, s1, s2;
+            int sp;
+            win.take(so, s0, s1, s2, sp);
+            composite(direct || (swap && sp >= 0), direct ? oms : so, direct ? fr.c0 : s0,
+                      direct ? fr.c1 : s1, direct ? fr.c2 : s2, direct ? pos : sp);
+            win.put(swap, key, oms, fr.c0, fr.c1, fr.c2, pos);
+            win.rescan();
+        }
+        __syncthreads();
+        if (!wave_any(act)) break;                          // every pixel has stopped
+    }
+    // end of the list: the window drains in key order (slots never filled
+    // take no part)
+#pragma unroll
+    for (int s = 0; s < WS; ++s) win.k[s] = win.k[s] == -INFINITY ? INFINITY : win.k[s];
+    win.rescan();
+    while (wave_any(act && win.mink < INFINITY)) {
+        const bool on = act && win.mink < INFINITY;
+        float so, s0, s1, s2;
+        int sp;
+        win.take(so, s0, s1, s2, sp);
+        composite(on, so, s0, s1, s2, sp);
+#pragma unroll
+        for (int s = 0; s < WS; ++s) win.k[s] = (on && s == win.mins) ? INFINITY : win.k[s];
+        win.rescan();
+    }
+
+    if (px < W && py < H) {
+        const int64_t HW = (int64_t)W * H;
+        const int64_t idx = (int64_t)py * W + px;
+        const int64_t pidx = vi.pix_off + idx;
+        vi.out[idx] = __fmaf_rn(T, rp.bg[0], C0);
+        vi.out[HW + idx] = __fmaf_rn(T, rp.bg[1], C1);
+        vi.out[2 * HW + idx] = __fmaf_rn(T, rp.bg[2], C2);
+        b.T_final[pidx] = T;
+        b.last_pos[pidx] = visited;
+        b.wcount[pidx] = nseq;
+        b.last_id[pidx] = lastp >= 0 ? (int32_t)((int64_t)b.inst_val[lastp] - (int64_t)v * rp.n) : -1;
+    }
+    if (timed && lane == 0)
+        b.wg_time[blockIdx.x] = make_uint2(cu_key(), (uint32_t)(wg_clock() - t_start));
+}
+
+// Reverse replay of each pixel's compositing sequence (per-pixel window):
+// T before a pair is T after it over its 1 - alpha, and GB = dL/dC . (colour
+// behind it) accumulates from T_final bg, as in the colour backward; writes
+// (dL/dy, alpha T_before) at the pair's list position.
+__global__ __launch_bounds__(64) void raster_bwd_window_replay_kernel(RenderParams rp, Buffers b)
+{
+    const int gt = (int)b.tile_order[blockIdx.x];
+    const int v = find_view(b.views, rp.n_views, gt);
+    const ViewInfo &vi = b.views[v];
+    const int lt = gt - vi.tile_off;
+    const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+    const int lane = threadIdx.x;
+    const int px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
+    if (px >= vi.width || py >= vi.height) return;
+    const int64_t HW = (int64_t)vi.width * vi.height;
+    const int64_t idx = (int64_t)py * vi.width + px;
+    const int64_t pidx = vi.pix_off + idx;
+    const int n = b.wcount[pidx];
+    float T = b.T_final[pidx];
+    float g[3], gbg = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        g[c] = vi.dL[c * HW + idx];
+        gbg = __fmaf_rn(g[c], rp.bg[c], gbg);
+    }
+    float GB = T * gbg;
+    const size_t seq0 = (size_t)b.ranges[gt].x * 64 + lane;
+    for (int k = n - 1; k >= 0; --k) {
+        const size_t q = seq0 + (size_t)k * 64;
+        const float4 e = b.wseq[q];
+        const int pos = b.wseq_pos[q];
+        const float om = fabsf(e.x);
+        const float inv = fast_rcp(om);
+        const float alpha = 1.0f - om;
+        const float Tb = T * inv;
+        // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
+        const float gc = __fmaf_rn(g[0], e.y, __fmaf_rn(g[1], e.z, g[2] * e.w));
+        const float da = __fmaf_rn(Tb, gc, -(inv * GB));
+        const float wgt = alpha * Tb;
+        GB = __fmaf_rn(gc, wgt, GB);
+        T = Tb;
+        b.wpair[(size_t)pos * 64 + lane] = make_float2(e.x < 0.0f ? 0.0f : da * kLn2 * om, wgt);
+    }
+}
+
+template <int MODE>
+hipError_t window_fwd_mode(const RenderParams &rp, const Buffers &b, hipStream_t s)
+{
+    const dim3 grid(rp.total_tiles), block(64);
+    const int ns = rp.pixel_window - 1;
+    if (ns <= 1) raster_fwd_window_kernel<MODE, 1><<<grid, block, 0, s>>>(rp, b);
+    else if (ns <= 3) raster_fwd_window_kernel<MODE, 3><<<grid, block, 0, s>>>(rp, b);
+    else if (ns <= 7) raster_fwd_window_kernel<MODE, 7><<<grid, block, 0, s>>>(rp, b);
+    else if (ns <= 15) raster_fwd_window_kernel<MODE, 15><<<grid, block, 0, s>>>(rp, b);
+    else raster_fwd_window_kernel<MODE, 31><<<grid, block, 0, s>>>(rp, b);
+    return hipGetLastError();
+}
+
+hipError_t window_fwd(const RenderParams &rp, const Buffers &b, hipStream_t s)
+{
+    if (rp.kernel == VGR_KERNEL_EPANECHNIKOV) return window_fwd_mode<kModeColorEpan>(rp, b, s);
+    if (rp.near_segment) return window_fwd_mode<kModeColorNear>(rp, b, s);
+    return window_fwd_mode<VGR_MODE_COLOR>(rp, b, s);
+}
+
+hipError_t window_bwd(const RenderParams &rp, const Buffers &b, hipStream_t s)
+{
+    const dim3 grid(rp.total_tiles), block(64);
+    raster_bwd_window_replay_kernel<<<grid, block, 0, s>>>(rp, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (rp.kernel == VGR_KERNEL_EPANECHNIKOV)
+        raster_bwd_kernel<8, 8, kModeColorEpan, false, 64, true><<<grid, block, 0, s>>>(rp, b);
+    else if (rp.near_segment)
+        raster_bwd_kernel<8, 8, kModeColorNear, false, 64, true><<<grid, block, 0, s>>>(rp, b);
+    else
+        raster_bwd_kernel<8, 8, VGR_MODE_COLOR, false, 64, true><<<grid, block, 0, s>>>(rp, b);
+    return hipGetLastError();
 }
 
 template <int TW, int TH, int B>
@@ -986,12 +1305,14 @@ hipError_t bwd_batch(const RenderParams &rp, const Buffers &b, bool count, hipSt
 hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     if (rp.total_tiles <= 0) return hipSuccess;
+    if (rp.pixel_window > 0) return window_fwd(rp, b, s);
     return rp.batch == 32 ? fwd_batch<32>(rp, b, count, s) : fwd_batch<64>(rp, b, count, s);
 }
 
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count, hipStream_t s)
 {
     if (rp.total_tiles <= 0) return hipSuccess;
+    if (rp.pixel_window > 0) return window_bwd(rp, b, s);
     return rp.batch == 32 ? bwd_batch<32>(rp, b, count, s) : bwd_batch<64>(rp, b, count, s);
 }
 

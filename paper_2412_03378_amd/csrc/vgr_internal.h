@@ -119,6 +119,7 @@ struct RenderParams {
     int32_t tile_resort; // per-tile order by the depth of the maximum on the tile-centre ray
     int32_t kernel;      // VGR_KERNEL_GAUSSIAN or VGR_KERNEL_EPANECHNIKOV
     int32_t batch;       // records staged per rasteriser batch: 32 or 64
+    int32_t pixel_window;// per-pixel re-sorting window W (0: off; 8x8 tiles, batch 64)
 };
 
 // Device workspace views handed to kernels.
@@ -142,12 +143,23 @@ struct Buffers {
     uint32_t *tile_key2; // total tiles, sort ping-pong
     uint32_t *tile_order2;
     float *T_final;      // total pixels
-    int32_t *last_pos;   // total pixels: list position of last blended (-1)
+    int32_t *last_pos;   // total pixels: list position of last blended (-1); with the
+                         // per-pixel window, of the last pair the pixel visited
     int32_t *last_id;    // total pixels: Gaussian index of last blended (-1)
     float4 *rgrad;       // n_views * n * 4 float4 (record gradients)
     uint64_t *pmask;     // pmask_words(): bound pre-test lane masks of each B-record
                          // batch of a tile list, written by the forward where
                          // raster_keeps_masks() and read by the backward
+    // per-pixel window (pixel_window > 0), pair slots (list position) * 64 + lane:
+    float4 *wseq;        // capacity * 64: the k-th composited pair of a tile pixel at
+                         // (tile start + k) * 64 + lane: (1 - alpha, negated where
+                         // alpha was clamped; colour)
+    int32_t *wseq_pos;   // capacity * 64: its list position, same slots
+    float2 *wpair;       // capacity * 64, by list position: (0, -1) for a pair the
+                         // forward took into the window; the backward replay
+                         // overwrites composited ones with (dL/dy, 0 where alpha
+                         // was clamped; alpha T_before)
+    int32_t *wcount;     // total pixels: pairs composited
     uint32_t *blk_counts;// preprocess blocks: instances per block
     uint32_t *d_total;   // [0] = instance count K, [1] overflow flag, [4] K from the
                          // preprocess, [6] items with instances (the first of the
@@ -207,6 +219,8 @@ hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool coun
                              hipStream_t s);
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
+// Per-pixel window: bytes of the pair buffers per instance of capacity.
+constexpr int64_t kWindowBytesPerInstance = 64 * (16 + 4 + 8);
 // accumulate: add to the gradient arrays; otherwise overwrite every element.
 // gnorm / vcount (may be null): densification statistics, always added to.
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,

@@ -33,6 +33,7 @@ class Settings:
     tile_resort: bool = False        # per-tile order by the depth of each maximum
     kernel: str = "gaussian"         # "gaussian" | "epanechnikov" (compact primitive)
     batch: int = 0                   # records per rasteriser batch: 32, 64, 0 = tuned
+    pixel_window: int = 0            # per-pixel re-sorting window (with tile_resort; 8x8)
 
     def to_c(self) -> L.vgr_settings:
         s = L.vgr_settings()
@@ -49,6 +50,7 @@ class Settings:
         s.tile_resort = 1 if self.tile_resort else 0
         s.kernel = L.VGR_KERNEL_EPANECHNIKOV if self.kernel == "epanechnikov" else L.VGR_KERNEL_GAUSSIAN
         s.batch = int(self.batch)
+        s.pixel_window = int(self.pixel_window)
         return s
 
     @staticmethod

@@ -48,24 +48,51 @@ def device_scene(sc, dev):
     return t(sc.means), t(sc.quats), t(sc.scales), t(sc.dens), sh
 
 
-def ok_mask(ref, xray=False):
-    """Pixels (spatial shape) with a unique correct value: every pixel in
-    X-ray mode, else those whose decisions all clear their margins."""
+def dec_ok_mask(ref, xray=False):
+    """Pixels whose threshold decisions (skip, clamp, stop) all clear their
+    margins (every pixel in X-ray mode)."""
     mx = np.asarray(ref["margin_x"])
     if xray:
         return np.ones(mx.shape, bool)
-    return ((mx > MARGIN_X) & (np.asarray(ref["margin_T"]) > MARGIN_T)
-            & (np.asarray(ref["margin_order"]) > MARGIN_ORDER))
+    return (mx > MARGIN_X) & (np.asarray(ref["margin_T"]) > MARGIN_T)
+
+
+def ok_mask(ref, xray=False):
+    """Pixels (spatial shape) with a unique correct value: every pixel in
+    X-ray mode, else those whose decisions all clear their margins and whose
+    order keys (re-sorting options) are further apart than MARGIN_ORDER."""
+    ok = dec_ok_mask(ref, xray)
+    if xray:
+        return ok
+    return ok & (np.asarray(ref["margin_order"]) > MARGIN_ORDER)
 
 
 def flag_limit(npix):
     return max(2, math.ceil(FLAG_SHARE * npix))
 
 
-def compare_image(img, ref, xray=False):
+def check_flag_share(ref, xray=False, order_share=None):
+    """At most FLAG_SHARE of the pixels may be set aside.  order_share (the
+    re-sorting options at full size): pixels set aside only for close order
+    keys are counted against this larger share instead; their number is a
+    property of the scene (how many of a pixel's Gaussians lie within
+    MARGIN_ORDER of each other in depth), not of the rule."""
+    ok = ok_mask(ref, xray)
+    if order_share is None:
+        nflag = int((~ok).sum())
+        assert nflag <= flag_limit(ok.size), f"{nflag} of {ok.size} pixels flagged"
+        return
+    dec = dec_ok_mask(ref, xray)
+    n_dec, n_order = int((~dec).sum()), int((dec & ~ok).sum())
+    assert n_dec <= flag_limit(ok.size), f"{n_dec} of {ok.size} pixels flagged (thresholds)"
+    assert n_order <= math.ceil(order_share * ok.size), \
+        f"{n_order} of {ok.size} pixels flagged (order keys)"
+
+
+def compare_image(img, ref, xray=False, order_share=None):
     """img: (C, P) or (C, H, W) against the oracle's render dict ``ref``.
     Returns (max error over unflagged pixels, n flagged, max error flagged);
-    asserts that at most FLAG_SHARE of the pixels are flagged."""
+    asserts the flagged share (check_flag_share)."""
     img = np.asarray(img, np.float64)
     r = np.asarray(ref["image"], np.float64)
     ok = ok_mask(ref, xray)
@@ -77,13 +104,13 @@ def compare_image(img, ref, xray=False):
     e_ok = float(err[ok].max()) if ok.any() else 0.0
     e_flag = float(err[~ok].max()) if (~ok).any() else 0.0
     nflag = int((~ok).sum())
-    assert nflag <= flag_limit(ok.size), f"{nflag} of {ok.size} pixels flagged"
+    check_flag_share(ref, xray, order_share)
     return e_ok, nflag, e_flag
 
 
-def check_image(img, ref, xray=False, label=""):
+def check_image(img, ref, xray=False, label="", order_share=None):
     """compare_image with the tolerances asserted."""
-    e_ok, nflag, e_flag = compare_image(img, ref, xray)
+    e_ok, nflag, e_flag = compare_image(img, ref, xray, order_share)
     print(f"{label}image err {e_ok:.3g}, flagged {nflag} (max {e_flag:.3g})")
     assert e_ok <= (XRAY_REL if xray else IMG_TOL), e_ok
     assert e_flag <= FLIP_TOL, e_flag

@@ -31,8 +31,8 @@ def test_header_structs_match_binding():
     from paper_2412_03378_amd import _lib
     assert ctypes.sizeof(_lib.vgr_camera) == 4 * (9 + 3 + 4 + 2 + 1 + 1)
     # mode, sh_degree; 4 thresholds; bg; act; tile_w, tile_h; density,
-    # alpha_model, near_segment, tile_resort, kernel, batch
-    assert ctypes.sizeof(_lib.vgr_settings) == 4 * (2 + 4 + 3 + 1 + 2 + 6)
+    # alpha_model, near_segment, tile_resort, kernel, batch, pixel_window
+    assert ctypes.sizeof(_lib.vgr_settings) == 4 * (2 + 4 + 3 + 1 + 2 + 7)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

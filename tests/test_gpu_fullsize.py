@@ -39,7 +39,9 @@ def _oset(st):
     return oracle.Settings(mode=st.mode, alpha_min=st.alpha_min, alpha_max=st.alpha_max,
                            T_min=st.T_min, x_min_xray=st.x_min_xray, bg=st.bg, act=st.act,
                            density=st.density, alpha_model=st.alpha_model,
-                           near_segment=st.near_segment)
+                           near_segment=st.near_segment, kernel=st.kernel,
+                           resort_tile=tuple(st.tile) if st.tile_resort else None,
+                           pixel_window=st.pixel_window)
 
 
 def _pixels(cam, n, seed):
@@ -50,13 +52,13 @@ def _pixels(cam, n, seed):
     return np.array(pts, np.int32)
 
 
-def _check_forward(img, T, last, sc, cam, st, pix, xray=False):
+def _check_forward(img, T, last, sc, cam, st, pix, xray=False, order_share=None):
     ref = oracle.render(sc, cam, _oset(st), pixels=pix)
     if xray:
         got = img[pix[:, 1], pix[:, 0]][None]
     else:
         got = img[:, pix[:, 1], pix[:, 0]]
-    G.check_image(got, ref, xray=xray, label=f"{len(pix)} pixels: ")
+    G.check_image(got, ref, xray=xray, label=f"{len(pix)} pixels: ", order_share=order_share)
     ok = G.ok_mask(ref, xray)
     if not xray:
         assert np.abs(T[pix[:, 1], pix[:, 0]] - ref["T"])[ok].max() <= G.IMG_TOL
@@ -64,7 +66,7 @@ def _check_forward(img, T, last, sc, cam, st, pix, xray=False):
     return ref
 
 
-def _sparse_upstream(sc, cams, st, pix_per_view, seed, dev):
+def _sparse_upstream(sc, cams, st, pix_per_view, seed, dev, order_share=None):
     """dL non-zero only at the sampled pixels of each view (unflagged ones in
     colour mode), zero on views without samples; returns the device tensors
     and, per sampled view, (view index, pixels, values)."""
@@ -78,7 +80,7 @@ def _sparse_upstream(sc, cams, st, pix_per_view, seed, dev):
         if pix is not None:
             ref = oracle.render(sc, cam, _oset(st), pixels=pix)
             keep = pix[G.ok_mask(ref, xray)]
-            assert len(pix) - len(keep) <= G.flag_limit(len(pix))
+            G.check_flag_share(ref, xray, order_share)
             g = rng.standard_normal((nch, len(keep)))
             full[:, keep[:, 1], keep[:, 0]] = g
             sparse.append((v, keep, g))
@@ -96,13 +98,13 @@ def _oracle_grads(sc, cams, st, sparse, names):
     return G.sum_backward(parts, names, flips or None)
 
 
-def _sparse_backward(R, dev, t, sc, cams, st, pix_per_view, seed, has_sh):
+def _sparse_backward(R, dev, t, sc, cams, st, pix_per_view, seed, has_sh, order_share=None):
     """Backward with dL non-zero only at sampled pixels (pix_per_view: a list
     aligned with cams, or a dict view -> pixels)."""
     if not isinstance(pix_per_view, dict):
         pix_per_view = dict(enumerate(pix_per_view))
     R.forward(*t, cams, st)
-    dLs, sparse = _sparse_upstream(sc, cams, st, pix_per_view, seed, dev)
+    dLs, sparse = _sparse_upstream(sc, cams, st, pix_per_view, seed, dev, order_share)
     grads = [torch.zeros_like(x) for x in t[:4]] + [torch.zeros_like(t[4]) if has_sh else None]
     R.backward(dLs, *grads)
     torch.cuda.synchronize()
@@ -167,6 +169,29 @@ def test_config2_near_segment_sampled(R, dev, cfg2):
     _check_forward(img, T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
                    _pixels(cam, 64, 27))
     _sparse_backward(R, dev, t, wl.scene, [cam], st, [_pixels(cam, 30, 28)], 29, True)
+
+
+# Share of sampled pixels of the headline scene whose order keys (per tile,
+# or the per-pixel window's) lie within MARGIN_ORDER of each other: about a
+# third at 1080p with 1M clustered Gaussians (26 blended per pixel at the
+# median), so the re-sorting options are checked on the other two thirds.
+ORDER_SHARE = 0.5
+
+
+@pytest.mark.parametrize("window", [0, 8])
+def test_config2_resort_sampled(R, dev, cfg2, window):
+    """The headline scene with the per-tile order, alone and with a per-pixel
+    window of 8 (the benchmark's option-cost configurations)."""
+    wl, t = cfg2
+    cam = wl.cams[0]
+    st = _settings(sh_degree=3, tile=TILE, tile_resort=True, pixel_window=window)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    T, last = R.aux(0, cam.height, cam.width)
+    G.check_emission(R)
+    _check_forward(img, T.cpu().numpy(), last.cpu().numpy(), wl.scene, cam, st,
+                   _pixels(cam, 128, 30 + window), order_share=ORDER_SHARE)
+    _sparse_backward(R, dev, t, wl.scene, [cam], st, [_pixels(cam, 60, 31 + window)], 32 + window,
+                     True, order_share=ORDER_SHARE)
 
 
 @pytest.mark.parametrize("tile", [TILE, (16, 16)])   # 16x16: the shape the benchmark's tuner picks
