@@ -360,9 +360,9 @@ def bench_xray(args, torch, dev):
     outs = [torch.empty((c.height, c.width), device=dev) for c in wl.cams]
     r = Renderer(0)
     _log("autotuning the tile shape (X-ray)")
-    tile, batch, tune_ms = r.autotune(params, wl.cams, Settings(mode="xray"), outs, dLs, grads,
-                                      iters=1)
-    st = Settings(mode="xray", tile=tile, batch=batch)
+    xst = Settings(mode="xray", x_min_xray=scenes.XRAY_X_MIN)
+    tile, batch, tune_ms = r.autotune(params, wl.cams, xst, outs, dLs, grads, iters=1)
+    st = Settings(mode="xray", x_min_xray=scenes.XRAY_X_MIN, tile=tile, batch=batch)
     for _ in range(max(1, args.warmup // 2)):
         _step(r, params, grads, wl.cams, st, dLs)
     torch.cuda.synchronize()
@@ -387,6 +387,7 @@ def bench_xray(args, torch, dev):
           "raster_bwd": _flops(stats["bwd_pairs_tested"], stats["bwd_pairs_full"],
                                stats["bwd_pairs_blended"], ppl, "xray", "bwd")}
     out = {"workload": "X-ray: 64 cone-beam views 512x512, 500k Gaussians, fwd+bwd in one call",
+           "x_min": scenes.XRAY_X_MIN,
            "tile": list(tile), "autotune_ms": [round(x, 2) for x in tune_ms],
            "ms_per_step": round(dtg * 1e3, 3), "views_per_s": round(len(wl.cams) / dtg, 1),
            "eager_ms_per_step": round(dt * 1e3, 3),
@@ -401,7 +402,8 @@ def bench_xray(args, torch, dev):
         import oracle
         _log("oracle on one X-ray view")
         out["oracle"] = oracle_per_view(wl.scene, wl.cams[0], wl.dL[0], 128,
-                                        oracle.Settings(mode="xray"))
+                                        oracle.Settings(mode="xray",
+                                                        x_min_xray=scenes.XRAY_X_MIN))
     return out
 
 

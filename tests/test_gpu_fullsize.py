@@ -198,7 +198,7 @@ def test_config2_resort_sampled(R, dev, cfg2, window):
 def test_config4_xray_sampled(R, dev, tile):
     wl = scenes.config4(with_grad=False)
     t = G.device_scene(wl.scene, dev)
-    st = _settings(mode="xray", tile=tile)
+    st = _settings(mode="xray", tile=tile, x_min_xray=scenes.XRAY_X_MIN)
     imgs = R.forward(*t, wl.cams, st)
     G.check_emission(R)
     for v in (0, 21, 42, 63):
