@@ -46,7 +46,8 @@ def _oset(st):
     (1, 8, "random"), (4095, 13, "random"), (4096, 13, "random"), (100003, 13, "random"),
     (262144, 32, "random"), (50000, 20, "equal"), (70001, 16, "sorted"),
     (70001, 16, "reversed"), (33333, 32, "max"), (65536, 7, "random"), (0, 8, "random"),
-    (4194304, 15, "random"), (4194305, 15, "random")])
+    (4194304, 15, "random"), (4194305, 15, "random"), (6000001, 32, "random"),
+    (1000000, 32, "narrow"), (3000000, 24, "narrow")])
 def test_radix_sort_stable(R, dev, n, bits, kind):
     rng = np.random.default_rng(n + bits)
     hi = (1 << bits) - 1
@@ -58,6 +59,9 @@ def test_radix_sort_stable(R, dev, n, bits, kind):
         k = np.sort(rng.integers(0, hi + 1, n, dtype=np.uint64))
     elif kind == "reversed":
         k = np.sort(rng.integers(0, hi + 1, n, dtype=np.uint64))[::-1].copy()
+    elif kind == "narrow":
+        # the upper bits are the same for every key (passes over them only copy)
+        k = (np.uint64(0x5A) << np.uint64(bits - 8)) | rng.integers(0, 1 << 12, n, dtype=np.uint64)
     else:
         k = np.full(n, hi, np.uint64)
         k[::7] = 0
