@@ -36,7 +36,7 @@ MARGIN_ORDER = 1e-5     # relative gap of per-tile order keys that flags a pixel
 FLIP_TOL = 0.05         # bound on the effect of one flipped decision (colour)
 FLAG_SHARE = 0.01       # most pixels a parity check may set aside
 GRAD_REL = 1e-3         # |g - g_ref| <= 1e-3 max(|g_ref|, 1e-2 A_row) + ERR_K u E_row
-ERR_K = 32
+ERR_K = 16
 
 GRAD_KEYS = ("means", "quats", "scales", "dens", "sh")
 
@@ -143,8 +143,11 @@ def grad_tolerance(ref, absref, errref=None, flip=None):
     each pair's contribution without the cancellation of its upstream factor,
     weighted by how much a relative rounding error is amplified on its way
     (1 + D^2/2 through the exponential, one rounding per compositing step of
-    the reverse replay); u = 2^-24 and ERR_K counts the roundings of one
-    pair's chain (about 30 operations) with a small margin."""
+    the reverse replay); u = 2^-24.  ERR_K is measured: over the gradient
+    checks of the GPU suite the largest error needs ERR_K <= 7.3 (the
+    full-size X-ray workload), and 16 keeps a factor 2 on that.  The row
+    maxima are needed: with per-element A and E a third of those checks
+    fail."""
     ref = np.asarray(ref, np.float64)
     tol = GRAD_REL * np.maximum(np.abs(ref), 1e-2 * _row_max(absref))
     if errref is not None:
@@ -204,17 +207,34 @@ def sum_backward(parts, keys, flips=None):
     return out
 
 
+def cut_ratios(g, ref, absref, errref, flip=None):
+    """Worst ratios under two cut-down forms of the bound (reported, not
+    asserted): 8 in place of ERR_K, and per-element A and E in place of the
+    row maxima."""
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if not g.size:
+        return 0.0, 0.0
+    d = np.abs(g - ref)
+    f = 0.0 if flip is None else np.asarray(flip, np.float64)
+    k8 = GRAD_REL * np.maximum(np.abs(ref), 1e-2 * _row_max(absref)) + 8 * U * _row_max(errref) + f
+    nr = (GRAD_REL * np.maximum(np.abs(ref), 1e-2 * np.asarray(absref, np.float64))
+          + ERR_K * U * np.asarray(errref, np.float64) + f)
+    return float((d / (k8 + 1e-30)).max()), float((d / (nr + 1e-30)).max())
+
+
 def check_grads(got, ref, label=""):
     """got: {key: array}; ref: sum_backward output.  Prints the worst ratio
-    under the bound in use and under the plain per-element bound; asserts
-    the former."""
+    under the bound in use, under its cut-down forms (cut_ratios) and under
+    the plain per-element bound; asserts the first."""
     ratios, plain = {}, {}
     for k, arr in got.items():
         g, a, e, f = ref[k]
         ratios[k] = grad_errors(arr, g, a, e, f)
         plain[k] = plain_errors(arr, g, a)
-        print(f"{label}{k}: ratio {ratios[k]:.3g} (plain bound {plain[k]:.3g}) "
-              + grad_worst(arr, g, a, e, f))
+        k8, nr = cut_ratios(arr, g, a, e, f)
+        print(f"{label}{k}: ratio {ratios[k]:.3g} (plain bound {plain[k]:.3g}, err_k8 {k8:.3g}, "
+              f"no_row_max {nr:.3g}) " + grad_worst(arr, g, a, e, f))
     assert max(ratios.values()) <= 1.0, ratios
     return ratios, plain
 
