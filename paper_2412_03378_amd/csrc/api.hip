@@ -84,11 +84,14 @@ struct vgr_ctx {
     DevBuf geom, depth_key, item_ids, key2, item2, counts, cnt_sorted, offsets, rect;
     DevBuf inst_key, inst_val, inst_key2, inst_val2, ranges, T_final, last_pos, last_id, pmask;
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
-    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, blk_counts, wg_time;
+    DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, views_b, blk_counts, wg_time;
     DevBuf rs_key, rs_idx, rs_key2, rs_idx2;   // per-tile re-sorting (instance-sized)
     DevBuf wseq, wseq_pos, wpair, wcount;      // per-pixel window (pair slots, pixels)
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
+    // the table last uploaded through each slot (forward: views, backward:
+    // views_b); an identical table is not copied again
+    std::vector<ViewInfo> uploaded[2];
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
     bool stage_pending[2] = { false, false };
     uint32_t *h_words = nullptr;      // pinned, 8 words
@@ -245,17 +248,30 @@ int bits_for(int64_t v)
     return b;
 }
 
-// Copy the view table to the device through pinned staging slot `slot`,
-// waiting first for the previous copy out of that slot to finish.
+// Device view table of slot 0 (forward) or 1 (backward).
+ViewInfo *view_table(vgr_ctx *c, int slot)
+{
+    return ptr<ViewInfo>(slot == 0 ? c->views : c->views_b);
+}
+
+// Copy the view table to slot `slot`'s device table through pinned staging,
+// waiting first for the previous copy out of that slot to finish; skipped
+// when the table equals the one that slot holds (a loop over the same
+// cameras and buffers uploads once).
 int upload_views(vgr_ctx *c, int slot, const std::vector<ViewInfo> &vinfo)
 {
+    std::vector<ViewInfo> &last = c->uploaded[slot];
+    const size_t bytes = sizeof(ViewInfo) * vinfo.size();
+    if (last.size() == vinfo.size() && memcmp(last.data(), vinfo.data(), bytes) == 0)
+        return VGR_OK;
     ViewInfo *h = c->h_views + slot * kMaxViews;
     if (c->stage_pending[slot]) HIP_TRY(c, hipEventSynchronize(c->stage_ev[slot]));
-    memcpy(h, vinfo.data(), sizeof(ViewInfo) * vinfo.size());
-    HIP_TRY(c, hipMemcpyAsync(c->views.p, h, sizeof(ViewInfo) * vinfo.size(),
-                              hipMemcpyHostToDevice, c->stream));
+    memcpy(h, vinfo.data(), bytes);
+    last.clear();
+    HIP_TRY(c, hipMemcpyAsync(view_table(c, slot), h, bytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipEventRecord(c->stage_ev[slot], c->stream));
     c->stage_pending[slot] = true;
+    last = vinfo;
     return VGR_OK;
 }
 
@@ -340,6 +356,7 @@ int vgr_create(vgr_ctx **out, int device)
         return VGR_ERR_HIP;
     }
     if ((rc = ensure(c, c->views, sizeof(ViewInfo) * kMaxViews)) ||
+        (rc = ensure(c, c->views_b, sizeof(ViewInfo) * kMaxViews)) ||
         (rc = ensure(c, c->words, sizeof(uint32_t) * 8)) ||
         (rc = ensure(c, c->counters, sizeof(unsigned long long) * 16))) {
         vgr_destroy(c);
@@ -370,7 +387,8 @@ void vgr_destroy(vgr_ctx *c)
                       &c->inst_val, &c->inst_key2, &c->inst_val2, &c->pmask, &c->ranges, &c->T_final,
                       &c->last_pos, &c->last_id, &c->tile_key, &c->tile_order, &c->tile_key2,
                       &c->tile_order2, &c->rgrad, &c->scan_tmp, &c->sort_tmp,
-                      &c->words, &c->counters, &c->views, &c->blk_counts, &c->wg_time,
+                      &c->words, &c->counters, &c->views, &c->views_b, &c->blk_counts,
+                      &c->wg_time,
                       &c->rs_key, &c->rs_idx, &c->rs_key2, &c->rs_idx2,
                       &c->wseq, &c->wseq_pos, &c->wpair, &c->wcount };
     for (DevBuf *b : all)
@@ -644,7 +662,8 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         mark_end(c, ST_PREPROCESS);
         // depth order of all (view, Gaussian) items; ties keep the item order
         mark(c, ST_SORT_DEPTH);
-        HIP_TRY(c, launch_fill_u32(b.d_total + 2, (uint32_t)m, 1, s));
+        // (the item count the depth sort reads, d_total[2] = m, comes from the
+        // preprocess's totals kernel)
         HIP_TRY(c, launch_radix_sort(b.depth_key, b.item_ids, b.key2, b.item2, b.d_total + 2, m, 32,
                                      ptr<uint32_t>(c->sort_tmp), s));
         mark_end(c, ST_SORT_DEPTH);
@@ -657,7 +676,7 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
             HIP_TRY(c, hipEventSynchronize(c->k_ev));
             mv = c->h_words[2] < (uint64_t)m ? (int64_t)c->h_words[2] : m;
         }
-        HIP_TRY(c, launch_gather_counts(b, mv, s));
+        HIP_TRY(c, launch_gather_counts(b, mv, rp.total_tiles, s));
         HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, mv, ptr<uint32_t>(c->scan_tmp), true,
                                    s));
         if (cap < 0) {
@@ -697,8 +716,9 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         HIP_TRY(c, launch_fill_u32(b.d_total, 0u, 2, s));
     }
     mark(c, ST_RANGES);
-    HIP_TRY(c, launch_ranges(b, K, rp.total_tiles, s));
-    HIP_TRY(c, launch_tile_order(b, rp.total_tiles, ptr<uint32_t>(c->sort_tmp), s));
+    // with items, the count gather cleared the ranges and the tile-order counters
+    HIP_TRY(c, launch_ranges(b, K, rp.total_tiles, m == 0, s));
+    HIP_TRY(c, launch_tile_order(b, rp.total_tiles, m == 0, s));
     mark_end(c, ST_RANGES);
     if (cap < 0 && raster_keeps_masks(rp.mode, rp.tile_w, rp.tile_h)) {
         // (a capture sizes this buffer for its capacity before it starts)
@@ -802,7 +822,7 @@ int vgr_render_forward(vgr_ctx *c, const vgr_settings *st, int64_t n, const floa
     if ((rc = timing_begin(c))) return rc;
     Buffers b;
     int64_t K;
-    if ((rc = enqueue_forward(c, p, means, quats, scales, dens, sh, ptr<ViewInfo>(c->views), -1,
+    if ((rc = enqueue_forward(c, p, means, quats, scales, dens, sh, view_table(c, 0), -1,
                               c->stream, b, K)))
         return rc;
     c->rp = p.rp;
@@ -834,7 +854,7 @@ int vgr_render_backward(vgr_ctx *c, const float *const *dL, float *d_means, floa
     if ((rc = ensure(c, c->rgrad, sizeof(float4) * 4 * (m > 0 ? m : 1)))) return rc;
     if ((rc = upload_views(c, 1, c->vinfo))) return rc;
     if ((rc = timing_begin(c))) return rc;
-    return enqueue_backward(c, rp, c->buf, ptr<ViewInfo>(c->views), c->means, c->quats, c->scales,
+    return enqueue_backward(c, rp, c->buf, view_table(c, 1), c->means, c->quats, c->scales,
                             c->dens, c->sh, d_means, d_quats, d_scales, d_dens, d_sh,
                             accumulate != 0, c->stream);
 }

@@ -622,28 +622,42 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     }
 }
 
+// Block 0: instance total into d_total[4] (and the item count m into
+// d_total[2], the count the depth sort reads); block 1: items with
+// instances into d_total[6].
 __global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__restrict__ parts,
-                                                           int64_t n, uint32_t *__restrict__ out)
+                                                           int64_t n, uint32_t *__restrict__ d_total,
+                                                           int64_t m)
 {
     __shared__ uint32_t s_part[4];
+    const uint32_t *src = parts + blockIdx.x * n;
     uint32_t acc = 0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) acc += parts[k];
+    for (int64_t k = threadIdx.x; k < n; k += 256) acc += src[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *out = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    if (threadIdx.x == 0) {
+        d_total[blockIdx.x == 0 ? 4 : 6] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        if (blockIdx.x == 0) d_total[2] = (uint32_t)m;
+    }
 }
 
 // Tile counts in depth order.  Items past the nvis[0] that have instances
-// (they sort last) have none, so their counts are not gathered.
+// (they sort last) have none, so their counts are not gathered.  The same
+// launch clears the per-tile ranges and the 64 tile-order counters (read by
+// the range and tile-order kernels later in the forward).
 __global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
                                      const uint32_t *__restrict__ counts,
                                      const uint32_t *__restrict__ nvis,
-                                     uint32_t *__restrict__ out, int64_t m)
+                                     uint32_t *__restrict__ out, int64_t m,
+                                     uint2 *__restrict__ ranges, int32_t n_tiles,
+                                     uint32_t *__restrict__ order_counters)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < m) out[j] = j < (int64_t)nvis[0] ? counts[sorted_items[j]] : 0u;
+    if (j < n_tiles) ranges[j] = make_uint2(0u, 0u);
+    if (j < 64) order_counters[j] = 0u;
 }
 
 // Instance count K = offsets[m], clamped to the capacity (overflow flag).
@@ -1333,8 +1347,8 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
 #undef VGR_PRE
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total + 4);
-    count_total_kernel<<<1, 256, 0, s>>>(b.blk_counts + grid, (int64_t)grid, b.d_total + 6);
+    count_total_kernel<<<2, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total,
+                                         rp.n * (int64_t)rp.n_views);
     return hipGetLastError();
 }
 
@@ -1344,10 +1358,13 @@ int64_t preprocess_blocks(int64_t n, int32_t n_views)
     return 2 * (int64_t)grid_for(n, 256);   // instance and visible-item partial sums
 }
 
-hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s)
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles, hipStream_t s)
 {
-    gather_counts_kernel<<<grid_for(m, 256), 256, 0, s>>>(b.item_ids, b.counts, b.d_total + 6,
-                                                          b.cnt_sorted, m);
+    int64_t n = m > total_tiles ? m : total_tiles;
+    if (n < 64) n = 64;
+    gather_counts_kernel<<<grid_for(n, 256), 256, 0, s>>>(b.item_ids, b.counts, b.d_total + 6,
+                                                          b.cnt_sorted, m, b.ranges, total_tiles,
+                                                          b.tile_key);
     return hipGetLastError();
 }
 
@@ -1364,11 +1381,14 @@ hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int6
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, hipStream_t s)
+hipError_t launch_ranges(const Buffers &b, int64_t bound, int32_t total_tiles, bool clear,
+                         hipStream_t s)
 {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u,
-                                   2 * (int64_t)total_tiles, s);
-    if (e != hipSuccess) return e;
+    if (clear) {
+        hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u,
+                                       2 * (int64_t)total_tiles, s);
+        if (e != hipSuccess) return e;
+    }
     if (bound <= 0) return hipSuccess;
     unsigned g = grid_for(bound, 256);
     if (g > 16384) g = 16384;
@@ -1402,14 +1422,14 @@ hipError_t launch_resort_permute(const Buffers &b, const uint32_t *idx, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
-                             hipStream_t s)
+hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, bool clear, hipStream_t s)
 {
-    (void)sort_tmp;
     if (total_tiles <= 0) return hipSuccess;
     uint32_t *hist = b.tile_key, *cursor = b.tile_key + 32;   // 64 words of scratch
-    hipError_t e = launch_fill_u32(hist, 0u, 64, s);
-    if (e != hipSuccess) return e;
+    if (clear) {
+        hipError_t e = launch_fill_u32(hist, 0u, 64, s);
+        if (e != hipSuccess) return e;
+    }
     tile_hist_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, hist, total_tiles);
     tile_place_kernel<<<grid_for(total_tiles, 256), 256, 0, s>>>(b.ranges, hist, cursor,
                                                                   b.tile_order, total_tiles);

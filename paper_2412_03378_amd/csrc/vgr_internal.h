@@ -197,12 +197,14 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
                              const float *sh, hipStream_t s);
 // Size of Buffers::blk_counts (two partial sums per preprocess block).
 int64_t preprocess_blocks(int64_t n, int32_t n_views);
-hipError_t launch_gather_counts(const Buffers &b, int64_t m, hipStream_t s);
+// Also clears the per-tile ranges and the tile-order counters.
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles, hipStream_t s);
 hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s);
 hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
                        hipStream_t s);
+// clear: zero the ranges first (done by launch_gather_counts when it ran).
 hipError_t launch_ranges(const Buffers &b, int64_t capacity_bound, int32_t total_tiles,
-                         hipStream_t s);
+                         bool clear, hipStream_t s);
 // Per-tile re-sorting: key[j] = order-preserving bits of the view depth of
 // the maximum of instance j's Gaussian on its tile-centre ray, idx[j] = j
 // (j < the device instance count, at most bound).
@@ -213,8 +215,8 @@ hipError_t launch_resort_keys(const RenderParams &rp, const Buffers &b, uint32_t
 hipError_t launch_resort_permute(const Buffers &b, const uint32_t *idx, uint32_t *tmp_key,
                                  uint32_t *tmp_val, int64_t bound, hipStream_t s);
 // Order tiles by decreasing list length (heaviest first) into b.tile_order.
-hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, uint32_t *sort_tmp,
-                             hipStream_t s);
+// clear: zero its counters first (done by launch_gather_counts when it ran).
+hipError_t launch_tile_order(const Buffers &b, int32_t total_tiles, bool clear, hipStream_t s);
 hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
