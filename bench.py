@@ -559,6 +559,49 @@ def cpu_baseline(wl, n_pix, n_pix_1core=16):
                       f"{cam.width * cam.height} pixels plus the per-view set-up"}
 
 
+def bench_parity(args, torch, dev, calls=200):
+    """The parity workload (one 128x128 view, 1000 Gaussians, SH0, 16x16
+    tiles, forward only): mean forward time over `calls` eager calls, pair
+    counts, and the oracle's whole frame beside it on all host threads and on
+    one (no extrapolation)."""
+    from paper_2412_03378_amd import Renderer, Settings, scenes
+    wl = scenes.config1()
+    params = _device_scene(wl.scene, dev, torch)
+    r = Renderer(0)
+    st = Settings(tile=(16, 16))
+    for _ in range(10):
+        r.forward(*params, wl.cams, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        r.forward(*params, wl.cams, st)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) / calls * 1e6
+    r.set_counting(True)
+    r.forward(*params, wl.cams, st)
+    stats = r.stats()
+    r.set_counting(False)
+    out = {"workload": "single view 128x128, 1000 Gaussians, SH0, 16x16 tiles, forward only",
+           "forward_us": round(us, 1), "pairs_tested": stats["pairs_tested"],
+           "pairs_blended": stats["pairs_blended"]}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.max_threads()
+        res = {}
+        for n in (threads, 1):
+            oracle.set_threads(n)
+            try:
+                t0 = time.perf_counter()
+                oracle.render(wl.scene, wl.cams[0], oracle.Settings())
+                res[n] = (time.perf_counter() - t0) * 1e3
+            finally:
+                oracle.set_threads(threads)
+        out["oracle"] = {"forward_ms": round(res[threads], 2), "cores": threads,
+                         "forward_ms_one_core": round(res[1], 2), "kind": "oracle",
+                         "sample": "the whole 128x128 frame over all 1000 Gaussians in FP64"}
+    return out
+
+
 def oracle_per_view(scene, cam, dL, n_pix, st):
     """The oracle beside a multi-view workload: one view, extrapolated, as
     views/s on the host cores."""
@@ -825,6 +868,8 @@ def main():
     if not args.no_xray:
         torch.cuda.empty_cache()
         out["xray"] = bench_xray(args, torch, dev)
+    if not args.profile:
+        out["parity_workload"] = bench_parity(args, torch, dev)
     if not args.no_train:
         torch.cuda.empty_cache()
         out["train"] = bench_train(args, torch, dev)
