@@ -148,7 +148,7 @@ enum { VGR_KERNEL_GAUSSIAN = 0, VGR_KERNEL_EPANECHNIKOV = 1 };
  *               64-record batches (tile_w/h and batch 0 or those values).
  *               The forward keeps, per (tile pixel, list entry), the
  *               compositing sequence and 8 bytes for the backward's replay:
- *               28 bytes x 64 per instance of workspace.  Pair counters
+ *               16 bytes x 64 per instance of workspace.  Pair counters
  *               (vgr_set_counting) stay zero [0]
  * Without tile_resort, Gaussians are composited in ascending order of the
  * FP32 view-space depth of their mean, z = fmaf(R20, mx, fmaf(R21, my,

@@ -86,7 +86,7 @@ struct vgr_ctx {
     DevBuf tile_key, tile_order, tile_key2, tile_order2;
     DevBuf rgrad, scan_tmp, sort_tmp, words, counters, views, views_b, blk_counts, wg_time;
     DevBuf rs_key, rs_idx, rs_key2, rs_idx2;   // per-tile re-sorting (instance-sized)
-    DevBuf wseq, wseq_pos, wpair, wcount;      // per-pixel window (pair slots, pixels)
+    DevBuf wseq, wpair, wcount;                // per-pixel window (pair slots, pixels)
     ViewInfo *h_views = nullptr;      // pinned staging: [0] forward, [kMaxViews] backward
     hipEvent_t stage_ev[2] = {};      // recorded after each staging copy
     // the table last uploaded through each slot (forward: views, backward:
@@ -301,8 +301,7 @@ Buffers make_buffers(vgr_ctx *c)
     b.last_pos = ptr<int32_t>(c->last_pos);
     b.last_id = ptr<int32_t>(c->last_id);
     b.rgrad = ptr<float4>(c->rgrad);
-    b.wseq = ptr<float4>(c->wseq);
-    b.wseq_pos = ptr<int32_t>(c->wseq_pos);
+    b.wseq = ptr<int2>(c->wseq);
     b.wpair = ptr<float2>(c->wpair);
     b.wcount = ptr<int32_t>(c->wcount);
     b.d_total = ptr<uint32_t>(c->words);
@@ -390,7 +389,7 @@ void vgr_destroy(vgr_ctx *c)
                       &c->words, &c->counters, &c->views, &c->views_b, &c->blk_counts,
                       &c->wg_time,
                       &c->rs_key, &c->rs_idx, &c->rs_key2, &c->rs_idx2,
-                      &c->wseq, &c->wseq_pos, &c->wpair, &c->wcount };
+                      &c->wseq, &c->wpair, &c->wcount };
     for (DevBuf *b : all)
         if (b->p) (void)hipFree(b->p);
     if (c->h_views) (void)hipHostFree(c->h_views);
@@ -730,12 +729,10 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     if (rp.pixel_window > 0) {
         // (a capture sizes these buffers before it starts)
         if (cap < 0 && ((rc = ensure(c, c->wcount, 4 * (size_t)(p.pix > 0 ? p.pix : 1))) ||
-                        (rc = ensure(c, c->wseq, 16 * 64 * (size_t)K)) ||
-                        (rc = ensure(c, c->wseq_pos, 4 * 64 * (size_t)K)) ||
+                        (rc = ensure(c, c->wseq, 8 * 64 * (size_t)K)) ||
                         (rc = ensure(c, c->wpair, 8 * 64 * (size_t)K))))
             return rc;
-        b.wseq = ptr<float4>(c->wseq);
-        b.wseq_pos = ptr<int32_t>(c->wseq_pos);
+        b.wseq = ptr<int2>(c->wseq);
         b.wpair = ptr<float2>(c->wpair);
         b.wcount = ptr<int32_t>(c->wcount);
     }
@@ -1052,8 +1049,7 @@ int vgr_graph_capture_calls(vgr_ctx *c, const vgr_settings *st, int64_t n, const
     for (const Prepared &p : ps) pixmax = p.pix > pixmax ? p.pix : pixmax;
     if (ps[0].rp.pixel_window > 0 &&
         ((rc = ensure(c, c->wcount, 4 * (size_t)pixmax)) ||
-         (rc = ensure(c, c->wseq, 16 * 64 * (size_t)cap)) ||
-         (rc = ensure(c, c->wseq_pos, 4 * 64 * (size_t)cap)) ||
+         (rc = ensure(c, c->wseq, 8 * 64 * (size_t)cap)) ||
          (rc = ensure(c, c->wpair, 8 * 64 * (size_t)cap))))
         return rc;
     c->inst_capacity = (int64_t)(c->inst_key.bytes / 4);

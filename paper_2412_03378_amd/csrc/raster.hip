@@ -738,12 +738,10 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             if (bm == 0) continue;                      // wave-uniform
             float dy_;
             if constexpr (WIN) {
-                // per-pixel window: the replay left this pair's dL/dy and
-                // alpha T_before over the forward's marker (0, -1); a pair the
-                // forward took in but never composited keeps the marker
-                float2 wv = make_float2(0.0f, -1.0f);
+                // per-pixel window: the forward's masks name only composited
+                // pairs, whose dL/dy and alpha T_before the replay left
+                float2 wv = make_float2(0.0f, 0.0f);
                 if (bl) wv = b.wpair[(size_t)jpos * 64 + lane];
-                bl = bl && wv.y >= 0.0f;
                 const float wgt = bl ? wv.y : 0.0f;
                 acc[10] = __fmaf_rn(g[k][0], wgt, acc[10]);
                 acc[11] = __fmaf_rn(g[k][1], wgt, acc[11]);
@@ -912,65 +910,55 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 //
 // Forward: each lane walks its pixel's passing pairs in list order as the
 // colour forward does.  A pair that reaches alpha_min meets a window of W - 1
-// register slots: whichever of the pair and the slots has the smallest key
-// (the view depth of the Gaussian's maximum on the pixel's own ray,
-// mz (v0 . w) / |w|^2; ties by list position) is composited, and the pair
-// takes the freed slot.  Empty slots count as smaller than every key, so the
-// first W - 1 pairs only fill the window; at the end of the list it drains
-// in key order.  Each composited pair is appended to the pixel's compositing
-// sequence (wseq, wseq_pos), and each pair taken in gets the marker (0, -1)
-// at its list position in wpair.
+// slots: whichever of the pair and the slots has the smallest key (the view
+// depth of the Gaussian's maximum on the pixel's own ray, mz (v0 . w) / |w|^2;
+// ties by list position) is composited, and the pair takes the freed slot.
+// Empty slots count as smaller than every key, so the first W - 1 pairs only
+// fill the window; at the end of the list it drains in key order.  Each
+// composited pair is appended to the pixel's compositing sequence (wseq:
+// 1 - alpha and list position, entry k of the tile's lanes side by side), and
+// its bit is set in the mask word of its batch (where the colour forward
+// keeps its pre-test masks).
 //
 // Backward: raster_bwd_window_replay_kernel walks each pixel's sequence from
 // its end with the colour backward's replay arithmetic and writes every
-// composited pair's dL/dy and alpha T_before over its marker; the rasteriser
-// backward (WIN) then visits the records as usual and reads those values
-// instead of replaying in list order.
+// composited pair's dL/dy and alpha T_before at its list position; the
+// rasteriser backward (WIN) then visits the composited pairs the masks name
+// and reads those values instead of replaying in list order.
+// One lane's window: keys and list positions in registers (the argmin runs
+// over them), each slot's payload (1 - alpha, negated if clamped; colour) in
+// LDS at pay[slot][lane], read and written at the slot index.
 template <int WS>
 struct Window {
-    float k[WS], o[WS], c0[WS], c1[WS], c2[WS];   // key, 1 - alpha (negated if clamped), colour
-    int p[WS];                                    // list position (-1: empty)
-    float mink;                                   // smallest (key, position) ...
-    int mins;                                     // ... and its slot
+    float k[WS];          // key (-inf: empty, taken first; +inf: unused)
+    int p[WS];            // list position (-1: empty)
+    float mink;           // smallest (key, position) ...
+    int mins, minp;       // ... its slot and position
+    float4 (*pay)[64];
+    int lane;
 
     __device__ __forceinline__ void rescan()
     {
         mink = k[0];
         mins = 0;
-        int mp = p[0];
+        minp = p[0];
 #pragma unroll
         for (int s = 1; s < WS; ++s) {
-            const bool lt = k[s] < mink || (k[s] == mink && p[s] < mp);
+            const bool lt = k[s] < mink || (k[s] == mink && p[s] < minp);
             mink = lt ? k[s] : mink;
             mins = lt ? s : mins;
-            mp = lt ? p[s] : mp;
+            minp = lt ? p[s] : minp;
         }
     }
-    // the smallest slot's entry
-    __device__ __forceinline__ void take(float &so, float &s0, float &s1, float &s2, int &sp) const
+    // the payload of the smallest slot (meaningless where that slot is empty)
+    __device__ __forceinline__ float4 take() const { return pay[mins][lane]; }
+    __device__ __forceinline__ void put(bool on, float key, int pos, const float4 &v)
     {
-        so = 1.0f; s0 = s1 = s2 = 0.0f; sp = -1;
-#pragma unroll
-        for (int s = 0; s < WS; ++s) {
-            const bool hit = s == mins;
-            so = hit ? o[s] : so;
-            s0 = hit ? c0[s] : s0;
-            s1 = hit ? c1[s] : s1;
-            s2 = hit ? c2[s] : s2;
-            sp = hit ? p[s] : sp;
-        }
-    }
-    __device__ __forceinline__ void put(bool on, float key, float om, float a0, float a1, float a2,
-                                        int pos)
-    {
+        if (on) pay[mins][lane] = v;
 #pragma unroll
         for (int s = 0; s < WS; ++s) {
             const bool w = on && s == mins;
             k[s] = w ? key : k[s];
-            o[s] = w ? om : o[s];
-            c0[s] = w ? a0 : c0[s];
-            c1[s] = w ? a1 : c1[s];
-            c2[s] = w ? a2 : c2[s];
             p[s] = w ? pos : p[s];
         }
     }
@@ -983,6 +971,7 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
     constexpr bool NEAR = MODE == kModeColorNear;
     constexpr bool EPAN = MODE == kModeColorEpan;
     __shared__ Stage<B> st;
+    __shared__ float4 wpay[WS][64];
 
     const bool timed = b.wg_time != nullptr;   // uniform
     const uint64_t t_start = timed ? wg_clock() : 0;
@@ -1006,17 +995,23 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
     const float zn = vi.znear;
     const int nslot = rp.pixel_window - 1;
     Window<WS> win;
+    win.pay = wpay;
+    win.lane = lane;
 #pragma unroll
     for (int s = 0; s < WS; ++s) {
         win.k[s] = s < nslot ? -INFINITY : INFINITY;   // empty: taken first; unused: never
-        win.o[s] = 1.0f;
-        win.c0[s] = win.c1[s] = win.c2[s] = 0.0f;
         win.p[s] = -1;
+        // a slot never filled is still read (and multiplied by a zero weight)
+        wpay[s][lane] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
     }
     win.rescan();
-    const size_t seq0 = (size_t)range.x * 64 + lane;
     // Composite one pair (oms: 1 - alpha, negated where alpha was clamped) if
     // `on`, or stop the pixel where T (1 - alpha) < T_min (Sec. 4.1).
+    // composited pairs of the current batch (bit q: list position cur + q);
+    // pairs of earlier batches are marked in their batch's word, which this
+    // lane alone owns and has written at the end of that batch
+    uint64_t cm = 0;
+    uint32_t cur = range.x;
     auto composite = [&](bool on, float oms, float c0, float c1, float c2, int pos) {
         const float om = fabsf(oms);
         const float Tn = T * om;
@@ -1027,9 +1022,14 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
         C1 = __fmaf_rn(c1, wgt, C1);
         C2 = __fmaf_rn(c2, wgt, C2);
         if (dob) {
-            const size_t q = seq0 + (size_t)nseq * 64;
-            b.wseq[q] = make_float4(oms, c0, c1, c2);
-            b.wseq_pos[q] = pos;
+            b.wseq[window_seq(range.x, nseq, lane)] = make_int2(__float_as_int(oms), pos);
+            if ((uint32_t)pos >= cur) {
+                cm |= 1ull << ((uint32_t)pos - cur);
+            } else {
+                const uint32_t ob = range.x + (((uint32_t)pos - range.x) / B) * B;
+                uint64_t &wd = b.pmask[mask_word<B>(ob, gt, lane)];
+                wd |= 1ull << ((uint32_t)pos - ob);
+            }
         }
         T = dob ? Tn : T;
         lastp = dob ? pos : lastp;
@@ -1056,7 +1056,8 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
             }
         }
         uint64_t mk = ((uint64_t)mh[1] << 32) | mh[0];
-        b.pmask[mask_word<B>(bs, gt, lane)] = mk;
+        cur = bs;
+        cm = 0;
         while (wave_any(mk != 0 && act)) {                 // wave-uniform loop
             const bool has = mk != 0 && act;
             const int qi = has ? (int)__builtin_ctzll(mk) : 0;
@@ -1083,20 +1084,22 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
             const float key = fr.mz * vw * (rq * rq);
             const int pos = (int)bs + qi;
             visited = has ? pos : visited;
-            if (cand) b.wpair[(size_t)pos * 64 + lane] = make_float2(0.0f, -1.0f);
             // the pair goes first if it precedes every entry; otherwise the
             // smallest entry leaves (none while its slot is empty) and the
             // pair takes the slot
             const bool direct = cand && key < win.mink;
             const bool swap = cand && !direct;
-            float so, s0, s1, s2;
-            int sp;
-            win.take(so, s0, s1, s2, sp);
-            composite(direct || (swap && sp >= 0), direct ? oms : so, direct ? fr.c0 : s0,
-                      direct ? fr.c1 : s1, direct ? fr.c2 : s2, direct ? pos : sp);
-            win.put(swap, key, oms, fr.c0, fr.c1, fr.c2, pos);
+            const float4 w = win.take();
+            const int sp = win.minp;
+            composite(direct || (swap && sp >= 0), direct ? oms : w.x, direct ? fr.c0 : w.y,
+                      direct ? fr.c1 : w.z, direct ? fr.c2 : w.w, direct ? pos : sp);
+            win.put(swap, key, pos, make_float4(oms, fr.c0, fr.c1, fr.c2));
             win.rescan();
         }
+        // the batch's composited pairs, for the backward (every later mark
+        // of this batch is a read-modify-write of this word)
+        b.pmask[mask_word<B>(bs, gt, lane)] = cm;
+        cur = range.y;
         __syncthreads();
         if (!wave_any(act)) break;                          // every pixel has stopped
     }
@@ -1107,10 +1110,8 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
     win.rescan();
     while (wave_any(act && win.mink < INFINITY)) {
         const bool on = act && win.mink < INFINITY;
-        float so, s0, s1, s2;
-        int sp;
-        win.take(so, s0, s1, s2, sp);
-        composite(on, so, s0, s1, s2, sp);
+        const float4 w = win.take();
+        composite(on, w.x, w.y, w.z, w.w, win.minp);
 #pragma unroll
         for (int s = 0; s < WS; ++s) win.k[s] = (on && s == win.mins) ? INFINITY : win.k[s];
         win.rescan();
@@ -1134,8 +1135,9 @@ __global__ __launch_bounds__(64) void raster_fwd_window_kernel(RenderParams rp, 
 
 // Reverse replay of each pixel's compositing sequence (per-pixel window):
 // T before a pair is T after it over its 1 - alpha, and GB = dL/dC . (colour
-// behind it) accumulates from T_final bg, as in the colour backward; writes
-// (dL/dy, alpha T_before) at the pair's list position.
+// behind it) accumulates from T_final bg, as in the colour backward, with the
+// colour read from the pair's record; writes (dL/dy, alpha T_before) at the
+// pair's list position.
 __global__ __launch_bounds__(64) void raster_bwd_window_replay_kernel(RenderParams rp, Buffers b)
 {
     const int gt = (int)b.tile_order[blockIdx.x];
@@ -1158,22 +1160,42 @@ __global__ __launch_bounds__(64) void raster_bwd_window_replay_kernel(RenderPara
         gbg = __fmaf_rn(g[c], rp.bg[c], gbg);
     }
     float GB = T * gbg;
-    const size_t seq0 = (size_t)b.ranges[gt].x * 64 + lane;
-    for (int k = n - 1; k >= 0; --k) {
-        const size_t q = seq0 + (size_t)k * 64;
-        const float4 e = b.wseq[q];
-        const int pos = b.wseq_pos[q];
-        const float om = fabsf(e.x);
-        const float inv = fast_rcp(om);
-        const float alpha = 1.0f - om;
-        const float Tb = T * inv;
-        // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
-        const float gc = __fmaf_rn(g[0], e.y, __fmaf_rn(g[1], e.z, g[2] * e.w));
-        const float da = __fmaf_rn(Tb, gc, -(inv * GB));
-        const float wgt = alpha * Tb;
-        GB = __fmaf_rn(gc, wgt, GB);
-        T = Tb;
-        b.wpair[(size_t)pos * 64 + lane] = make_float2(e.x < 0.0f ? 0.0f : da * kLn2 * om, wgt);
+    const uint2 range = b.ranges[gt];
+    // eight steps at a time: their sequence entries, then their records'
+    // item ids, then their colours are loaded together (three round trips
+    // per eight steps instead of one per load), then the eight steps run in
+    // order
+    constexpr int U = 8;
+    for (int k = n - 1; k >= 0; k -= U) {
+        int2 e[U];
+        uint32_t item[U];
+        float4 cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            e[u] = k - u >= 0 ? b.wseq[window_seq(range.x, k - u, lane)] : make_int2(0, 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) item[u] = k - u >= 0 ? b.inst_val[e[u].y] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            cc[u] = k - u >= 0 ? b.geom[(size_t)item[u] * kRecVec + 5] : make_float4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k - u < 0) break;
+            const float oms = __int_as_float(e[u].x);
+            const int pos = e[u].y;
+            const float om = fabsf(oms);
+            const float inv = fast_rcp(om);
+            const float alpha = 1.0f - om;
+            const float Tb = T * inv;
+            // dL/dalpha = T_before (g.c) - (g.B) / (1 - alpha)
+            const float gc = __fmaf_rn(g[0], cc[u].x, __fmaf_rn(g[1], cc[u].y, g[2] * cc[u].z));
+            const float da = __fmaf_rn(Tb, gc, -(inv * GB));
+            const float wgt = alpha * Tb;
+            GB = __fmaf_rn(gc, wgt, GB);
+            T = Tb;
+            b.wpair[(size_t)pos * 64 + lane] =
+                make_float2(oms < 0.0f ? 0.0f : da * kLn2 * om, wgt);
+        }
     }
 }
 

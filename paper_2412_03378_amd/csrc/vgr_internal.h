@@ -149,16 +149,16 @@ struct Buffers {
     float4 *rgrad;       // n_views * n * 4 float4 (record gradients)
     uint64_t *pmask;     // pmask_words(): bound pre-test lane masks of each B-record
                          // batch of a tile list, written by the forward where
-                         // raster_keeps_masks() and read by the backward
-    // per-pixel window (pixel_window > 0), pair slots (list position) * 64 + lane:
-    float4 *wseq;        // capacity * 64: the k-th composited pair of a tile pixel at
-                         // (tile start + k) * 64 + lane: (1 - alpha, negated where
-                         // alpha was clamped; colour)
-    int32_t *wseq_pos;   // capacity * 64: its list position, same slots
-    float2 *wpair;       // capacity * 64, by list position: (0, -1) for a pair the
-                         // forward took into the window; the backward replay
-                         // overwrites composited ones with (dL/dy, 0 where alpha
-                         // was clamped; alpha T_before)
+                         // raster_keeps_masks() and read by the backward (with
+                         // the per-pixel window: the pairs composited)
+    // per-pixel window (pixel_window > 0), capacity * 64 slots each:
+    int2 *wseq;          // the k-th composited pair of tile lane l (tile list
+                         // starting at s) at window_seq(s, k, l) = (s + k) 64 + l:
+                         // (bits of 1 - alpha, negated where alpha was clamped;
+                         // list position)
+    float2 *wpair;       // at (list position) * 64 + lane, written by the backward
+                         // replay for composited pairs: (dL/dy, 0 where alpha was
+                         // clamped; alpha T_before)
     int32_t *wcount;     // total pixels: pairs composited
     uint32_t *blk_counts;// preprocess blocks: instances per block
     uint32_t *d_total;   // [0] = instance count K, [1] overflow flag, [4] K from the
@@ -222,7 +222,14 @@ hipError_t launch_raster_fwd(const RenderParams &rp, const Buffers &b, bool coun
 hipError_t launch_raster_bwd(const RenderParams &rp, const Buffers &b, bool count,
                              hipStream_t s);
 // Per-pixel window: bytes of the pair buffers per instance of capacity.
-constexpr int64_t kWindowBytesPerInstance = 64 * (16 + 4 + 8);
+constexpr int64_t kWindowBytesPerInstance = 64 * (8 + 8);
+// Entry k of tile lane `lane`'s compositing sequence (tile list starting at
+// `start`; k below the list length): entry k of the tile's 64 lanes side by
+// side, so that lanes at the same length store to one line.
+__host__ __device__ inline size_t window_seq(uint32_t start, int k, int lane)
+{
+    return ((size_t)start + (size_t)k) * 64 + (size_t)lane;
+}
 // accumulate: add to the gradient arrays; otherwise overwrite every element.
 // gnorm / vcount (may be null): densification statistics, always added to.
 hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const float *means,
