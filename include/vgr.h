@@ -187,7 +187,11 @@ typedef struct {
                                 /*   pairs tested, and visits = evaluation */
                                 /*   steps, where it reuses the forward's  */
                                 /*   bound-test masks: colour mode, or one */
-                                /*   pixel per lane)                       */
+                                /*   pixel per lane).  With 8x8 tiles each */
+                                /*   4x4 quarter walks its own Gaussians:  */
+                                /*   bwd_visits counts wave steps (up to   */
+                                /*   four Gaussians each), bwd_visits_full */
+                                /*   (Gaussian, quarter) visits            */
     int64_t bwd_pairs_blended;
     int64_t bwd_visits;
     int64_t bwd_visits_full;

@@ -558,10 +558,42 @@ __device__ __forceinline__ uint32_t dpp_move_u(uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ float wave_reduce16(float v[16], int lane)
+// With N13 only v[0..12] are summed (v[13..15] are zero): step 1 pairs
+// (v[k], v[k+8]) for k < 5, then (v[5], v[6]) and (v[7], 0), leaving seven
+// slots.  Slot s and the lane bit h that picked the pair member give the
+// index of the total a lane ends with, n13_index(s, h); -1: the lane holds
+// no total.
+__device__ __forceinline__ int n13_index(int s, int h)
 {
+    return s < 5 ? s + 8 * h : (s == 5 ? 5 + h : ((s == 6 && h == 0) ? 7 : -1));
+}
+
+template <bool N13, class SWAP>
+__device__ __forceinline__ void pair_step1(float (&v)[16], SWAP swap_add)
+{
+    if constexpr (N13) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = swap_add32(v[k], v[k + 8]);
+        for (int k = 0; k < 5; ++k) v[k] = swap_add(v[k], v[k + 8]);
+        v[5] = swap_add(v[5], v[6]);
+        v[6] = swap_add(v[7], 0.0f);
+        v[7] = 0.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = swap_add(v[k], v[k + 8]);
+    }
+}
+
+// Index of the total lane l holds after wave_reduce16 (lanes l & 3 == 0).
+template <bool N13>
+__device__ __forceinline__ int wave_index(int lane)
+{
+    return N13 ? n13_index((lane >> 2) & 7, (lane >> 5) & 1) : lane >> 2;
+}
+
+template <bool N13>
+__device__ __forceinline__ float wave_reduce16(float (&v)[16], int lane)
+{
+    pair_step1<N13>(v, [](float a, float b) { return swap_add32(a, b); });
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = swap_add16(v[k], v[k + 4]);
     {
@@ -584,6 +616,69 @@ __device__ __forceinline__ float wave_reduce16(float v[16], int lane)
     return v[0];
 }
 
+// 8x8 tiles, one pixel per lane (x = lane bits 0-2, y = lane bits 3-5): the
+// 4x4 quarter of lane l is (l bit 2, l bit 5).  Sum v[0..15] over the 16
+// lanes of each quarter at once.  Afterwards every lane holds one total of its
+// quarter, of index quarter_index(l) (-1: none).
+//   step 1: v_permlane16_swap pairs across lanes l, l ^ 16;
+//   step 2: lanes l and l ^ 8 (DPP row rotate by 8) keep half of the slots
+//           and send the other half;
+//   steps 3, 4: the same within each quad, across l ^ 2 and then l ^ 1.
+template <bool N13>
+__device__ __forceinline__ int quarter_index(int lane)
+{
+    const int s = (lane & 3) | ((lane >> 1) & 4);
+    return N13 ? n13_index(s, (lane >> 4) & 1) : s | ((lane >> 1) & 8);
+}
+
+// Slots k and k + D for k < n: lanes with hi keep slot k + D and send slot k,
+// the others the reverse; slot k then holds the pair's sum across the lanes.
+template <int CTRL, int D>
+__device__ __forceinline__ void keep_send_add(float (&v)[16], int n, bool hi)
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < n) {
+            const float send = hi ? v[k] : v[k + D];
+            const float keep = hi ? v[k + D] : v[k];
+            v[k] = keep + dpp_move<CTRL>(send);
+        }
+    }
+}
+
+template <bool N13>
+__device__ __forceinline__ float quarter_reduce16(float (&v)[16], int lane)
+{
+    pair_step1<N13>(v, [](float a, float b) { return swap_add16(a, b); });
+    if constexpr (N13) {
+        // slot 7 is empty: slot 3 only needs its sum across l ^ 8
+        keep_send_add<kDppRowRor8, 4>(v, 3, lane & 8);
+        v[3] += dpp_move<kDppRowRor8>(v[3]);
+    } else {
+        keep_send_add<kDppRowRor8, 4>(v, 4, lane & 8);
+    }
+    keep_send_add<kDppQuadXor2, 2>(v, 2, lane & 2);
+    keep_send_add<kDppQuadXor1, 1>(v, 1, lane & 1);
+    return v[0];
+}
+
+// OR of a 64-bit lane mask over the lane's quarter (as in quarter_reduce16).
+__device__ __forceinline__ uint64_t quarter_or(uint64_t m)
+{
+    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    lo = a[0] | a[1];
+    hi = c[0] | c[1];
+    lo |= dpp_move_u<kDppRowRor8>(lo);
+    hi |= dpp_move_u<kDppRowRor8>(hi);
+    lo |= dpp_move_u<kDppQuadXor2>(lo);
+    hi |= dpp_move_u<kDppQuadXor2>(hi);
+    lo |= dpp_move_u<kDppQuadXor1>(lo);
+    hi |= dpp_move_u<kDppQuadXor1>(hi);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int TW, int TH, int MODE, bool COUNT, int B, bool WIN = false>
 __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers b)
 {
@@ -597,6 +692,9 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     constexpr int NCH = COLOR ? 3 : 1;
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
+    // 8x8 tiles: each 4x4 quarter walks the records of its own pixels, so that
+    // one step of the wave handles up to four records (quarter_reduce16)
+    constexpr bool QUAD = PPL == 1;
     __shared__ Stage<B> st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
@@ -669,7 +767,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             const uint64_t pm = __builtin_amdgcn_ballot_w64(pass[k]);
-            if (COUNT) n.visits_full += (lane == 0 && pm != 0) ? 1u : 0u;
+            if (COUNT && !QUAD) n.visits_full += (lane == 0 && pm != 0) ? 1u : 0u;
             if (pm == 0) continue;                  // wave-uniform
             if (COUNT) n.full += pass[k] ? 1u : 0u;
             const float dy = (pyc[k] - pr.hy) - pr.ly;
@@ -789,7 +887,7 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             const float tz0 = tzw * z0, tz1 = tzw * z1, tz2 = tzw * z2;
             float tw = t;   // weight of w' w'^T
             if constexpr (NEAR) {
-                if (fr.K < 0.0f) {   // wave-uniform: the whole wave is on one record
+                if (fr.K < 0.0f) {   // uniform over the lanes on this record
                     tw = __fmaf_rn(t, hn, t);
                     const float th = t * hh;
                     acc[13] += th * p0;
@@ -809,9 +907,20 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
             acc[5] += __fmaf_rn(tp2, p2, tz2 * z2);
         }
         if (touched != 0) {
-            const float tot = wave_reduce16(acc, lane);
-            if ((lane & 3) == 0)
-                atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + (lane >> 2), tot);
+            if constexpr (QUAD) {
+                // lanes of the quarter that blended this step's record
+                const uint64_t qm = ((lane & 4) ? 0xF0F0F0F0F0F0F0F0ull : 0x0F0F0F0F0F0F0F0Full) &
+                                    ((lane & 32) ? ~0ull << 32 : ~0ull >> 32);
+                const float tot = quarter_reduce16<!NEAR>(acc, lane);
+                const int e = quarter_index<!NEAR>(lane);
+                if ((touched & qm) != 0 && e >= 0)
+                    atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + e, tot);
+            } else {
+                const float tot = wave_reduce16<!NEAR>(acc, lane);
+                const int e = wave_index<!NEAR>(lane);
+                if ((lane & 3) == 0 && e >= 0)
+                    atomicAdd(rg + (size_t)st.item[qi] * kGradFloats + e, tot);
+            }
         }
     };
 
@@ -831,6 +940,33 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 const uint64_t lim = d < 0 ? 0ull : (d >= 63 ? ~0ull : (2ull << d) - 1ull);
                 mask[k] = b.pmask[mask_word<B>((uint32_t)bs, gt, lane) * PPL + k] & lim;
                 any |= mask[k];
+            }
+            if constexpr (QUAD) {
+                // the records some pixel of the lane's quarter admits, walked
+                // from the back; a quarter with none left idles on record 0
+                // (staged, so its arithmetic stays finite) with no pixel passing
+                // (bit-reversed masks: the next record is the lowest set bit)
+                uint64_t ur = __builtin_bitreverse64(quarter_or(any));
+                const uint64_t mr = __builtin_bitreverse64(mask[0]);
+                __syncthreads();
+                while (wave_any(ur != 0)) {
+                    const bool act = ur != 0;
+                    const int jr = act ? __builtin_ctzll(ur) : 63;
+                    const int qi = 63 - jr;
+                    ur &= ur - 1ull;
+                    if (COUNT) {
+                        n.visits += lane == 0 ? 1u : 0u;
+                        n.visits_full += (act && (lane & 0x1B) == 0) ? 1u : 0u;
+                    }
+                    const RecRegs rr = load_regs(st, qi);
+                    const PreRec pr = pre_of(rr);
+                    const float dx = (pxc - pr.hx) - pr.lx;
+                    bool pass[PPL];
+                    pass[0] = act && ((mr >> jr) & 1u);
+                    record(qi, pr, dx, pass, bs + qi);
+                }
+                __syncthreads();
+                continue;
             }
             // union over the wave: OR within each row of 16 lanes, then of the rows
             uint32_t lo = (uint32_t)any, hi = (uint32_t)(any >> 32);
