@@ -308,13 +308,28 @@ def bench_batched(args, torch, dev):
     r.graph_capture(params, wl.cams, st, outs, dLs, grads, capacity_factor=1.1, zero_grads=True)
     res["batched"] = nv / _graph_time(r, args.batched_steps, torch)
     _log("single-view calls")
-    # single-view calls get their own tuned tile (tuned on the largest view)
-    big = max(range(nv), key=lambda k: wl.cams[k].width * wl.cams[k].height)
-    tile1, batch1, _ = r.autotune(params, [wl.cams[big]], Settings(sh_degree=3), [outs[big]],
-                                  [dLs[big]], grads, iters=2)
+    # single-view calls get their own launch shape: the 16 calls timed for
+    # each shape the autotuner tries, the fastest kept
+    def single_calls(stx):
+        for k, (c, d) in enumerate(zip(wl.cams, dLs)):
+            r.forward(*params, [c], stx)
+            r.backward([d], *grads, accumulate=k > 0)
+    shapes = [((w, h), bb) for bb in (64, 32) for (w, h) in ((8, 8), (16, 8), (16, 16), (32, 8))]
+    single_ms = []
+    for (tw, th), bb in shapes:
+        stx = Settings(sh_degree=3, tile=(tw, th), batch=bb)
+        single_calls(stx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            single_calls(stx)
+        torch.cuda.synchronize()
+        single_ms.append((time.perf_counter() - t0) / 2 * 1e3)
+    tile1, batch1 = shapes[min(range(len(shapes)), key=lambda i: single_ms[i])]
     st1 = Settings(sh_degree=3, tile=tile1, batch=batch1)
     res["tile_single"] = list(tile1)
     res["batch_single"] = batch1
+    res["single_tune_ms"] = [round(x, 3) for x in single_ms]
 
     def eager(calls):
         for _ in range(max(1, args.warmup // 2)):
@@ -327,9 +342,7 @@ def bench_batched(args, torch, dev):
         return nv / ((time.perf_counter() - t0) / args.batched_steps)
 
     def run_single():
-        for k, (c, d) in enumerate(zip(wl.cams, dLs)):
-            r.forward(*params, [c], st1)
-            r.backward([d], *grads, accumulate=k > 0)
+        single_calls(st1)
     # like for like: eager against eager (each single-view call waits on the
     # host for its instance count, as the batched call does once), and one
     # captured graph against one captured graph of the 16 single-view calls
@@ -847,6 +860,7 @@ def main():
                           "tile": res["tile"], "batch": res["batch"],
                           "autotune_ms": res["autotune_ms"],
                           "tile_single": res["tile_single"], "batch_single": res["batch_single"],
+                          "single_tune_ms": res["single_tune_ms"],
                           "views_per_s_batched": round(res["batched"], 2),
                           "views_per_s_single": round(res["single"], 2),
                           "speedup": round(res["batched"] / res["single"], 3),
