@@ -347,8 +347,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
     #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 uint64_t mk = mask[k];
-                while (wave_any(mk != 0 && act[k])) {           // wave-uniform loop
-                    const bool has = mk != 0 && act[k];
+                bool has = mk != 0 && act[k];
+                if (wave_any(has)) do {                          // wave-uniform loop
                     const int qi = has ? (int)__builtin_ctzll(mk) : 0;
                     mk &= mk - 1;
                     if (COUNT) {
@@ -403,7 +403,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RenderParams rp, Buffers
                         last[k] += bl ? 1 : 0;   // number of terms (starts at -1)
                         if (COUNT) n.blend += bl ? 1u : 0u;
                     }
-                }
+                    has = mk != 0 && act[k];
+                } while (wave_any(has));
             }
         } else {
             // X-ray with several pixels per lane: every record of the list is
@@ -951,8 +952,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                 uint64_t ur = __builtin_bitreverse64(quarter_or(any));
                 const uint64_t mr = __builtin_bitreverse64(mask[0]);
                 __syncthreads();
-                while (wave_any(ur != 0)) {
-                    const bool act = ur != 0;
+                bool act = ur != 0;
+                if (wave_any(act)) do {
                     const int jr = act ? __builtin_ctzll(ur) : 63;
                     const int qi = 63 - jr;
                     ur &= ur - 1ull;
@@ -966,7 +967,8 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
                     bool pass[PPL];
                     pass[0] = act && ((mr >> jr) & 1u);
                     record(qi, pr, dx, pass, bs + qi);
-                }
+                    act = ur != 0;
+                } while (wave_any(act));
                 __syncthreads();
                 continue;
             }
