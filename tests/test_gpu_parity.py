@@ -405,3 +405,42 @@ def test_workgroup_timing_and_pair_counts(R, dev, cfg1):
     assert s["pairs_blended"] > 0 and s["pairs_blended"] == s["bwd_pairs_blended"]
     assert s["bwd_pairs_tested"] == 0
     assert s["pairs_full"] >= s["pairs_blended"] and s["pairs_tested"] >= s["pairs_full"]
+
+
+@pytest.mark.parametrize("act", ["softplus", "clamp"])
+def test_backward_quarters_with_uneven_lists(R, dev, act):
+    """8x8 tiles, where each 4x4 quarter of a tile walks its own Gaussians in
+    the backward: sub-pixel Gaussians (one quarter each, so the quarters'
+    lists differ in length and content) over a few that span whole tiles,
+    some tiles left with one busy quarter; image and gradients against the
+    oracle, then the walk's counters: every wave step carries one to four
+    (Gaussian, quarter) visits."""
+    rng = np.random.default_rng(51)
+    cam = scenes.axis_camera(4.0, 64, 48, 50.0)
+    n_small, n_big = 500, 12
+    means = np.r_[np.c_[rng.uniform(-0.9, 0.9, (n_small, 2)), rng.uniform(-0.5, 0.5, n_small)],
+                  np.c_[rng.uniform(-0.5, 0.5, (n_big, 2)), rng.uniform(0.3, 0.6, n_big)]]
+    # the left third of the frame holds only the small ones
+    means[:n_small, 0] = np.where(rng.random(n_small) < 0.4, -0.85 + 0.3 * rng.random(n_small),
+                                  means[:n_small, 0])
+    scales = np.r_[np.exp(rng.uniform(np.log(0.004), np.log(0.012), (n_small, 3))),
+                   np.exp(rng.uniform(np.log(0.15), np.log(0.35), (n_big, 3)))]
+    dens = np.r_[np.exp(rng.uniform(np.log(5.0), np.log(60.0), n_small)),
+                 np.exp(rng.uniform(np.log(0.3), np.log(2.0), n_big))]
+    sc = H.scene(means, scales, dens, quats=rng.standard_normal((n_small + n_big, 4)),
+                 rgb=rng.uniform(0, 1, (n_small + n_big, 3)))
+    st = _settings(act=act, tile=(8, 8), bg=(0.2, 0.1, 0.3))
+    _fwd_bwd_check(R, dev, sc, cam, st, seed=52)
+    t = G.device_scene(sc, dev)
+    R.set_counting(True)
+    R.forward(*t, [cam], st)
+    grads = [torch.zeros_like(x) for x in t]
+    R.backward([torch.ones((3, cam.height, cam.width), device=dev)], *grads)
+    s = R.stats()
+    R.set_counting(False)
+    steps, visits = s["bwd_visits"], s["bwd_visits_full"]
+    print(f"backward steps {steps}, (Gaussian, quarter) visits {visits}, "
+          f"pairs {s['bwd_pairs_full']}")
+    assert 0 < steps <= visits <= 4 * steps
+    assert s["bwd_pairs_full"] <= 16 * visits
+    assert s["pairs_blended"] == s["bwd_pairs_blended"]
