@@ -694,10 +694,11 @@ __global__ __launch_bounds__(64) void raster_bwd_kernel(RenderParams rp, Buffers
     // the forward kept its pre-test masks for this shape and mode
     constexpr bool KEEP = COLOR || PPL == 1;
     // 8x8 tiles: each 4x4 quarter walks the records of its own pixels, so that
-    // one step of the wave handles up to four records (quarter_reduce16).  Not
-    // for the splatting opacity, whose few operations per pair do not pay for
-    // the per-lane walk (measured slower).
-    constexpr bool QUAD = PPL == 1 && !SPLAT;
+    // one step of the wave handles up to four records (quarter_reduce16).  Colour
+    // modes with the volumetric opacity only: the splatting opacity's and the
+    // X-ray backward's few operations per pair do not pay for the per-lane walk
+    // (measured slower).
+    constexpr bool QUAD = PPL == 1 && COLOR && !SPLAT;
     __shared__ Stage<B> st;
 
     const bool timed = b.wg_time != nullptr;   // uniform
