@@ -674,11 +674,6 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         if (cap < 0) {
             HIP_TRY(c, hipEventSynchronize(c->k_ev));
             mv = c->h_words[2] < (uint64_t)m ? (int64_t)c->h_words[2] : m;
-        }
-        HIP_TRY(c, launch_gather_counts(b, mv, rp.total_tiles, s));
-        HIP_TRY(c, launch_scan_u32(b.cnt_sorted, b.offsets, mv, ptr<uint32_t>(c->scan_tmp), true,
-                                   s));
-        if (cap < 0) {
             K = c->h_words[0];
             if ((rc = ensure(c, c->inst_key, 4 * K)) || (rc = ensure(c, c->inst_val, 4 * K)) ||
                 (rc = ensure(c, c->inst_key2, 4 * K)) || (rc = ensure(c, c->inst_val2, 4 * K)) ||
@@ -694,7 +689,11 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
         } else {
             K = cap;
         }
-        HIP_TRY(c, launch_finalize_count(b, mv, K, s));
+        // per-item counts in depth order with their block sums, then their
+        // scan, whose total is the instance count (clamped to the capacity K)
+        HIP_TRY(c, launch_gather_counts(b, mv, rp.total_tiles, ptr<uint32_t>(c->scan_tmp), s));
+        HIP_TRY(c, launch_count_scan(b.cnt_sorted, b.offsets, mv, ptr<uint32_t>(c->scan_tmp),
+                                     b.d_total, K, s));
         HIP_TRY(c, launch_emit(rp, b, mv, K, s));
         mark_end(c, ST_SCAN_EMIT);
         mark(c, ST_SORT_TILES);

@@ -643,33 +643,39 @@ __global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__rest
     }
 }
 
-// Tile counts in depth order.  Items past the nvis[0] that have instances
-// (they sort last) have none, so their counts are not gathered.  The same
-// launch clears the per-tile ranges and the 64 tile-order counters (read by
-// the range and tile-order kernels later in the forward).
-__global__ void gather_counts_kernel(const uint32_t *__restrict__ sorted_items,
-                                     const uint32_t *__restrict__ counts,
-                                     const uint32_t *__restrict__ nvis,
-                                     uint32_t *__restrict__ out, int64_t m,
-                                     uint2 *__restrict__ ranges, int32_t n_tiles,
-                                     uint32_t *__restrict__ order_counters)
+// Tile counts in depth order, one item per thread, with each block's sum
+// (kScanGrain items) into partial[block] for the scan.  Items past the
+// nvis[0] that have instances (they sort last) have none, so their counts are
+// not gathered.  The same launch clears the per-tile ranges and the 64
+// tile-order counters (read by the range and tile-order kernels later in the
+// forward).
+constexpr int kGatherThreads = (int)kScanGrain;
+
+__global__ __launch_bounds__(kGatherThreads) void gather_counts_kernel(
+    const uint32_t *__restrict__ sorted_items, const uint32_t *__restrict__ counts,
+    const uint32_t *__restrict__ nvis, uint32_t *__restrict__ out, int64_t m,
+    uint32_t *__restrict__ partial, uint2 *__restrict__ ranges, int32_t n_tiles,
+    uint32_t *__restrict__ order_counters)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m) out[j] = j < (int64_t)nvis[0] ? counts[sorted_items[j]] : 0u;
+    __shared__ uint32_t s_w[kGatherThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kGatherThreads;
+    const int64_t j = base + threadIdx.x;
+    uint32_t c = 0;
+    if (j < m) {
+        c = j < (int64_t)nvis[0] ? counts[sorted_items[j]] : 0u;
+        out[j] = c;
+    }
     if (j < n_tiles) ranges[j] = make_uint2(0u, 0u);
     if (j < 64) order_counters[j] = 0u;
-}
-
-// Instance count K = offsets[m], clamped to the capacity (overflow flag).
-__global__ void finalize_count_kernel(const uint32_t *__restrict__ offsets, int64_t m,
-                                      int64_t capacity, uint32_t *__restrict__ d_total)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const uint32_t K = offsets[m];
-        d_total[0] = (int64_t)K > capacity ? (uint32_t)capacity : K;
-        d_total[1] = (int64_t)K > capacity ? 1u : 0u;
-        if ((int64_t)K > capacity) d_total[5] = 1u;   // sticky until the host clears it
-        d_total[7] = 0u;   // items whose emission will not match their count (emit_kernel)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0 && base < m) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kGatherThreads / 64; ++w) t += s_w[w];
+        partial[blockIdx.x] = t;
     }
 }
 
@@ -1358,19 +1364,14 @@ int64_t preprocess_blocks(int64_t n, int32_t n_views)
     return 2 * (int64_t)grid_for(n, 256);   // instance and visible-item partial sums
 }
 
-hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles, hipStream_t s)
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles,
+                                uint32_t *partial, hipStream_t s)
 {
     int64_t n = m > total_tiles ? m : total_tiles;
     if (n < 64) n = 64;
-    gather_counts_kernel<<<grid_for(n, 256), 256, 0, s>>>(b.item_ids, b.counts, b.d_total + 6,
-                                                          b.cnt_sorted, m, b.ranges, total_tiles,
-                                                          b.tile_key);
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s)
-{
-    finalize_count_kernel<<<1, 64, 0, s>>>(b.offsets, m, capacity, b.d_total);
+    gather_counts_kernel<<<grid_for(n, kGatherThreads), kGatherThreads, 0, s>>>(
+        b.item_ids, b.counts, b.d_total + 6, b.cnt_sorted, m, partial, b.ranges, total_tiles,
+        b.tile_key);
     return hipGetLastError();
 }
 

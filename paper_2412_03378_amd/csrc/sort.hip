@@ -21,6 +21,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;   // 4096
+static_assert(kTile % kScanGrain == 0, "scan grain");
 constexpr int kWaves = kThreads / 64;
 
 __device__ inline uint32_t wave_inclusive_scan(uint32_t v)
@@ -54,26 +55,15 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total)
     return off + inc - v;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *__restrict__ in,
-                                                               int64_t n,
-                                                               uint32_t *__restrict__ partial)
-{
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-        int64_t idx = base + (int64_t)i * kThreads + threadIdx.x;
-        if (idx < n) acc += in[idx];
-    }
-    uint32_t total;
-    block_exclusive_scan(acc, &total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
-}
-
 // Single block: exclusive scan of the nb block sums in place, chunk by chunk.
+// With d_total, the total is also the instance count K: d_total[0] = K
+// clamped to capacity, d_total[1] = overflow, d_total[5] set (sticky) on
+// overflow, d_total[7] = 0 (the emission's mismatch counter).
 __global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t *__restrict__ partial,
                                                                  int64_t nb,
-                                                                 uint32_t *__restrict__ total_out)
+                                                                 uint32_t *__restrict__ total_out,
+                                                                 uint32_t *__restrict__ d_total,
+                                                                 int64_t capacity)
 {
     uint32_t carry = 0;
     for (int64_t base = 0; base < nb; base += kTile) {
@@ -97,6 +87,13 @@ __global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t *__res
         __syncthreads();
     }
     if (threadIdx.x == 0 && total_out) *total_out = carry;
+    if (threadIdx.x == 0 && d_total) {
+        const bool over = (int64_t)carry > capacity;
+        d_total[0] = over ? (uint32_t)capacity : carry;
+        d_total[1] = over ? 1u : 0u;
+        if (over) d_total[5] = 1u;   // sticky until the host clears it
+        d_total[7] = 0u;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t *__restrict__ in,
@@ -120,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t *__r
         s += v[i];
     }
     uint32_t total;
-    uint32_t off = block_exclusive_scan(s, &total) + partial[blockIdx.x];
+    uint32_t off = block_exclusive_scan(s, &total) + partial[blockIdx.x * (kTile / kScanGrain)];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         tile[threadIdx.x * kItems + i] = off;
@@ -305,20 +302,17 @@ inline int64_t blocks_for(int64_t n) { return (n + kTile - 1) / kTile; }
 
 int64_t scan_tmp_words(int64_t n)
 {
-    return blocks_for(n) + 1;
+    return (n + kScanGrain - 1) / kScanGrain + 1;
 }
 
-hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
-                           bool write_total, hipStream_t s)
+hipError_t launch_count_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                             uint32_t *d_total, int64_t capacity, hipStream_t s)
 {
-    if (n <= 0) {
-        if (write_total) return launch_fill_u32(out, 0u, 1, s);
-        return hipSuccess;
-    }
-    const int64_t nb = blocks_for(n);
-    scan_reduce_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(in, n, tmp);
-    scan_partials_kernel<<<1, kThreads, 0, s>>>(tmp, nb, write_total ? out + n : nullptr);
-    scan_down_kernel<<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(in, out, n, tmp);
+    const int64_t ng = n > 0 ? (n + kScanGrain - 1) / kScanGrain : 0;
+    scan_partials_kernel<<<1, kThreads, 0, s>>>(tmp, ng, out + (n > 0 ? n : 0), d_total,
+                                                capacity);
+    if (n > 0)
+        scan_down_kernel<<<dim3((unsigned)blocks_for(n)), dim3(kThreads), 0, s>>>(in, out, n, tmp);
     return hipGetLastError();
 }
 

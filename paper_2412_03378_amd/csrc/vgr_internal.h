@@ -197,9 +197,11 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
                              const float *sh, hipStream_t s);
 // Size of Buffers::blk_counts (two partial sums per preprocess block).
 int64_t preprocess_blocks(int64_t n, int32_t n_views);
-// Also clears the per-tile ranges and the tile-order counters.
-hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles, hipStream_t s);
-hipError_t launch_finalize_count(const Buffers &b, int64_t m, int64_t capacity, hipStream_t s);
+// Tile counts of the m items in depth order into cnt_sorted, with their sums
+// per kScanGrain items into partial (for launch_count_scan).  Also clears the
+// per-tile ranges and the tile-order counters.
+hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles,
+                                uint32_t *partial, hipStream_t s);
 hipError_t launch_emit(const RenderParams &rp, const Buffers &b, int64_t m, int64_t capacity,
                        hipStream_t s);
 // clear: zero the ranges first (done by launch_gather_counts when it ran).
@@ -238,11 +240,15 @@ hipError_t launch_preprocess_bwd(const RenderParams &rp, const Buffers &b, const
                                  float *d_scales, float *d_dens, float *d_sh, bool accumulate,
                                  float *gnorm, int32_t *vcount, hipStream_t s);
 
-// Exclusive scan of n u32 values (n host-known), out may alias nothing;
-// out[n] receives the total when write_total.  tmp: scan_tmp_words(n) u32.
+// Exclusive scan of the per-item instance counts in (n host-known, out may
+// alias nothing), whose sums per kScanGrain values, tmp[0..ceil(n /
+// kScanGrain)), the count gather already wrote: out = exclusive scan, out[n] =
+// total K, and K (clamped to capacity, with the overflow flags) into
+// d_total[0], [1], [5]; d_total[7] = 0.  tmp: scan_tmp_words(n) u32.
+constexpr int64_t kScanGrain = 256;
 int64_t scan_tmp_words(int64_t n);
-hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
-                           bool write_total, hipStream_t s);
+hipError_t launch_count_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                             uint32_t *d_total, int64_t capacity, hipStream_t s);
 
 // Radix sort of (key, val) u32 pairs; element count read from *d_n on the
 // device, grids sized for n_bound.  Ping-pong buffers keys/vals <-> keys2/vals2;
