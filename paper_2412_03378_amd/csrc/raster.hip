@@ -13,10 +13,12 @@
 // the backward.  The X-ray forward with several pixels per lane walks the
 // batch together, reading the three float4 of the bound pre-test first and
 // the other three only when some pixel of the slot passes.  The backward
-// (whose per-Gaussian reduction needs the wave on one record) walks the
-// batch together too: where the forward kept its masks, it visits only the
-// records that the union of the lanes' masks names; otherwise it pre-tests
-// each record as the X-ray forward does.
+// reduces its per-pair gradients per Gaussian, so lanes that share a record
+// walk together: on 8x8 tiles in the volumetric colour modes each 4x4
+// quarter of the tile (16 lanes) walks the records its own pixels' masks
+// name, four records per step; elsewhere the whole wave walks the records
+// that the union of the lanes' masks names, or, where the forward kept no
+// masks, pre-tests each record as the X-ray forward does.
 //
 // Per (pixel, Gaussian) pair, with the record (centre h + l, A, v0, mz, K',
 // bound form Q, l; see vgr_internal.h) and d = pixel centre - h - l:
@@ -39,9 +41,10 @@
 // dot product with dL/dC, which is all the replay needs) as a running sum
 // starting at T_final * bg.  The geometric gradient of each pair is kept
 // as moments in the Gaussian's L-frame (see the record-gradient layout in
-// vgr_internal.h).  Per Gaussian, the 16 partial sums of the wave are reduced
-// with a transpose-reduce (lane-swap and DPP moves, no LDS) and added with one
-// 16-lane atomic.
+// vgr_internal.h).  The partial sums (13, or 16 with the near-plane segment)
+// of the lanes on one record are reduced with a transpose-reduce (lane-swap
+// and DPP moves, no LDS), after which each lane holds one total, and added
+// with one atomic instruction (for all four records of a quarter-walk step).
 #include "vgr_internal.h"
 
 namespace vgr {
