@@ -95,3 +95,53 @@ def test_tile_resort_rejects_other_modes(R, dev):
         with pytest.raises(L.VgrError) as ei:
             R.forward(*t, wl.cams, _settings(tile=(8, 8), **kw))
         assert ei.value.code == L.VGR_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [2000, 9000])
+def test_tile_resort_long_lists(R, dev, n):
+    """Tile lists longer than one wave's sort (2000 entries: one block sorts
+    it in LDS) and than one block's (9000: sorted runs of 4096 merged).
+    Large isotropic Gaussians cover the whole 16x16 image, so every tile lists
+    all n; their means sit at view depths 6 + i 1e-3 with lateral offsets of
+    +-(5 + 1/3) 1e-3 / a along x (a: the tile-centre ray's x slope), so that
+    on every tile-centre ray the keys lie on a grid of 1e-3 / 3, distinct and
+    further apart than MARGIN_ORDER, in an order that differs from the
+    depth order.  Low opacities keep every Gaussian in every pixel's sum:
+    image and gradients against the oracle."""
+    cam = scenes.axis_camera(4.0, 16, 16, 20.0)
+    a = 4.0 / cam.fx
+    rng = np.random.default_rng(81 + n)
+    delta = 1e-3
+    z = 6.0 + delta * np.arange(n)
+    sgn = rng.choice([-1.0, 1.0], n)
+    x = sgn * (5.0 + 1.0 / 3.0) * delta / a
+    means = np.c_[x, np.zeros(n), z - 4.0]          # world = view - (0, 0, 4)
+    # reddish on one side, bluish on the other: the re-sorting moves one
+    # group forward on each tile, which shows in the image
+    rgb = (np.where(sgn[:, None] > 0, [0.9, 0.1, 0.2], [0.1, 0.2, 0.9])
+           + rng.uniform(-0.05, 0.05, (n, 3)))
+    sigma = 10.0
+    alpha = 0.002 if n < 5000 else 0.001
+    kappa = alpha / (math.sqrt(2.0 * math.pi) * sigma)
+    perm = rng.permutation(n)
+    sc = H.scene(means[perm], [[sigma] * 3], [kappa], rgb=rgb[perm])
+    st = _settings(tile=(8, 8), alpha_min=1e-4, T_min=1e-6, bg=(0.1, 0.2, 0.3))
+    ost = oracle.Settings(alpha_min=st.alpha_min, T_min=st.T_min, bg=st.bg, act=st.act,
+                          resort_tile=(8, 8))
+    ref = oracle.render(sc, cam, ost)
+    base = oracle.render(sc, cam, oracle.Settings(alpha_min=st.alpha_min, T_min=st.T_min,
+                                                  bg=st.bg, act=st.act))
+    moved = float(np.abs(ref["image"] - base["image"]).max())
+    t = G.device_scene(sc, dev)
+    img = R.forward(*t, [cam], st)[0].cpu().numpy()
+    G.check_image(img, ref, label=f"n={n}: largest change from the depth order {moved:.3g}; ")
+    assert moved > 1e-3            # the order matters on this scene
+    assert int((np.asarray(ref["margin_order"]) <= G.MARGIN_ORDER).sum()) == 0
+    rng2 = np.random.default_rng(91 + n)
+    dL = G.upstream(rng2, ref, 3)
+    grads = [torch.zeros_like(v) for v in t]
+    R.backward([torch.from_numpy(dL.astype(np.float32)).to(dev)], *grads)
+    torch.cuda.synchronize()
+    g = oracle.render_backward(sc, cam, ost, dL)
+    G.check_grads({k: gr.cpu().numpy() for k, gr in zip(G.GRAD_KEYS, grads)},
+                  G.sum_backward([g], G.GRAD_KEYS), label=f"n={n} ")
