@@ -659,11 +659,13 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
             HIP_TRY(c, hipEventRecord(c->k_ev, s));
         }
         mark_end(c, ST_PREPROCESS);
-        // depth order of all (view, Gaussian) items; ties keep the item order
+        // depth order of the (view, Gaussian) items that have instances (about
+        // half of them in a wide scene: the others are culled or out of view);
+        // ties keep the item order
         mark(c, ST_SORT_DEPTH);
-        // (the item count the depth sort reads, d_total[2] = m, comes from the
-        // preprocess's totals kernel)
-        HIP_TRY(c, launch_radix_sort(b.depth_key, b.item_ids, b.key2, b.item2, b.d_total + 2, m, 32,
+        // (their number, d_total[6], comes from the preprocess's totals kernel)
+        HIP_TRY(c, launch_compact_items(rp, b, s));
+        HIP_TRY(c, launch_radix_sort(b.depth_key, b.item_ids, b.key2, b.item2, b.d_total + 6, m, 32,
                                      ptr<uint32_t>(c->sort_tmp), s));
         mark_end(c, ST_SORT_DEPTH);
         mark(c, ST_SCAN_EMIT);

@@ -431,8 +431,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
     bool have_sh = false;
     uint32_t total = 0;
 
-    uint32_t nvis = 0;   // views in which this Gaussian has instances
+    // per view, this block's items with instances (wave ballots, added in LDS)
+    __shared__ uint32_t s_vis[kMaxViews];
     const int n_views = MULTI ? rp.n_views : 1;
+    for (int v = (int)threadIdx.x; v < n_views; v += (int)blockDim.x) s_vis[v] = 0u;
+    __syncthreads();
     for (int v = 0; v < n_views; ++v) {
         const ViewInfo &vi = b.views[v];
         const int64_t item = (int64_t)v * rp.n + i;
@@ -591,55 +594,117 @@ __global__ __launch_bounds__(256) void preprocess_kernel(RenderParams rp, Buffer
         }
         if (count == 0) key = 0xFFFFFFFFu;
         if (valid) {
-            b.depth_key[item] = key;
-            b.item_ids[item] = (uint32_t)item;
+            b.key2[item] = key;   // item order; the compaction moves the items with instances
             b.counts[item] = count;
             b.rect[item] = rect;
             total += count;
-            nvis += count > 0 ? 1u : 0u;
         }
+        const uint64_t vis = __builtin_amdgcn_ballot_w64(valid && count > 0);
+        if ((threadIdx.x & 63) == 0 && vis != 0) atomicAdd(&s_vis[v], (uint32_t)__popcll(vis));
     }
     // total instance count K, for sizing the instance lists before the scan,
     // and the number of items with instances (they come first in depth order,
     // so the scan and the emission need cover no more): one partial sum of
     // each per block (count_total_kernel adds them; one atomic per wave on a
     // single address would serialise thousands of updates)
-    __shared__ uint32_t s_wsum[4], s_vsum[4];
-    uint32_t wsum = total, vsum = nvis;
+    __shared__ uint32_t s_wsum[4];
+    uint32_t wsum = total;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        wsum += __shfl_xor(wsum, off, 64);
-        vsum += __shfl_xor(vsum, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s_wsum[threadIdx.x >> 6] = wsum;
-        s_vsum[threadIdx.x >> 6] = vsum;
-    }
+    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+    if ((threadIdx.x & 63) == 0) s_wsum[threadIdx.x >> 6] = wsum;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         b.blk_counts[blockIdx.x] = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-        b.blk_counts[gridDim.x + blockIdx.x] = s_vsum[0] + s_vsum[1] + s_vsum[2] + s_vsum[3];
-    }
+    // items with instances per (view, block), in item order (view-major)
+    for (int v = (int)threadIdx.x; v < n_views; v += (int)blockDim.x)
+        b.blk_counts[gridDim.x + (size_t)v * gridDim.x + blockIdx.x] = s_vis[v];
 }
 
-// Block 0: instance total into d_total[4] (and the item count m into
-// d_total[2], the count the depth sort reads); block 1: items with
-// instances into d_total[6].
-__global__ __launch_bounds__(256) void count_total_kernel(const uint32_t *__restrict__ parts,
-                                                           int64_t n, uint32_t *__restrict__ d_total,
-                                                           int64_t m)
+// Exclusive scan over the 256 threads of a block; *total gets the sum.
+__device__ __forceinline__ uint32_t emit_block_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {   // 256 threads
+        const uint32_t ws = wsum[i];
+        off += i < w ? ws : 0u;
+        tot += ws;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Block 0: instance total into d_total[4].  Block 1: exclusive scan, in
+// place, of the nc per-(view, block) counts of items with instances that
+// follow the nb instance partials, and their total (the items the depth sort
+// takes) into d_total[6].
+__global__ __launch_bounds__(256) void count_total_kernel(uint32_t *__restrict__ parts,
+                                                           int64_t nb, int64_t nc,
+                                                           uint32_t *__restrict__ d_total)
 {
     __shared__ uint32_t s_part[4];
-    const uint32_t *src = parts + blockIdx.x * n;
-    uint32_t acc = 0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) acc += src[k];
+    if (blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int64_t k = threadIdx.x; k < nb; k += 256) acc += parts[k];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        d_total[blockIdx.x == 0 ? 4 : 6] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-        if (blockIdx.x == 0) d_total[2] = (uint32_t)m;
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) d_total[4] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        return;
+    }
+    // 4096 counts per round, 16 consecutive ones per thread
+    uint32_t *c = parts + nb;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nc; base += 4096) {   // uniform
+        const int64_t k0 = base + (int64_t)threadIdx.x * 16;
+        uint32_t v[16], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            v[q] = k0 + q < nc ? c[k0 + q] : 0u;
+            sum += v[q];
+        }
+        uint32_t tot;
+        uint32_t off = carry + emit_block_scan(sum, s_part, &tot);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (k0 + q < nc) c[k0 + q] = off;
+            off += v[q];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) d_total[6] = carry;
+}
+
+// The items with instances, in item order, to the front of (depth_key,
+// item_ids) for the depth sort: one block per (view, preprocess block) of 256
+// items, at the offset the count scan gave it.
+__global__ __launch_bounds__(256) void compact_items_kernel(RenderParams rp, Buffers b,
+                                                             int64_t nb)
+{
+    __shared__ uint32_t s_w[4];
+    const int64_t c = blockIdx.x;
+    const int64_t v = c / nb, blk = c - v * nb;
+    const int64_t i = blk * 256 + threadIdx.x;
+    const int64_t item = v * rp.n + i;
+    const uint32_t key = i < rp.n ? b.key2[item] : 0xFFFFFFFFu;
+    const bool vis = key != 0xFFFFFFFFu;
+    uint32_t tot;
+    const uint32_t r = emit_block_scan(vis ? 1u : 0u, s_w, &tot);
+    if (vis) {
+        const uint32_t pos = b.blk_counts[nb + c] + r;
+        b.depth_key[pos] = key;
+        b.item_ids[pos] = (uint32_t)item;
     }
 }
 
@@ -692,30 +757,6 @@ __global__ __launch_bounds__(kGatherThreads) void gather_counts_kernel(
 constexpr int kEmitRows = 1024;
 constexpr int kEmitThreads = 256;
 constexpr int kEmitRowsPerThread = kEmitRows / kEmitThreads;
-
-// Exclusive scan over the 256 threads of an emission block; *total gets the sum.
-__device__ __forceinline__ uint32_t emit_block_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += t;
-    }
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kEmitThreads / 64; ++i) {
-        const uint32_t ws = wsum[i];
-        off += i < w ? ws : 0u;
-        tot += ws;
-    }
-    __syncthreads();
-    *total = tot;
-    return off + inc - v;
-}
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(RenderParams rp, Buffers b, int64_t m,
                                                   int64_t capacity)
@@ -1353,15 +1394,25 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
 #undef VGR_PRE
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    count_total_kernel<<<2, 256, 0, s>>>(b.blk_counts, (int64_t)grid, b.d_total,
-                                         rp.n * (int64_t)rp.n_views);
+    count_total_kernel<<<2, 256, 0, s>>>(b.blk_counts, (int64_t)grid,
+                                         (int64_t)grid * rp.n_views, b.d_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_items(const RenderParams &rp, const Buffers &b, hipStream_t s)
+{
+    const int64_t nb = grid_for(rp.n, 256);
+    const int64_t blocks = nb * rp.n_views;
+    if (blocks <= 0) return hipSuccess;
+    compact_items_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(rp, b, nb);
     return hipGetLastError();
 }
 
 int64_t preprocess_blocks(int64_t n, int32_t n_views)
 {
-    (void)n_views;   // one thread per Gaussian covers all views
-    return 2 * (int64_t)grid_for(n, 256);   // instance and visible-item partial sums
+    // instance partial sums, then the per-(view, block) counts of items with
+    // instances (one thread per Gaussian covers all views)
+    return (1 + (int64_t)n_views) * (int64_t)grid_for(n, 256);
 }
 
 hipError_t launch_gather_counts(const Buffers &b, int64_t m, int32_t total_tiles,

@@ -126,8 +126,9 @@ struct RenderParams {
 struct Buffers {
     float4 *geom;        // n_views * n records (kRecVec float4 each)
     uint32_t *depth_key; // n_views * n
-    uint32_t *item_ids;  // n_views * n (item = view * n + Gaussian; sorted by depth)
-    uint32_t *key2;      // n_views * n, sort ping-pong
+    uint32_t *item_ids;  // n_views * n (item = view * n + Gaussian; the items with
+                         // instances, sorted by depth)
+    uint32_t *key2;      // n_views * n: depth keys in item order, then sort ping-pong
     uint32_t *item2;     // n_views * n, sort ping-pong
     uint32_t *counts;    // n_views * n, tiles per item (item order)
     uint32_t *cnt_sorted;// n_views * n, tiles per item in depth order
@@ -195,8 +196,13 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const float *means,
                              const float *quats, const float *scales, const float *dens,
                              const float *sh, hipStream_t s);
-// Size of Buffers::blk_counts (two partial sums per preprocess block).
+// Size of Buffers::blk_counts: the instance partial sums per preprocess block,
+// then the counts of items with instances per (view, block).
 int64_t preprocess_blocks(int64_t n, int32_t n_views);
+// The items with instances (depth key != 0xFFFFFFFF in key2, item order) to
+// the front of (depth_key, item_ids), in item order, for the depth sort of
+// d_total[6] items (after the preprocess's count scan).
+hipError_t launch_compact_items(const RenderParams &rp, const Buffers &b, hipStream_t s);
 // Tile counts of the m items in depth order into cnt_sorted, with their sums
 // per kScanGrain items into partial (for launch_count_scan).  Also clears the
 // per-tile ranges and the tile-order counters.
