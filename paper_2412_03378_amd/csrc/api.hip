@@ -95,6 +95,7 @@ struct vgr_ctx {
     hipEvent_t k_ev = nullptr;        // recorded after the instance count copy
     bool stage_pending[2] = { false, false };
     uint32_t *h_words = nullptr;      // pinned, 8 words
+    uint32_t *h_words_dev = nullptr;  // the same words as the device addresses them
     int64_t inst_capacity = 0;
 
     // saved forward
@@ -350,7 +351,8 @@ int vgr_create(vgr_ctx **out, int device)
         hipEventCreateWithFlags(&c->stage_ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->stage_ev[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_words, sizeof(uint32_t) * 8, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_words, sizeof(uint32_t) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->h_words_dev, c->h_words, 0) != hipSuccess) {
         vgr_destroy(c);
         return VGR_ERR_HIP;
     }
@@ -652,12 +654,13 @@ int enqueue_forward(vgr_ctx *c, const Prepared &p, const float *means, const flo
     int64_t K = 0;
     if (m > 0) {
         mark(c, ST_PREPROCESS);
+        // eager: the totals kernel also stores the instance count K and the
+        // number of items with instances in the pinned words, which the host
+        // reads (after k_ev) while the depth sort runs
+        b.h_total = cap < 0 ? c->h_words_dev : nullptr;
         HIP_TRY(c, launch_preprocess(rp, b, means, quats, scales, dens, sh, s));
-        if (cap < 0) {
-            // the instance count K travels to the host while the depth sort runs
-            HIP_TRY(c, hipMemcpyAsync(c->h_words, b.d_total + 4, 12, hipMemcpyDeviceToHost, s));
-            HIP_TRY(c, hipEventRecord(c->k_ev, s));
-        }
+        b.h_total = nullptr;
+        if (cap < 0) HIP_TRY(c, hipEventRecord(c->k_ev, s));
         mark_end(c, ST_PREPROCESS);
         // depth order of the (view, Gaussian) items that have instances (about
         // half of them in a wide scene: the others are culled or out of view);

@@ -650,7 +650,8 @@ __device__ __forceinline__ uint32_t emit_block_scan(uint32_t v, uint32_t *wsum, 
 // takes) into d_total[6].
 __global__ __launch_bounds__(256) void count_total_kernel(uint32_t *__restrict__ parts,
                                                            int64_t nb, int64_t nc,
-                                                           uint32_t *__restrict__ d_total)
+                                                           uint32_t *__restrict__ d_total,
+                                                           uint32_t *__restrict__ h_total)
 {
     __shared__ uint32_t s_part[4];
     if (blockIdx.x == 0) {
@@ -660,7 +661,11 @@ __global__ __launch_bounds__(256) void count_total_kernel(uint32_t *__restrict__
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) d_total[4] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        if (threadIdx.x == 0) {
+            const uint32_t K = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+            d_total[4] = K;
+            if (h_total) h_total[0] = K;
+        }
         return;
     }
     // 4096 counts per round, 16 consecutive ones per thread
@@ -683,7 +688,10 @@ __global__ __launch_bounds__(256) void count_total_kernel(uint32_t *__restrict__
         }
         carry += tot;
     }
-    if (threadIdx.x == 0) d_total[6] = carry;
+    if (threadIdx.x == 0) {
+        d_total[6] = carry;
+        if (h_total) h_total[2] = carry;
+    }
 }
 
 // The items with instances, in item order, to the front of (depth_key,
@@ -1395,7 +1403,7 @@ hipError_t launch_preprocess(const RenderParams &rp, const Buffers &b, const flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     count_total_kernel<<<2, 256, 0, s>>>(b.blk_counts, (int64_t)grid,
-                                         (int64_t)grid * rp.n_views, b.d_total);
+                                         (int64_t)grid * rp.n_views, b.d_total, b.h_total);
     return hipGetLastError();
 }
 

@@ -165,6 +165,8 @@ struct Buffers {
     uint32_t *d_total;   // [0] = instance count K, [1] overflow flag, [4] K from the
                          // preprocess, [6] items with instances (the first of the
                          // depth order)
+    uint32_t *h_total;   // or null: pinned host words (device address) that the totals
+                         // kernel fills with d_total[4] at [0] and d_total[6] at [2]
     unsigned long long *counters;  // pair and visit counters: forward [0..4], backward [8..12]
     uint2 *wg_time;      // timed runs (else null): per rasteriser workgroup (launch slot) the
                          // compute unit key and its duration in clock ticks, forward
