@@ -650,16 +650,54 @@ __device__ __forceinline__ void keep_send_add(float (&v)[16], int n, bool hi)
     }
 }
 
+// Step 2 for the pairs (v[k], v[k+4]), k < 3: lanes with bit 3 clear (banks
+// 0-1 of each row) add slot k across l ^ 8, the others slot k + 4, each lane
+// writing the sum of the slot it keeps with one bank-masked DPP add (the
+// compiler forms DPP adds only with every bank enabled, and then needs two
+// selects to route the slots).  The s_nop gives the two wait states a DPP read
+// needs after a VALU write of its source VGPR.
+#define VGR_PAIR_ADD8(D, A, C)                                                   \
+    "v_add_f32_dpp " D ", " A ", " A " row_ror:8 row_mask:0xf bank_mask:0x3\n\t" \
+    "v_add_f32_dpp " D ", " C ", " C " row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+
+__device__ __forceinline__ void pair_add8x3(float (&v)[16])
+{
+    float r0, r1, r2;
+    asm volatile("s_nop 1\n\t" VGR_PAIR_ADD8("%0", "%3", "%6") VGR_PAIR_ADD8("%1", "%4", "%7")
+                     VGR_PAIR_ADD8("%2", "%5", "%8")
+                 : "=&v"(r0), "=&v"(r1), "=&v"(r2)
+                 : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[4]), "v"(v[5]), "v"(v[6]));
+    v[0] = r0;
+    v[1] = r1;
+    v[2] = r2;
+}
+
+// The same for the four pairs k < 4.
+__device__ __forceinline__ void pair_add8x4(float (&v)[16])
+{
+    float r0, r1, r2, r3;
+    asm volatile("s_nop 1\n\t" VGR_PAIR_ADD8("%0", "%4", "%8") VGR_PAIR_ADD8("%1", "%5", "%9")
+                     VGR_PAIR_ADD8("%2", "%6", "%10") VGR_PAIR_ADD8("%3", "%7", "%11")
+                 : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+                 : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]),
+                   "v"(v[6]), "v"(v[7]));
+    v[0] = r0;
+    v[1] = r1;
+    v[2] = r2;
+    v[3] = r3;
+}
+#undef VGR_PAIR_ADD8
+
 template <bool N13>
 __device__ __forceinline__ float quarter_reduce16(float (&v)[16], int lane)
 {
     pair_step1<N13>(v, [](float a, float b) { return swap_add16(a, b); });
     if constexpr (N13) {
         // slot 7 is empty: slot 3 only needs its sum across l ^ 8
-        keep_send_add<kDppRowRor8, 4>(v, 3, lane & 8);
+        pair_add8x3(v);
         v[3] += dpp_move<kDppRowRor8>(v[3]);
     } else {
-        keep_send_add<kDppRowRor8, 4>(v, 4, lane & 8);
+        pair_add8x4(v);
     }
     keep_send_add<kDppQuadXor2, 2>(v, 2, lane & 2);
     keep_send_add<kDppQuadXor1, 1>(v, 1, lane & 1);
