@@ -539,10 +539,9 @@ __device__ __forceinline__ float swap_add16(float a, float b)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// DPP lane moves (gfx9 encodings): row rotate right by 8, half-row mirror,
-// quad permutations [2,3,0,1] and [1,0,3,2].
+// DPP lane moves (gfx9 encodings): row rotate right by 8, quad permutations
+// [2,3,0,1] and [1,0,3,2].
 constexpr int kDppRowRor8 = 0x128;
-constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor2 = 0x4E;
 constexpr int kDppQuadXor1 = 0xB1;
 
@@ -594,27 +593,38 @@ __device__ __forceinline__ int wave_index(int lane)
     return N13 ? n13_index((lane >> 2) & 7, (lane >> 5) & 1) : lane >> 2;
 }
 
+// Steps 3 and 4 of wave_reduce16 as DPP adds with bank masks, each lane
+// writing the sum of the slot it keeps: across l ^ 8 the lanes of banks 0-1 of
+// each row keep slot 0 or 1 and those of banks 2-3 slot 2 or 3; across the
+// half-row mirror (7 - i within each 8 lanes) banks 0 and 2 keep the first
+// and banks 1 and 3 the second.  The compiler forms DPP adds only with every
+// bank enabled and then routes the slots with selects.  The s_nops give the
+// two wait states a DPP read needs after a VALU write of its source VGPR.
+__device__ __forceinline__ float wave_steps34(float v0, float v1, float v2, float v3)
+{
+    float r0, r1, out;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %1, %3, %3 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %1, %5, %5 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %2, %4, %4 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %2, %6, %6 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "s_nop 0\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa"
+        : "=&v"(out), "=&v"(r0), "=&v"(r1)
+        : "v"(v0), "v"(v1), "v"(v2), "v"(v3));
+    return out;
+}
+
 template <bool N13>
 __device__ __forceinline__ float wave_reduce16(float (&v)[16], int lane)
 {
+    (void)lane;
     pair_step1<N13>(v, [](float a, float b) { return swap_add32(a, b); });
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = swap_add16(v[k], v[k + 4]);
-    {
-        const bool hi = lane & 8;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float send = hi ? v[k] : v[k + 2];
-            const float keep = hi ? v[k + 2] : v[k];
-            v[k] = keep + dpp_move<kDppRowRor8>(send);
-        }
-    }
-    {
-        const bool hi = lane & 4;
-        const float send = hi ? v[0] : v[1];
-        const float keep = hi ? v[1] : v[0];
-        v[0] = keep + dpp_move<kDppRowHalfMirror>(send);
-    }
+    v[0] = wave_steps34(v[0], v[1], v[2], v[3]);
     v[0] += dpp_move<kDppQuadXor2>(v[0]);
     v[0] += dpp_move<kDppQuadXor1>(v[0]);
     return v[0];
@@ -700,8 +710,18 @@ __device__ __forceinline__ float quarter_reduce16(float (&v)[16], int lane)
         pair_add8x4(v);
     }
     keep_send_add<kDppQuadXor2, 2>(v, 2, lane & 2);
-    keep_send_add<kDppQuadXor1, 1>(v, 1, lane & 1);
-    return v[0];
+    // across l ^ 1 both slots are summed, then each lane takes its own: two
+    // DPP adds (written out, so that the compiler neither sinks the adds into
+    // the atomic's branch nor leaves the moves apart) and a select, instead of
+    // two selects, a DPP move and an add.  The s_nop: two wait states before a
+    // DPP read of a VGPR that a VALU instruction has just written.
+    float s0, s1;
+    asm volatile("s_nop 1\n\t"
+                 "v_add_f32_dpp %0, %2, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+                 "v_add_f32_dpp %1, %3, %3 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+                 : "=&v"(s0), "=&v"(s1)
+                 : "v"(v[0]), "v"(v[1]));
+    return (lane & 1) ? s1 : s0;
 }
 
 // OR of a 64-bit lane mask over the lane's quarter (as in quarter_reduce16).
